@@ -1,0 +1,549 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+Every check here compares the oracle with something independent of its code:
+hand-worked fixtures from the sketch definition, published reference values,
+library shortest paths (scipy), closed forms derived from the paper's
+equations, brute force, and statistical properties of the estimator.
+"""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.sparse.csgraph import dijkstra as sp_dijkstra
+
+import graphgen as gg
+import oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def csr_matrix(g):
+    w = g.w if g.w is not None else np.ones(g.n_arcs, np.uint32)
+    return sp.csr_matrix((w.astype(np.float64), g.col.astype(np.int64), g.row_ptr.astype(np.int64)),
+                         shape=(g.n, g.n))
+
+
+def apsp(g):
+    return sp_dijkstra(csr_matrix(g), directed=True)
+
+
+ZOO = [
+    lambda: gg.er(150, 6, 1, wmax=10),
+    lambda: gg.er(200, 3, 2),                       # sparse: several components
+    lambda: gg.rmat(8, 1500, 3),                    # R-MAT with isolated vertices
+    lambda: gg.rmat(7, 900, 4, wmax=100),
+    lambda: gg.grid(9, 9),                          # massive distance ties
+    lambda: gg.clique(16, wmax=3),
+    lambda: gg.disjoint_union(gg.path(25), gg.star(15, wmax=5), gg.empty(3)),
+    lambda: gg.random_tree(120, 5, wmax=4),
+    lambda: gg.cycle(31),
+]
+
+
+# ---------------------------------------------------------------- ranks
+def test_splitmix64_published_outputs():
+    vals = [int(x, 16) for x in open(os.path.join(GOLDEN, "splitmix64_state0.txt"))
+            if x.strip() and not x.startswith("#")]
+    golden_gamma = 0x9E3779B97F4A7C15
+    got = [O.splitmix64((i * golden_gamma) % (1 << 64)) for i in range(3)]
+    assert got == vals
+
+
+def test_rank_permutation_inverts():
+    for seed in (0, 1, 12345):
+        key = O.rank_key(seed)
+        assert O.perm_check_range(key, 0, 1 << 22)
+        assert O.perm_check_range(key, 0xFFFFFFFF - (1 << 20) + 1, 1 << 20)
+    r, p = O.ranks(100000, 3)
+    assert len(np.unique(r)) == 100000 and len(np.unique(p)) == 100000
+
+
+def test_ranks_look_uniform():
+    r, _ = O.ranks(1 << 16, 9)
+    # each of 16 equal bins of [0, 2^32) should hold 4096 +- a few sigma
+    counts = np.bincount((r >> np.uint32(28)).astype(np.int64), minlength=16)
+    assert np.all(np.abs(counts - 4096) < 6 * math.sqrt(4096))
+
+
+# ---------------------------------------------------------------- ADS
+def _parse_path4():
+    rows = {}
+    for line in open(os.path.join(GOLDEN, "ads_path4.txt")):
+        if not line.strip() or line.startswith("#"):
+            continue
+        head, body = line.split(":")
+        k, v = map(int, head.split())
+        ents = [tuple(map(int, e.strip("()").split(","))) for e in body.split()]
+        rows[(k, v)] = ents
+    return rows
+
+
+def test_ads_hand_worked_path4():
+    g = gg.path(4)
+    rank = np.array([30, 10, 40, 20], np.uint32)
+    rows = _parse_path4()
+    for fn in (O.ads_brute, O.ads_pruned, O.ads_rounds):
+        for k in (1, 2):
+            sk = fn(g, k, rank=rank)
+            for v in range(4):
+                a, b = sk["off"][v], sk["off"][v + 1]
+                got = list(zip(sk["rank"][a:b].tolist(), sk["dist"][a:b].tolist()))
+                assert got == rows[(k, v)], (fn.__name__, k, v)
+
+
+def test_hipest_hand_worked_path4():
+    g = gg.path(4)
+    rank = np.array([30, 10, 40, 20], np.uint32)
+    sk = O.ads_brute(g, 1, rank=rank)
+    T, a = O.hipest(sk, 1)
+    # ADS(0) = (30,0) (10,1): T = [2^32, 30]
+    assert T[0] == 1 << 32 and T[1] == 30
+    assert a[0] == 1.0 and a[1] == 2.0 ** 32 / 30
+
+
+@pytest.mark.parametrize("gi", range(len(ZOO)))
+@pytest.mark.parametrize("k", [1, 2, 3, 16])
+def test_ads_three_ways_agree(gi, k):
+    """P1: brute force (Alg. 1) = pruned Dijkstra = Alg. 2 supersteps."""
+    g = ZOO[gi]()
+    seed = 11 + gi
+    a = O.ads_brute(g, k, seed=seed)
+    b = O.ads_pruned(g, k, seed=seed)
+    c = O.ads_rounds(g, k, seed=seed)
+    for key in ("off", "rank", "dist", "id"):
+        assert np.array_equal(a[key], b[key]), key
+        assert np.array_equal(a[key], c[key]), key
+
+
+@pytest.mark.parametrize("gi", [0, 2, 3, 6])
+def test_ads_k_at_least_n_is_exact_ball(gi):
+    """P2: with k >= n every reachable vertex is in the sketch at its exact
+    shortest-path distance (scipy Dijkstra), and every HIP weight is 1."""
+    g = ZOO[gi]()
+    k = g.n
+    sk = O.ads_pruned(g, k, seed=3)
+    D = apsp(g)
+    T, a = O.hipest(sk, k)
+    assert np.all(a == 1.0)
+    rank, _ = O.ranks(g.n, 3)
+    for v in range(g.n):
+        lo, hi = sk["off"][v], sk["off"][v + 1]
+        reach = np.nonzero(np.isfinite(D[v]))[0]
+        assert hi - lo == len(reach)
+        ids = sk["id"][lo:hi]
+        assert np.array_equal(np.sort(ids), reach)
+        assert np.array_equal(sk["dist"][lo:hi], D[v, ids].astype(np.uint32))
+        assert np.array_equal(sk["rank"][lo:hi], rank[ids])
+
+
+@pytest.mark.parametrize("gi", [0, 1, 3, 4, 7])
+@pytest.mark.parametrize("k", [1, 4, 8])
+def test_ads_bottomk_of_every_ball(gi, k):
+    """P3: for every v and radius D, the k smallest ranks among sketch entries
+    with distance <= D are the k smallest ranks of the true ball B(v, D)
+    (scipy distances); first entry is (r(v), 0); entries sorted by (d, id);
+    recorded distances are the true distances."""
+    g = ZOO[gi]()
+    seed = 5
+    sk = O.ads_pruned(g, k, seed=seed)
+    rank, _ = O.ranks(g.n, seed)
+    D = apsp(g)
+    for v in range(0, g.n, 3):
+        lo, hi = sk["off"][v], sk["off"][v + 1]
+        ids, dist, rk = sk["id"][lo:hi], sk["dist"][lo:hi].astype(np.int64), sk["rank"][lo:hi]
+        assert ids[0] == v and dist[0] == 0 and rk[0] == rank[v]
+        key = dist * (1 << 32) + ids.astype(np.int64)
+        assert np.all(np.diff(key) > 0)
+        assert np.array_equal(dist, D[v, ids].astype(np.int64))
+        fin = D[v][np.isfinite(D[v])]
+        for rad in np.unique(fin):
+            ball = np.nonzero(D[v] <= rad)[0]
+            want = np.sort(rank[ball])[:k]
+            got = np.sort(rk[dist <= rad])[:k]
+            assert np.array_equal(want, got), (v, rad)
+
+
+def test_ads_mean_size_matches_expectation():
+    """P4: with a rank-independent order the i-th listed vertex enters with
+    probability min(1, k/i), so E|ADS(v)| = sum_{i<=reach(v)} min(1, k/i)."""
+    g = gg.er(400, 8, 21)
+    D = apsp(g)
+    reach = np.isfinite(D).sum(axis=1)
+    for k in (2, 8):
+        expect = sum(sum(min(1.0, k / i) for i in range(1, r + 1)) for r in reach)
+        tot = [O.ads_pruned(g, k, seed=s)["off"][-1] for s in range(6)]
+        assert abs(np.mean(tot) / expect - 1.0) < 0.03
+        # the paper's size order k log n bounds the mean size
+        assert np.mean(tot) / g.n <= k * math.log(g.n) + k
+
+
+def test_prune_is_associative():
+    """P5: prune(A u B) = prune(prune(A) u prune(B)) on random multisets."""
+    rng = np.random.default_rng(0)
+    for trial in range(200):
+        k = int(rng.integers(1, 6))
+        m = int(rng.integers(1, 60))
+        ids = rng.integers(0, 30, m).astype(np.uint32)
+        rank = O.ranks(30, trial)[0][ids]
+        d = rng.integers(0, 8, m).astype(np.uint64)
+        cut = int(rng.integers(0, m + 1))
+        full = O.prune(d, ids, rank, k)
+        pa = O.prune(d[:cut], ids[:cut], rank[:cut], k)
+        pb = O.prune(d[cut:], ids[cut:], rank[cut:], k)
+        both = O.prune(np.concatenate([pa[0], pb[0]]), np.concatenate([pa[1], pb[1]]),
+                       np.concatenate([pa[2], pb[2]]), k)
+        for x, y in zip(full, both):
+            assert np.array_equal(x, y)
+        # idempotent
+        again = O.prune(*full, k)
+        for x, y in zip(full, again):
+            assert np.array_equal(x, y)
+
+
+def test_hip_estimator_unbiased():
+    """P6: over many seeds the HIP estimate of |B(v, d)| averages to the
+    true size (within 4 standard errors)."""
+    g = gg.er(60, 4, 3, wmax=3)
+    D = apsp(g)
+    k = 2
+    queries = [(0, 2.0), (0, 4.0), (7, 3.0), (13, 6.0)]
+    est = {q: [] for q in queries}
+    S = 1500
+    for s in range(S):
+        sk = O.ads_brute(g, k, seed=1000 + s)
+        _, a = O.hipest(sk, k)
+        for (v, rad) in queries:
+            lo, hi = sk["off"][v], sk["off"][v + 1]
+            est[(v, rad)].append(a[lo:hi][sk["dist"][lo:hi] <= rad].sum())
+    for (v, rad) in queries:
+        x = np.array(est[(v, rad)])
+        truth = (D[v] <= rad).sum()
+        se = x.std(ddof=1) / math.sqrt(S)
+        assert abs(x.mean() - truth) <= 4 * se + 1e-9, (v, rad, x.mean(), truth)
+        # the paper reports average relative error below 50% even for small k
+        assert np.mean(np.abs(x - truth) / truth) < 0.5
+
+
+# ---------------------------------------------------------------- solve
+def _problems():
+    out = []
+    out.append(gg.tiny_er(1))
+    out.append(gg.with_problem(gg.er(300, 5, 7, wmax=10), 7, cost="uniform", cost_lo=1, cost_hi=200))
+    out.append(gg.with_problem(gg.rmat(9, 3000, 8), 8, cost="uniform", cost_lo=1, cost_hi=1000))
+    out.append(gg.with_problem(gg.rmat(9, 3000, 9, wmax=100), 9, cost="lognormal", fac_frac=0.1))
+    out.append(gg.with_problem(gg.grid(12, 12, wmax=4), 4, cost="uniform", cost_lo=1, cost_hi=60))
+    return out
+
+
+PROBLEMS = _problems()
+
+
+def _solve(g, k, seed, eps=0.1):
+    rc, r = O.solve(g, k, seed, eps)
+    assert rc == 0
+    return r
+
+
+def _ladder(r, count):
+    return O.ladder(r["alpha0"], 0.1, count) if count else np.zeros(0)
+
+
+@pytest.mark.parametrize("pi", range(len(PROBLEMS)))
+def test_telescoping_identity(pi):
+    """P7: the incremental q(f) of Eq. 2/Eq. 3 equals the telescoped closed
+    form sum_j a_j ((1+eps) a[min(t, t_c)] - beta(d_j)) over sampled clients
+    counted from rung max(1, j(d_j)), in exact rational arithmetic."""
+    from fractions import Fraction as Fr
+    g = PROBLEMS[pi]
+    k, seed, eps = 8, 3, 0.1
+    r = _solve(g, k, seed, eps)
+    T = r["n_rungs"]
+    lad = O.ladder(r["alpha0"], eps, T + 2)
+    sk = O.ads_pruned(g, k, seed=seed)
+    _, a = O.hipest(sk, k)
+    fr = r["freeze_rung"]
+    isC = np.ones(g.n, bool) if g.is_client is None else g.is_client.astype(bool)
+    served = isC & (r["assign"] != O.NONE)
+    one_eps = Fr(1) + Fr(eps)
+    checked = 0
+    for f in range(g.n):
+        if g.fac_cost[f] == O.NOT_FACILITY:
+            continue
+        tf = r["open_rung"][f]
+        t_end = tf if 1 <= tf <= T else T
+        total = Fr(0)
+        for j in range(sk["off"][f], sk["off"][f + 1]):
+            c = sk["id"][j]
+            if not served[c]:
+                continue
+            d = float(sk["dist"][j])
+            if not d <= lad[T]:
+                continue                      # never crossed
+            jb = 0
+            while not d <= lad[jb]:
+                jb += 1
+            first = max(1, jb)
+            tc = fr[c] if 1 <= fr[c] <= T else 10 ** 9
+            last = min(t_end, tc)
+            if first > last:
+                continue
+            total += Fr(a[j]) * (one_eps * Fr(lad[last]) - Fr(lad[jb]))
+        q = r["q"][f]
+        if total == 0:
+            assert q == 0.0
+        else:
+            assert abs(Fr(q) / total - 1) <= Fr(1, 10 ** 12), (f, q, float(total))
+        checked += 1
+    assert checked > 0
+
+
+def _alg3_exact(g, eps, lad, T):
+    """Alg. 3 on exact shortest-path distances with the paper's bucketing:
+    LHS(f) = sum over clients with beta(d) <= alpha(c) of (1+eps)alpha(c) -
+    beta(d), alpha(c) = current alpha for unfrozen clients and the freeze
+    rung's alpha for frozen ones; freezing with (1+eps)alpha(c)."""
+    from fractions import Fraction as Fr
+    D = apsp(g)
+    n = g.n
+    isF = g.fac_cost != O.NOT_FACILITY
+    isC = np.ones(n, bool) if g.is_client is None else g.is_client.astype(bool)
+    served = isC & np.isfinite(D[:, isF].min(axis=1) if isF.any() else np.zeros(n))
+    frz = np.full(n, -1)
+    opn = np.full(n, -1)
+    near = []
+    jb = {}
+    for t in range(1, T + 1):
+        alpha = lad[t]
+        for f in np.nonzero(isF & (opn < 0))[0]:
+            lhs = Fr(0)
+            for c in np.nonzero(served & np.isfinite(D[f]))[0]:
+                d = float(D[f, c])
+                if not d <= lad[T]:
+                    continue                  # beyond every evaluated rung
+                if d not in jb:
+                    j = 0
+                    while not d <= lad[j]:
+                        j += 1
+                    jb[d] = j
+                ac = t if frz[c] < 0 else frz[c]
+                if max(1, jb[d]) <= ac:
+                    lhs += (Fr(1) + Fr(eps)) * Fr(lad[ac]) - Fr(lad[jb[d]])
+            cf = Fr(int(g.fac_cost[f]))
+            if abs(lhs - cf) < Fr(1, 10 ** 9) * max(cf, 1):
+                near.append(f)
+            if lhs >= cf:
+                opn[f] = t
+        O_now = np.nonzero(opn >= 0)[0]
+        rho = (1.0 + eps) * alpha
+        if len(O_now):
+            dO = D[:, O_now].min(axis=1)
+            for c in np.nonzero(served & (frz < 0))[0]:
+                if dO[c] <= rho:
+                    frz[c] = t
+    return opn, frz, near
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_exact_alg3_when_k_covers_graph(seed):
+    """P8: with k >= n the sketches are exact balls, and the opening phase is
+    Alg. 3 evaluated on exact distances (bucketed); decisions agree except at
+    flagged near-ties."""
+    g = gg.with_problem(gg.er(40, 4, seed, wmax=4), seed, cost="uniform", cost_lo=1, cost_hi=30)
+    eps = 0.1
+    r = _solve(g, g.n, seed, eps)
+    T = r["n_rungs"]
+    lad = O.ladder(r["alpha0"], eps, T + 2)
+    opn, frz, near = _alg3_exact(g, eps, lad, T)
+    assert not near
+    for f in range(g.n):
+        want = opn[f] if opn[f] >= 0 else O.RUNG_NONE
+        assert r["open_rung"][f] == want
+    for c in range(g.n):
+        if r["freeze_rung"][c] in (O.RUNG_END, O.RUNG_GUARD, O.RUNG_NONE):
+            assert frz[c] < 0
+        else:
+            assert r["freeze_rung"][c] == frz[c]
+
+
+@pytest.mark.parametrize("pi", range(len(PROBLEMS)))
+def test_freeze_rungs_match_multisource_distance(pi):
+    """P9: freeze_rung[c] = min{t : d(c, O_t) <= (1+eps) a[t]} with O_t the
+    facilities open by rung t (scipy distances)."""
+    g = PROBLEMS[pi]
+    eps = 0.1
+    r = _solve(g, 8, 4, eps)
+    T = r["n_rungs"]
+    lad = O.ladder(r["alpha0"], eps, T + 2)
+    D = apsp(g)
+    orung = r["open_rung"]
+    served = r["assign"] != O.NONE
+    best = np.full(g.n, np.inf)
+    want = np.full(g.n, -1)
+    for t in range(1, T + 1):
+        new = np.nonzero(orung == t)[0]
+        if len(new):
+            best = np.minimum(best, D[:, new].min(axis=1))
+        rho = (1.0 + eps) * lad[t]
+        hit = served & (want < 0) & (best <= rho)
+        want[hit] = t
+    for c in np.nonzero(served)[0]:
+        fr = r["freeze_rung"][c]
+        if fr == O.RUNG_END:
+            assert want[c] < 0
+        else:
+            assert fr == want[c]
+
+
+@pytest.mark.parametrize("pi", range(len(PROBLEMS)))
+def test_mis_is_greedy_maximal_independent(pi):
+    """P10: per rung, S_t is independent and maximal in the explicit H-bar_t
+    built from scipy distances, and equals the greedy MIS in priority order."""
+    g = PROBLEMS[pi]
+    eps, seed = 0.1, 6
+    r = _solve(g, 8, seed, eps)
+    T = r["n_rungs"]
+    lad = O.ladder(r["alpha0"], eps, T + 2)
+    D = apsp(g)
+    _, prio = O.ranks(g.n, seed)
+    orung, frung, opened = r["open_rung"], r["freeze_rung"], r["open"].astype(bool)
+    for t in np.unique(orung[(orung >= 1) & (orung <= T)]):
+        Ft = np.nonzero(orung == t)[0]
+        Ct = np.nonzero(frung == t)[0]
+        rho = (1.0 + eps) * lad[t]
+        H = D[np.ix_(Ft, Ct)] <= rho
+        conf = (H.astype(np.int64) @ H.T.astype(np.int64)) > 0
+        np.fill_diagonal(conf, False)
+        order = np.argsort(prio[Ft])
+        chosen = np.zeros(len(Ft), bool)
+        for i in order:
+            if not (conf[i] & chosen).any():
+                chosen[i] = True
+        assert np.array_equal(opened[Ft], chosen)
+        sel = np.nonzero(chosen)[0]
+        assert not conf[np.ix_(sel, sel)].any()          # independent
+        for i in range(len(Ft)):                          # maximal
+            assert chosen[i] or (conf[i] & chosen).any()
+    # guard facilities are open; nothing else outside a rung is
+    outside = ~((orung >= 1) & (orung <= T))
+    assert np.array_equal(opened[outside], orung[outside] == O.RUNG_GUARD)
+
+
+@pytest.mark.parametrize("pi", range(len(PROBLEMS)))
+def test_assignment_and_cost_brute_force(pi):
+    """P11 (part): assignment = nearest facility of S with smaller id on ties,
+    dist = d(c, S), cost = sum c(f) + sum d(c, S), all from scipy APSP."""
+    g = PROBLEMS[pi]
+    r = _solve(g, 8, 2)
+    D = apsp(g)
+    S = np.nonzero(r["open"])[0]
+    isF = g.fac_cost != O.NOT_FACILITY
+    isC = np.ones(g.n, bool) if g.is_client is None else g.is_client.astype(bool)
+    reach = np.isfinite(D[:, isF]).any(axis=1) & isC
+    cost = int(g.fac_cost[S].astype(np.int64).sum())
+    for c in range(g.n):
+        if not reach[c]:
+            assert r["assign"][c] == O.NONE and r["dist"][c] == O.NONE
+            continue
+        dS = D[c, S]
+        m = dS.min()
+        assert np.isfinite(m)
+        f = S[np.nonzero(dS == m)[0][0]]
+        assert r["assign"][c] == f and r["dist"][c] == int(m)
+        cost += int(m)
+    assert r["total_cost"] == cost
+    assert r["n_unreachable"] == int((isC & ~reach).sum())
+    assert r["n_open"] == len(S)
+
+
+def _opt_python(g):
+    D = apsp(g)
+    F = np.nonzero(g.fac_cost != O.NOT_FACILITY)[0]
+    isC = np.ones(g.n, bool) if g.is_client is None else g.is_client.astype(bool)
+    C = np.nonzero(isC & np.isfinite(D[:, F]).any(axis=1))[0]
+    best = math.inf
+    for size in range(1, len(F) + 1):
+        for S in itertools.combinations(F, size):
+            d = D[np.ix_(C, list(S))].min(axis=1)
+            if not np.all(np.isfinite(d)):
+                continue
+            best = min(best, int(g.fac_cost[list(S)].sum()) + int(d.sum()))
+    return best
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_cost_vs_exhaustive_opt(seed):
+    """P11: cost >= OPT (exhaustive over facility subsets, n <= 12).  The
+    (3+eps) bound is logged, not asserted: same-rung H edges and sketch
+    estimates fall outside the theorems' proofs."""
+    n = 8 + seed % 5
+    g = gg.with_problem(gg.er(n, 3, seed, wmax=6), seed, cost="uniform", cost_lo=1, cost_hi=25)
+    opt = _opt_python(g)
+    assert O.opt_exhaustive(g) == opt
+    for k in (1, 4, n):
+        r = _solve(g, k, seed)
+        assert r["total_cost"] >= opt
+        print(f"n={n} seed={seed} k={k} cost/OPT={r['total_cost'] / opt:.3f}")
+
+
+def test_stall_guard_facilities_not_clients():
+    """When facilities are not clients and sit away from every client, no
+    sketch sees an unfrozen client and no client sees an open facility: the
+    guard opens each client's gamma minimiser (reading of the stall case)."""
+    g = gg.path(6)
+    g.fac_cost = np.array([gg.NOT_FACILITY, gg.NOT_FACILITY, gg.NOT_FACILITY, 5, 7, gg.NOT_FACILITY],
+                          np.uint32)
+    g.is_client = np.array([1, 1, 1, 0, 0, 0], np.uint8)
+    r = _solve(g, 1, 3)
+    # rank order decides whether the sketches of 3 and 4 hold a client; in
+    # every case each client ends served and the cost is consistent
+    assert np.all(r["assign"][:3] != O.NONE)
+    D = apsp(g)
+    S = np.nonzero(r["open"])[0]
+    assert r["total_cost"] == int(g.fac_cost[S].sum()) + int(D[:3][:, S].min(axis=1).sum())
+
+
+def test_stall_guard_fires():
+    """A facility that no client's distance can reach within its sketch: the
+    facility is a client-free leaf, and k=1 hides every client from it."""
+    # star: centre 0 is a facility but not a client; leaves are clients, no
+    # other facility.  The centre's sketch holds only vertices with rank below
+    # its own along (d,id) order; pick a seed where it holds no client.
+    for seed in range(200):
+        g = gg.star(5)
+        g.fac_cost = np.array([3, gg.NOT_FACILITY, gg.NOT_FACILITY, gg.NOT_FACILITY, gg.NOT_FACILITY],
+                              np.uint32)
+        g.is_client = np.array([0, 1, 1, 1, 1], np.uint8)
+        sk = O.ads_pruned(g, 1, seed=seed)
+        if sk["off"][1] - sk["off"][0] == 1:
+            r = _solve(g, 1, seed)
+            assert r["n_guard"] == 1
+            assert r["open_rung"][0] == O.RUNG_GUARD
+            assert np.all(r["freeze_rung"][1:] == O.RUNG_GUARD)
+            assert r["total_cost"] == 3 + 4
+            return
+    pytest.fail("no seed hides every client from the centre")
+
+
+def test_validation_errors():
+    g = gg.er(30, 3, 1, wmax=5)
+    g = gg.with_problem(g, 1)
+    assert O.validate(g, 4, 0.1) == O.OK
+    assert O.validate(g, 0, 0.1) == O.EINVAL
+    assert O.validate(g, 4, 0.0) == O.EINVAL
+    assert O.validate(g, 4, float("nan")) == O.EINVAL
+    bad = gg.Graph(g.n, g.row_ptr.copy(), g.col.copy(), g.w.copy(), g.fac_cost)
+    bad.w[0] = 0
+    assert O.validate(bad, 4, 0.1) == O.EINVAL
+    bad = gg.Graph(g.n, g.row_ptr.copy(), g.col.copy(), g.w.copy(), g.fac_cost)
+    bad.w[0] += 1                                    # asymmetric weight
+    assert O.validate(bad, 4, 0.1) == O.EINVAL
+    bad = gg.Graph(g.n, g.row_ptr.copy(), g.col.copy(), g.w.copy(), g.fac_cost)
+    bad.col[0] = 0 if bad.col[0] != 0 else 1         # breaks symmetry / self loop
+    assert O.validate(bad, 4, 0.1) == O.EINVAL
+    huge = gg.path(3, wmax=None)
+    huge.w = np.full(huge.n_arcs, 0x7FFFFFFF, np.uint32)
+    huge.fac_cost = np.array([1, 1, 1], np.uint32)
+    assert O.validate(huge, 1, 0.1) == O.ERANGE
