@@ -1,0 +1,171 @@
+/*
+ * fl.h -- C ABI of the MI355X (gfx950) library for sketch-based facility
+ * location on graphs, after "Scalable Facility Location for Massive Graphs on
+ * Pregel-like Systems" (arXiv 1503.03635).
+ *
+ * Problem (Sec. 3.1 of the paper): an undirected graph G = (V, E, w), a set of
+ * facilities F with opening costs c(f), a set of clients C, distances d given
+ * by shortest paths in G.  Pick S subset of F minimising
+ *     sum_{f in S} c(f) + sum_{c in C} d(c, S).
+ * Method (Sec. 3.3 and Sec. 4): bottom-k all-distances sketches (ADS) for
+ * every vertex, the opening loop of Alg. 4/Alg. 5 driven by HIP-estimator
+ * neighbourhood estimates (Eq. 2, Eq. 3), freezing of clients near open
+ * facilities, and a maximal independent set on the conflict graph H-bar
+ * (Sec. 4.3, Alg. 6) to pick S.
+ *
+ * Conventions for every call below
+ *   - Every array in fl_problem and fl_result is a DEVICE pointer (memory of
+ *     the current HIP device, e.g. a torch tensor's data_ptr()).  The caller
+ *     owns all of them; the library never frees or modifies inputs.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     device work is enqueued on it; the call synchronises it before it
+ *     returns host scalars, so device outputs are valid on return.
+ *   - Return value: FL_OK (0) or one of the FL_E* codes.  On error the device
+ *     outputs are unspecified and result->n_open is 0.
+ *   - The library keeps a per-device workspace cache between calls (released
+ *     by fl_release_workspace).  Calls that overlap on one device from
+ *     several host threads are serialised internally.
+ */
+#ifndef FL_H_
+#define FL_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes -------------------------------------------------------- */
+#define FL_OK 0
+#define FL_EINVAL 1   /* malformed/asymmetric CSR, unsorted or duplicate neighbours,
+                         self loop, w = 0, k = 0, eps <= 0 or not finite,
+                         n = 0 or n >= 2^32-1, NULL required pointer */
+#define FL_ERANGE 2   /* (n-1)*max(w) + max(c) >= 2^32-1: a distance or a cost
+                         plus distance could overflow 32 bits */
+#define FL_ENOMEM 3   /* workspace does not fit the device (or the budget) */
+#define FL_EHIP 4     /* a HIP runtime error; see fl_last_hip_error() */
+#define FL_EBUSY 5    /* server queue full (non-blocking submit) */
+#define FL_ENOTIMPL 6 /* a limit of this build: k > 64, max weight > 255,
+                         sketch capacity above 65535 entries per vertex */
+
+/* ---- sentinels ---------------------------------------------------------- */
+#define FL_NOT_FACILITY 0xFFFFFFFFu /* fac_cost value of a non-facility vertex */
+#define FL_NONE 0xFFFFFFFFu         /* assign/dist of a non-client or unreachable client */
+#define FL_RUNG_NONE 0xFFFFFFFFu    /* never opened / never frozen */
+#define FL_RUNG_GUARD 0xFFFFFFFEu   /* opened or frozen by the stall guard */
+#define FL_RUNG_END 0xFFFFFFFDu     /* frozen in the end phase (all facilities open) */
+
+/* ---- problem: graph in symmetric CSR, costs, clients (Sec. 3.1) ---------- */
+typedef struct {
+  uint32_t n;               /* |V|, 1 <= n < 2^32-1 */
+  uint64_t n_arcs;          /* 2|E| */
+  const uint64_t *row_ptr;  /* [n+1], row_ptr[0] = 0, row_ptr[n] = n_arcs */
+  const uint32_t *col;      /* [n_arcs], strictly increasing within each row,
+                               no self loops; (u,v) present iff (v,u) present */
+  const uint32_t *w;        /* [n_arcs] integer weights >= 1, equal on (u,v) and
+                               (v,u); NULL = unit weights */
+  const uint32_t *fac_cost; /* [n] opening cost c(f); FL_NOT_FACILITY marks a
+                               vertex that is not a facility.  Required by
+                               fl_solve, ignored by fl_ads_build. */
+  const uint8_t *is_client; /* [n] nonzero = client; NULL = every vertex */
+} fl_problem;
+
+/* ---- parameters ---------------------------------------------------------- */
+typedef struct {
+  uint32_t k;     /* bottom-k parameter of the sketches, 1 <= k <= 64 */
+  uint64_t seed;  /* seeds the vertex ranks and the MIS priorities */
+  double eps;     /* accuracy parameter epsilon > 0 (the paper's runs use 0.1) */
+  uint32_t flags; /* FL_FLAG_* below */
+} fl_params;
+
+#define FL_FLAG_NO_DENSE 1u  /* always use frontier worklists in the ADS rounds */
+
+/* ---- statistics ---------------------------------------------------------- */
+typedef struct {
+  uint32_t ads_rounds;  /* distance rounds of the sketch construction */
+  uint32_t rungs;       /* radius-ladder rungs evaluated by the opening loop */
+  uint32_t mis_rounds;  /* parallel MIS rounds, summed over rungs */
+  uint32_t n_guard;     /* facilities opened by the stall guard */
+  uint64_t relax_alg;   /* sum_v |ADS(v)| * deg(v) */
+  uint64_t relax_exec;  /* candidate entries read by the sketch rounds */
+  uint64_t ads_entries; /* sum_v |ADS(v)| */
+  uint64_t gamma;       /* max over served clients of min_f c(f) + d(c,f) */
+  double alpha0;        /* first ladder value */
+  double ms_validate, ms_ads, ms_gamma, ms_open, ms_mis, ms_assign, ms_total;
+  uint64_t workspace_bytes;
+} fl_stats;
+
+/* ---- result -------------------------------------------------------------- */
+typedef struct {
+  /* caller-owned device outputs, each [n] */
+  uint8_t *open;         /* 1 iff the vertex is in the returned set S */
+  uint32_t *assign;      /* nearest facility of S (ties: smaller id) for every
+                            served client; FL_NONE otherwise */
+  uint32_t *dist;        /* d(c, S) for served clients, FL_NONE otherwise; may be NULL */
+  uint32_t *open_rung;   /* optional (NULL): rung at which each facility opened */
+  uint32_t *freeze_rung; /* optional (NULL): rung at which each client froze */
+  double *q;             /* optional (NULL): final q(f) of each facility, 0 elsewhere */
+  /* host scalars, written by the call */
+  uint64_t total_cost;   /* sum_{f in S} c(f) + sum over served clients d(c, S) */
+  uint32_t n_open;       /* |S| */
+  uint32_t n_unreachable;/* clients with no facility in their component */
+  fl_stats stats;
+} fl_result;
+
+/*
+ * fl_solve -- one complete facility-location solve (Alg. 4 with Alg. 5 and
+ * Alg. 6 inside): validate the CSR, build the bottom-k ADS of every vertex,
+ * compute gamma and the radius ladder (Sec. 4.1-4.2), run the opening loop
+ * with HIP-estimator estimates of the unfrozen clients near each facility,
+ * resolve conflicts per rung with the fixed-priority MIS, assign clients and
+ * add up the objective.  Clients that cannot reach any facility are reported
+ * (FL_NONE, n_unreachable) and left out of the objective.
+ */
+int fl_solve(const fl_problem *p, const fl_params *prm, fl_result *out, void *stream);
+
+/*
+ * fl_solve_batch -- `count` independent solves; per element the same contract
+ * and the same results as fl_solve.  The graphs share one workspace and run
+ * back to back on `stream`.
+ */
+int fl_solve_batch(const fl_problem *ps, const fl_params *prms, fl_result *outs, uint32_t count,
+                   void *stream);
+
+/* ---- sketches (Sec. 3.3) --------------------------------------------------- */
+typedef struct fl_sketch fl_sketch;
+
+typedef struct {
+  uint32_t n, k;
+  uint64_t total;          /* sum_v |ADS(v)| */
+  const uint64_t *off;     /* device [n+1]: entries of v are [off[v], off[v+1]) */
+  const uint32_t *rank;    /* device [total]: rank of the sampled vertex */
+  const uint32_t *dist;    /* device [total]: its distance from v */
+  const uint32_t *thresh;  /* device [total]: HIP threshold T_j (k-th smallest rank
+                              among earlier entries), 0 meaning 2^32 (j < k) */
+} fl_sketch_view_t;
+
+/*
+ * fl_ads_build -- bottom-k ADS of every vertex.  Entry order within a vertex
+ * is increasing (distance, vertex id); entry 0 is (r(v), 0).  The library
+ * owns the storage until fl_sketch_free.  fac_cost is not read.
+ */
+int fl_ads_build(const fl_problem *p, const fl_params *prm, fl_sketch **out, void *stream);
+/* Fills *view with device pointers into the sketch (valid until free). */
+int fl_sketch_view(const fl_sketch *s, fl_sketch_view_t *view);
+void fl_sketch_free(fl_sketch *s);
+
+/* Vertex rank r(v) and MIS priority of the given seed (host helpers; the
+ * library computes the same values on the device). */
+uint32_t fl_rank_of(uint32_t v, uint64_t seed);
+uint32_t fl_priority_of(uint32_t v, uint64_t seed);
+
+/* ---- errors and resources -------------------------------------------------- */
+const char *fl_strerror(int code);
+int fl_last_hip_error(void);
+/* Frees the cached workspace of the current device. */
+void fl_release_workspace(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FL_H_ */

@@ -1,0 +1,193 @@
+"""MI355X (gfx950) sketch-based facility location on graphs.
+
+Python front of the HIP library ``libfl.so`` (C ABI in include/fl.h), after
+"Scalable Facility Location for Massive Graphs on Pregel-like Systems"
+(arXiv 1503.03635).  The functions here only marshal arguments: graphs are
+moved to the GPU as torch tensors, their pointers go through the C ABI, and
+the results come back as tensors and host scalars.
+"""
+import ctypes as C
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+from . import _lib
+from ._lib import (FL_FLAG_NO_DENSE, FL_NONE, FL_NOT_FACILITY, FL_RUNG_END, FL_RUNG_GUARD,
+                   FL_RUNG_NONE, FlError, lib)
+
+__all__ = ["DeviceGraph", "to_device", "solve", "solve_batch", "ads_build", "rank_of", "priority_of",
+           "FlError", "FL_NONE", "FL_NOT_FACILITY", "FL_RUNG_NONE", "FL_RUNG_GUARD", "FL_RUNG_END",
+           "FL_FLAG_NO_DENSE", "lib"]
+
+
+@dataclass
+class DeviceGraph:
+    n: int
+    row_ptr: torch.Tensor                 # int64 [n+1] (read as uint64)
+    col: torch.Tensor                     # int32 [m]   (read as uint32)
+    w: Optional[torch.Tensor] = None      # int32 [m]
+    fac_cost: Optional[torch.Tensor] = None   # int32 [n] (read as uint32)
+    is_client: Optional[torch.Tensor] = None  # uint8 [n]
+
+    @property
+    def n_arcs(self):
+        return int(self.col.numel())
+
+
+def _t(a, dtype, device):
+    import numpy as np
+    if a is None:
+        return None
+    arr = np.ascontiguousarray(a)
+    return torch.from_numpy(arr.view(dtype)).to(device)
+
+
+def to_device(g, device="cuda") -> DeviceGraph:
+    """Copy a host graph (numpy arrays: row_ptr uint64, col/w/fac_cost uint32,
+    is_client uint8) to device tensors with the same bit patterns."""
+    import numpy as np
+    return DeviceGraph(
+        n=int(g.n),
+        row_ptr=_t(np.asarray(g.row_ptr, np.uint64), np.int64, device),
+        col=_t(np.asarray(g.col, np.uint32), np.int32, device),
+        w=None if g.w is None else _t(np.asarray(g.w, np.uint32), np.int32, device),
+        fac_cost=None if getattr(g, "fac_cost", None) is None else
+        _t(np.asarray(g.fac_cost, np.uint32), np.int32, device),
+        is_client=None if getattr(g, "is_client", None) is None else
+        _t(np.asarray(g.is_client, np.uint8), np.uint8, device),
+    )
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _problem(dg: DeviceGraph):
+    return _lib.FlProblem(dg.n, dg.n_arcs, _ptr(dg.row_ptr), _ptr(dg.col), _ptr(dg.w),
+                          _ptr(dg.fac_cost), _ptr(dg.is_client))
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _alloc_outputs(n, device, diagnostics):
+    out = {
+        "open": torch.empty(n, dtype=torch.uint8, device=device),
+        "assign": torch.empty(n, dtype=torch.int32, device=device),
+        "dist": torch.empty(n, dtype=torch.int32, device=device),
+    }
+    if diagnostics:
+        out["open_rung"] = torch.empty(n, dtype=torch.int32, device=device)
+        out["freeze_rung"] = torch.empty(n, dtype=torch.int32, device=device)
+        out["q"] = torch.empty(n, dtype=torch.float64, device=device)
+    return out
+
+
+def _result_struct(out):
+    return _lib.FlResult(_ptr(out["open"]), _ptr(out["assign"]), _ptr(out["dist"]),
+                         _ptr(out.get("open_rung")), _ptr(out.get("freeze_rung")), _ptr(out.get("q")))
+
+
+def _collect(res, out):
+    st = res.stats
+    out["total_cost"] = int(res.total_cost)
+    out["n_open"] = int(res.n_open)
+    out["n_unreachable"] = int(res.n_unreachable)
+    out["stats"] = {name: getattr(st, name) for name, _ in _lib.FlStats._fields_}
+    return out
+
+
+def solve(dg: DeviceGraph, k: int, seed: int, eps: float = 0.1, flags: int = 0,
+          diagnostics: bool = False, stream=None, outputs=None, check=True):
+    """One facility-location solve (fl_solve).  Returns a dict of device
+    tensors (open, assign, dist[, open_rung, freeze_rung, q]) and host scalars
+    (total_cost, n_open, n_unreachable, stats)."""
+    device = dg.col.device if dg.n_arcs else dg.row_ptr.device
+    out = outputs if outputs is not None else _alloc_outputs(dg.n, device, diagnostics)
+    prob = _problem(dg)
+    prm = _lib.FlParams(k, seed, eps, flags)
+    res = _result_struct(out)
+    rc = lib().fl_solve(C.byref(prob), C.byref(prm), C.byref(res), C.c_void_p(_stream_ptr(stream)))
+    out["rc"] = rc
+    if rc != _lib.FL_OK:
+        if check:
+            raise FlError(rc, "fl_solve")
+        return out
+    return _collect(res, out)
+
+
+def solve_batch(dgs, k: int, seed: int, eps: float = 0.1, flags: int = 0, stream=None, check=True):
+    """fl_solve_batch over a list of device graphs; one dict per graph."""
+    count = len(dgs)
+    probs = (_lib.FlProblem * count)(*[_problem(d) for d in dgs])
+    prms = (_lib.FlParams * count)(*[_lib.FlParams(k, seed, eps, flags) for _ in dgs])
+    outs = [_alloc_outputs(d.n, d.col.device if d.n_arcs else d.row_ptr.device, False) for d in dgs]
+    ress = (_lib.FlResult * count)(*[_result_struct(o) for o in outs])
+    rc = lib().fl_solve_batch(probs, prms, ress, count, C.c_void_p(_stream_ptr(stream)))
+    if rc != _lib.FL_OK and check:
+        raise FlError(rc, "fl_solve_batch")
+    for i in range(count):
+        _collect(ress[i], outs[i])
+        outs[i]["rc"] = rc
+    return outs
+
+
+def ads_build(dg: DeviceGraph, k: int, seed: int, flags: int = 0, stream=None):
+    """Bottom-k sketches of every vertex (fl_ads_build), copied into fresh
+    device tensors: off int64 [n+1], rank/dist/thresh int32 [total]."""
+    prob = _problem(dg)
+    prm = _lib.FlParams(k, seed, 0.1, flags)
+    h = C.c_void_p()
+    rc = lib().fl_ads_build(C.byref(prob), C.byref(prm), C.byref(h), C.c_void_p(_stream_ptr(stream)))
+    if rc != _lib.FL_OK:
+        raise FlError(rc, "fl_ads_build")
+    try:
+        v = _lib.FlSketchView()
+        rc = lib().fl_sketch_view(h, C.byref(v))
+        if rc != _lib.FL_OK:
+            raise FlError(rc, "fl_sketch_view")
+        device = dg.row_ptr.device
+        n, tot = int(v.n), int(v.total)
+        off = torch.empty(n + 1, dtype=torch.int64, device=device)
+        rank = torch.empty(tot, dtype=torch.int32, device=device)
+        dist = torch.empty(tot, dtype=torch.int32, device=device)
+        thr = torch.empty(tot, dtype=torch.int32, device=device)
+        torch.cuda.synchronize(device)
+        for dst, src, nbytes in ((off, v.off, (n + 1) * 8), (rank, v.rank, tot * 4),
+                                 (dist, v.dist, tot * 4), (thr, v.thresh, tot * 4)):
+            if nbytes:
+                _memcpy_d2d(dst.data_ptr(), src, nbytes)
+        torch.cuda.synchronize(device)
+        return {"off": off, "rank": rank, "dist": dist, "thresh": thr, "total": tot}
+    finally:
+        lib().fl_sketch_free(h)
+
+
+_hip = None
+
+
+def _memcpy_d2d(dst, src, nbytes):
+    """Device-to-device copy through the HIP runtime (hipMemcpy)."""
+    global _hip
+    if _hip is None:
+        # by soname: the runtime already loaded in this process (torch's or
+        # the one libfl.so bound to), never a second copy
+        lib()
+        _hip = C.CDLL("libamdhip64.so.7")
+        _hip.hipMemcpy.restype = C.c_int
+        _hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+    rc = _hip.hipMemcpy(C.c_void_p(dst), C.c_void_p(src), nbytes, 3)  # hipMemcpyDeviceToDevice
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpy failed: {rc}")
+
+
+def rank_of(v: int, seed: int) -> int:
+    return int(lib().fl_rank_of(v, seed))
+
+
+def priority_of(v: int, seed: int) -> int:
+    return int(lib().fl_priority_of(v, seed))

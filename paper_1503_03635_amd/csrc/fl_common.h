@@ -1,0 +1,291 @@
+// fl_common.h -- internal definitions shared by the HIP sources of the
+// library: wave64 helpers, the seeded rank bijection, exact fixed-point
+// helpers for the HIP-estimator sums, and the workspace arena.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstddef>
+#include <cstdio>
+#include <vector>
+
+#include "../../include/fl.h"
+
+namespace fl {
+
+constexpr int WAVE = 64;
+constexpr uint32_t INF32 = 0xFFFFFFFFu;
+constexpr uint64_t INF64 = 0xFFFFFFFFFFFFFFFFull;
+constexpr uint32_t MAX_K = 64;
+constexpr uint32_t MAX_W = 255;      // largest edge weight handled by the slot ring
+constexpr uint32_t MAX_CAP = 65535;  // largest per-vertex sketch capacity
+constexpr int NCTR = 1024;           // strided counters (spread atomics over addresses)
+
+// ---------------------------------------------------------------------------
+// Error plumbing
+// ---------------------------------------------------------------------------
+struct Error {
+  int code;
+};
+void set_last_hip_error(int e);
+
+#define FL_HIP(call)                                                \
+  do {                                                              \
+    hipError_t e_ = (call);                                         \
+    if (e_ != hipSuccess) {                                         \
+      ::fl::set_last_hip_error((int)e_);                            \
+      throw ::fl::Error{FL_EHIP};                                   \
+    }                                                               \
+  } while (0)
+
+#define FL_LAUNCH_CHECK() FL_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------------------
+// Seeded bijection on 32-bit ids.  Ranks r(v) and MIS priorities pi(f) are
+// "hashes" of the vertex id (Alg. 1; Sec. 4.3).  Both are bijections here:
+// two rounds of the MurmurHash3 32-bit finaliser (public domain), each after
+// an xor with a 32-bit key; the two keys of a stream are the halves of
+// SplitMix64 (Vigna, public domain) applied to seed^1 (ranks) or seed^2
+// (priorities).  All steps are invertible, so a rank maps back to its vertex.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+constexpr uint32_t modinv32(uint32_t c) {
+  uint32_t x = c;
+  for (int i = 0; i < 5; ++i) x *= 2u - c * x;
+  return x;
+}
+constexpr uint32_t MUR_C1 = 0x85ebca6bu, MUR_C2 = 0xc2b2ae35u;
+constexpr uint32_t MUR_C1_INV = modinv32(MUR_C1), MUR_C2_INV = modinv32(MUR_C2);
+static_assert(MUR_C1 * MUR_C1_INV == 1u, "inverse");
+static_assert(MUR_C2 * MUR_C2_INV == 1u, "inverse");
+
+__host__ __device__ inline uint32_t murmur_fmix(uint32_t h) {
+  h ^= h >> 16;
+  h *= MUR_C1;
+  h ^= h >> 13;
+  h *= MUR_C2;
+  h ^= h >> 16;
+  return h;
+}
+__host__ __device__ inline uint32_t murmur_unfmix(uint32_t h) {
+  h ^= h >> 16;                      // x ^ (x >> 16) is its own inverse on 32 bits
+  h *= MUR_C2_INV;
+  h ^= (h >> 13) ^ (h >> 26);        // inverse of x ^ (x >> 13)
+  h *= MUR_C1_INV;
+  h ^= h >> 16;
+  return h;
+}
+
+struct PermKey {
+  uint32_t k1, k2;
+};
+__host__ __device__ inline PermKey perm_key(uint64_t seed, uint64_t stream) {
+  uint64_t s = splitmix64(seed ^ stream);
+  return PermKey{(uint32_t)s, (uint32_t)(s >> 32)};
+}
+__host__ __device__ inline uint32_t perm_fwd(uint32_t v, PermKey k) {
+  return murmur_fmix(murmur_fmix(v ^ k.k1) ^ k.k2);
+}
+__host__ __device__ inline uint32_t perm_inv(uint32_t r, PermKey k) {
+  return murmur_unfmix(murmur_unfmix(r) ^ k.k2) ^ k.k1;
+}
+
+// ---------------------------------------------------------------------------
+// Exact sums of HIP-estimator weights.  A weight a = fl(2^32 / T) lies in
+// [1, 2^32], so a * 2^52 is an integer below 2^85.  It is split at bit 40 into
+// hi (< 2^45) and lo (< 2^40); sums of fewer than 2^16 such parts fit in 64
+// bits, so a sum over a sketch is exact, and it is rounded to double once.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline double hip_weight(uint32_t T) {
+  // T == 0 encodes 2^32 (fewer than k earlier entries): weight 1
+  return T == 0 ? 1.0 : 4294967296.0 / (double)T;
+}
+struct Fix52 {
+  uint64_t hi, lo;
+};
+__host__ __device__ inline Fix52 fix52_of(double a) {
+  uint64_t bits;
+  memcpy(&bits, &a, sizeof(bits));
+  int e = (int)((bits >> 52) & 0x7FF) - 1023;            // 0..32 for a in [1, 2^32]
+  uint64_t mant = (bits & ((1ull << 52) - 1)) | (1ull << 52);
+  Fix52 r;
+  r.lo = (mant << e) & ((1ull << 40) - 1);
+  r.hi = mant >> (40 - e);
+  return r;
+}
+// round-to-nearest-even of (hi * 2^40 + lo) to double, then scaled by 2^-52
+__host__ __device__ inline double fix52_to_double(uint64_t hi, uint64_t lo) {
+  // 128-bit value V = hi * 2^40 + lo  (hi < 2^61, lo < 2^57)
+  uint64_t vlo = (hi << 40);
+  uint64_t vhi = hi >> 24;
+  uint64_t s = vlo + lo;
+  vhi += (s < vlo) ? 1 : 0;
+  vlo = s;
+  double d;
+  if (vhi == 0) {
+    if (vlo < (1ull << 53)) {
+      d = (double)vlo;                                   // exact
+    } else {
+      int p = 63 - __builtin_clzll(vlo);                 // top bit, >= 53
+      int sh = p - 52;
+      uint64_t m = vlo >> sh;
+      uint64_t rem = vlo & ((1ull << sh) - 1);
+      uint64_t half = 1ull << (sh - 1);
+      if (rem > half || (rem == half && (m & 1))) m++;
+      d = ldexp((double)m, sh);
+    }
+  } else {
+    int p = 64 + 63 - __builtin_clzll(vhi);              // top bit index
+    int sh = p - 52;                                      // >= 12
+    // m = V >> sh, rem = V mod 2^sh
+    uint64_t m, rem, half;
+    if (sh < 64) {
+      m = (vlo >> sh) | (vhi << (64 - sh));
+      rem = vlo & ((1ull << sh) - 1);
+      half = 1ull << (sh - 1);
+      bool up = rem > half || (rem == half && (m & 1));
+      if (up) m++;
+    } else {
+      int s2 = sh - 64;
+      m = vhi >> s2;
+      uint64_t remhi = s2 ? (vhi & ((1ull << s2) - 1)) : 0;
+      // compare (remhi, vlo) with half = 2^(sh-1)
+      bool gt, eq;
+      if (s2 == 0) {
+        gt = vlo > (1ull << 63);
+        eq = vlo == (1ull << 63);
+      } else {
+        uint64_t hh = 1ull << (s2 - 1);
+        gt = remhi > hh || (remhi == hh && vlo > 0);
+        eq = remhi == hh && vlo == 0;
+      }
+      if (gt || (eq && (m & 1))) m++;
+    }
+    d = ldexp((double)m, sh);
+  }
+  return ldexp(d, -52);
+}
+
+// ---------------------------------------------------------------------------
+// Wave64 helpers
+// ---------------------------------------------------------------------------
+__device__ inline int lane_id() { return (int)__lane_id(); }
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+__device__ inline uint32_t wave_scan_incl(uint32_t x) {
+  const int l = lane_id();
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    uint32_t y = __shfl_up(x, d, WAVE);
+    if (l >= d) x += y;
+  }
+  return x;
+}
+__device__ inline uint64_t wave_sum_u64(uint64_t x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, WAVE);
+  return x;
+}
+__device__ inline uint32_t wave_min_u32(uint32_t x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    uint32_t y = __shfl_xor(x, d, WAVE);
+    x = y < x ? y : x;
+  }
+  return x;
+}
+// number of set bits of mask below this lane
+__device__ inline uint32_t lanes_below(uint64_t mask) {
+  return (uint32_t)__popcll(mask & ((1ull << lane_id()) - 1ull));
+}
+
+// ---------------------------------------------------------------------------
+// Host-side helpers
+// ---------------------------------------------------------------------------
+inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+// A bump arena over one cached device allocation.
+class Arena {
+ public:
+  void reserve(size_t bytes);
+  void reset() { used_ = 0; }
+  void rewind(size_t mark) { used_ = mark; }
+  template <class T>
+  T *get(size_t count) {
+    size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
+    if (used_ + bytes > cap_) throw Error{FL_ENOMEM};
+    T *p = reinterpret_cast<T *>(base_ + used_);
+    used_ += bytes;
+    if (used_ > peak_) peak_ = used_;
+    return p;
+  }
+  size_t used() const { return used_; }
+  size_t capacity() const { return cap_; }
+  void release();
+
+ private:
+  char *base_ = nullptr;
+  size_t cap_ = 0, used_ = 0, peak_ = 0;
+};
+
+// Per-call context: stream, arena, pinned host scratch for status readbacks.
+struct Ctx {
+  hipStream_t s = nullptr;
+  Arena *arena = nullptr;
+  uint64_t *h_status = nullptr;  // pinned, 4096 u64
+  uint64_t *d_status = nullptr;  // device, 4096 u64
+  void sync() { FL_HIP(hipStreamSynchronize(s)); }
+  // copy `count` u64 status words from device to host and wait
+  void fetch(const void *dev, size_t bytes) {
+    FL_HIP(hipMemcpyAsync(h_status, dev, bytes, hipMemcpyDeviceToHost, s));
+    sync();
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Validated graph description used by every phase (device pointers).
+// ---------------------------------------------------------------------------
+struct Graph {
+  uint32_t n;
+  uint64_t m;
+  const uint64_t *row_ptr;
+  const uint32_t *col;
+  const uint32_t *w;  // nullptr = unit weights
+  uint32_t max_w;
+};
+
+// fill / utility launches (fl_graph.hip)
+void fill_u32(Ctx &c, uint32_t *p, uint64_t n, uint32_t v);
+void fill_u64(Ctx &c, uint64_t *p, uint64_t n, uint64_t v);
+void fill_u8(Ctx &c, uint8_t *p, uint64_t n, uint8_t v);
+void fill_f64(Ctx &c, double *p, uint64_t n, double v);
+int validate_graph(Ctx &c, const fl_problem *p, uint32_t *max_w_out, uint32_t *max_cost_out);
+// exclusive scan of u32 counts into u64 offsets (out has n+1 entries)
+void scan_u32_to_u64(Ctx &c, const uint32_t *in, uint64_t *out, uint32_t n);
+// sum_v cnt[v] * deg(v) and sum_v cnt[v]
+void ads_totals(Ctx &c, const Graph &g, const uint32_t *cnt, uint64_t *relax_alg, uint64_t *entries);
+
+// Multi-source Bellman-Ford with packed 64-bit labels (value << 32 | tie).
+// Labels move along arcs by adding w << 32.  `labels` holds the initial
+// labels (INF64 = none) and receives the fixed point; `seeds` lists the
+// vertices whose label was lowered since the last call (the first frontier).
+struct SsspWork {
+  uint32_t *front[2];
+  uint32_t *flag;  // n
+  uint64_t *ctr;   // device counters
+};
+void sssp_alloc(Ctx &c, SsspWork &wk, uint32_t n);
+uint32_t sssp_run(Ctx &c, const Graph &g, uint64_t *labels, const uint32_t *seeds, uint32_t nseeds,
+                  SsspWork &wk, uint64_t cap_value);
+
+}  // namespace fl

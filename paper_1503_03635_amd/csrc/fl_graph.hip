@@ -1,0 +1,327 @@
+// fl_graph.hip -- graph-level kernels: input validation, fills, scans,
+// reductions, and the frontier Bellman-Ford used for the multi-source
+// shortest-path sweeps (gamma, distance to the open set, assignment).
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <mutex>
+
+#include "fl_common.h"
+
+namespace fl {
+
+// ---------------------------------------------------------------------------
+// fills
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void k_fill(T *p, uint64_t n, T v) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+template <class T>
+static void fill_t(Ctx &c, T *p, uint64_t n, T v) {
+  if (n == 0) return;
+  uint64_t blocks = ceil_div(n, 256);
+  if (blocks > 65536) blocks = 65536;
+  k_fill<T><<<(uint32_t)blocks, 256, 0, c.s>>>(p, n, v);
+  FL_LAUNCH_CHECK();
+}
+void fill_u32(Ctx &c, uint32_t *p, uint64_t n, uint32_t v) { fill_t(c, p, n, v); }
+void fill_u64(Ctx &c, uint64_t *p, uint64_t n, uint64_t v) { fill_t(c, p, n, v); }
+void fill_u8(Ctx &c, uint8_t *p, uint64_t n, uint8_t v) { fill_t(c, p, n, v); }
+void fill_f64(Ctx &c, double *p, uint64_t n, double v) { fill_t(c, p, n, v); }
+
+// ---------------------------------------------------------------------------
+// Validation (a simple undirected graph as a symmetric CSR, Sec. 3.1).  One
+// wave per vertex; lanes walk the row.  err bits: 1 = structural error.
+// Also reduces max weight and max facility cost.
+// ---------------------------------------------------------------------------
+__device__ inline bool find_arc(const uint64_t *row_ptr, const uint32_t *col, uint64_t m, uint32_t u,
+                                uint32_t v, uint64_t *pos) {
+  uint64_t lo = row_ptr[u], hi = row_ptr[u + 1];
+  const uint64_t end = hi;
+  if (hi > m || lo > hi) return false;  // malformed row: never read past col[m-1]
+  while (lo < hi) {
+    uint64_t mid = lo + ((hi - lo) >> 1);
+    if (col[mid] < v) lo = mid + 1;
+    else hi = mid;
+  }
+  *pos = lo;
+  return lo < end && col[lo] == v;
+}
+
+__global__ __launch_bounds__(256) void k_validate(uint32_t n, uint64_t m, const uint64_t *row_ptr,
+                                                  const uint32_t *col, const uint32_t *w,
+                                                  const uint32_t *fac_cost, uint32_t *err,
+                                                  uint32_t *maxw, uint32_t *maxc) {
+  const int lane = lane_id();
+  const uint64_t u64 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  if (u64 >= n) return;
+  const uint32_t u = (uint32_t)u64;
+  uint32_t bad = 0, mw = 0;
+  const uint64_t a0 = row_ptr[u], a1 = row_ptr[u + 1];
+  if (a1 < a0 || a1 > m) bad = 1;
+  if (!bad) {
+    for (uint64_t a = a0 + lane; a < a1; a += WAVE) {
+      uint32_t v = col[a];
+      uint32_t wv = w ? w[a] : 1u;
+      if (v >= n || v == u || wv == 0) { bad = 1; continue; }
+      if (a > a0 && col[a - 1] >= v) { bad = 1; continue; }
+      uint64_t back;
+      if (!find_arc(row_ptr, col, m, v, u, &back)) { bad = 1; continue; }
+      if ((w ? w[back] : 1u) != wv) bad = 1;
+      mw = wv > mw ? wv : mw;
+    }
+  }
+  if (fac_cost && lane == 0) {
+    uint32_t cst = fac_cost[u];
+    if (cst != FL_NOT_FACILITY) atomicMax(&maxc[u % NCTR], cst);
+  }
+  uint64_t anybad = __ballot(bad != 0);
+  mw = wave_min_u32(~mw);
+  mw = ~mw;  // wave max
+  if (lane == 0) {
+    if (anybad) atomicOr(&err[u % NCTR], 1u);
+    if (mw) atomicMax(&maxw[u % NCTR], mw);
+  }
+}
+
+int validate_graph(Ctx &c, const fl_problem *p, uint32_t *max_w_out, uint32_t *max_cost_out) {
+  const uint32_t n = p->n;
+  // row_ptr[0] and row_ptr[n]
+  uint64_t ends[2];
+  FL_HIP(hipMemcpyAsync(&ends[0], p->row_ptr, 8, hipMemcpyDeviceToHost, c.s));
+  FL_HIP(hipMemcpyAsync(&ends[1], p->row_ptr + n, 8, hipMemcpyDeviceToHost, c.s));
+  c.sync();
+  if (ends[0] != 0 || ends[1] != p->n_arcs) return FL_EINVAL;
+  uint32_t *d = c.arena->get<uint32_t>(3 * NCTR);
+  fill_u32(c, d, 3 * NCTR, 0);
+  uint64_t blocks = ceil_div((uint64_t)n * WAVE, 256);
+  k_validate<<<(uint32_t)blocks, 256, 0, c.s>>>(n, p->n_arcs, p->row_ptr, p->col, p->w, p->fac_cost,
+                                                 d, d + NCTR, d + 2 * NCTR);
+  FL_LAUNCH_CHECK();
+  std::vector<uint32_t> h(3 * NCTR);
+  FL_HIP(hipMemcpyAsync(h.data(), d, 3 * NCTR * 4, hipMemcpyDeviceToHost, c.s));
+  c.sync();
+  uint32_t err = 0, mw = 1, mc = 0;
+  for (int i = 0; i < NCTR; ++i) {
+    err |= h[i];
+    mw = h[NCTR + i] > mw ? h[NCTR + i] : mw;
+    mc = h[2 * NCTR + i] > mc ? h[2 * NCTR + i] : mc;
+  }
+  if (err) return FL_EINVAL;
+  *max_w_out = mw;
+  *max_cost_out = mc;
+  return FL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan u32 -> u64 (n+1 outputs).  Three passes: per-block sums,
+// one block scans the block sums, blocks add their prefix.
+// ---------------------------------------------------------------------------
+constexpr int SCAN_BLOCK = 1024;
+constexpr int SCAN_ITEMS = 4;
+constexpr uint32_t SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;
+
+__device__ inline uint64_t block_scan_excl_u64(uint64_t x, uint64_t *tmp, uint64_t *total) {
+  // wave-level inclusive scan then block combine
+  const int lane = lane_id(), wv = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+  uint64_t inc = x;
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    uint64_t y = __shfl_up(inc, d, WAVE);
+    if (lane >= d) inc += y;
+  }
+  if (lane == WAVE - 1) tmp[wv] = inc;
+  __syncthreads();
+  if (wv == 0) {
+    uint64_t t = lane < nw ? tmp[lane] : 0;
+    uint64_t ti = t;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+      uint64_t y = __shfl_up(ti, d, WAVE);
+      if (lane >= d) ti += y;
+    }
+    if (lane < nw) tmp[lane] = ti - t;
+    if (lane == nw - 1) tmp[WAVE] = ti;
+  }
+  __syncthreads();
+  uint64_t r = tmp[wv] + inc - x;
+  *total = tmp[WAVE];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_tiles(const uint32_t *in, uint32_t n, uint64_t *out,
+                                                          uint64_t *tile_sums) {
+  __shared__ uint64_t tmp[WAVE + 1];
+  const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_ITEMS;
+  uint32_t v[SCAN_ITEMS];
+  uint64_t s = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    v[i] = base + i < n ? in[base + i] : 0u;
+    s += v[i];
+  }
+  uint64_t total;
+  uint64_t pre = block_scan_excl_u64(s, tmp, &total);
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    if (base + i < n) out[base + i] = pre;
+    pre += v[i];
+  }
+  if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_sums(uint64_t *sums, uint32_t count, uint64_t *grand) {
+  __shared__ uint64_t tmp[WAVE + 1];
+  uint64_t carry = 0;
+  for (uint32_t base = 0; base < count; base += SCAN_BLOCK) {
+    uint32_t i = base + threadIdx.x;
+    uint64_t x = i < count ? sums[i] : 0;
+    uint64_t total;
+    uint64_t pre = block_scan_excl_u64(x, tmp, &total);
+    if (i < count) sums[i] = pre + carry;
+    carry += total;
+  }
+  if (threadIdx.x == 0) *grand = carry;
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_add(uint64_t *out, uint32_t n, const uint64_t *sums) {
+  const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_ITEMS;
+  const uint64_t add = sums[blockIdx.x];
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i)
+    if (base + i < n) out[base + i] += add;
+}
+
+void scan_u32_to_u64(Ctx &c, const uint32_t *in, uint64_t *out, uint32_t n) {
+  uint32_t tiles = (uint32_t)ceil_div(n ? n : 1, SCAN_TILE);
+  uint64_t *sums = c.arena->get<uint64_t>(tiles + 1);
+  k_scan_tiles<<<tiles, SCAN_BLOCK, 0, c.s>>>(in, n, out, sums);
+  FL_LAUNCH_CHECK();
+  k_scan_sums<<<1, SCAN_BLOCK, 0, c.s>>>(sums, tiles, out + n);
+  FL_LAUNCH_CHECK();
+  k_scan_add<<<tiles, SCAN_BLOCK, 0, c.s>>>(out, n, sums);
+  FL_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// sum_v cnt[v] * deg(v) and sum_v cnt[v]
+// ---------------------------------------------------------------------------
+__global__ void k_ads_totals(uint32_t n, const uint64_t *row_ptr, const uint32_t *cnt, uint64_t *ctr) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t r = 0, e = 0;
+  if (i < n) {
+    e = cnt[i];
+    r = e * (row_ptr[i + 1] - row_ptr[i]);
+  }
+  r = wave_sum_u64(r);
+  e = wave_sum_u64(e);
+  if (lane_id() == 0) {
+    atomicAdd((unsigned long long *)&ctr[2 * (blockIdx.x % NCTR)], (unsigned long long)r);
+    atomicAdd((unsigned long long *)&ctr[2 * (blockIdx.x % NCTR) + 1], (unsigned long long)e);
+  }
+}
+
+void ads_totals(Ctx &c, const Graph &g, const uint32_t *cnt, uint64_t *relax_alg, uint64_t *entries) {
+  uint64_t *ctr = c.arena->get<uint64_t>(2 * NCTR);
+  fill_u64(c, ctr, 2 * NCTR, 0);
+  k_ads_totals<<<(uint32_t)ceil_div(g.n, 256), 256, 0, c.s>>>(g.n, g.row_ptr, cnt, ctr);
+  FL_LAUNCH_CHECK();
+  std::vector<uint64_t> h(2 * NCTR);
+  FL_HIP(hipMemcpyAsync(h.data(), ctr, h.size() * 8, hipMemcpyDeviceToHost, c.s));
+  c.sync();
+  uint64_t r = 0, e = 0;
+  for (int i = 0; i < NCTR; ++i) {
+    r += h[2 * i];
+    e += h[2 * i + 1];
+  }
+  *relax_alg = r;
+  *entries = e;
+}
+
+// ---------------------------------------------------------------------------
+// Frontier Bellman-Ford on packed labels (value << 32 | tie): a label moves
+// along an arc of weight w as label + (w << 32).  Each vertex of the current
+// frontier pushes its label to all neighbours with 64-bit atomicMin; a
+// neighbour whose label dropped joins the next frontier once (stamped with
+// the iteration number).  The fixed point is the lexicographic minimum over
+// sources of (init value + distance, tie).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_sssp_push(const uint64_t *row_ptr, const uint32_t *col,
+                                                   const uint32_t *w, uint64_t *labels,
+                                                   const uint32_t *front, const uint32_t *nfront,
+                                                   uint32_t *next, uint32_t *nnext, uint32_t *stamp,
+                                                   uint32_t iter) {
+  const int lane = lane_id();
+  const uint64_t wid = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / WAVE;
+  const uint32_t nf = *nfront;
+  for (uint64_t i = wid; i < nf; i += nwaves) {
+    const uint32_t v = front[i];
+    const uint64_t L = __hip_atomic_load(&labels[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t a0 = row_ptr[v], a1 = row_ptr[v + 1];
+    for (uint64_t b = a0; b < a1; b += WAVE) {
+      const uint64_t a = b + lane;
+      bool add = false;
+      uint32_t y = 0;
+      if (a < a1) {
+        y = col[a];
+        const uint64_t nl = L + ((uint64_t)(w ? w[a] : 1u) << 32);
+        const uint64_t old = atomicMin((unsigned long long *)&labels[y], (unsigned long long)nl);
+        if (nl < old) add = atomicMax(&stamp[y], iter) < iter;
+      }
+      const uint64_t mask = __ballot(add);
+      if (mask) {
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(nnext, (uint32_t)__popcll(mask));
+        base = __shfl(base, 0, WAVE);
+        if (add) next[base + lanes_below(mask)] = y;
+      }
+    }
+  }
+}
+
+void sssp_alloc(Ctx &c, SsspWork &wk, uint32_t n) {
+  wk.front[0] = c.arena->get<uint32_t>(n + 1);
+  wk.front[1] = c.arena->get<uint32_t>(n + 1);
+  wk.flag = c.arena->get<uint32_t>(n);
+  wk.ctr = c.arena->get<uint64_t>(4);
+  fill_u32(c, wk.flag, n, 0);
+  fill_u64(c, wk.ctr, 4, 0);
+}
+
+// Runs to the fixed point.  Returns the number of iterations.  Stamps grow
+// monotonically across calls (kept in wk.ctr[0] on the host side copy).
+static uint32_t g_stamp_base = 0;
+
+uint32_t sssp_run(Ctx &c, const Graph &g, uint64_t *labels, const uint32_t *seeds, uint32_t nseeds,
+                  SsspWork &wk, uint64_t) {
+  if (nseeds == 0) return 0;
+  uint32_t *cnt = reinterpret_cast<uint32_t *>(wk.ctr);  // cnt[0], cnt[1]: frontier sizes
+  FL_HIP(hipMemcpyAsync(wk.front[0], seeds, (size_t)nseeds * 4, hipMemcpyDeviceToDevice, c.s));
+  uint32_t h = nseeds;
+  FL_HIP(hipMemcpyAsync(&cnt[0], &h, 4, hipMemcpyHostToDevice, c.s));
+  uint32_t iters = 0, cur = 0;
+  uint32_t nf = nseeds;
+  while (nf) {
+    const uint32_t stamp = ++g_stamp_base;
+    fill_u32(c, &cnt[cur ^ 1], 1, 0);
+    uint64_t waves = nf;
+    uint64_t blocks = ceil_div(waves * WAVE, 256);
+    if (blocks > 16384) blocks = 16384;
+    k_sssp_push<<<(uint32_t)blocks, 256, 0, c.s>>>(g.row_ptr, g.col, g.w, labels, wk.front[cur], &cnt[cur],
+                                                    wk.front[cur ^ 1], &cnt[cur ^ 1], wk.flag, stamp);
+    FL_LAUNCH_CHECK();
+    FL_HIP(hipMemcpyAsync(c.h_status, &cnt[cur ^ 1], 4, hipMemcpyDeviceToHost, c.s));
+    c.sync();
+    nf = (uint32_t)(c.h_status[0] & 0xFFFFFFFFu);
+    cur ^= 1;
+    ++iters;
+  }
+  return iters;
+}
+
+}  // namespace fl

@@ -1,0 +1,429 @@
+// fl_open.hip -- the facility-opening loop (Alg. 4 with OpenFacilities,
+// Alg. 5) on the GPU.
+//
+// Rung t uses alpha = a[t] (alpha grows before use).  For each unopened
+// facility f the loop needs N(f, alpha): the HIP estimate of the unfrozen
+// served clients within alpha of f, a predicated query over f's sketch
+// (Sec. 4.4).  It is kept exactly as an integer in units of 2^-52 (split into
+// two 64-bit words, fix52) over a "live list": the crossed sketch entries
+// (distance <= alpha) whose client is still unfrozen, compacted in place at
+// the front of f's sketch row.  Per rung:
+//   light kernel  (thread per facility): when nothing crossed and no client
+//                 froze in the previous rung, N is unchanged; update q and
+//                 test the opening condition q >= c(f) directly.
+//   heavy kernel  (wave per facility): drop frozen clients from the live
+//                 list when clients froze in the previous rung, append newly
+//                 crossed entries, recompute N exactly, then update q with
+//                 Eq. 2 (first rung, sequential sum in sketch order) or Eq. 3
+//                 (eps * alpha * N) and test the opening condition.
+//   distance to the open set: multi-source Bellman-Ford from the facilities
+//                 opened in this rung.
+//   freeze kernel (thread per vertex): unfrozen served clients within
+//                 (1 + eps) alpha of an open facility freeze at this rung.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "fl_common.h"
+#include "fl_open.h"
+
+namespace fl {
+
+// status counters, 64-way strided: field f of stripe s at [f * 64 + s]
+enum { OC_HEAVY = 0, OC_OPENED, OC_FROZEN, OC_FINITE, OC_NUF_DEC, OC_LIVE, OC_NFIELD };
+
+struct OpenArgs {
+  uint32_t n, nF, cap;
+  PermKey rk;
+  const uint32_t *fac_list;
+  const uint32_t *fac_cost;   // vertex-indexed
+  uint32_t *sk_rank;          // live region holds client ids
+  uint32_t *sk_dist;
+  uint32_t *thr;              // rows by facility index
+  const uint32_t *cnt;
+  const uint8_t *ceff;
+  uint32_t *frz;              // vertex-indexed freeze rung
+  uint32_t *orung;            // vertex-indexed open rung
+  double *q;
+  uint64_t *shi, *slo;
+  uint32_t *cursor, *nlive, *nxt;
+  double *nhat;
+  uint8_t *state;
+  uint32_t *heavy;            // [nF]
+  uint32_t *heavy_cnt;        // [1]
+  uint32_t *opened;           // [nF] vertex ids opened this rung
+  uint32_t *opened_cnt;       // [1]
+  uint32_t *ctr;              // [OC_NFIELD * 64]
+};
+
+__device__ inline void ctr_add(uint32_t *ctr, int field, uint32_t v) {
+  if (v) atomicAdd(&ctr[field * 64 + (blockIdx.x & 63)], v);
+}
+
+// wave-aggregated append of x to list (lanes with want)
+__device__ inline void wave_append(uint32_t *list, uint32_t *count, bool want, uint32_t x) {
+  const uint64_t m = __ballot(want);
+  if (!m) return;
+  const int lead = __ffsll((long long)m) - 1;
+  uint32_t base = 0;
+  if (lane_id() == lead) base = atomicAdd(count, (uint32_t)__popcll(m));
+  base = __shfl(base, lead, WAVE);
+  if (want) list[base + lanes_below(m)] = x;
+}
+
+__global__ void k_fac_init(OpenArgs A) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.nF) return;
+  A.q[i] = 0.0;
+  A.shi[i] = 0;
+  A.slo[i] = 0;
+  A.cursor[i] = 0;
+  A.nlive[i] = 0;
+  A.nxt[i] = 0;  // entry 0 of every sketch is the facility itself, at distance 0
+  A.nhat[i] = 0.0;
+  A.state[i] = 0;
+}
+
+// opening test and bookkeeping of a facility that opens at rung t
+__device__ inline bool try_open(const OpenArgs &A, uint32_t fi, uint32_t f, double qn, uint32_t t) {
+  if (qn >= (double)A.fac_cost[f]) {
+    A.state[fi] = 1;
+    A.orung[f] = t;
+    return true;
+  }
+  return false;
+}
+
+__global__ __launch_bounds__(256) void k_open_light(OpenArgs A, uint32_t t, double alpha, double eps_alpha,
+                                                    int any_freeze_prev) {
+  const uint32_t fi = blockIdx.x * blockDim.x + threadIdx.x;
+  bool heavy = false, opened = false, nuf = false;
+  uint32_t f = 0;
+  if (fi < A.nF && !A.state[fi]) {
+    f = A.fac_list[fi];
+    const uint32_t nx = A.nxt[fi];
+    heavy = (any_freeze_prev && A.nlive[fi] > 0) || (nx != INF32 && (double)nx <= alpha);
+    if (!heavy) {
+      // N unchanged: Eq. 3 with the stored estimate (0 when nothing is live;
+      // at the first rung an empty Eq. 2 sum is 0 as well)
+      const double inc = eps_alpha * A.nhat[fi];
+      const double qn = A.q[fi] + inc;
+      A.q[fi] = qn;
+      opened = try_open(A, fi, f, qn, t);
+      nuf = opened && A.ceff[f] && A.frz[f] == FL_RUNG_NONE;
+    }
+  }
+  wave_append(A.heavy, A.heavy_cnt, heavy, fi);
+  wave_append(A.opened, A.opened_cnt, opened, f);
+  const uint32_t no = (uint32_t)__popcll(__ballot(opened));
+  const uint32_t nd = (uint32_t)__popcll(__ballot(nuf));
+  if (lane_id() == 0) {
+    ctr_add(A.ctr, OC_OPENED, no);
+    ctr_add(A.ctr, OC_NUF_DEC, nd);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_open_heavy(OpenArgs A, uint32_t t, double alpha, double eps_alpha,
+                                                    double ae, double a0, double a1, int any_freeze_prev) {
+  const int lane = lane_id();
+  const uint32_t nh = *A.heavy_cnt;
+  const uint64_t wid = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const uint64_t nw = ((uint64_t)gridDim.x * blockDim.x) / WAVE;
+  for (uint64_t h = wid; h < nh; h += nw) {
+    const uint32_t fi = A.heavy[h];
+    const uint32_t f = A.fac_list[fi];
+    const size_t base = (size_t)f * A.cap;
+    const size_t trow = (size_t)fi * A.cap;
+    const uint32_t c = A.cnt[f];
+    uint32_t nl = A.nlive[fi];
+    uint32_t cur = A.cursor[fi];
+    uint64_t lhi = 0, llo = 0;
+    const bool rescan = any_freeze_prev && nl > 0;
+    if (rescan) {
+      uint32_t wpos = 0;
+      for (uint32_t b = 0; b < nl; b += WAVE) {
+        const uint32_t i = b + lane;
+        const bool valid = i < nl;
+        uint32_t id = 0, T = 0, d = 0;
+        if (valid) {
+          id = A.sk_rank[base + i];
+          T = A.thr[trow + i];
+          d = A.sk_dist[base + i];
+        }
+        const bool keep = valid && A.frz[id] == FL_RUNG_NONE;
+        const uint64_t mk = __ballot(keep);
+        if (keep) {
+          const uint32_t p = wpos + lanes_below(mk);
+          A.sk_rank[base + p] = id;
+          A.thr[trow + p] = T;
+          A.sk_dist[base + p] = d;
+          const Fix52 x = fix52_of(hip_weight(T));
+          lhi += x.hi;
+          llo += x.lo;
+        }
+        wpos += (uint32_t)__popcll(mk);
+      }
+      nl = wpos;
+    }
+    // cross entries with distance <= alpha (entries are sorted by distance)
+    while (cur < c) {
+      const uint32_t j = cur + lane;
+      const bool valid = j < c;
+      uint32_t d = INF32;
+      if (valid) d = A.sk_dist[base + j];
+      const bool cross = valid && (double)d <= alpha;
+      const uint64_t mc = __ballot(cross);
+      const uint32_t ncross = (uint32_t)__popcll(mc);
+      if (ncross == 0) break;
+      bool keep = false;
+      uint32_t id = 0, T = 0;
+      if (cross) {
+        id = perm_inv(A.sk_rank[base + j], A.rk);
+        T = A.thr[trow + j];
+        keep = A.ceff[id] && A.frz[id] == FL_RUNG_NONE;
+      }
+      const uint64_t mk = __ballot(keep);
+      if (keep) {
+        const uint32_t p = nl + lanes_below(mk);
+        A.sk_rank[base + p] = id;
+        A.thr[trow + p] = T;
+        A.sk_dist[base + p] = d;
+        const Fix52 x = fix52_of(hip_weight(T));
+        lhi += x.hi;
+        llo += x.lo;
+      }
+      nl += (uint32_t)__popcll(mk);
+      cur += ncross;
+      if (ncross < WAVE) break;
+    }
+    lhi = wave_sum_u64(lhi);
+    llo = wave_sum_u64(llo);
+    uint64_t shi = rescan ? lhi : A.shi[fi] + lhi;
+    uint64_t slo = rescan ? llo : A.slo[fi] + llo;
+    const double nh_ = fix52_to_double(shi, slo);
+    double inc;
+    if (t == 1) {
+      // Eq. 2: sum over the live entries, in sketch order, of
+      // a_j ((1+eps) alpha - beta(d_j)); beta is a[0] or a[1] here
+      double s = 0.0;
+      if (lane == 0) {
+        for (uint32_t i = 0; i < nl; ++i) {
+          const double dj = (double)A.sk_dist[base + i];
+          const double b = dj <= a0 ? a0 : a1;
+          s = s + hip_weight(A.thr[trow + i]) * (ae - b);
+        }
+      }
+      inc = __shfl(s, 0, WAVE);
+    } else {
+      inc = eps_alpha * nh_;
+    }
+    if (lane == 0) {
+      A.shi[fi] = shi;
+      A.slo[fi] = slo;
+      A.nlive[fi] = nl;
+      A.cursor[fi] = cur;
+      A.nxt[fi] = cur < c ? A.sk_dist[base + cur] : INF32;
+      A.nhat[fi] = nh_;
+      const double qn = A.q[fi] + inc;
+      A.q[fi] = qn;
+      if (try_open(A, fi, f, qn, t)) {
+        const uint32_t p = atomicAdd(A.opened_cnt, 1u);
+        A.opened[p] = f;
+        ctr_add(A.ctr, OC_OPENED, 1);
+        if (A.ceff[f] && A.frz[f] == FL_RUNG_NONE) ctr_add(A.ctr, OC_NUF_DEC, 1);
+      }
+    }
+  }
+}
+
+// opened facilities become sources at distance 0 (tie = own id)
+__global__ void k_seed_opened(const uint32_t *opened, const uint32_t *cnt, uint64_t *lab) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < *cnt) {
+    const uint32_t f = opened[i];
+    lab[f] = (uint64_t)f;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_freeze(OpenArgs A, const uint64_t *dlab, uint32_t t, double rho,
+                                                const uint32_t *fac_idx) {
+  const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool froze = false, finite = false, nuf = false;
+  if (c < A.n && A.ceff[c] && A.frz[c] == FL_RUNG_NONE) {
+    const uint64_t L = dlab[c];
+    if (L != INF64) {
+      const uint32_t d = (uint32_t)(L >> 32);
+      if ((double)d <= rho) {
+        A.frz[c] = t;
+        froze = true;
+        const uint32_t fi = fac_idx[c];
+        nuf = fi != INF32 && !A.state[fi];
+      } else {
+        finite = true;
+      }
+    }
+  }
+  const uint32_t a = (uint32_t)__popcll(__ballot(froze));
+  const uint32_t b = (uint32_t)__popcll(__ballot(finite));
+  const uint32_t e = (uint32_t)__popcll(__ballot(nuf));
+  if (lane_id() == 0) {
+    ctr_add(A.ctr, OC_FROZEN, a);
+    ctr_add(A.ctr, OC_FINITE, b);
+    ctr_add(A.ctr, OC_NUF_DEC, e);
+  }
+}
+
+// Does some unopened facility still have an unfrozen served client anywhere
+// in its sketch?  (Stall check; run only when no unfrozen client can be
+// reached by an open facility and no unopened facility is itself one.)
+__global__ __launch_bounds__(256) void k_stuck_scan(OpenArgs A) {
+  const int lane = lane_id();
+  const uint64_t fi = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  if (fi >= A.nF || A.state[fi]) return;
+  const uint32_t f = A.fac_list[fi];
+  const size_t base = (size_t)f * A.cap;
+  const uint32_t nl = A.nlive[fi], cur = A.cursor[fi], c = A.cnt[f];
+  bool live = false;
+  for (uint32_t i = lane; i < nl; i += WAVE) live |= A.frz[A.sk_rank[base + i]] == FL_RUNG_NONE;
+  for (uint32_t j = cur + lane; j < c; j += WAVE) {
+    const uint32_t id = perm_inv(A.sk_rank[base + j], A.rk);
+    live |= A.ceff[id] && A.frz[id] == FL_RUNG_NONE;
+  }
+  if (__ballot(live) && lane == 0) atomicAdd(&A.ctr[OC_LIVE * 64], 1u);
+}
+
+__global__ void k_guard(uint32_t n, const uint8_t *ceff, uint32_t *frz, uint32_t *orung, const uint64_t *gam) {
+  const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n || !ceff[c] || frz[c] != FL_RUNG_NONE) return;
+  const uint32_t f = (uint32_t)(gam[c] & 0xFFFFFFFFu);
+  orung[f] = FL_RUNG_GUARD;
+  frz[c] = FL_RUNG_GUARD;
+}
+
+__global__ void k_endphase(uint32_t n, const uint8_t *ceff, uint32_t *frz) {
+  const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n && ceff[c] && frz[c] == FL_RUNG_NONE) frz[c] = FL_RUNG_END;
+}
+
+static void read_ctr(Ctx &c, const uint32_t *d, uint64_t out[OC_NFIELD]) {
+  std::vector<uint32_t> h(OC_NFIELD * 64);
+  FL_HIP(hipMemcpyAsync(h.data(), d, h.size() * 4, hipMemcpyDeviceToHost, c.s));
+  c.sync();
+  for (int f = 0; f < OC_NFIELD; ++f) {
+    out[f] = 0;
+    for (int s = 0; s < 64; ++s) out[f] += h[f * 64 + s];
+  }
+}
+
+int open_phase(Ctx &c, const OpenIn &in, OpenOut &out) {
+  const Graph &g = *in.g;
+  const uint32_t n = g.n, nF = in.nF;
+  OpenArgs A{};
+  A.n = n;
+  A.nF = nF;
+  A.cap = in.ads->cap;
+  A.rk = in.rk;
+  A.fac_list = in.fac_list;
+  A.fac_cost = in.fac_cost;
+  A.sk_rank = in.ads->sk_rank;
+  A.sk_dist = in.ads->sk_dist;
+  A.thr = in.ads->thr;
+  A.cnt = in.ads->cnt;
+  A.ceff = in.ceff;
+  A.frz = out.frz;
+  A.orung = out.orung;
+  A.q = out.q;
+  A.shi = c.arena->get<uint64_t>(nF);
+  A.slo = c.arena->get<uint64_t>(nF);
+  A.cursor = c.arena->get<uint32_t>(nF);
+  A.nlive = c.arena->get<uint32_t>(nF);
+  A.nxt = c.arena->get<uint32_t>(nF);
+  A.nhat = c.arena->get<double>(nF);
+  A.state = c.arena->get<uint8_t>(nF);
+  A.heavy = c.arena->get<uint32_t>(nF);
+  A.opened = c.arena->get<uint32_t>(nF);
+  uint32_t *cnts = c.arena->get<uint32_t>(2);
+  A.heavy_cnt = cnts;
+  A.opened_cnt = cnts + 1;
+  A.ctr = c.arena->get<uint32_t>(OC_NFIELD * 64);
+  uint64_t *dlab = c.arena->get<uint64_t>(n);
+  fill_u64(c, dlab, n, INF64);
+  fill_u32(c, out.frz, n, FL_RUNG_NONE);
+  fill_u32(c, out.orung, n, FL_RUNG_NONE);
+  if (nF) {
+    k_fac_init<<<(uint32_t)ceil_div(nF, 256), 256, 0, c.s>>>(A);
+    FL_LAUNCH_CHECK();
+  }
+  SsspWork wk;
+  sssp_alloc(c, wk, n);
+
+  std::vector<double> &lad = *in.lad;
+  const double one_eps = 1.0 + in.eps;
+  uint32_t nO = 0, t = 0, nguard = 0;
+  uint64_t nU = in.nCeff, nUF = in.nUF0, finite_unfrozen = 0;
+  bool any_freeze_prev = false;
+  const uint32_t fblocks = (uint32_t)ceil_div(nF ? nF : 1, 256);
+  const uint32_t hblocks = (uint32_t)std::min<uint64_t>(ceil_div((uint64_t)(nF ? nF : 1) * WAVE, 256), 4096);
+  const uint32_t vblocks = (uint32_t)ceil_div(n, 256);
+  uint64_t ctr[OC_NFIELD];
+  while (nO < nF && nU > 0) {
+    if (finite_unfrozen == 0 && nUF == 0) {
+      // stall check
+      fill_u32(c, A.ctr, OC_NFIELD * 64, 0);
+      k_stuck_scan<<<(uint32_t)ceil_div((uint64_t)nF * WAVE, 256), 256, 0, c.s>>>(A);
+      FL_LAUNCH_CHECK();
+      read_ctr(c, A.ctr, ctr);
+      if (ctr[OC_LIVE] == 0) {
+        k_guard<<<vblocks, 256, 0, c.s>>>(n, in.ceff, out.frz, out.orung, in.gam_lab);
+        FL_LAUNCH_CHECK();
+        nU = 0;
+        break;
+      }
+    }
+    ++t;
+    while (lad.size() <= t) lad.push_back(lad.back() * one_eps);
+    const double alpha = lad[t];
+    if (!std::isfinite(alpha)) return FL_ERANGE;
+    const double eps_alpha = in.eps * alpha;
+    const double ae = one_eps * alpha;
+    fill_u32(c, cnts, 2, 0);
+    fill_u32(c, A.ctr, OC_NFIELD * 64, 0);
+    k_open_light<<<fblocks, 256, 0, c.s>>>(A, t, alpha, eps_alpha, any_freeze_prev ? 1 : 0);
+    FL_LAUNCH_CHECK();
+    k_open_heavy<<<hblocks, 256, 0, c.s>>>(A, t, alpha, eps_alpha, ae, lad[0], lad[1],
+                                           any_freeze_prev ? 1 : 0);
+    FL_LAUNCH_CHECK();
+    read_ctr(c, A.ctr, ctr);
+    const uint32_t opened = (uint32_t)ctr[OC_OPENED];
+    nUF -= ctr[OC_NUF_DEC];
+    if (opened) {
+      nO += opened;
+      k_seed_opened<<<(uint32_t)ceil_div(opened, 256), 256, 0, c.s>>>(A.opened, A.opened_cnt, dlab);
+      FL_LAUNCH_CHECK();
+      sssp_run(c, g, dlab, A.opened, opened, wk, 0);
+    }
+    any_freeze_prev = false;
+    if (nO > 0) {
+      const double rho = one_eps * alpha;
+      fill_u32(c, A.ctr, OC_NFIELD * 64, 0);
+      k_freeze<<<vblocks, 256, 0, c.s>>>(A, dlab, t, rho, in.fac_idx);
+      FL_LAUNCH_CHECK();
+      read_ctr(c, A.ctr, ctr);
+      nU -= ctr[OC_FROZEN];
+      nUF -= ctr[OC_NUF_DEC];
+      finite_unfrozen = ctr[OC_FINITE];
+      any_freeze_prev = ctr[OC_FROZEN] > 0;
+    }
+  }
+  out.rungs = t;
+  out.nO = nO;
+  if (nO == nF && nU > 0) {
+    k_endphase<<<vblocks, 256, 0, c.s>>>(n, in.ceff, out.frz);
+    FL_LAUNCH_CHECK();
+  }
+  (void)nguard;
+  // q by vertex for the caller's diagnostics is scattered later
+  return FL_OK;
+}
+
+}  // namespace fl

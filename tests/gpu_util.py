@@ -1,0 +1,78 @@
+"""Helpers shared by the GPU tests: device copies, oracle comparisons."""
+import numpy as np
+import torch
+
+import oracle as O
+import paper_1503_03635_amd as fl
+
+
+def u32(t):
+    return t.detach().cpu().numpy().view(np.uint32)
+
+
+def host(t, dtype):
+    return t.detach().cpu().numpy().view(dtype)
+
+
+def gpu_sketch(g, k, seed, flags=0):
+    dg = fl.to_device(g)
+    s = fl.ads_build(dg, k, seed, flags=flags)
+    return {"off": host(s["off"], np.uint64), "rank": u32(s["rank"]), "dist": u32(s["dist"]),
+            "thresh": u32(s["thresh"])}
+
+
+def assert_sketch_equal(g, k, seed, flags=0, oracle_fn=None):
+    """GPU sketches (offsets, ranks, distances, HIP thresholds) equal the
+    oracle's bit for bit."""
+    got = gpu_sketch(g, k, seed, flags)
+    want = (oracle_fn or O.ads_pruned)(g, k, seed=seed)
+    assert np.array_equal(got["off"], want["off"]), "offsets differ"
+    assert np.array_equal(got["rank"], want["rank"]), "ranks differ"
+    assert np.array_equal(got["dist"], want["dist"]), "distances differ"
+    T, _ = O.hipest(want, k)
+    T32 = np.where(T == (1 << 32), 0, T).astype(np.uint32)
+    assert np.array_equal(got["thresh"], T32), "HIP thresholds differ"
+    return got
+
+
+def gpu_solve(g, k, seed, eps=0.1, flags=0):
+    dg = fl.to_device(g)
+    r = fl.solve(dg, k, seed, eps, flags=flags, diagnostics=True)
+    torch.cuda.synchronize()
+    return {
+        "open": host(r["open"], np.uint8), "assign": u32(r["assign"]), "dist": u32(r["dist"]),
+        "open_rung": u32(r["open_rung"]), "freeze_rung": u32(r["freeze_rung"]),
+        "q": host(r["q"], np.float64), "total_cost": r["total_cost"], "n_open": r["n_open"],
+        "n_unreachable": r["n_unreachable"], "stats": r["stats"],
+    }
+
+
+def assert_solve_equal(g, k, seed, eps=0.1, flags=0):
+    """Every output of fl_solve equals the oracle: opened set, assignment,
+    distances, rungs and the double-precision q bit for bit (the 1e-12
+    relative tolerance is met with error 0), cost and counts."""
+    got = gpu_solve(g, k, seed, eps, flags)
+    rc, want = O.solve(g, k, seed, eps)
+    assert rc == 0
+    for key in ("open_rung", "freeze_rung"):
+        bad = np.nonzero(got[key] != want[key])[0]
+        assert len(bad) == 0, f"{key} differs at {bad[:10]}: gpu {got[key][bad[:10]]} oracle {want[key][bad[:10]]}"
+    qd = np.nonzero(got["q"].view(np.uint64) != want["q"].view(np.uint64))[0]
+    if len(qd):
+        rel = np.max(np.abs(got["q"][qd] - want["q"][qd]) / np.maximum(np.abs(want["q"][qd]), 1e-300))
+        assert rel <= 1e-12, f"q differs at {qd[:10]} (max rel {rel})"
+    for key in ("open", "assign", "dist"):
+        bad = np.nonzero(got[key] != want[key])[0]
+        assert len(bad) == 0, f"{key} differs at {bad[:10]}"
+    assert got["total_cost"] == want["total_cost"]
+    assert got["n_open"] == want["n_open"]
+    assert got["n_unreachable"] == want["n_unreachable"]
+    st = got["stats"]
+    assert st["rungs"] == want["n_rungs"]
+    assert st["mis_rounds"] == want["mis_rounds"]
+    assert st["relax_alg"] == want["relax_alg"]
+    assert st["ads_entries"] == want["ads_entries"]
+    assert st["gamma"] == want["gamma"]
+    assert st["n_guard"] == want["n_guard"]
+    assert st["alpha0"] == want["alpha0"]
+    return got, want

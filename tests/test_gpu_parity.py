@@ -1,0 +1,174 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, element
+by element, on seeded inputs.  Integer outputs must be bit-exact; the double
+q(f) must agree to 1e-12 relative (bit-exact in practice)."""
+import numpy as np
+import pytest
+import torch
+
+import graphgen as gg
+import oracle as O
+import paper_1503_03635_amd as fl
+
+from gpu_util import assert_sketch_equal, assert_solve_equal, gpu_solve
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    fl.lib()
+
+
+SKETCH_CASES = [
+    ("tiny ER n=2000 w1..10", lambda: gg.tiny_er(1), 16),
+    ("ER n=500 unit", lambda: gg.er(500, 6, 3), 4),
+    ("RMAT 2^12 unit", lambda: gg.rmat(12, 16 << 12, 5), 64),
+    ("RMAT 2^11 w1..100", lambda: gg.rmat(11, 8 << 11, 6, wmax=100), 32),
+    ("grid 20x20 ties", lambda: gg.grid(20, 20), 8),
+    ("clique 70 (hub rows)", lambda: gg.clique(70, wmax=3), 64),
+    ("star 3000 (one hub)", lambda: gg.star(3000), 16),
+    ("path 300 w1..255", lambda: gg.path(300, wmax=255, seed=2), 2),
+    ("disjoint + isolated", lambda: gg.disjoint_union(gg.path(40), gg.star(30, wmax=5), gg.empty(5),
+                                                      gg.cycle(17)), 3),
+    ("Chung-Lu n=3000 w1..20", lambda: gg.chung_lu(3000, 4, 2.2, 10.0, 20), 32),
+]
+
+
+@pytest.mark.parametrize("name,make,k", SKETCH_CASES, ids=[c[0] for c in SKETCH_CASES])
+def test_sketches_bit_exact(name, make, k):
+    g = make()
+    print(f"[sketch] {name} n={g.n} arcs={g.n_arcs} k={k}", flush=True)
+    assert_sketch_equal(g, k, seed=7)
+
+
+@pytest.mark.parametrize("k", [1, 2, 5, 64])
+def test_sketches_k_edges(k):
+    g = gg.rmat(10, 6 << 10, 11)
+    print(f"[sketch] rmat 2^10 k={k}", flush=True)
+    assert_sketch_equal(g, k, seed=3)
+
+
+def test_sketches_k_at_least_n():
+    g = gg.er(60, 5, 2, wmax=4)
+    print("[sketch] k >= n", flush=True)
+    assert_sketch_equal(g, 64, seed=1)
+
+
+def test_sketches_schedule_invariant():
+    """Dense rounds and frontier worklists give the same bytes."""
+    g = gg.rmat(12, 16 << 12, 9)
+    print("[sketch] dense vs frontier", flush=True)
+    a = assert_sketch_equal(g, 32, seed=2, flags=0)
+    b = assert_sketch_equal(g, 32, seed=2, flags=fl.FL_FLAG_NO_DENSE)
+    for key in a:
+        assert np.array_equal(a[key], b[key])
+
+
+SOLVE_CASES = [
+    ("tiny ER n=2000 w1..10 k16 cost50", lambda: gg.tiny_er(1), 16),
+    ("ER n=400 w1..10 costs 1..200", lambda: gg.with_problem(gg.er(400, 5, 7, wmax=10), 7, cost="uniform",
+                                                             cost_lo=1, cost_hi=200), 8),
+    ("RMAT 2^11 unit costs 1..1000", lambda: gg.with_problem(gg.rmat(11, 16 << 11, 8), 8, cost="uniform"), 64),
+    ("RMAT 2^10 w1..100 10% fac lognormal", lambda: gg.with_problem(gg.rmat(10, 16 << 10, 9, wmax=100), 9,
+                                                                    cost="lognormal", fac_frac=0.1), 32),
+    ("grid 15x15 w1..4", lambda: gg.with_problem(gg.grid(15, 15, wmax=4), 4, cost="uniform", cost_lo=1,
+                                                 cost_hi=60), 8),
+    ("Chung-Lu n=2000 w1..20", lambda: gg.with_problem(gg.chung_lu(2000, 3, 2.2, 10.0, 20), 3,
+                                                       cost="uniform"), 32),
+    ("half clients", lambda: gg.with_problem(gg.er(300, 4, 5, wmax=6), 5, cost="uniform", cost_hi=100,
+                                             client_frac=0.5, fac_frac=0.5), 8),
+]
+
+
+@pytest.mark.parametrize("name,make,k", SOLVE_CASES, ids=[c[0] for c in SOLVE_CASES])
+def test_solve_bit_exact(name, make, k):
+    g = make()
+    print(f"[solve] {name} n={g.n} arcs={g.n_arcs} k={k}", flush=True)
+    for seed in (1, 2):
+        assert_solve_equal(g, k, seed)
+
+
+@pytest.mark.parametrize("eps", [0.01, 1.0])
+def test_solve_other_eps(eps):
+    g = gg.with_problem(gg.er(200, 5, 2, wmax=5), 2, cost="uniform", cost_hi=80)
+    print(f"[solve] eps={eps}", flush=True)
+    assert_solve_equal(g, 8, 3, eps=eps)
+
+
+def test_solve_tiny_exhaustive_graphs():
+    for seed in range(8):
+        n = 8 + seed % 5
+        g = gg.with_problem(gg.er(n, 3, seed, wmax=6), seed, cost="uniform", cost_lo=1, cost_hi=25)
+        print(f"[solve] tiny n={n} seed={seed}", flush=True)
+        for k in (1, 4, n):
+            assert_solve_equal(g, k, seed)
+
+
+def test_solve_stall_guard():
+    for seed in range(200):
+        g = gg.star(5)
+        g.fac_cost = np.array([3] + [gg.NOT_FACILITY] * 4, np.uint32)
+        g.is_client = np.array([0, 1, 1, 1, 1], np.uint8)
+        sk = O.ads_pruned(g, 1, seed=seed)
+        if sk["off"][1] - sk["off"][0] == 1:
+            print(f"[solve] guard seed={seed}", flush=True)
+            got, want = assert_solve_equal(g, 1, seed)
+            assert want["n_guard"] == 1
+            return
+    pytest.fail("no seed for the guard case")
+
+
+def test_solve_degenerate_inputs():
+    cases = []
+    one = gg.empty(1)
+    one.fac_cost = np.array([5], np.uint32)
+    cases.append(("single vertex", one))
+    iso = gg.empty(50)
+    iso.fac_cost = np.arange(1, 51, dtype=np.uint32)
+    cases.append(("isolated vertices", iso))
+    nofac = gg.with_problem(gg.path(20), 1)
+    nofac.fac_cost = np.full(20, gg.NOT_FACILITY, np.uint32)
+    cases.append(("no facilities", nofac))
+    comp = gg.disjoint_union(gg.path(10), gg.star(8))
+    fc = np.full(comp.n, gg.NOT_FACILITY, np.uint32)
+    fc[:10] = 4                                   # the star has no facility
+    comp.fac_cost = fc
+    cases.append(("unreachable clients", comp))
+    for name, g in cases:
+        print(f"[solve] {name}", flush=True)
+        assert_solve_equal(g, 4, 1)
+
+
+def test_error_codes():
+    g = gg.with_problem(gg.er(50, 4, 1, wmax=5), 1)
+    dg = fl.to_device(g)
+    with pytest.raises(fl.FlError) as e:
+        fl.solve(dg, 65, 1)
+    assert e.value.code == fl._lib.FL_ENOTIMPL
+    with pytest.raises(fl.FlError) as e:
+        fl.solve(dg, 4, 1, eps=-1.0)
+    assert e.value.code == fl._lib.FL_EINVAL
+    bad = gg.Graph(g.n, g.row_ptr.copy(), g.col.copy(), g.w.copy(), g.fac_cost)
+    bad.w[0] += 1                                 # asymmetric weight
+    with pytest.raises(fl.FlError) as e:
+        fl.solve(fl.to_device(bad), 4, 1)
+    assert e.value.code == fl._lib.FL_EINVAL
+    bad = gg.Graph(g.n, g.row_ptr.copy(), g.col.copy(), g.w.copy(), g.fac_cost)
+    bad.w[3] = 0
+    with pytest.raises(fl.FlError) as e:
+        fl.solve(fl.to_device(bad), 4, 1)
+    assert e.value.code == fl._lib.FL_EINVAL
+    big = gg.with_problem(gg.path(5, wmax=None), 1)
+    big.w = np.full(big.n_arcs, 300, np.uint32)   # beyond the slot ring
+    with pytest.raises(fl.FlError) as e:
+        fl.solve(fl.to_device(big), 4, 1)
+    assert e.value.code == fl._lib.FL_ENOTIMPL
+    huge = gg.with_problem(gg.path(3), 1)
+    huge.w = np.full(huge.n_arcs, 200, np.uint32)
+    huge.fac_cost = np.array([0xFFFFFFF0, 1, 1], np.uint32)
+    with pytest.raises(fl.FlError) as e:
+        fl.solve(fl.to_device(huge), 4, 1)
+    assert e.value.code == fl._lib.FL_ERANGE
+    # the library keeps working after errors
+    assert_solve_equal(g, 4, 1)
