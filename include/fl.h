@@ -92,6 +92,8 @@ typedef struct {
   uint64_t gamma;       /* max over served clients of min_f c(f) + d(c,f) */
   double alpha0;        /* first ladder value */
   double ms_validate, ms_ads, ms_gamma, ms_open, ms_mis, ms_assign, ms_total;
+  double ms_ads_kernel;          /* summed device time of the sketch-round kernel launches */
+  uint32_t ads_kernel_launches;  /* number of those launches */
   uint64_t workspace_bytes;
 } fl_stats;
 

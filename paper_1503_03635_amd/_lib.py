@@ -36,7 +36,8 @@ class FlStats(C.Structure):
                 ("ads_entries", C.c_uint64), ("gamma", C.c_uint64), ("alpha0", C.c_double),
                 ("ms_validate", C.c_double), ("ms_ads", C.c_double), ("ms_gamma", C.c_double),
                 ("ms_open", C.c_double), ("ms_mis", C.c_double), ("ms_assign", C.c_double),
-                ("ms_total", C.c_double), ("workspace_bytes", C.c_uint64)]
+                ("ms_total", C.c_double), ("ms_ads_kernel", C.c_double),
+                ("ads_kernel_launches", C.c_uint32), ("workspace_bytes", C.c_uint64)]
 
 
 class FlResult(C.Structure):

@@ -21,6 +21,8 @@ struct AdsOut {
   const uint32_t *thr_idx = nullptr;
   uint32_t rounds = 0;
   uint64_t relax_exec = 0;
+  double kernel_ms = 0.0;     // summed device time of the round-kernel launches
+  uint32_t launches = 0;
 };
 
 uint32_t ads_capacity(uint32_t n, uint32_t k);

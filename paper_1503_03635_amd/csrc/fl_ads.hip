@@ -32,7 +32,7 @@
 namespace fl {
 
 constexpr int ADS_WPB = 4;     // waves per block
-constexpr int ADS_SB = 512;    // survivor buffer per wave (power of two)
+constexpr uint32_t ADS_SB_MAX = 2048;  // largest survivor buffer per wave (ids; 4 waves fit 64 KB)
 
 struct AdsArgs {
   uint32_t n, k, cap, W, NS, FW;
@@ -126,15 +126,12 @@ __global__ __launch_bounds__(256) void k_ads_init(AdsArgs P, int mark) {
   if (mark) mark_neighbours<UNITW>(P, u, 0);
 }
 
-// Sort s_id/s_rank[0..ns) by id (bitonic over the next power of two).
-__device__ inline void wave_sort_by_id(uint32_t *s_id, uint32_t *s_rank, uint32_t ns) {
+// Sort s_id[0..ns) ascending (bitonic over the next power of two <= SB).
+__device__ inline void wave_sort_ids(uint32_t *s_id, uint32_t ns) {
   const int lane = lane_id();
   uint32_t p2 = 2;
   while (p2 < ns) p2 <<= 1;
-  for (uint32_t i = ns + lane; i < p2; i += WAVE) {
-    s_id[i] = INF32;
-    s_rank[i] = INF32;
-  }
+  for (uint32_t i = ns + lane; i < p2; i += WAVE) s_id[i] = INF32;
   wave_lds_sync();
   for (uint32_t k2 = 2; k2 <= p2; k2 <<= 1) {
     for (uint32_t j = k2 >> 1; j > 0; j >>= 1) {
@@ -146,9 +143,6 @@ __device__ inline void wave_sort_by_id(uint32_t *s_id, uint32_t *s_rank, uint32_
           if ((a > b) == asc) {
             s_id[i] = b;
             s_id[ixj] = a;
-            const uint32_t ra = s_rank[i];
-            s_rank[i] = s_rank[ixj];
-            s_rank[ixj] = ra;
           }
         }
       }
@@ -157,19 +151,21 @@ __device__ inline void wave_sort_by_id(uint32_t *s_id, uint32_t *s_rank, uint32_
   }
 }
 
-// Bottom-k pass over the sorted survivors (duplicates adjacent).  bkv/nb is
-// the running set (one rank per lane, INF32 above nb).  Accepted entries are
-// compacted to the front of s_id/s_rank (and their thresholds to s_thr).
+// Bottom-k pass over the id-sorted survivors (duplicates adjacent).  bkv/nb
+// is the running set (one rank per lane, INF32 above nb).  Accepted ids are
+// compacted to the front of s_id.  When thr_out is given, the HIP threshold
+// of the i-th accepted entry goes to thr_out[i] (lane 0 writes; the caller
+// guarantees room for `room` entries and the pass stops writing beyond it).
 // Returns the number accepted.
-__device__ inline uint32_t wave_bottomk_pass(uint32_t *s_id, uint32_t *s_rank, uint32_t *s_thr, uint32_t ns,
-                                             uint32_t k, uint32_t &bkv, uint32_t &nb) {
+__device__ inline uint32_t wave_bottomk_pass(uint32_t *s_id, uint32_t ns, uint32_t k, PermKey rk,
+                                             uint32_t &bkv, uint32_t &nb, uint32_t *thr_out, uint32_t room) {
   const int lane = lane_id();
   uint32_t m = 0, prev = INF32;
   for (uint32_t i = 0; i < ns; ++i) {
     const uint32_t id = s_id[i];
-    const uint32_t r = s_rank[i];
     if (id == prev) continue;
     prev = id;
+    const uint32_t r = perm_fwd(id, rk);
     const uint32_t below = (uint32_t)__popcll(__ballot(bkv < r));
     if (below < k) {
       const uint32_t Tj = nb < k ? 0u : __shfl(bkv, (int)k - 1, WAVE);
@@ -179,8 +175,7 @@ __device__ inline uint32_t wave_bottomk_pass(uint32_t *s_id, uint32_t *s_rank, u
       if (nb < k) ++nb;
       if (lane == 0) {
         s_id[m] = id;
-        s_rank[m] = r;
-        if (s_thr) s_thr[m] = Tj;
+        if (thr_out && m < room) thr_out[m] = Tj;
       }
       ++m;
     }
@@ -191,19 +186,14 @@ __device__ inline uint32_t wave_bottomk_pass(uint32_t *s_id, uint32_t *s_rank, u
 
 template <bool UNITW>
 __global__ __launch_bounds__(256) void k_ads_round(AdsArgs P, uint32_t D, const uint32_t *list,
-                                                   uint32_t count, int sparse, int mark) {
-  __shared__ uint32_t s_id_all[ADS_WPB][ADS_SB];
-  __shared__ uint32_t s_rank_all[ADS_WPB][ADS_SB];
-  __shared__ uint32_t s_thr_all[ADS_WPB][ADS_SB];
-  __shared__ uint32_t s_bk_all[ADS_WPB][WAVE];
+                                                   uint32_t count, int sparse, int mark, uint32_t SB) {
+  extern __shared__ uint32_t lds[];
   const int lane = lane_id();
   const int wv = threadIdx.x / WAVE;
   const uint64_t item = (uint64_t)blockIdx.x * ADS_WPB + wv;
   if (item >= count) return;
-  uint32_t *s_id = s_id_all[wv];
-  uint32_t *s_rank = s_rank_all[wv];
-  uint32_t *s_thr = s_thr_all[wv];
-  uint32_t *s_bk = s_bk_all[wv];
+  uint32_t *s_bk = lds + wv * (SB + WAVE);
+  uint32_t *s_id = s_bk + WAVE;
 
   const uint32_t u = list[item];
   const uint32_t slotD = D % P.NS;
@@ -271,22 +261,18 @@ __global__ __launch_bounds__(256) void k_ads_round(AdsArgs P, uint32_t D, const 
       }
       uint64_t msk = __ballot(pass);
       if (msk) {
-        uint32_t np = (uint32_t)__popcll(msk);
-        if (ns + np > ADS_SB) {
+        const uint32_t np = (uint32_t)__popcll(msk);
+        if (ns + np > SB) {
           // shrink the buffer: keep what survives against the current set
-          wave_sort_by_id(s_id, s_rank, ns);
+          wave_sort_ids(s_id, ns);
           uint32_t tb = bkv0, tn = nb0;
-          ns = wave_bottomk_pass(s_id, s_rank, nullptr, ns, k, tb, tn);
-          if (ns + np > ADS_SB) {
+          ns = wave_bottomk_pass(s_id, ns, k, P.rk, tb, tn, nullptr, 0);
+          if (ns + np > SB) {
             if (lane == 0) atomicOr(&P.status[1], 1u);
             return;
           }
         }
-        if (pass) {
-          const uint32_t p = ns + lanes_below(msk);
-          s_rank[p] = r;
-          s_id[p] = perm_inv(r, P.rk);
-        }
+        if (pass) s_id[ns + lanes_below(msk)] = perm_inv(r, P.rk);
         ns += np;
         wave_lds_sync();
       }
@@ -295,19 +281,19 @@ __global__ __launch_bounds__(256) void k_ads_round(AdsArgs P, uint32_t D, const 
   if (lane == 0) atomicAdd((unsigned long long *)&P.ctr[blockIdx.x & 63], (unsigned long long)examined);
   if (ns == 0) return;
 
-  wave_sort_by_id(s_id, s_rank, ns);
-  const uint32_t m = wave_bottomk_pass(s_id, s_rank, s_thr, ns, k, bkv, nb);
+  wave_sort_ids(s_id, ns);
+  const uint32_t ti = P.thr ? (P.thr_idx ? P.thr_idx[u] : u) : INF32;
+  uint32_t *thr_out = ti != INF32 ? P.thr + (size_t)ti * P.cap + cu : nullptr;
+  const uint32_t m = wave_bottomk_pass(s_id, ns, k, P.rk, bkv, nb, thr_out, P.cap - cu);
   if (m == 0) return;
   if (cu + m > P.cap) {
     if (lane == 0) atomicOr(&P.status[0], 1u);
     return;
   }
   const size_t base = (size_t)u * P.cap + cu;
-  const uint32_t ti = P.thr ? (P.thr_idx ? P.thr_idx[u] : u) : INF32;
   for (uint32_t i = lane; i < m; i += WAVE) {
-    P.sk_rank[base + i] = s_rank[i];
+    P.sk_rank[base + i] = perm_fwd(s_id[i], P.rk);
     P.sk_dist[base + i] = D;
-    if (ti != INF32) P.thr[(size_t)ti * P.cap + cu + i] = s_thr[i];
   }
   if ((uint32_t)lane < nb) P.bk[(size_t)u * k + lane] = bkv;
   if (lane == 0) {
@@ -423,6 +409,23 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
     FL_LAUNCH_CHECK();
   }
   bool sparse = mark;  // mode of round 1
+  // survivor buffer: a whole distance level of one sketch (at most cap
+  // entries) plus one chunk of candidates fits
+  uint32_t SB = 256;
+  while (SB < cap + WAVE && SB < ADS_SB_MAX) SB <<= 1;
+  const size_t lds_bytes = (size_t)ADS_WPB * (SB + WAVE) * sizeof(uint32_t);
+  hipEvent_t e0, e1;
+  FL_HIP(hipEventCreate(&e0));
+  FL_HIP(hipEventCreate(&e1));
+  struct EvDel {
+    hipEvent_t a, b;
+    ~EvDel() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } evdel{e0, e1};
+  o.kernel_ms = 0.0;
+  o.launches = 0;
   uint64_t active_prev = n;
   uint32_t rounds = 0;
   std::vector<uint32_t> hwl(NS);
@@ -445,11 +448,15 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
     fill_u64(c, P.ctr + 64, 64, 0);
     if (count) {
       const uint64_t blocks = ceil_div(count, ADS_WPB);
+      FL_HIP(hipEventRecord(e0, c.s));
       if (unit)
-        k_ads_round<true><<<(uint32_t)blocks, 256, 0, c.s>>>(P, D, list, count, sparse ? 1 : 0, mark ? 1 : 0);
+        k_ads_round<true><<<(uint32_t)blocks, 256, lds_bytes, c.s>>>(P, D, list, count, sparse ? 1 : 0,
+                                                                     mark ? 1 : 0, SB);
       else
-        k_ads_round<false><<<(uint32_t)blocks, 256, 0, c.s>>>(P, D, list, count, sparse ? 1 : 0, mark ? 1 : 0);
+        k_ads_round<false><<<(uint32_t)blocks, 256, lds_bytes, c.s>>>(P, D, list, count, sparse ? 1 : 0,
+                                                                      mark ? 1 : 0, SB);
       FL_LAUNCH_CHECK();
+      FL_HIP(hipEventRecord(e1, c.s));
     }
     if (sparse) fill_u32(c, P.wl_cnt + slot, 1, 0);
     ++rounds;
@@ -459,6 +466,12 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
     FL_HIP(hipMemcpyAsync(c.h_status + 1, P.ctr + 64, 64 * 8, hipMemcpyDeviceToHost, c.s));
     FL_HIP(hipMemcpyAsync(hwl.data(), P.wl_cnt, NS * 4, hipMemcpyDeviceToHost, c.s));
     c.sync();
+    if (count) {
+      float ms = 0.f;
+      FL_HIP(hipEventElapsedTime(&ms, e0, e1));
+      o.kernel_ms += ms;
+      o.launches += 1;
+    }
     const uint32_t st0 = (uint32_t)(c.h_status[0] & 0xFFFFFFFFu);
     const uint32_t st1 = (uint32_t)(c.h_status[0] >> 32);
     if (st0) {
@@ -511,6 +524,8 @@ int ads_build(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o) {
     // scratch of the run is no longer needed; keep the outputs
     (void)mark;
     c.arena->rewind(after_out);
+    if (std::getenv("FL_DEBUG"))
+      std::fprintf(stderr, "[fl] sketches: cap %u rounds %u overflow %d\n", cap, o.rounds, (int)more);
     if (!more) return FL_OK;
     uint64_t nc = (uint64_t)cap * 3 / 2 + 16;
     if (nc > g.n) nc = g.n;

@@ -27,6 +27,7 @@ void Arena::reserve(size_t bytes) {
   release();
   void *p = nullptr;
   hipError_t e = hipMalloc(&p, bytes);
+  if (std::getenv("FL_DEBUG")) std::fprintf(stderr, "[fl] workspace %zu bytes: %s\n", bytes, hipGetErrorString(e));
   if (e != hipSuccess) {
     (void)hipGetLastError();
     throw Error{FL_ENOMEM};
@@ -273,6 +274,8 @@ static int solve_one(const fl_problem *p, const fl_params *prm, fl_result *out, 
   ads_totals(c, g, ads.cnt, &out->stats.relax_alg, &out->stats.ads_entries);
   out->stats.ads_rounds = ads.rounds;
   out->stats.relax_exec = ads.relax_exec;
+  out->stats.ms_ads_kernel = ads.kernel_ms;
+  out->stats.ads_kernel_launches = ads.launches;
   FL_HIP(hipEventRecord(ev[2], s));
 
   // gamma (Sec. 4.1) and served clients

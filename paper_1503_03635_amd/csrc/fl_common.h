@@ -8,6 +8,7 @@
 
 #include <cstddef>
 #include <cstdio>
+#include <cstdlib>
 #include <vector>
 
 #include "../../include/fl.h"
@@ -223,7 +224,11 @@ class Arena {
   template <class T>
   T *get(size_t count) {
     size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
-    if (used_ + bytes > cap_) throw Error{FL_ENOMEM};
+    if (used_ + bytes > cap_) {
+      if (std::getenv("FL_DEBUG"))
+        std::fprintf(stderr, "[fl] arena exhausted: used %zu + %zu > cap %zu\n", used_, bytes, cap_);
+      throw Error{FL_ENOMEM};
+    }
     T *p = reinterpret_cast<T *>(base_ + used_);
     used_ += bytes;
     if (used_ > peak_) peak_ = used_;
