@@ -10,6 +10,7 @@ struct AdsConfig {
   uint32_t flags;
   uint32_t thr_rows;         // rows of the HIP-threshold table (0 = none)
   const uint32_t *thr_idx;   // [n] row of each vertex (INF32 = none); nullptr = row u
+  const uint32_t *thr_rows_vertex;  // [thr_rows] vertex of each row; nullptr = row r is vertex r
 };
 
 struct AdsOut {
@@ -26,6 +27,8 @@ struct AdsOut {
 };
 
 uint32_t ads_capacity(uint32_t n, uint32_t k);
+// device bytes the construction needs besides its outputs
+size_t ads_scratch_bytes(uint32_t n, uint64_t m, uint32_t k, uint32_t NS);
 int ads_build(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o);
 int ads_export(Ctx &c, const Graph &g, const AdsOut &o, uint64_t *off, uint32_t *rank, uint32_t *dist,
                uint32_t *thr);

@@ -8,31 +8,39 @@
 // (distance, id) order, and no entry is ever evicted (the CleanUp of Alg. 2 is
 // never needed).  With unit weights this is the superstep order of Alg. 2.
 //
-// Per round and vertex u (one wave64 per vertex):
-//   1. stream the entries neighbours inserted at distance D - w (pull), drop
-//      those whose rank is not below T_u, the k-th smallest rank of u's sketch
-//      so far (k entries that all come first have a smaller rank), and those
-//      already in u's bottom-k set (same vertex, shorter distance);
-//   2. sort the survivors by vertex id in LDS (ties in distance go by id);
-//   3. walk them in id order with the running bottom-k set in registers (one
-//      rank per lane): a survivor enters iff fewer than k ranks of the set are
-//      below it, and then joins the set;
-//   4. append the accepted entries to u's sketch, record where they are for
-//      the next rounds, and mark the neighbours that will have candidates.
-// The running k-th smallest rank before each accepted entry is the HIP
-// threshold T_j of that entry; it is stored for the estimator.
+// Work items.  A vertex with at most TASK_ARCS arcs is one task; a larger one
+// is split into tasks of TASK_ARCS arcs.  Each task (one wave64) streams the
+// entries its neighbours inserted at distance D - w (pull), drops those whose
+// rank is not below T_u (the k-th smallest rank of u's sketch so far: k
+// entries that all come first have a smaller rank) and those already in u's
+// bottom-k set, and prunes the rest.  A split vertex's tasks leave their kept
+// sets in scratch; a merge wave prunes their union (the prune is associative
+// and idempotent, so the split does not change the result).
+//
+// Level prune.  A candidate of level D is accepted iff fewer than k ranks
+// below its own belong to entries that come first: the sketch so far, or
+// level-D candidates with a smaller vertex id (ties in distance go by id).
+// Candidates are counting-sorted into id buckets; buckets are walked in id
+// order, filtered in parallel against the running k-th smallest rank, and
+// the survivors of a bucket are decided 64 at a time by one parallel count
+// (set elements below + earlier candidates of the chunk below < k).
+// The HIP thresholds T_j (k-th smallest rank before entry j) are computed
+// afterwards for the rows that need them.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
-#include "fl_common.h"
 #include "fl_ads.h"
+#include "fl_common.h"
 
 namespace fl {
 
-constexpr int ADS_WPB = 4;     // waves per block
-constexpr uint32_t ADS_SB_MAX = 2048;  // largest survivor buffer per wave (ids; 4 waves fit 64 KB)
+constexpr int ADS_WPB = 4;          // waves per block
+constexpr uint32_t ADS_SB = 1024;   // survivor ids per wave: one level of one sketch plus a chunk
+constexpr uint32_t TASK_ARCS = 256; // arcs per task of a split vertex
+constexpr uint32_t NBKT = 32;       // id buckets of the level prune
 
 struct AdsArgs {
   uint32_t n, k, cap, W, NS, FW;
@@ -42,16 +50,17 @@ struct AdsArgs {
   const uint32_t *w;
   uint32_t *sk_rank;
   uint32_t *sk_dist;
-  uint32_t *thr;
-  const uint32_t *thr_idx;  // nullptr: thr row = vertex
   uint32_t *bk;
   uint32_t *cnt;
   uint64_t *dinfo;
   uint32_t *flags;
   uint32_t *wl;
   uint32_t *wl_cnt;
-  uint64_t *ctr;     // [64] relax_exec, [64] active vertices this round
-  uint32_t *status;  // [0] capacity overflow, [1] survivor-buffer overflow
+  uint32_t *kept;      // [slots * ADS_SB] kept ids of split tasks
+  uint32_t *kept_cnt;  // [slots]
+  uint64_t *ctr;       // [64] relax_exec, [64] active vertices this round
+  uint32_t *status;    // [0] capacity overflow, [1] survivor-buffer overflow
+  uint32_t bshift;     // id bucket = id >> bshift < NBKT
 };
 
 __device__ inline uint64_t pack_info(uint32_t round, uint32_t start, uint32_t count) {
@@ -115,10 +124,6 @@ __global__ __launch_bounds__(256) void k_ads_init(AdsArgs P, int mark) {
   if (lane == 0) {
     P.sk_rank[(size_t)u * P.cap] = r;
     P.sk_dist[(size_t)u * P.cap] = 0;
-    if (P.thr) {
-      const uint32_t ti = P.thr_idx ? P.thr_idx[u] : u;
-      if (ti != INF32) P.thr[(size_t)ti * P.cap] = 0;
-    }
     P.bk[(size_t)u * P.k] = r;
     P.cnt[u] = 1;
     P.dinfo[u] = pack_info(0, 0, 1);  // slot 0
@@ -126,23 +131,26 @@ __global__ __launch_bounds__(256) void k_ads_init(AdsArgs P, int mark) {
   if (mark) mark_neighbours<UNITW>(P, u, 0);
 }
 
-// Sort s_id[0..ns) ascending (bitonic over the next power of two <= SB).
-__device__ inline void wave_sort_ids(uint32_t *s_id, uint32_t ns) {
+// ---------------------------------------------------------------------------
+// sorting helpers
+// ---------------------------------------------------------------------------
+// Sort s[0..n) ascending in LDS (bitonic over the next power of two; the
+// caller guarantees that many slots).
+__device__ inline void wave_sort_lds(uint32_t *s, uint32_t n) {
   const int lane = lane_id();
   uint32_t p2 = 2;
-  while (p2 < ns) p2 <<= 1;
-  for (uint32_t i = ns + lane; i < p2; i += WAVE) s_id[i] = INF32;
+  while (p2 < n) p2 <<= 1;
+  for (uint32_t i = n + lane; i < p2; i += WAVE) s[i] = INF32;
   wave_lds_sync();
   for (uint32_t k2 = 2; k2 <= p2; k2 <<= 1) {
     for (uint32_t j = k2 >> 1; j > 0; j >>= 1) {
       for (uint32_t i = lane; i < p2; i += WAVE) {
         const uint32_t ixj = i ^ j;
         if (ixj > i) {
-          const uint32_t a = s_id[i], b = s_id[ixj];
-          const bool asc = (i & k2) == 0;
-          if ((a > b) == asc) {
-            s_id[i] = b;
-            s_id[ixj] = a;
+          const uint32_t a = s[i], b = s[ixj];
+          if ((a > b) == ((i & k2) == 0)) {
+            s[i] = b;
+            s[ixj] = a;
           }
         }
       }
@@ -151,77 +159,239 @@ __device__ inline void wave_sort_ids(uint32_t *s_id, uint32_t ns) {
   }
 }
 
-// Bottom-k pass over the id-sorted survivors (duplicates adjacent).  bkv/nb
-// is the running set (one rank per lane, INF32 above nb).  Accepted ids are
-// compacted to the front of s_id.  When thr_out is given, the HIP threshold
-// of the i-th accepted entry goes to thr_out[i] (lane 0 writes; the caller
-// guarantees room for `room` entries and the pass stops writing beyond it).
-// Returns the number accepted.
-__device__ inline uint32_t wave_bottomk_pass(uint32_t *s_id, uint32_t ns, uint32_t k, PermKey rk,
-                                             uint32_t &bkv, uint32_t &nb, uint32_t *thr_out, uint32_t room) {
+// Sort one value per lane ascending across the wave (bitonic network).
+__device__ inline uint32_t wave_sort_reg(uint32_t x) {
   const int lane = lane_id();
-  uint32_t m = 0, prev = INF32;
-  for (uint32_t i = 0; i < ns; ++i) {
-    const uint32_t id = s_id[i];
-    if (id == prev) continue;
-    prev = id;
-    const uint32_t r = perm_fwd(id, rk);
-    const uint32_t below = (uint32_t)__popcll(__ballot(bkv < r));
-    if (below < k) {
-      const uint32_t Tj = nb < k ? 0u : __shfl(bkv, (int)k - 1, WAVE);
-      const uint32_t up = __shfl_up(bkv, 1, WAVE);
-      if ((uint32_t)lane > below && (uint32_t)lane < k) bkv = up;
-      if ((uint32_t)lane == below) bkv = r;
-      if (nb < k) ++nb;
-      if (lane == 0) {
-        s_id[m] = id;
-        if (thr_out && m < room) thr_out[m] = Tj;
-      }
-      ++m;
+#pragma unroll
+  for (int k2 = 2; k2 <= WAVE; k2 <<= 1) {
+#pragma unroll
+    for (int j = k2 >> 1; j > 0; j >>= 1) {
+      const uint32_t y = __shfl_xor(x, j, WAVE);
+      const bool keep_min = ((lane & k2) == 0) == ((lane & j) == 0);
+      x = keep_min ? (x < y ? x : y) : (x > y ? x : y);
     }
   }
+  return x;
+}
+
+// number of values below r in a set held one value per lane, ascending, with
+// INF32 above its size (per-lane r; every lane runs the shuffles)
+__device__ inline uint32_t set_count_below(uint32_t setv, uint32_t r) {
+  uint32_t q = 0;
+#pragma unroll
+  for (uint32_t s = 32; s >= 1; s >>= 1) {
+    const uint32_t val = __shfl(setv, (int)(q + s - 1), WAVE);
+    if (val < r) q += s;
+  }
+  const uint32_t atq = __shfl(setv, (int)q, WAVE);
+  if (atq < r) ++q;  // all 64 values below r
+  return q;
+}
+
+// One chunk of candidates, one id per lane in ascending lane order (INF32 =
+// empty slot at the end); duplicates are adjacent; `prev` is the last id of
+// the previous chunk of this level.  Candidate i is accepted iff
+//   #(running set below r_i) + #(earlier distinct candidates of the chunk below r_i) < k.
+// The running set becomes the k smallest ranks of itself and the chunk.
+// Returns the mask of accepted lanes.
+__device__ inline uint64_t chunk_accept(uint32_t id, uint32_t k, PermKey rk, uint32_t &setv, uint32_t &nset,
+                                        uint32_t &prev) {
+  const int lane = lane_id();
+  uint32_t left = __shfl_up(id, 1, WAVE);
+  if (lane == 0) left = prev;
+  const bool valid = id != INF32 && id != left;
+  const uint32_t r = valid ? perm_fwd(id, rk) : INF32;
+  const uint32_t q = set_count_below(setv, r);
+  const uint64_t vm = __ballot(valid);
+  uint32_t cp = 0;
+  uint64_t it = vm;
+  while (it) {
+    const int j = __ffsll((long long)it) - 1;
+    it &= it - 1;
+    const uint32_t rj = __shfl(r, j, WAVE);
+    if (j < lane && rj < r) ++cp;
+  }
+  const bool acc = valid && q + cp < k;
+  const uint64_t am = __ballot(acc);
+  // merge: the k smallest of (set, chunk ranks)
+  uint32_t x = wave_sort_reg(valid ? r : INF32);
+  const uint32_t y = __shfl(x, WAVE - 1 - lane, WAVE);
+  uint32_t mm = setv < y ? setv : y;  // bitonic, holds the 64 smallest of both
+#pragma unroll
+  for (int j = 32; j >= 1; j >>= 1) {
+    const uint32_t o = __shfl_xor(mm, j, WAVE);
+    mm = (lane & j) == 0 ? (mm < o ? mm : o) : (mm > o ? mm : o);
+  }
+  setv = (uint32_t)lane < k ? mm : INF32;
+  const uint32_t tot = nset + (uint32_t)__popcll(vm);
+  nset = tot < k ? tot : k;
+  const uint64_t real = __ballot(id != INF32);
+  if (real) prev = __shfl(id, 63 - __clzll(real), WAVE);
+  return am;
+}
+
+// Prune of one distance level.  s_id[0..ns) holds candidate ids (unsorted,
+// duplicates allowed); setv/nset the running set.  Accepted ids end in
+// s_tmp[0..m) in increasing id order; returns m.  s_id is clobbered.
+__device__ inline uint32_t prune_level(uint32_t *s_id, uint32_t *s_tmp, uint32_t *s_cnt, uint32_t ns,
+                                       uint32_t bshift, uint32_t k, PermKey rk, uint32_t &setv,
+                                       uint32_t &nset, uint32_t *tbk = nullptr) {
+  const int lane = lane_id();
+  uint32_t m = 0, prev = INF32;
+  if (ns <= (uint32_t)WAVE && !tbk) {
+    uint32_t x = (uint32_t)lane < ns ? s_id[lane] : INF32;
+    x = wave_sort_reg(x);
+    const uint64_t am = chunk_accept(x, k, rk, setv, nset, prev);
+    if ((am >> lane) & 1) s_tmp[lanes_below(am)] = x;
+    wave_lds_sync();
+    return (uint32_t)__popcll(am);
+  }
+  if ((uint32_t)lane < NBKT) s_cnt[lane] = 0;
   wave_lds_sync();
+  for (uint32_t i = lane; i < ns; i += WAVE) atomicAdd(&s_cnt[s_id[i] >> bshift], 1u);
+  wave_lds_sync();
+  const uint32_t bc = (uint32_t)lane < NBKT ? s_cnt[lane] : 0u;
+  const uint32_t bstart = wave_scan_incl(bc) - bc;
+  if ((uint32_t)lane < NBKT) s_cnt[lane] = bstart;
+  wave_lds_sync();
+  for (uint32_t i = lane; i < ns; i += WAVE) {
+    const uint32_t id = s_id[i];
+    s_tmp[atomicAdd(&s_cnt[id >> bshift], 1u)] = id;
+  }
+  wave_lds_sync();
+  uint64_t nonempty = __ballot(bc != 0);
+  uint32_t tb = INF32;  // lane b: running k-th smallest rank when bucket b starts
+  int done_b = -1;
+  while (nonempty) {
+    const int b = __ffsll((long long)nonempty) - 1;
+    nonempty &= nonempty - 1;
+    const uint32_t cb = __shfl(bc, b, WAVE);
+    const uint32_t sb = __shfl(bstart, b, WAVE);
+    const bool open = nset < k;
+    const uint32_t Trun = open ? INF32 : __shfl(setv, (int)k - 1, WAVE);
+    if (lane > done_b && lane <= b) tb = Trun;
+    done_b = b;
+    // every candidate of an earlier bucket comes first: filter in parallel
+    uint32_t np = 0;
+    for (uint32_t j0 = 0; j0 < cb; j0 += WAVE) {
+      const uint32_t j = j0 + lane;
+      uint32_t id = INF32;
+      bool pass = false;
+      if (j < cb) {
+        id = s_tmp[sb + j];
+        pass = open || perm_fwd(id, rk) < Trun;
+      }
+      const uint64_t pm = __ballot(pass);
+      if (pass) s_tmp[sb + np + lanes_below(pm)] = id;
+      np += (uint32_t)__popcll(pm);
+    }
+    wave_lds_sync();
+    if (np == 0) continue;
+    if (np <= (uint32_t)WAVE) {
+      uint32_t x = (uint32_t)lane < np ? s_tmp[sb + lane] : INF32;
+      x = wave_sort_reg(x);
+      const uint64_t am = chunk_accept(x, k, rk, setv, nset, prev);
+      if ((am >> lane) & 1) s_tmp[m + lanes_below(am)] = x;  // m <= sb: earlier buckets only
+      m += (uint32_t)__popcll(am);
+    } else {
+      // many survivors in one bucket: sort them in s_id (free now), then chunks in order
+      for (uint32_t i = lane; i < np; i += WAVE) s_id[i] = s_tmp[sb + i];
+      wave_sort_lds(s_id, np);
+      for (uint32_t c0 = 0; c0 < np; c0 += WAVE) {
+        const uint32_t x = c0 + lane < np ? s_id[c0 + lane] : INF32;
+        const uint64_t am = chunk_accept(x, k, rk, setv, nset, prev);
+        if ((am >> lane) & 1) s_tmp[m + lanes_below(am)] = x;
+        m += (uint32_t)__popcll(am);
+      }
+    }
+    wave_lds_sync();
+  }
+  if (tbk) {
+    const uint32_t Tend = nset < k ? INF32 : __shfl(setv, (int)k - 1, WAVE);
+    if (lane > done_b) tb = Tend;
+    *tbk = tb;
+  }
   return m;
 }
 
-template <bool UNITW>
-__global__ __launch_bounds__(256) void k_ads_round(AdsArgs P, uint32_t D, const uint32_t *list,
-                                                   uint32_t count, int sparse, int mark, uint32_t SB) {
-  extern __shared__ uint32_t lds[];
+// ---------------------------------------------------------------------------
+// per-wave level state: candidate intake with filtering and buffering
+// ---------------------------------------------------------------------------
+struct Level {
+  uint32_t set0, nset0;  // u's bottom-k set at the start of the level
+  uint32_t T0;           // its k-th smallest rank (INF32 while fewer than k)
+  bool full0;
+  uint32_t cu;           // entries of u so far
+  uint32_t ns;           // buffered candidates
+  uint32_t tb;           // lane b < NBKT: rank bound for candidates of id bucket b
+  bool overflow;
+};
+
+__device__ inline void level_init(const AdsArgs &P, uint32_t u, Level &L) {
   const int lane = lane_id();
-  const int wv = threadIdx.x / WAVE;
-  const uint64_t item = (uint64_t)blockIdx.x * ADS_WPB + wv;
-  if (item >= count) return;
-  uint32_t *s_bk = lds + wv * (SB + WAVE);
-  uint32_t *s_id = s_bk + WAVE;
-
-  const uint32_t u = list[item];
-  const uint32_t slotD = D % P.NS;
-  if (sparse && lane == 0)
-    atomicAnd(&P.flags[(size_t)u * P.FW + (slotD >> 5)], ~(1u << (slotD & 31)));
-
   const uint32_t k = P.k;
-  const uint32_t cu = P.cnt[u];
-  uint32_t nb = cu < k ? cu : k;
-  uint32_t bkv = (uint32_t)lane < nb ? P.bk[(size_t)u * k + lane] : INF32;
-  s_bk[lane] = bkv;
-  wave_lds_sync();
-  const bool full = nb == k;
-  const uint32_t T = full ? __shfl(bkv, (int)k - 1, WAVE) : INF32;
-  const uint32_t nb0 = nb;
-  const uint32_t bkv0 = bkv;
+  L.cu = P.cnt[u];
+  L.nset0 = L.cu < k ? L.cu : k;
+  L.set0 = (uint32_t)lane < L.nset0 ? P.bk[(size_t)u * k + lane] : INF32;
+  L.full0 = L.nset0 == k;
+  L.T0 = L.full0 ? __shfl(L.set0, (int)k - 1, WAVE) : INF32;
+  L.ns = 0;
+  L.tb = L.T0;
+  L.overflow = false;
+}
 
-  uint32_t ns = 0;
+// One candidate per lane (valid, rank r, id if known): keep it if its rank is
+// below T0 and it is not already in the set; buffer kept ids, shrinking the
+// buffer by a prune against the set when full.
+__device__ inline void level_offer(const AdsArgs &P, Level &L, bool valid, uint32_t r, bool have_id, uint32_t id,
+                                   uint32_t *s_id, uint32_t *s_tmp, uint32_t *s_cnt) {
+  const int lane = lane_id();
+  bool pass = valid && (!L.full0 || r < L.T0);
+  const uint32_t q = set_count_below(L.set0, r);
+  const uint32_t atq = __shfl(L.set0, (int)(q < 63 ? q : 63), WAVE);
+  if (pass && q < L.nset0 && atq == r) pass = false;
+  // bucket bound from the last prune: all candidates of earlier id buckets
+  // come first, and k of them (or of the set) already rank below it
+  const uint32_t cid = have_id ? id : perm_inv(r, P.rk);
+  const uint32_t bnd = __shfl(L.tb, (int)((pass ? cid : 0u) >> P.bshift), WAVE);
+  if (pass && r >= bnd) pass = false;
+  uint64_t msk = __ballot(pass);
+  if (!msk) return;
+  uint32_t np = (uint32_t)__popcll(msk);
+  if (L.ns + np > ADS_SB) {
+    uint32_t tv = L.set0, tn = L.nset0;
+    L.ns = prune_level(s_id, s_tmp, s_cnt, L.ns, P.bshift, P.k, P.rk, tv, tn, &L.tb);
+    for (uint32_t i = lane; i < L.ns; i += WAVE) s_id[i] = s_tmp[i];
+    wave_lds_sync();
+    // the new bounds may reject some of this chunk too
+    const uint32_t bnd2 = __shfl(L.tb, (int)((pass ? cid : 0u) >> P.bshift), WAVE);
+    if (pass && r >= bnd2) pass = false;
+    msk = __ballot(pass);
+    np = (uint32_t)__popcll(msk);
+    if (L.ns + np > ADS_SB) {
+      L.overflow = true;
+      return;
+    }
+  }
+  if (pass) s_id[L.ns + lanes_below(msk)] = cid;
+  L.ns += np;
+  wave_lds_sync();
+}
+
+// Stream the candidates of arcs [a0, a1) of u for level D.
+template <bool UNITW>
+__device__ inline uint64_t gather_arcs(const AdsArgs &P, uint32_t D, uint64_t a0, uint64_t a1, Level &L,
+                                       uint32_t *s_id, uint32_t *s_tmp, uint32_t *s_cnt) {
+  const int lane = lane_id();
   uint64_t examined = 0;
-  const uint64_t a0 = P.row_ptr[u], a1 = P.row_ptr[u + 1];
-  for (uint64_t b = a0; b < a1; b += WAVE) {
+  for (uint64_t b = a0; b < a1 && !L.overflow; b += WAVE) {
     const uint64_t a = b + lane;
     uint32_t v = 0, st = 0, cn = 0;
     if (a < a1) {
       v = P.col[a];
-      const uint32_t wv_ = UNITW ? 1u : P.w[a];
-      if (wv_ <= D) {
-        const uint32_t src = D - wv_;
+      const uint32_t wv = UNITW ? 1u : P.w[a];
+      if (wv <= D) {
+        const uint32_t src = D - wv;
         const uint64_t info = P.dinfo[(size_t)(src % P.NS) * P.n + v];
         if ((uint32_t)(info >> 32) == src) {
           st = (uint32_t)(info >> 16) & 0xFFFFu;
@@ -233,10 +403,9 @@ __global__ __launch_bounds__(256) void k_ads_round(AdsArgs P, uint32_t D, const 
     const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
     const uint32_t excl = incl - cn;
     examined += total;
-    for (uint32_t c0 = 0; c0 < total; c0 += WAVE) {
+    for (uint32_t c0 = 0; c0 < total && !L.overflow; c0 += WAVE) {
       const uint32_t idx = c0 + lane;
-      // owner lane: first lane whose inclusive count exceeds idx
-      uint32_t pos = 0;
+      uint32_t pos = 0;  // owner lane: first lane whose inclusive count exceeds idx
 #pragma unroll
       for (uint32_t s = 32; s >= 1; s >>= 1) {
         const uint32_t val = __shfl(incl, (int)(pos + s - 1), WAVE);
@@ -248,63 +417,247 @@ __global__ __launch_bounds__(256) void k_ads_round(AdsArgs P, uint32_t D, const 
       const uint32_t oex = __shfl(excl, (int)pos, WAVE);
       uint32_t r = INF32;
       if (valid) r = P.sk_rank[(size_t)ov * P.cap + ost + (idx - oex)];
-      bool pass = valid && (!full || r < T);
-      if (pass) {
-        // already in the bottom-k set?  (binary search in the sorted set)
-        uint32_t lo = 0, hi = nb0;
-        while (lo < hi) {
-          const uint32_t mid = (lo + hi) >> 1;
-          if (s_bk[mid] < r) lo = mid + 1;
-          else hi = mid;
-        }
-        if (lo < nb0 && s_bk[lo] == r) pass = false;
-      }
-      uint64_t msk = __ballot(pass);
-      if (msk) {
-        const uint32_t np = (uint32_t)__popcll(msk);
-        if (ns + np > SB) {
-          // shrink the buffer: keep what survives against the current set
-          wave_sort_ids(s_id, ns);
-          uint32_t tb = bkv0, tn = nb0;
-          ns = wave_bottomk_pass(s_id, ns, k, P.rk, tb, tn, nullptr, 0);
-          if (ns + np > SB) {
-            if (lane == 0) atomicOr(&P.status[1], 1u);
-            return;
-          }
-        }
-        if (pass) s_id[ns + lanes_below(msk)] = perm_inv(r, P.rk);
-        ns += np;
-        wave_lds_sync();
-      }
+      level_offer(P, L, valid, r, false, 0, s_id, s_tmp, s_cnt);
     }
   }
-  if (lane == 0) atomicAdd((unsigned long long *)&P.ctr[blockIdx.x & 63], (unsigned long long)examined);
-  if (ns == 0) return;
+  return examined;
+}
 
-  wave_sort_ids(s_id, ns);
-  const uint32_t ti = P.thr ? (P.thr_idx ? P.thr_idx[u] : u) : INF32;
-  uint32_t *thr_out = ti != INF32 ? P.thr + (size_t)ti * P.cap + cu : nullptr;
-  const uint32_t m = wave_bottomk_pass(s_id, ns, k, P.rk, bkv, nb, thr_out, P.cap - cu);
+// Final prune of u's level-D candidates and the append of the accepted ones.
+template <bool UNITW>
+__device__ inline void level_commit(const AdsArgs &P, uint32_t u, uint32_t D, Level &L, int mark, uint32_t *s_id,
+                                    uint32_t *s_tmp, uint32_t *s_cnt) {
+  const int lane = lane_id();
+  if (L.ns == 0) return;
+  uint32_t setv = L.set0, nset = L.nset0;
+  const uint32_t m = prune_level(s_id, s_tmp, s_cnt, L.ns, P.bshift, P.k, P.rk, setv, nset);
   if (m == 0) return;
+  const uint32_t cu = L.cu;
   if (cu + m > P.cap) {
     if (lane == 0) atomicOr(&P.status[0], 1u);
     return;
   }
   const size_t base = (size_t)u * P.cap + cu;
   for (uint32_t i = lane; i < m; i += WAVE) {
-    P.sk_rank[base + i] = perm_fwd(s_id[i], P.rk);
+    P.sk_rank[base + i] = perm_fwd(s_tmp[i], P.rk);
     P.sk_dist[base + i] = D;
   }
-  if ((uint32_t)lane < nb) P.bk[(size_t)u * k + lane] = bkv;
+  if ((uint32_t)lane < nset) P.bk[(size_t)u * P.k + lane] = setv;
   if (lane == 0) {
     P.cnt[u] = cu + m;
-    P.dinfo[(size_t)slotD * P.n + u] = pack_info(D, cu, m);
+    P.dinfo[(size_t)(D % P.NS) * P.n + u] = pack_info(D, cu, m);
     atomicAdd((unsigned long long *)&P.ctr[64 + (blockIdx.x & 63)], 1ull);
   }
   if (mark) mark_neighbours<UNITW>(P, u, D);
 }
 
-// list of vertices with at least one arc, hubs first is not needed: any order
+// One wave per task.  task_slot == INF32: the task is the whole vertex and
+// commits; otherwise it leaves its kept set in scratch slot task_slot.
+template <bool UNITW>
+__global__ __launch_bounds__(256) void k_ads_tasks(AdsArgs P, uint32_t D, const uint32_t *task_u,
+                                                   const uint32_t *task_sub, const uint32_t *task_slot,
+                                                   uint32_t ntasks, int sparse, int mark) {
+  __shared__ uint32_t lds_id[ADS_WPB][ADS_SB];
+  __shared__ uint32_t lds_tmp[ADS_WPB][ADS_SB];
+  __shared__ uint32_t lds_cnt[ADS_WPB][WAVE];
+  const int lane = lane_id();
+  const int wv = threadIdx.x / WAVE;
+  const uint64_t item = (uint64_t)blockIdx.x * ADS_WPB + wv;
+  if (item >= ntasks) return;
+  uint32_t *s_id = lds_id[wv];
+  uint32_t *s_tmp = lds_tmp[wv];
+  uint32_t *s_cnt = lds_cnt[wv];
+  const uint32_t u = task_u[item];
+  const uint32_t sub = task_sub[item];
+  const uint32_t slot = task_slot[item];
+  if (sparse && sub == 0 && lane == 0) {
+    const uint32_t sD = D % P.NS;
+    atomicAnd(&P.flags[(size_t)u * P.FW + (sD >> 5)], ~(1u << (sD & 31)));
+  }
+  Level L;
+  level_init(P, u, L);
+  const uint64_t r0 = P.row_ptr[u], r1 = P.row_ptr[u + 1];
+  uint64_t a0 = r0, a1 = r1;
+  if (slot != INF32) {
+    a0 = r0 + (uint64_t)sub * TASK_ARCS;
+    a1 = a0 + TASK_ARCS < r1 ? a0 + TASK_ARCS : r1;
+  }
+  const uint64_t examined = gather_arcs<UNITW>(P, D, a0, a1, L, s_id, s_tmp, s_cnt);
+  if (lane == 0) atomicAdd((unsigned long long *)&P.ctr[blockIdx.x & 63], (unsigned long long)examined);
+  if (L.overflow) {
+    if (lane == 0) atomicOr(&P.status[1], 1u);
+    return;
+  }
+  if (slot == INF32) {
+    level_commit<UNITW>(P, u, D, L, mark, s_id, s_tmp, s_cnt);
+  } else {
+    uint32_t m = 0;
+    if (L.ns) {
+      uint32_t setv = L.set0, nset = L.nset0;
+      m = prune_level(s_id, s_tmp, s_cnt, L.ns, P.bshift, P.k, P.rk, setv, nset);
+      for (uint32_t i = lane; i < m; i += WAVE) P.kept[(size_t)slot * ADS_SB + i] = s_tmp[i];
+    }
+    if (lane == 0) P.kept_cnt[slot] = m;
+  }
+}
+
+// One wave per split vertex: prune the union of its tasks' kept sets, commit.
+template <bool UNITW>
+__global__ __launch_bounds__(256) void k_ads_merge(AdsArgs P, uint32_t D, const uint32_t *split_u,
+                                                   const uint32_t *split_first, const uint32_t *split_nt,
+                                                   uint32_t nsplit, int mark) {
+  __shared__ uint32_t lds_id[ADS_WPB][ADS_SB];
+  __shared__ uint32_t lds_tmp[ADS_WPB][ADS_SB];
+  __shared__ uint32_t lds_cnt[ADS_WPB][WAVE];
+  const int lane = lane_id();
+  const int wv = threadIdx.x / WAVE;
+  const uint64_t item = (uint64_t)blockIdx.x * ADS_WPB + wv;
+  if (item >= nsplit) return;
+  uint32_t *s_id = lds_id[wv];
+  uint32_t *s_tmp = lds_tmp[wv];
+  uint32_t *s_cnt = lds_cnt[wv];
+  const uint32_t u = split_u[item];
+  const uint32_t first = split_first[item];
+  const uint32_t nt = split_nt[item];
+  Level L;
+  level_init(P, u, L);
+  for (uint32_t g0 = 0; g0 < nt && !L.overflow; g0 += WAVE) {
+    const uint32_t cn = g0 + lane < nt ? P.kept_cnt[first + g0 + lane] : 0u;
+    const uint32_t incl = wave_scan_incl(cn);
+    const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
+    const uint32_t excl = incl - cn;
+    for (uint32_t c0 = 0; c0 < total && !L.overflow; c0 += WAVE) {
+      const uint32_t idx = c0 + lane;
+      uint32_t pos = 0;
+#pragma unroll
+      for (uint32_t s = 32; s >= 1; s >>= 1) {
+        const uint32_t val = __shfl(incl, (int)(pos + s - 1), WAVE);
+        if (val <= idx) pos += s;
+      }
+      const bool valid = idx < total;
+      const uint32_t oex = __shfl(excl, (int)pos, WAVE);
+      uint32_t id = INF32, r = INF32;
+      if (valid) {
+        id = P.kept[(size_t)(first + g0 + pos) * ADS_SB + (idx - oex)];
+        r = perm_fwd(id, P.rk);
+      }
+      level_offer(P, L, valid, r, true, id, s_id, s_tmp, s_cnt);
+    }
+  }
+  if (L.overflow) {
+    if (lane == 0) atomicOr(&P.status[1], 1u);
+    return;
+  }
+  level_commit<UNITW>(P, u, D, L, mark, s_id, s_tmp, s_cnt);
+}
+
+// HIP thresholds of the sketch rows that need them: T_j = k-th smallest rank
+// among entries 0..j-1 of the row (0 encodes 2^32 while fewer than k).  One
+// wave per row, the running bottom-k in registers.
+__global__ __launch_bounds__(256) void k_hip_thresholds(uint32_t rows, const uint32_t *row_vertex, uint32_t cap,
+                                                        uint32_t k, const uint32_t *cnt, const uint32_t *sk_rank,
+                                                        uint32_t *thr) {
+  const int lane = lane_id();
+  const uint64_t row = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  if (row >= rows) return;
+  const uint32_t u = row_vertex ? row_vertex[row] : (uint32_t)row;
+  const uint32_t c = cnt[u];
+  const uint32_t *rk = sk_rank + (size_t)u * cap;
+  uint32_t *out = thr + (size_t)row * cap;
+  uint32_t setv = INF32, nset = 0;
+  for (uint32_t j0 = 0; j0 < c; j0 += WAVE) {
+    const uint32_t mine = j0 + lane < c ? rk[j0 + lane] : INF32;
+    uint32_t tout = 0;
+    const uint32_t lim = c - j0 < (uint32_t)WAVE ? c - j0 : (uint32_t)WAVE;
+    for (uint32_t i = 0; i < lim; ++i) {
+      const uint32_t r = __shfl(mine, (int)i, WAVE);
+      const uint32_t T = nset < k ? 0u : __shfl(setv, (int)k - 1, WAVE);
+      if ((uint32_t)lane == i) tout = T;
+      const uint32_t below = (uint32_t)__popcll(__ballot(setv < r));
+      if (below < k) {
+        const uint32_t up = __shfl_up(setv, 1, WAVE);
+        if ((uint32_t)lane > below && (uint32_t)lane < k) setv = up;
+        if ((uint32_t)lane == below) setv = r;
+        if (nset < k) ++nset;
+      }
+    }
+    if (j0 + lane < c) out[j0 + lane] = tout;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// task lists
+// ---------------------------------------------------------------------------
+__global__ void k_task_count(const uint32_t *list, uint32_t count, const uint64_t *row_ptr, uint32_t *ntask,
+                             uint32_t *nslot, uint32_t *isplit) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const uint32_t u = list[i];
+  const uint64_t d = row_ptr[u + 1] - row_ptr[u];
+  const uint32_t nt = d <= TASK_ARCS ? 1u : (uint32_t)((d + TASK_ARCS - 1) / TASK_ARCS);
+  ntask[i] = nt;
+  nslot[i] = nt > 1 ? nt : 0u;
+  isplit[i] = nt > 1 ? 1u : 0u;
+}
+
+__global__ void k_task_fill(const uint32_t *list, uint32_t count, const uint32_t *ntask, const uint64_t *task_off,
+                            const uint64_t *slot_off, const uint64_t *split_off, uint32_t *task_u,
+                            uint32_t *task_sub, uint32_t *task_slot, uint32_t *split_u, uint32_t *split_first,
+                            uint32_t *split_nt) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const uint32_t u = list[i];
+  const uint32_t nt = ntask[i];
+  const uint64_t t0 = task_off[i];
+  for (uint32_t j = 0; j < nt; ++j) {
+    task_u[t0 + j] = u;
+    task_sub[t0 + j] = j;
+    task_slot[t0 + j] = nt > 1 ? (uint32_t)(slot_off[i] + j) : INF32;
+  }
+  if (nt > 1) {
+    const uint64_t s = split_off[i];
+    split_u[s] = u;
+    split_first[s] = (uint32_t)slot_off[i];
+    split_nt[s] = nt;
+  }
+}
+
+struct TaskList {
+  uint32_t *task_u, *task_sub, *task_slot;
+  uint32_t *split_u, *split_first, *split_nt;
+  uint32_t ntasks = 0, nsplit = 0, nslots = 0;
+};
+
+// scratch of build_tasks: 3 count arrays + 3 offset arrays
+struct TaskScratch {
+  uint32_t *ntask, *nslot, *isplit;
+  uint64_t *toff, *soff, *poff;
+};
+
+static void build_tasks(Ctx &c, const Graph &g, const uint32_t *list, uint32_t count, TaskScratch &ts,
+                        TaskList &tl) {
+  tl.ntasks = tl.nsplit = tl.nslots = 0;
+  if (count == 0) return;
+  const uint32_t blocks = (uint32_t)ceil_div(count, 256);
+  k_task_count<<<blocks, 256, 0, c.s>>>(list, count, g.row_ptr, ts.ntask, ts.nslot, ts.isplit);
+  FL_LAUNCH_CHECK();
+  scan_u32_to_u64(c, ts.ntask, ts.toff, count);
+  scan_u32_to_u64(c, ts.nslot, ts.soff, count);
+  scan_u32_to_u64(c, ts.isplit, ts.poff, count);
+  k_task_fill<<<blocks, 256, 0, c.s>>>(list, count, ts.ntask, ts.toff, ts.soff, ts.poff, tl.task_u, tl.task_sub,
+                                        tl.task_slot, tl.split_u, tl.split_first, tl.split_nt);
+  FL_LAUNCH_CHECK();
+  uint64_t h[3];
+  FL_HIP(hipMemcpyAsync(&h[0], ts.toff + count, 8, hipMemcpyDeviceToHost, c.s));
+  FL_HIP(hipMemcpyAsync(&h[1], ts.soff + count, 8, hipMemcpyDeviceToHost, c.s));
+  FL_HIP(hipMemcpyAsync(&h[2], ts.poff + count, 8, hipMemcpyDeviceToHost, c.s));
+  c.sync();
+  tl.ntasks = (uint32_t)h[0];
+  tl.nslots = (uint32_t)h[1];
+  tl.nsplit = (uint32_t)h[2];
+}
+
+// list of vertices with at least one arc
 __global__ void k_nonisolated_flags(uint32_t n, const uint64_t *row_ptr, uint32_t *flag) {
   uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) flag[i] = row_ptr[i + 1] > row_ptr[i] ? 1u : 0u;
@@ -312,6 +665,14 @@ __global__ void k_nonisolated_flags(uint32_t n, const uint64_t *row_ptr, uint32_
 __global__ void k_compact(uint32_t n, const uint32_t *flag, const uint64_t *pos, uint32_t *out) {
   uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n && flag[i]) out[pos[i]] = (uint32_t)i;
+}
+// number of scratch slots a vertex needs when split
+__global__ void k_slot_need(uint32_t n, const uint64_t *row_ptr, uint32_t *need) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const uint64_t d = row_ptr[i + 1] - row_ptr[i];
+    need[i] = d > TASK_ARCS ? (uint32_t)((d + TASK_ARCS - 1) / TASK_ARCS) : 0u;
+  }
 }
 
 // Compact the per-vertex sketches into CSR (one wave per vertex).
@@ -342,6 +703,21 @@ uint32_t ads_capacity(uint32_t n, uint32_t k) {
   return (uint32_t)c;
 }
 
+size_t ads_scratch_bytes(uint32_t n, uint64_t m, uint32_t k, uint32_t NS) {
+  const size_t FW = (NS + 31) / 32;
+  const uint64_t slots = 2 * (m / TASK_ARCS) + 2;  // >= sum of ceil(deg/TASK_ARCS) over vertices with deg > TASK_ARCS
+  const uint64_t tasks = (uint64_t)n + m / TASK_ARCS + 64;
+  size_t b = 0;
+  b += (size_t)n * k * 4;                  // bottom-k sets
+  b += (size_t)NS * n * (8 + 4);           // per-slot entry index + worklists
+  b += (size_t)n * FW * 4;                 // worklist flags
+  b += (size_t)slots * (ADS_SB + 1) * 4;   // kept sets of split tasks
+  b += (size_t)tasks * 4 * 3 * 2 + (size_t)n * 4 * 3 * 2;  // two task lists
+  b += (size_t)n * (4 * 3 + 8 * 3) + (size_t)n * 24;       // task scratch, dense list
+  b += (size_t)8 << 20;
+  return b;
+}
+
 // Builds the sketches.  Returns FL_OK, or FL_ENOMEM / FL_ENOTIMPL.  The
 // caller provides cap; on capacity overflow the call reports *need_more.
 static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool *need_more) {
@@ -365,8 +741,6 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
   P.w = g.w;
   P.sk_rank = o.sk_rank;
   P.sk_dist = o.sk_dist;
-  P.thr = o.thr;
-  P.thr_idx = o.thr_idx;
   P.bk = c.arena->get<uint32_t>((size_t)n * k);
   P.cnt = o.cnt;
   P.dinfo = c.arena->get<uint64_t>((size_t)NS * n);
@@ -375,20 +749,55 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
   P.wl_cnt = c.arena->get<uint32_t>(NS);
   P.ctr = c.arena->get<uint64_t>(128);
   P.status = c.arena->get<uint32_t>(4);
+  uint32_t bits = 0;
+  while (bits < 32 && (1ull << bits) < (uint64_t)n) ++bits;
+  P.bshift = bits > 5 ? bits - 5 : 0;  // NBKT = 32 buckets
   fill_u64(c, P.dinfo, (size_t)NS * n, INF64);
   fill_u32(c, P.flags, (size_t)n * FW, 0);
   fill_u32(c, P.wl_cnt, NS, 0);
   fill_u64(c, P.ctr, 128, 0);
   fill_u32(c, P.status, 4, 0);
 
-  // dense list: vertices with at least one arc
-  uint32_t *dense = nullptr;
+  // scratch slots: enough for every vertex split at once
+  {
+    uint32_t *need = c.arena->get<uint32_t>(n);
+    uint64_t *noff = c.arena->get<uint64_t>((size_t)n + 1);
+    k_slot_need<<<(uint32_t)ceil_div(n, 256), 256, 0, c.s>>>(n, g.row_ptr, need);
+    FL_LAUNCH_CHECK();
+    scan_u32_to_u64(c, need, noff, n);
+    FL_HIP(hipMemcpyAsync(c.h_status, noff + n, 8, hipMemcpyDeviceToHost, c.s));
+    c.sync();
+    const uint64_t slots = c.h_status[0] + 1;
+    P.kept = c.arena->get<uint32_t>(slots * ADS_SB);
+    P.kept_cnt = c.arena->get<uint32_t>(slots);
+  }
+  // task-list scratch and lists (sized for a list of all vertices)
+  const uint64_t max_tasks = (uint64_t)n + g.m / TASK_ARCS + 64;
+  TaskScratch ts;
+  ts.ntask = c.arena->get<uint32_t>(n);
+  ts.nslot = c.arena->get<uint32_t>(n);
+  ts.isplit = c.arena->get<uint32_t>(n);
+  ts.toff = c.arena->get<uint64_t>((size_t)n + 1);
+  ts.soff = c.arena->get<uint64_t>((size_t)n + 1);
+  ts.poff = c.arena->get<uint64_t>((size_t)n + 1);
+  TaskList tl_dense, tl;
+  auto alloc_list = [&](TaskList &t) {
+    t.task_u = c.arena->get<uint32_t>(max_tasks);
+    t.task_sub = c.arena->get<uint32_t>(max_tasks);
+    t.task_slot = c.arena->get<uint32_t>(max_tasks);
+    t.split_u = c.arena->get<uint32_t>(n);
+    t.split_first = c.arena->get<uint32_t>(n);
+    t.split_nt = c.arena->get<uint32_t>(n);
+  };
+  alloc_list(tl);
+
+  // dense list: vertices with at least one arc, and its static task list
   uint32_t n_dense = 0;
   const bool dense_ok = unit && !(cfg.flags & FL_FLAG_NO_DENSE);
   if (dense_ok) {
     uint32_t *fl = c.arena->get<uint32_t>(n);
     uint64_t *pos = c.arena->get<uint64_t>((size_t)n + 1);
-    dense = c.arena->get<uint32_t>(n);
+    uint32_t *dense = c.arena->get<uint32_t>(n);
     k_nonisolated_flags<<<(uint32_t)ceil_div(n, 256), 256, 0, c.s>>>(n, g.row_ptr, fl);
     FL_LAUNCH_CHECK();
     scan_u32_to_u64(c, fl, pos, n);
@@ -397,6 +806,8 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
     FL_HIP(hipMemcpyAsync(c.h_status, pos + n, 8, hipMemcpyDeviceToHost, c.s));
     c.sync();
     n_dense = (uint32_t)c.h_status[0];
+    alloc_list(tl_dense);
+    build_tasks(c, g, dense, n_dense, ts, tl_dense);
   }
   const uint64_t dense_threshold = (uint64_t)n_dense / 32;
 
@@ -409,11 +820,6 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
     FL_LAUNCH_CHECK();
   }
   bool sparse = mark;  // mode of round 1
-  // survivor buffer: a whole distance level of one sketch (at most cap
-  // entries) plus one chunk of candidates fits
-  uint32_t SB = 256;
-  while (SB < cap + WAVE && SB < ADS_SB_MAX) SB <<= 1;
-  const size_t lds_bytes = (size_t)ADS_WPB * (SB + WAVE) * sizeof(uint32_t);
   hipEvent_t e0, e1;
   FL_HIP(hipEventCreate(&e0));
   FL_HIP(hipEventCreate(&e1));
@@ -431,46 +837,52 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
   std::vector<uint32_t> hwl(NS);
   for (uint32_t D = 1;; ++D) {
     const uint32_t slot = D % NS;
-    // worklist size of this round
-    uint32_t count;
-    const uint32_t *list;
+    const TaskList *T = &tl_dense;
     if (sparse) {
       FL_HIP(hipMemcpyAsync(c.h_status, P.wl_cnt + slot, 4, hipMemcpyDeviceToHost, c.s));
       c.sync();
-      count = (uint32_t)(c.h_status[0] & 0xFFFFFFFFu);
-      list = P.wl + (size_t)slot * n;
-    } else {
-      count = n_dense;
-      list = dense;
+      const uint32_t count = (uint32_t)(c.h_status[0] & 0xFFFFFFFFu);
+      build_tasks(c, g, P.wl + (size_t)slot * n, count, ts, tl);
+      T = &tl;
     }
     // marking decision for this round (decides the mode of the next one)
     mark = !dense_ok || active_prev <= dense_threshold;
     fill_u64(c, P.ctr + 64, 64, 0);
-    if (count) {
-      const uint64_t blocks = ceil_div(count, ADS_WPB);
+    if (T->ntasks) {
       FL_HIP(hipEventRecord(e0, c.s));
+      const uint32_t tb = (uint32_t)ceil_div(T->ntasks, ADS_WPB);
       if (unit)
-        k_ads_round<true><<<(uint32_t)blocks, 256, lds_bytes, c.s>>>(P, D, list, count, sparse ? 1 : 0,
-                                                                     mark ? 1 : 0, SB);
+        k_ads_tasks<true><<<tb, 256, 0, c.s>>>(P, D, T->task_u, T->task_sub, T->task_slot, T->ntasks,
+                                               sparse ? 1 : 0, mark ? 1 : 0);
       else
-        k_ads_round<false><<<(uint32_t)blocks, 256, lds_bytes, c.s>>>(P, D, list, count, sparse ? 1 : 0,
-                                                                      mark ? 1 : 0, SB);
+        k_ads_tasks<false><<<tb, 256, 0, c.s>>>(P, D, T->task_u, T->task_sub, T->task_slot, T->ntasks,
+                                                sparse ? 1 : 0, mark ? 1 : 0);
       FL_LAUNCH_CHECK();
+      if (T->nsplit) {
+        const uint32_t mb = (uint32_t)ceil_div(T->nsplit, ADS_WPB);
+        if (unit)
+          k_ads_merge<true><<<mb, 256, 0, c.s>>>(P, D, T->split_u, T->split_first, T->split_nt, T->nsplit,
+                                                 mark ? 1 : 0);
+        else
+          k_ads_merge<false><<<mb, 256, 0, c.s>>>(P, D, T->split_u, T->split_first, T->split_nt, T->nsplit,
+                                                  mark ? 1 : 0);
+        FL_LAUNCH_CHECK();
+      }
       FL_HIP(hipEventRecord(e1, c.s));
     }
     if (sparse) fill_u32(c, P.wl_cnt + slot, 1, 0);
     ++rounds;
-    // status: overflow flags, active count, pending worklists
-    static_assert(sizeof(uint64_t) * 64 <= 4096 * 8, "status");
     FL_HIP(hipMemcpyAsync(c.h_status, P.status, 8, hipMemcpyDeviceToHost, c.s));
     FL_HIP(hipMemcpyAsync(c.h_status + 1, P.ctr + 64, 64 * 8, hipMemcpyDeviceToHost, c.s));
     FL_HIP(hipMemcpyAsync(hwl.data(), P.wl_cnt, NS * 4, hipMemcpyDeviceToHost, c.s));
     c.sync();
-    if (count) {
+    if (T->ntasks) {
       float ms = 0.f;
       FL_HIP(hipEventElapsedTime(&ms, e0, e1));
       o.kernel_ms += ms;
       o.launches += 1;
+      if (std::getenv("FL_DEBUG"))
+        std::fprintf(stderr, "[fl] round %u: %u tasks, %u split, %.2f ms\n", D, T->ntasks, T->nsplit, ms);
     }
     const uint32_t st0 = (uint32_t)(c.h_status[0] & 0xFFFFFFFFu);
     const uint32_t st1 = (uint32_t)(c.h_status[0] >> 32);
@@ -521,12 +933,17 @@ int ads_build(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o) {
     bool more = false;
     int rc = ads_run(c, g, cfg, o, &more);
     if (rc != FL_OK) return rc;
-    // scratch of the run is no longer needed; keep the outputs
-    (void)mark;
     c.arena->rewind(after_out);
     if (std::getenv("FL_DEBUG"))
       std::fprintf(stderr, "[fl] sketches: cap %u rounds %u overflow %d\n", cap, o.rounds, (int)more);
-    if (!more) return FL_OK;
+    if (!more) {
+      if (o.thr && thr_rows) {
+        k_hip_thresholds<<<(uint32_t)ceil_div((uint64_t)thr_rows * WAVE, 256), 256, 0, c.s>>>(
+            thr_rows, cfg.thr_rows_vertex, cap, cfg.k, o.cnt, o.sk_rank, o.thr);
+        FL_LAUNCH_CHECK();
+      }
+      return FL_OK;
+    }
     uint64_t nc = (uint64_t)cap * 3 / 2 + 16;
     if (nc > g.n) nc = g.n;
     if (nc == cap) return FL_ENOMEM;

@@ -188,18 +188,15 @@ static int check_params(const fl_problem *p, const fl_params *prm) {
   return FL_OK;
 }
 
-static size_t estimate_bytes(uint32_t n, uint64_t nF, uint32_t k, uint32_t cap, uint32_t NS) {
-  const size_t FW = (NS + 31) / 32;
+static size_t estimate_bytes(uint32_t n, uint64_t m, uint64_t nF, uint32_t k, uint32_t cap, uint32_t NS) {
   size_t b = 0;
-  b += (size_t)n * cap * 8;          // sketch ranks + distances
-  b += (size_t)nF * cap * 4;         // HIP thresholds
-  b += (size_t)n * k * 4;            // bottom-k sets
-  b += (size_t)NS * n * (8 + 4);     // per-slot entry index + worklists
-  b += (size_t)n * FW * 4;           // worklist flags
-  b += (size_t)NS * n * 8;           // sweep pending labels + lists
-  b += (size_t)n * 160;              // per-vertex scratch of all phases
-  b += (size_t)nF * 96;              // per-facility state
-  b += (size_t)64 << 20;             // counters, scans
+  b += (size_t)n * cap * 8;                // sketch ranks + distances
+  b += (size_t)nF * cap * 4;               // HIP thresholds
+  b += (size_t)n * 32;                     // outputs kept while the sketches are built
+  const size_t ads = ads_scratch_bytes(n, m, k, NS);
+  const size_t later = (size_t)NS * n * 8 + (size_t)n * 160 + (size_t)nF * 96;  // opening loop, MIS, assignment
+  b += ads > later ? ads : later;
+  b += (size_t)64 << 20;                   // counters, scans
   return b;
 }
 
@@ -218,7 +215,7 @@ static int solve_one(const fl_problem *p, const fl_params *prm, fl_result *out, 
   const uint32_t n = p->n;
   const uint32_t cap0 = ads_capacity(n, prm->k);
   // facilities are counted after validation; reserve for all vertices first
-  dc.arena.reserve(estimate_bytes(n, n, prm->k, cap0, 2));
+  dc.arena.reserve(estimate_bytes(n, p->n_arcs, n, prm->k, cap0, 2));
   dc.arena.reset();
   Ctx c;
   c.s = s;
@@ -261,13 +258,13 @@ static int solve_one(const fl_problem *p, const fl_params *prm, fl_result *out, 
   const uint32_t nF = (uint32_t)c.h_status[0];
   // re-reserve now that the sizes are known (keeps what is allocated so far
   // valid only if no reallocation happens; reserve before any use instead)
-  if (estimate_bytes(n, nF, prm->k, cap0, NS) > dc.arena.capacity()) {
-    dc.arena.reserve(estimate_bytes(n, nF, prm->k, cap0, NS));
+  if (estimate_bytes(n, p->n_arcs, nF, prm->k, cap0, NS) > dc.arena.capacity()) {
+    dc.arena.reserve(estimate_bytes(n, p->n_arcs, nF, prm->k, cap0, NS));
     return solve_one(p, prm, out, s, dc);  // restart with the larger arena
   }
 
   // sketches
-  AdsConfig acfg{prm->k, prm->seed, prm->flags, nF, fac_idx};
+  AdsConfig acfg{prm->k, prm->seed, prm->flags, nF, fac_idx, fac_list};
   AdsOut ads;
   rc = ads_build(c, g, acfg, ads);
   if (rc) return rc;
@@ -423,7 +420,7 @@ int fl_ads_build(const fl_problem *p, const fl_params *prm, fl_sketch **out, voi
     hipStream_t s = (hipStream_t)stream;
     const uint32_t n = p->n;
     const uint32_t cap0 = fl::ads_capacity(n, prm->k);
-    dc.arena.reserve(fl::estimate_bytes(n, n, prm->k, cap0, 2));
+    dc.arena.reserve(fl::estimate_bytes(n, p->n_arcs, n, prm->k, cap0, 2));
     dc.arena.reset();
     fl::Ctx c;
     c.s = s;
@@ -437,14 +434,14 @@ int fl_ads_build(const fl_problem *p, const fl_params *prm, fl_sketch **out, voi
     if ((uint64_t)(n - 1) * (p->w ? max_w : 1u) >= 0xFFFFFFFFull) return FL_ERANGE;
     if (p->w && max_w > fl::MAX_W) return FL_ENOTIMPL;
     const uint32_t NS = (p->w ? max_w : 1u) + 1;
-    if (fl::estimate_bytes(n, n, prm->k, cap0, NS) > dc.arena.capacity()) {
-      dc.arena.reserve(fl::estimate_bytes(n, n, prm->k, cap0, NS));
+    if (fl::estimate_bytes(n, p->n_arcs, n, prm->k, cap0, NS) > dc.arena.capacity()) {
+      dc.arena.reserve(fl::estimate_bytes(n, p->n_arcs, n, prm->k, cap0, NS));
       dc.arena.reset();
       rc = fl::validate_graph(c, &q, &max_w, &max_c);
       if (rc) return rc;
     }
     fl::Graph g{n, p->n_arcs, p->row_ptr, p->col, p->w, p->w ? max_w : 1u};
-    fl::AdsConfig acfg{prm->k, prm->seed, prm->flags, n, nullptr};
+    fl::AdsConfig acfg{prm->k, prm->seed, prm->flags, n, nullptr, nullptr};
     fl::AdsOut ads;
     rc = fl::ads_build(c, g, acfg, ads);
     if (rc) return rc;
