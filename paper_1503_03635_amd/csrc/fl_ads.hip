@@ -41,6 +41,7 @@ constexpr int ADS_WPB = 4;          // waves per block
 constexpr uint32_t ADS_SB = 1024;   // survivor ids per wave: one level of one sketch plus a chunk
 constexpr uint32_t TASK_ARCS = 256; // arcs per task of a split vertex
 constexpr uint32_t NBKT = 32;       // id buckets of the level prune
+constexpr uint32_t LONG_LIST = 24;  // entry lists at least this long are streamed one arc at a time
 
 struct AdsArgs {
   uint32_t n, k, cap, W, NS, FW;
@@ -58,7 +59,7 @@ struct AdsArgs {
   uint32_t *wl_cnt;
   uint32_t *kept;      // [slots * ADS_SB] kept ids of split tasks
   uint32_t *kept_cnt;  // [slots]
-  uint64_t *ctr;       // [64] relax_exec, [64] active vertices this round
+  uint64_t *ctr;       // [64] relax_exec, [64] active vertices this round, [64] survivors, [64] prunes
   uint32_t *status;    // [0] capacity overflow, [1] survivor-buffer overflow
   uint32_t bshift;     // id bucket = id >> bshift < NBKT
 };
@@ -199,9 +200,13 @@ __device__ inline uint64_t chunk_accept(uint32_t id, uint32_t k, PermKey rk, uin
   const int lane = lane_id();
   uint32_t left = __shfl_up(id, 1, WAVE);
   if (lane == 0) left = prev;
-  const bool valid = id != INF32 && id != left;
+  bool valid = id != INF32 && id != left;
   const uint32_t r = valid ? perm_fwd(id, rk) : INF32;
   const uint32_t q = set_count_below(setv, r);
+  // a candidate already in the set (same vertex at a shorter distance) is
+  // not new; one that dropped out of the set is rejected by the count
+  const uint32_t atq = __shfl(setv, (int)(q < 63 ? q : 63), WAVE);
+  if (q < nset && atq == r) valid = false;
   const uint64_t vm = __ballot(valid);
   uint32_t cp = 0;
   uint64_t it = vm;
@@ -213,17 +218,32 @@ __device__ inline uint64_t chunk_accept(uint32_t id, uint32_t k, PermKey rk, uin
   }
   const bool acc = valid && q + cp < k;
   const uint64_t am = __ballot(acc);
-  // merge: the k smallest of (set, chunk ranks)
-  uint32_t x = wave_sort_reg(valid ? r : INF32);
-  const uint32_t y = __shfl(x, WAVE - 1 - lane, WAVE);
-  uint32_t mm = setv < y ? setv : y;  // bitonic, holds the 64 smallest of both
+  // the running set becomes the k smallest of (set, accepted ranks); rejected
+  // candidates have k smaller ranks before them and never enter it
+  const uint32_t na = (uint32_t)__popcll(am);
+  if (na <= 8) {
+    uint64_t it2 = am;
+    while (it2) {
+      const int j = __ffsll((long long)it2) - 1;
+      it2 &= it2 - 1;
+      const uint32_t rj = __shfl(r, j, WAVE);
+      const uint32_t below = (uint32_t)__popcll(__ballot(setv < rj));
+      const uint32_t up = __shfl_up(setv, 1, WAVE);
+      if ((uint32_t)lane > below && (uint32_t)lane < k) setv = up;
+      if ((uint32_t)lane == below) setv = rj;
+    }
+  } else {
+    uint32_t x = wave_sort_reg(acc ? r : INF32);
+    const uint32_t y = __shfl(x, WAVE - 1 - lane, WAVE);
+    uint32_t mm = setv < y ? setv : y;  // bitonic, holds the 64 smallest of both
 #pragma unroll
-  for (int j = 32; j >= 1; j >>= 1) {
-    const uint32_t o = __shfl_xor(mm, j, WAVE);
-    mm = (lane & j) == 0 ? (mm < o ? mm : o) : (mm > o ? mm : o);
+    for (int j = 32; j >= 1; j >>= 1) {
+      const uint32_t o = __shfl_xor(mm, j, WAVE);
+      mm = (lane & j) == 0 ? (mm < o ? mm : o) : (mm > o ? mm : o);
+    }
+    setv = (uint32_t)lane < k ? mm : INF32;
   }
-  setv = (uint32_t)lane < k ? mm : INF32;
-  const uint32_t tot = nset + (uint32_t)__popcll(vm);
+  const uint32_t tot = nset + na;
   nset = tot < k ? tot : k;
   const uint64_t real = __ballot(id != INF32);
   if (real) prev = __shfl(id, 63 - __clzll(real), WAVE);
@@ -325,19 +345,23 @@ struct Level {
   uint32_t ns;           // buffered candidates
   uint32_t tb;           // lane b < NBKT: rank bound for candidates of id bucket b
   bool overflow;
+  uint32_t nsurv, nprune;  // statistics
 };
 
-__device__ inline void level_init(const AdsArgs &P, uint32_t u, Level &L) {
+__device__ inline void level_init(const AdsArgs &P, uint32_t u, Level &L, uint32_t *s_cnt) {
   const int lane = lane_id();
   const uint32_t k = P.k;
   L.cu = P.cnt[u];
   L.nset0 = L.cu < k ? L.cu : k;
   L.set0 = (uint32_t)lane < L.nset0 ? P.bk[(size_t)u * k + lane] : INF32;
+  s_cnt[WAVE + lane] = L.set0;
+  wave_lds_sync();
   L.full0 = L.nset0 == k;
   L.T0 = L.full0 ? __shfl(L.set0, (int)k - 1, WAVE) : INF32;
   L.ns = 0;
   L.tb = L.T0;
   L.overflow = false;
+  L.nsurv = L.nprune = 0;
 }
 
 // One candidate per lane (valid, rank r, id if known): keep it if its rank is
@@ -345,14 +369,23 @@ __device__ inline void level_init(const AdsArgs &P, uint32_t u, Level &L) {
 // buffer by a prune against the set when full.
 __device__ inline void level_offer(const AdsArgs &P, Level &L, bool valid, uint32_t r, bool have_id, uint32_t id,
                                    uint32_t *s_id, uint32_t *s_tmp, uint32_t *s_cnt) {
+  const uint32_t *s_set0 = s_cnt + WAVE;  // LDS copy of the set at the level start
   const int lane = lane_id();
   bool pass = valid && (!L.full0 || r < L.T0);
-  const uint32_t q = set_count_below(L.set0, r);
-  const uint32_t atq = __shfl(L.set0, (int)(q < 63 ? q : 63), WAVE);
-  if (pass && q < L.nset0 && atq == r) pass = false;
+  if (!__ballot(pass)) return;
+  if (pass) {
+    // already in the set (same vertex at a shorter distance)?
+    uint32_t lo = 0, hi = L.nset0;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (s_set0[mid] < r) lo = mid + 1;
+      else hi = mid;
+    }
+    if (lo < L.nset0 && s_set0[lo] == r) pass = false;
+  }
   // bucket bound from the last prune: all candidates of earlier id buckets
   // come first, and k of them (or of the set) already rank below it
-  const uint32_t cid = have_id ? id : perm_inv(r, P.rk);
+  const uint32_t cid = pass ? (have_id ? id : perm_inv(r, P.rk)) : 0u;
   const uint32_t bnd = __shfl(L.tb, (int)((pass ? cid : 0u) >> P.bshift), WAVE);
   if (pass && r >= bnd) pass = false;
   uint64_t msk = __ballot(pass);
@@ -360,6 +393,7 @@ __device__ inline void level_offer(const AdsArgs &P, Level &L, bool valid, uint3
   uint32_t np = (uint32_t)__popcll(msk);
   if (L.ns + np > ADS_SB) {
     uint32_t tv = L.set0, tn = L.nset0;
+    ++L.nprune;
     L.ns = prune_level(s_id, s_tmp, s_cnt, L.ns, P.bshift, P.k, P.rk, tv, tn, &L.tb);
     for (uint32_t i = lane; i < L.ns; i += WAVE) s_id[i] = s_tmp[i];
     wave_lds_sync();
@@ -375,6 +409,7 @@ __device__ inline void level_offer(const AdsArgs &P, Level &L, bool valid, uint3
   }
   if (pass) s_id[L.ns + lanes_below(msk)] = cid;
   L.ns += np;
+  L.nsurv += np;
   wave_lds_sync();
 }
 
@@ -399,10 +434,29 @@ __device__ inline uint64_t gather_arcs(const AdsArgs &P, uint32_t D, uint64_t a0
         }
       }
     }
-    const uint32_t incl = wave_scan_incl(cn);
+    examined += wave_sum_u64(cn);
+    // long lists: one arc at a time, the whole wave on its list, two loads in flight
+    uint64_t lm = __ballot(cn >= LONG_LIST);
+    while (lm && !L.overflow) {
+      const int j = __ffsll((long long)lm) - 1;
+      lm &= lm - 1;
+      const uint32_t vj = __shfl(v, j, WAVE);
+      const uint32_t stj = __shfl(st, j, WAVE);
+      const uint32_t cnj = __shfl(cn, j, WAVE);
+      const uint32_t *src = P.sk_rank + (size_t)vj * P.cap + stj;
+      for (uint32_t c0 = 0; c0 < cnj && !L.overflow; c0 += 2 * WAVE) {
+        const uint32_t i0 = c0 + lane, i1 = i0 + WAVE;
+        const uint32_t r0 = i0 < cnj ? src[i0] : INF32;
+        const uint32_t r1 = i1 < cnj ? src[i1] : INF32;
+        level_offer(P, L, i0 < cnj, r0, false, 0, s_id, s_tmp, s_cnt);
+        if (c0 + WAVE < cnj) level_offer(P, L, i1 < cnj, r1, false, 0, s_id, s_tmp, s_cnt);
+      }
+    }
+    // short lists: flattened over the group, owner lane found by binary search
+    const uint32_t cs = cn < LONG_LIST ? cn : 0u;
+    const uint32_t incl = wave_scan_incl(cs);
     const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
-    const uint32_t excl = incl - cn;
-    examined += total;
+    const uint32_t excl = incl - cs;
     for (uint32_t c0 = 0; c0 < total && !L.overflow; c0 += WAVE) {
       const uint32_t idx = c0 + lane;
       uint32_t pos = 0;  // owner lane: first lane whose inclusive count exceeds idx
@@ -459,7 +513,7 @@ __global__ __launch_bounds__(256) void k_ads_tasks(AdsArgs P, uint32_t D, const 
                                                    uint32_t ntasks, int sparse, int mark) {
   __shared__ uint32_t lds_id[ADS_WPB][ADS_SB];
   __shared__ uint32_t lds_tmp[ADS_WPB][ADS_SB];
-  __shared__ uint32_t lds_cnt[ADS_WPB][WAVE];
+  __shared__ uint32_t lds_cnt[ADS_WPB][2 * WAVE];
   const int lane = lane_id();
   const int wv = threadIdx.x / WAVE;
   const uint64_t item = (uint64_t)blockIdx.x * ADS_WPB + wv;
@@ -475,7 +529,7 @@ __global__ __launch_bounds__(256) void k_ads_tasks(AdsArgs P, uint32_t D, const 
     atomicAnd(&P.flags[(size_t)u * P.FW + (sD >> 5)], ~(1u << (sD & 31)));
   }
   Level L;
-  level_init(P, u, L);
+  level_init(P, u, L, s_cnt);
   const uint64_t r0 = P.row_ptr[u], r1 = P.row_ptr[u + 1];
   uint64_t a0 = r0, a1 = r1;
   if (slot != INF32) {
@@ -483,7 +537,11 @@ __global__ __launch_bounds__(256) void k_ads_tasks(AdsArgs P, uint32_t D, const 
     a1 = a0 + TASK_ARCS < r1 ? a0 + TASK_ARCS : r1;
   }
   const uint64_t examined = gather_arcs<UNITW>(P, D, a0, a1, L, s_id, s_tmp, s_cnt);
-  if (lane == 0) atomicAdd((unsigned long long *)&P.ctr[blockIdx.x & 63], (unsigned long long)examined);
+  if (lane == 0) {
+    atomicAdd((unsigned long long *)&P.ctr[blockIdx.x & 63], (unsigned long long)examined);
+    atomicAdd((unsigned long long *)&P.ctr[128 + (blockIdx.x & 63)], (unsigned long long)L.nsurv);
+    atomicAdd((unsigned long long *)&P.ctr[192 + (blockIdx.x & 63)], (unsigned long long)L.nprune);
+  }
   if (L.overflow) {
     if (lane == 0) atomicOr(&P.status[1], 1u);
     return;
@@ -508,7 +566,7 @@ __global__ __launch_bounds__(256) void k_ads_merge(AdsArgs P, uint32_t D, const 
                                                    uint32_t nsplit, int mark) {
   __shared__ uint32_t lds_id[ADS_WPB][ADS_SB];
   __shared__ uint32_t lds_tmp[ADS_WPB][ADS_SB];
-  __shared__ uint32_t lds_cnt[ADS_WPB][WAVE];
+  __shared__ uint32_t lds_cnt[ADS_WPB][2 * WAVE];
   const int lane = lane_id();
   const int wv = threadIdx.x / WAVE;
   const uint64_t item = (uint64_t)blockIdx.x * ADS_WPB + wv;
@@ -520,7 +578,7 @@ __global__ __launch_bounds__(256) void k_ads_merge(AdsArgs P, uint32_t D, const 
   const uint32_t first = split_first[item];
   const uint32_t nt = split_nt[item];
   Level L;
-  level_init(P, u, L);
+  level_init(P, u, L, s_cnt);
   for (uint32_t g0 = 0; g0 < nt && !L.overflow; g0 += WAVE) {
     const uint32_t cn = g0 + lane < nt ? P.kept_cnt[first + g0 + lane] : 0u;
     const uint32_t incl = wave_scan_incl(cn);
@@ -747,7 +805,7 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
   P.flags = c.arena->get<uint32_t>((size_t)n * FW);
   P.wl = c.arena->get<uint32_t>((size_t)NS * n);
   P.wl_cnt = c.arena->get<uint32_t>(NS);
-  P.ctr = c.arena->get<uint64_t>(128);
+  P.ctr = c.arena->get<uint64_t>(256);
   P.status = c.arena->get<uint32_t>(4);
   uint32_t bits = 0;
   while (bits < 32 && (1ull << bits) < (uint64_t)n) ++bits;
@@ -755,7 +813,7 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
   fill_u64(c, P.dinfo, (size_t)NS * n, INF64);
   fill_u32(c, P.flags, (size_t)n * FW, 0);
   fill_u32(c, P.wl_cnt, NS, 0);
-  fill_u64(c, P.ctr, 128, 0);
+  fill_u64(c, P.ctr, 256, 0);
   fill_u32(c, P.status, 4, 0);
 
   // scratch slots: enough for every vertex split at once
@@ -881,8 +939,18 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
       FL_HIP(hipEventElapsedTime(&ms, e0, e1));
       o.kernel_ms += ms;
       o.launches += 1;
-      if (std::getenv("FL_DEBUG"))
-        std::fprintf(stderr, "[fl] round %u: %u tasks, %u split, %.2f ms\n", D, T->ntasks, T->nsplit, ms);
+      if (std::getenv("FL_DEBUG")) {
+        std::vector<uint64_t> hs(256);
+        FL_HIP(hipMemcpy(hs.data(), P.ctr, 256 * 8, hipMemcpyDeviceToHost));
+        uint64_t ex = 0, sv = 0, pr = 0;
+        for (int i = 0; i < 64; ++i) {
+          ex += hs[i];
+          sv += hs[128 + i];
+          pr += hs[192 + i];
+        }
+        std::fprintf(stderr, "[fl] round %u: %u tasks, %u split, %.2f ms, examined(cum) %.3fG survivors(cum) %.3fG prunes(cum) %.3fM\n",
+                     D, T->ntasks, T->nsplit, ms, ex / 1e9, sv / 1e9, pr / 1e6);
+      }
     }
     const uint32_t st0 = (uint32_t)(c.h_status[0] & 0xFFFFFFFFu);
     const uint32_t st1 = (uint32_t)(c.h_status[0] >> 32);
