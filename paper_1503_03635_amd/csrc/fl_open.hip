@@ -4,7 +4,7 @@
 // Rung t uses alpha = a[t] (alpha grows before use).  For each unopened
 // facility f the loop needs N(f, alpha): the HIP estimate of the unfrozen
 // served clients within alpha of f, a predicated query over f's sketch
-// (Sec. 4.4).  It is kept exactly as an integer in units of 2^-52 (split into
+// (Sec. 4.5).  It is kept exactly as an integer in units of 2^-52 (split into
 // two 64-bit words, fix52) over a "live list": the crossed sketch entries
 // (distance <= alpha) whose client is still unfrozen, compacted in place at
 // the front of f's sketch row.  Per rung:
