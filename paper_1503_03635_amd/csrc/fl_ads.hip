@@ -40,7 +40,7 @@ namespace fl {
 constexpr int ADS_WPB = 4;          // waves per block
 constexpr uint32_t ADS_SB = 1024;   // survivor ids per wave: one level of one sketch plus a chunk
 constexpr uint32_t TASK_ARCS = 256; // arcs per task of a split vertex
-constexpr uint32_t NBKT = 32;       // id buckets of the level prune
+constexpr uint32_t NBKT = 64;       // id buckets of the level prune (one per lane)
 constexpr uint32_t LONG_LIST = 24;  // entry lists at least this long are streamed one arc at a time
 
 struct AdsArgs {
@@ -196,7 +196,7 @@ __device__ inline uint32_t set_count_below(uint32_t setv, uint32_t r) {
 // The running set becomes the k smallest ranks of itself and the chunk.
 // Returns the mask of accepted lanes.
 __device__ inline uint64_t chunk_accept(uint32_t id, uint32_t k, PermKey rk, uint32_t &setv, uint32_t &nset,
-                                        uint32_t &prev) {
+                                        uint32_t &prev, uint32_t *s_r) {
   const int lane = lane_id();
   uint32_t left = __shfl_up(id, 1, WAVE);
   if (lane == 0) left = prev;
@@ -208,14 +208,20 @@ __device__ inline uint64_t chunk_accept(uint32_t id, uint32_t k, PermKey rk, uin
   const uint32_t atq = __shfl(setv, (int)(q < 63 ? q : 63), WAVE);
   if (q < nset && atq == r) valid = false;
   const uint64_t vm = __ballot(valid);
+  // earlier candidates of the chunk with a smaller rank: ranks staged in LDS,
+  // read four at a time by every lane from the same address (broadcast)
+  s_r[lane] = valid ? r : INF32;
+  wave_lds_sync();
+  const int top = vm ? 64 - __clzll(vm) : 0;  // lanes above the last valid one are empty
   uint32_t cp = 0;
-  uint64_t it = vm;
-  while (it) {
-    const int j = __ffsll((long long)it) - 1;
-    it &= it - 1;
-    const uint32_t rj = __shfl(r, j, WAVE);
-    if (j < lane && rj < r) ++cp;
+  for (int j4 = 0; j4 < top; j4 += 4) {
+    const uint4 v = *reinterpret_cast<const uint4 *>(&s_r[j4]);
+    cp += (j4 + 0 < lane && v.x < r) ? 1u : 0u;
+    cp += (j4 + 1 < lane && v.y < r) ? 1u : 0u;
+    cp += (j4 + 2 < lane && v.z < r) ? 1u : 0u;
+    cp += (j4 + 3 < lane && v.w < r) ? 1u : 0u;
   }
+  wave_lds_sync();
   const bool acc = valid && q + cp < k;
   const uint64_t am = __ballot(acc);
   // the running set becomes the k smallest of (set, accepted ranks); rejected
@@ -253,45 +259,63 @@ __device__ inline uint64_t chunk_accept(uint32_t id, uint32_t k, PermKey rk, uin
 // Prune of one distance level.  s_id[0..ns) holds candidate ids (unsorted,
 // duplicates allowed); setv/nset the running set.  Accepted ids end in
 // s_tmp[0..m) in increasing id order; returns m.  s_id is clobbered.
+// s_cnt holds 3 * WAVE words: [0, WAVE) bucket offsets, then the pending
+// chunk; [WAVE, 2 WAVE) belongs to the caller; [2 WAVE, 3 WAVE) chunk ranks.
+// With tbk, lane b of *tbk receives a rank bound for id bucket b: the running
+// k-th smallest rank when the bucket was reached, which no later candidate of
+// that bucket can beat.
 __device__ inline uint32_t prune_level(uint32_t *s_id, uint32_t *s_tmp, uint32_t *s_cnt, uint32_t ns,
                                        uint32_t bshift, uint32_t k, PermKey rk, uint32_t &setv,
                                        uint32_t &nset, uint32_t *tbk = nullptr) {
   const int lane = lane_id();
+  uint32_t *s_pend = s_cnt;
+  uint32_t *s_r = s_cnt + 2 * WAVE;
   uint32_t m = 0, prev = INF32;
   if (ns <= (uint32_t)WAVE && !tbk) {
     uint32_t x = (uint32_t)lane < ns ? s_id[lane] : INF32;
     x = wave_sort_reg(x);
-    const uint64_t am = chunk_accept(x, k, rk, setv, nset, prev);
+    const uint64_t am = chunk_accept(x, k, rk, setv, nset, prev, s_r);
     if ((am >> lane) & 1) s_tmp[lanes_below(am)] = x;
     wave_lds_sync();
     return (uint32_t)__popcll(am);
   }
-  if ((uint32_t)lane < NBKT) s_cnt[lane] = 0;
+  // counting sort by id bucket (bucket order is id order)
+  s_cnt[lane] = 0;
   wave_lds_sync();
   for (uint32_t i = lane; i < ns; i += WAVE) atomicAdd(&s_cnt[s_id[i] >> bshift], 1u);
   wave_lds_sync();
-  const uint32_t bc = (uint32_t)lane < NBKT ? s_cnt[lane] : 0u;
+  const uint32_t bc = s_cnt[lane];
   const uint32_t bstart = wave_scan_incl(bc) - bc;
-  if ((uint32_t)lane < NBKT) s_cnt[lane] = bstart;
+  wave_lds_sync();
+  s_cnt[lane] = bstart;
   wave_lds_sync();
   for (uint32_t i = lane; i < ns; i += WAVE) {
     const uint32_t id = s_id[i];
     s_tmp[atomicAdd(&s_cnt[id >> bshift], 1u)] = id;
   }
   wave_lds_sync();
+  // Buckets are walked in id order.  The survivors of consecutive buckets are
+  // gathered in one pending chunk of at most WAVE ids and decided together;
+  // accepted ids are written back to s_tmp[m..), which never reaches a bucket
+  // not yet read (accepted ones are a subset of the buckets already read).
   uint64_t nonempty = __ballot(bc != 0);
-  uint32_t tb = INF32;  // lane b: running k-th smallest rank when bucket b starts
+  uint32_t tb = INF32;
   int done_b = -1;
-  while (nonempty) {
-    const int b = __ffsll((long long)nonempty) - 1;
-    nonempty &= nonempty - 1;
-    const uint32_t cb = __shfl(bc, b, WAVE);
-    const uint32_t sb = __shfl(bstart, b, WAVE);
+  uint32_t npend = 0;
+  auto flush = [&]() {
+    uint32_t x = (uint32_t)lane < npend ? s_pend[lane] : INF32;
+    x = wave_sort_reg(x);
+    const uint64_t am = chunk_accept(x, k, rk, setv, nset, prev, s_r);
+    if ((am >> lane) & 1) s_tmp[m + lanes_below(am)] = x;
+    m += (uint32_t)__popcll(am);
+    npend = 0;
+    wave_lds_sync();
+  };
+  // keep the ids of bucket [sb, sb + cb) whose rank beats the running
+  // threshold, compacted in place; returns their number
+  auto filter = [&](uint32_t sb, uint32_t cb) -> uint32_t {
     const bool open = nset < k;
     const uint32_t Trun = open ? INF32 : __shfl(setv, (int)k - 1, WAVE);
-    if (lane > done_b && lane <= b) tb = Trun;
-    done_b = b;
-    // every candidate of an earlier bucket comes first: filter in parallel
     uint32_t np = 0;
     for (uint32_t j0 = 0; j0 < cb; j0 += WAVE) {
       const uint32_t j = j0 + lane;
@@ -306,26 +330,45 @@ __device__ inline uint32_t prune_level(uint32_t *s_id, uint32_t *s_tmp, uint32_t
       np += (uint32_t)__popcll(pm);
     }
     wave_lds_sync();
+    return np;
+  };
+  while (nonempty) {
+    const int b = __ffsll((long long)nonempty) - 1;
+    nonempty &= nonempty - 1;
+    const uint32_t cb = __shfl(bc, b, WAVE);
+    const uint32_t sb = __shfl(bstart, b, WAVE);
+    // the running threshold now bounds every bucket up to b
+    const uint32_t Tnow = nset < k ? INF32 : __shfl(setv, (int)k - 1, WAVE);
+    if (lane > done_b && lane <= b) tb = Tnow;
+    done_b = b;
+    uint32_t np = filter(sb, cb);
     if (np == 0) continue;
-    if (np <= (uint32_t)WAVE) {
-      uint32_t x = (uint32_t)lane < np ? s_tmp[sb + lane] : INF32;
-      x = wave_sort_reg(x);
-      const uint64_t am = chunk_accept(x, k, rk, setv, nset, prev);
-      if ((am >> lane) & 1) s_tmp[m + lanes_below(am)] = x;  // m <= sb: earlier buckets only
-      m += (uint32_t)__popcll(am);
-    } else {
+    if (npend + np > (uint32_t)WAVE) {
+      flush();
+      // every earlier candidate is decided: the threshold is exact for bucket b
+      const uint32_t T2 = nset < k ? INF32 : __shfl(setv, (int)k - 1, WAVE);
+      if (lane == b) tb = T2;
+      np = filter(sb, np);
+      if (np == 0) continue;
+    }
+    if (np > (uint32_t)WAVE) {
       // many survivors in one bucket: sort them in s_id (free now), then chunks in order
       for (uint32_t i = lane; i < np; i += WAVE) s_id[i] = s_tmp[sb + i];
       wave_sort_lds(s_id, np);
       for (uint32_t c0 = 0; c0 < np; c0 += WAVE) {
         const uint32_t x = c0 + lane < np ? s_id[c0 + lane] : INF32;
-        const uint64_t am = chunk_accept(x, k, rk, setv, nset, prev);
+        const uint64_t am = chunk_accept(x, k, rk, setv, nset, prev, s_r);
         if ((am >> lane) & 1) s_tmp[m + lanes_below(am)] = x;
         m += (uint32_t)__popcll(am);
+        wave_lds_sync();
       }
+      continue;
     }
+    if ((uint32_t)lane < np) s_pend[npend + lane] = s_tmp[sb + lane];
+    npend += np;
     wave_lds_sync();
   }
+  if (npend) flush();
   if (tbk) {
     const uint32_t Tend = nset < k ? INF32 : __shfl(setv, (int)k - 1, WAVE);
     if (lane > done_b) tb = Tend;
@@ -513,7 +556,7 @@ __global__ __launch_bounds__(256) void k_ads_tasks(AdsArgs P, uint32_t D, const 
                                                    uint32_t ntasks, int sparse, int mark) {
   __shared__ uint32_t lds_id[ADS_WPB][ADS_SB];
   __shared__ uint32_t lds_tmp[ADS_WPB][ADS_SB];
-  __shared__ uint32_t lds_cnt[ADS_WPB][2 * WAVE];
+  __shared__ __align__(16) uint32_t lds_cnt[ADS_WPB][3 * WAVE];
   const int lane = lane_id();
   const int wv = threadIdx.x / WAVE;
   const uint64_t item = (uint64_t)blockIdx.x * ADS_WPB + wv;
@@ -566,7 +609,7 @@ __global__ __launch_bounds__(256) void k_ads_merge(AdsArgs P, uint32_t D, const 
                                                    uint32_t nsplit, int mark) {
   __shared__ uint32_t lds_id[ADS_WPB][ADS_SB];
   __shared__ uint32_t lds_tmp[ADS_WPB][ADS_SB];
-  __shared__ uint32_t lds_cnt[ADS_WPB][2 * WAVE];
+  __shared__ __align__(16) uint32_t lds_cnt[ADS_WPB][3 * WAVE];
   const int lane = lane_id();
   const int wv = threadIdx.x / WAVE;
   const uint64_t item = (uint64_t)blockIdx.x * ADS_WPB + wv;
@@ -809,7 +852,7 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
   P.status = c.arena->get<uint32_t>(4);
   uint32_t bits = 0;
   while (bits < 32 && (1ull << bits) < (uint64_t)n) ++bits;
-  P.bshift = bits > 5 ? bits - 5 : 0;  // NBKT = 32 buckets
+  P.bshift = bits > 6 ? bits - 6 : 0;  // NBKT = 64 buckets
   fill_u64(c, P.dinfo, (size_t)NS * n, INF64);
   fill_u32(c, P.flags, (size_t)n * FW, 0);
   fill_u32(c, P.wl_cnt, NS, 0);
