@@ -477,8 +477,9 @@ __device__ inline uint64_t gather_arcs(const AdsArgs &P, uint32_t D, uint64_t a0
         }
       }
     }
-    examined += wave_sum_u64(cn);
-    // long lists: one arc at a time, the whole wave on its list, two loads in flight
+    // long lists: one arc at a time, the whole wave on its list, two loads in
+    // flight.  A level is stored in increasing rank order, so once a rank
+    // reaches T0 the rest of the list cannot enter u's sketch.
     uint64_t lm = __ballot(cn >= LONG_LIST);
     while (lm && !L.overflow) {
       const int j = __ffsll((long long)lm) - 1;
@@ -491,8 +492,10 @@ __device__ inline uint64_t gather_arcs(const AdsArgs &P, uint32_t D, uint64_t a0
         const uint32_t i0 = c0 + lane, i1 = i0 + WAVE;
         const uint32_t r0 = i0 < cnj ? src[i0] : INF32;
         const uint32_t r1 = i1 < cnj ? src[i1] : INF32;
+        examined += cnj - c0 < 2 * WAVE ? cnj - c0 : 2 * WAVE;
         level_offer(P, L, i0 < cnj, r0, false, 0, s_id, s_tmp, s_cnt);
         if (c0 + WAVE < cnj) level_offer(P, L, i1 < cnj, r1, false, 0, s_id, s_tmp, s_cnt);
+        if (L.full0 && __ballot((i0 < cnj && r0 >= L.T0) || (i1 < cnj && r1 >= L.T0))) break;
       }
     }
     // short lists: flattened over the group, owner lane found by binary search
@@ -500,6 +503,7 @@ __device__ inline uint64_t gather_arcs(const AdsArgs &P, uint32_t D, uint64_t a0
     const uint32_t incl = wave_scan_incl(cs);
     const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
     const uint32_t excl = incl - cs;
+    examined += total;
     for (uint32_t c0 = 0; c0 < total && !L.overflow; c0 += WAVE) {
       const uint32_t idx = c0 + lane;
       uint32_t pos = 0;  // owner lane: first lane whose inclusive count exceeds idx
@@ -534,10 +538,24 @@ __device__ inline void level_commit(const AdsArgs &P, uint32_t u, uint32_t D, Le
     if (lane == 0) atomicOr(&P.status[0], 1u);
     return;
   }
+  // The level is stored in increasing rank order, so that a neighbour reads
+  // it only up to its own threshold; rows get (distance, id) order after the
+  // last round (k_ads_canon).
   const size_t base = (size_t)u * P.cap + cu;
-  for (uint32_t i = lane; i < m; i += WAVE) {
-    P.sk_rank[base + i] = perm_fwd(s_tmp[i], P.rk);
-    P.sk_dist[base + i] = D;
+  if (m <= (uint32_t)WAVE) {
+    uint32_t x = (uint32_t)lane < m ? perm_fwd(s_tmp[lane], P.rk) : INF32;
+    x = wave_sort_reg(x);
+    if ((uint32_t)lane < m) {
+      P.sk_rank[base + lane] = x;
+      P.sk_dist[base + lane] = D;
+    }
+  } else {
+    for (uint32_t i = lane; i < m; i += WAVE) s_id[i] = perm_fwd(s_tmp[i], P.rk);
+    wave_sort_lds(s_id, m);  // m <= ADS_SB
+    for (uint32_t i = lane; i < m; i += WAVE) {
+      P.sk_rank[base + i] = s_id[i];
+      P.sk_dist[base + i] = D;
+    }
   }
   if ((uint32_t)lane < nset) P.bk[(size_t)u * P.k + lane] = setv;
   if (lane == 0) {
@@ -650,6 +668,51 @@ __global__ __launch_bounds__(256) void k_ads_merge(AdsArgs P, uint32_t D, const 
     return;
   }
   level_commit<UNITW>(P, u, D, L, mark, s_id, s_tmp, s_cnt);
+}
+
+// Restore (distance, id) order inside each level of every row (levels were
+// stored in increasing rank order while the rounds ran).  One wave per row;
+// a level holds at most ADS_SB entries (the survivor buffer of its commit).
+__global__ __launch_bounds__(256) void k_ads_canon(uint32_t n, uint32_t cap, PermKey rk, const uint32_t *cnt,
+                                                   uint32_t *sk_rank, const uint32_t *sk_dist, uint32_t *status) {
+  __shared__ uint32_t lds[ADS_WPB][ADS_SB];
+  const int lane = lane_id();
+  const int wv = threadIdx.x / WAVE;
+  const uint64_t u64 = (uint64_t)blockIdx.x * ADS_WPB + wv;
+  if (u64 >= n) return;
+  const uint32_t u = (uint32_t)u64;
+  const uint32_t c = cnt[u];
+  uint32_t *rr = sk_rank + (size_t)u * cap;
+  const uint32_t *dd = sk_dist + (size_t)u * cap;
+  uint32_t *s = lds[wv];
+  uint32_t pos = 1;  // entry 0 is u itself, alone at distance 0
+  while (pos < c) {
+    const uint32_t d0 = dd[pos];
+    uint32_t e = pos;
+    for (;;) {
+      const uint32_t i = e + lane;
+      const uint64_t other = __ballot(!(i < c && dd[i] == d0));
+      if (other) {
+        e += (uint32_t)(__ffsll((long long)other) - 1);
+        break;
+      }
+      e += WAVE;
+    }
+    const uint32_t len = e - pos;
+    if (len > 1 && len <= (uint32_t)WAVE) {
+      uint32_t x = (uint32_t)lane < len ? perm_inv(rr[pos + lane], rk) : INF32;
+      x = wave_sort_reg(x);
+      if ((uint32_t)lane < len) rr[pos + lane] = perm_fwd(x, rk);
+    } else if (len > 1 && len <= ADS_SB) {
+      for (uint32_t i = lane; i < len; i += WAVE) s[i] = perm_inv(rr[pos + i], rk);
+      wave_sort_lds(s, len);
+      for (uint32_t i = lane; i < len; i += WAVE) rr[pos + i] = perm_fwd(s[i], rk);
+      wave_lds_sync();
+    } else if (len > ADS_SB && lane == 0) {
+      atomicOr(&status[1], 1u);
+    }
+    pos = e;
+  }
 }
 
 // HIP thresholds of the sketch rows that need them: T_j = k-th smallest rank
@@ -1048,6 +1111,17 @@ int ads_build(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o) {
     if (std::getenv("FL_DEBUG"))
       std::fprintf(stderr, "[fl] sketches: cap %u rounds %u overflow %d\n", cap, o.rounds, (int)more);
     if (!more) {
+      {
+        uint32_t *st = c.arena->get<uint32_t>(4);
+        fill_u32(c, st, 4, 0);
+        k_ads_canon<<<(uint32_t)ceil_div(g.n, ADS_WPB), ADS_WPB * WAVE, 0, c.s>>>(
+            g.n, cap, perm_key(cfg.seed, 1), o.cnt, o.sk_rank, o.sk_dist, st);
+        FL_LAUNCH_CHECK();
+        FL_HIP(hipMemcpyAsync(c.h_status, st, 8, hipMemcpyDeviceToHost, c.s));
+        c.sync();
+        c.arena->rewind(after_out);
+        if (c.h_status[0] >> 32) return FL_EHIP;
+      }
       if (o.thr && thr_rows) {
         k_hip_thresholds<<<(uint32_t)ceil_div((uint64_t)thr_rows * WAVE, 256), 256, 0, c.s>>>(
             thr_rows, cfg.thr_rows_vertex, cap, cfg.k, o.cnt, o.sk_rank, o.thr);
