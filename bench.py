@@ -12,6 +12,12 @@ Printed (one JSON line): edge relaxations per second over whole solves
 (sum_v |ADS(v)| deg(v) per solve, divided by the solve time), solves per
 second, the HBM roofline of the sketch-round kernel, and the CPU oracle timed
 on a bounded sample of the same graph.
+
+Measured HBM traffic of the sketch-round kernel comes from two rocprofv3
+counter runs of this script with --pmc-calibration (one with FETCH_SIZE, one
+with WRITE_SIZE); `--traffic FETCH_DIR WRITE_DIR` turns their CSV output into
+profiles/ads_round_rmat22_traffic.json.  Each counter is scaled by what it
+reads for a plain 1 GiB device copy (torch.neg on int32) in the same run.
 """
 import argparse
 import json
@@ -26,6 +32,8 @@ sys.path.insert(0, ROOT)
 METRIC = "ADS edge-relaxations/s + facility-location solves/s, batched vs plain, 1 GPU"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ads_round_rmat22_traffic.json")
+ROUND_KERNEL = "k_ads_tasks"
+CALIB_BYTES = 1 << 30
 
 
 def log(*a):
@@ -54,6 +62,51 @@ def cpu_baseline(g, k, seed, sources):
                       f"graph ({relax} relaxations in {dt:.1f} s, 1 thread, {cpu_model()})"}
 
 
+def kernel_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("fl_ads.hip", "fl_ads.h", "fl_common.h"):
+        h.update(open(os.path.join(ROOT, "paper_1503_03635_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def write_traffic(fetch_dir, write_dir):
+    """Per-launch HBM bytes of the sketch-round kernel from two rocprofv3
+    counter runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by the
+    counter's reading for the 1 GiB calibration copy of the same run."""
+    import csv
+    import glob
+
+    def read(d, counter):
+        path = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        assert path, f"no counter_collection.csv under {d}"
+        calib, launches = [], {}
+        for row in csv.DictReader(open(path[0])):
+            if row["Counter_Name"] != counter:
+                continue
+            name, val = row["Kernel_Name"], float(row["Counter_Value"])
+            if "neg_kernel" in name:
+                calib.append(val)
+            elif ROUND_KERNEL in name:
+                launches[row["Dispatch_Id"]] = launches.get(row["Dispatch_Id"], 0.0) + val
+        assert calib and launches, f"{counter}: calibration copy or {ROUND_KERNEL} missing in {path[0]}"
+        return calib[0], launches
+
+    fc, fl_ = read(fetch_dir, "FETCH_SIZE")
+    wc, wl = read(write_dir, "WRITE_SIZE")
+    f_scale = CALIB_BYTES / (fc * 1024.0)
+    w_scale = CALIB_BYTES / (wc * 1024.0)
+    fetch = sum(fl_.values()) / len(fl_) * 1024.0 * f_scale
+    write = sum(wl.values()) / len(wl) * 1024.0 * w_scale
+    out = {"kernel": ROUND_KERNEL, "kernel_source_hash": kernel_hash(), "launches": len(fl_),
+           "fetch_bytes_per_launch": round(fetch), "write_bytes_per_launch": round(write),
+           "bytes_per_launch": round(fetch + write),
+           "calibration": {"bytes": CALIB_BYTES, "fetch_kib": fc, "write_kib": wc,
+                           "fetch_scale": f_scale, "write_scale": w_scale}}
+    json.dump(out, open(TRAFFIC_FILE, "w"), indent=1)
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -66,7 +119,14 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-sources", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pmc-calibration", action="store_true",
+                    help="run a 1 GiB device copy first (counter calibration)")
+    ap.add_argument("--traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the measured traffic file from two rocprofv3 counter runs and exit")
     args = ap.parse_args()
+    if args.traffic:
+        write_traffic(*args.traffic)
+        return
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -85,6 +145,12 @@ def main():
     log(f"[bench] generated R-MAT 2^{args.scale}: n={g.n} arcs={g.n_arcs} in {time.perf_counter() - t0:.1f}s")
     dg = fl.to_device(g, "cuda:0")
     torch.cuda.synchronize()
+    if args.pmc_calibration:
+        x = torch.ones(CALIB_BYTES // 4, dtype=torch.int32, device="cuda:0")
+        y = torch.empty_like(x)
+        torch.neg(x, out=y)
+        torch.cuda.synchronize()
+        del x, y
     outputs = fl._alloc_outputs(g.n, dg.col.device, False)
 
     for i in range(args.warmup):
@@ -111,8 +177,9 @@ def main():
     value = relax / elapsed
     kern_ms = sum(s["ms_ads_kernel"] for s in stats)
     launches = sum(s["ads_kernel_launches"] for s in stats)
-    # algorithmic bytes of the sketch rounds: 8 B per relaxation (the entry read
-    # once per neighbour) + 8 B per entry written
+    # algorithmic bytes of the sketch rounds: 8 B per relaxation (each final
+    # entry read once per neighbour) + 8 B per entry written, over the summed
+    # duration of the round-kernel launches (HIP events on the launch stream)
     alg_bytes = 8.0 * relax + 8.0 * entries
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
     traffic = None
@@ -125,8 +192,9 @@ def main():
             traffic = None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "k_ads_round", "avg_launch_ms": round(kern_ms / max(launches, 1), 3),
-            "alg_bytes_per_launch": round(alg_bytes / max(launches, 1))}
+            "kernel": ROUND_KERNEL, "avg_launch_ms": round(kern_ms / max(launches, 1), 3),
+            "alg_bytes_per_launch": round(alg_bytes / max(launches, 1)),
+            "merge_ms_per_step": round(sum(s["ms_ads_merge"] for s in stats) / args.steps, 2)}
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "edge-relaxations/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 2),
@@ -150,14 +218,6 @@ def main():
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
-
-
-def kernel_hash():
-    import hashlib
-    h = hashlib.sha256()
-    for name in ("fl_ads.hip", "fl_common.h"):
-        h.update(open(os.path.join(ROOT, "paper_1503_03635_amd", "csrc", name), "rb").read())
-    return h.hexdigest()[:16]
 
 
 if __name__ == "__main__":

@@ -92,8 +92,10 @@ typedef struct {
   uint64_t gamma;       /* max over served clients of min_f c(f) + d(c,f) */
   double alpha0;        /* first ladder value */
   double ms_validate, ms_ads, ms_gamma, ms_open, ms_mis, ms_assign, ms_total;
-  double ms_ads_kernel;          /* summed device time of the sketch-round kernel launches */
-  uint32_t ads_kernel_launches;  /* number of those launches */
+  double ms_ads_kernel;          /* summed device time of the sketch-round kernel launches
+                                    (k_ads_tasks, one per distance round) */
+  double ms_ads_merge;           /* summed device time of the merges of split hub vertices */
+  uint32_t ads_kernel_launches;  /* number of sketch-round kernel launches */
   uint64_t workspace_bytes;
 } fl_stats;
 
@@ -111,6 +113,8 @@ typedef struct {
   uint64_t total_cost;   /* sum_{f in S} c(f) + sum over served clients d(c, S) */
   uint32_t n_open;       /* |S| */
   uint32_t n_unreachable;/* clients with no facility in their component */
+  int32_t status;        /* FL_OK or this element's error code (set by fl_solve
+                            and by fl_solve_batch for every element) */
   fl_stats stats;
 } fl_result;
 
@@ -127,8 +131,14 @@ int fl_solve(const fl_problem *p, const fl_params *prm, fl_result *out, void *st
 
 /*
  * fl_solve_batch -- `count` independent solves; per element the same contract
- * and the same results as fl_solve.  The graphs share one workspace and run
- * back to back on `stream`.
+ * and the same results as fl_solve (its status field says whether it
+ * succeeded).  Elements with equal k, eps and flags are solved together as one
+ * disjoint union of their graphs: every phase (sketch rounds, opening rungs,
+ * MIS sweeps, assignment) runs once for the whole group instead of once per
+ * graph, with per-graph ranks, priorities, ladders and rung counters.  Groups
+ * are cut to fit the device memory.  Statistics that describe the whole group
+ * (ads_rounds, relax_exec, the ms_* times, workspace_bytes) are reported for
+ * every element of the group.  Returns FL_OK or the first element error.
  */
 int fl_solve_batch(const fl_problem *ps, const fl_params *prms, fl_result *outs, uint32_t count,
                    void *stream);

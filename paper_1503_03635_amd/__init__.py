@@ -94,6 +94,7 @@ def _result_struct(out):
 
 def _collect(res, out):
     st = res.stats
+    out["status"] = int(res.status)
     out["total_cost"] = int(res.total_cost)
     out["n_open"] = int(res.n_open)
     out["n_unreachable"] = int(res.n_unreachable)
@@ -120,19 +121,27 @@ def solve(dg: DeviceGraph, k: int, seed: int, eps: float = 0.1, flags: int = 0,
     return _collect(res, out)
 
 
-def solve_batch(dgs, k: int, seed: int, eps: float = 0.1, flags: int = 0, stream=None, check=True):
-    """fl_solve_batch over a list of device graphs; one dict per graph."""
+def solve_batch(dgs, k, seed, eps=0.1, flags=0, diagnostics=False, stream=None, check=True, outputs=None):
+    """fl_solve_batch over a list of device graphs; one dict per graph.  k,
+    seed, eps and flags are scalars or per-graph sequences.  Each dict holds
+    the element's own status (0 = FL_OK); with check=True any failing element
+    raises."""
     count = len(dgs)
+
+    def per(x):
+        return list(x) if isinstance(x, (list, tuple)) else [x] * count
+    ks, seeds, epss, flagss = per(k), per(seed), per(eps), per(flags)
     probs = (_lib.FlProblem * count)(*[_problem(d) for d in dgs])
-    prms = (_lib.FlParams * count)(*[_lib.FlParams(k, seed, eps, flags) for _ in dgs])
-    outs = [_alloc_outputs(d.n, d.col.device if d.n_arcs else d.row_ptr.device, False) for d in dgs]
+    prms = (_lib.FlParams * count)(*[_lib.FlParams(ks[i], seeds[i], epss[i], flagss[i]) for i in range(count)])
+    outs = outputs if outputs is not None else [
+        _alloc_outputs(d.n, d.col.device if d.n_arcs else d.row_ptr.device, diagnostics) for d in dgs]
     ress = (_lib.FlResult * count)(*[_result_struct(o) for o in outs])
     rc = lib().fl_solve_batch(probs, prms, ress, count, C.c_void_p(_stream_ptr(stream)))
-    if rc != _lib.FL_OK and check:
-        raise FlError(rc, "fl_solve_batch")
     for i in range(count):
         _collect(ress[i], outs[i])
-        outs[i]["rc"] = rc
+        outs[i]["rc"] = outs[i]["status"]
+    if rc != _lib.FL_OK and check:
+        raise FlError(rc, "fl_solve_batch")
     return outs
 
 

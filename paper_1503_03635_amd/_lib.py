@@ -36,7 +36,7 @@ class FlStats(C.Structure):
                 ("ads_entries", C.c_uint64), ("gamma", C.c_uint64), ("alpha0", C.c_double),
                 ("ms_validate", C.c_double), ("ms_ads", C.c_double), ("ms_gamma", C.c_double),
                 ("ms_open", C.c_double), ("ms_mis", C.c_double), ("ms_assign", C.c_double),
-                ("ms_total", C.c_double), ("ms_ads_kernel", C.c_double),
+                ("ms_total", C.c_double), ("ms_ads_kernel", C.c_double), ("ms_ads_merge", C.c_double),
                 ("ads_kernel_launches", C.c_uint32), ("workspace_bytes", C.c_uint64)]
 
 
@@ -44,7 +44,7 @@ class FlResult(C.Structure):
     _fields_ = [("open", C.c_void_p), ("assign", C.c_void_p), ("dist", C.c_void_p),
                 ("open_rung", C.c_void_p), ("freeze_rung", C.c_void_p), ("q", C.c_void_p),
                 ("total_cost", C.c_uint64), ("n_open", C.c_uint32), ("n_unreachable", C.c_uint32),
-                ("stats", FlStats)]
+                ("status", C.c_int32), ("stats", FlStats)]
 
 
 class FlSketchView(C.Structure):

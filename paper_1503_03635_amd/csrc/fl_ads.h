@@ -6,11 +6,13 @@ namespace fl {
 
 struct AdsConfig {
   uint32_t k;
-  uint64_t seed;
+  const uint32_t *gid;       // [n] graph of each vertex of a union (nullptr: one graph)
+  const SegInfo *seg;        // device table of the graphs (keys, base, bucket shift)
   uint32_t flags;
   uint32_t thr_rows;         // rows of the HIP-threshold table (0 = none)
   const uint32_t *thr_idx;   // [n] row of each vertex (INF32 = none); nullptr = row u
   const uint32_t *thr_rows_vertex;  // [thr_rows] vertex of each row; nullptr = row r is vertex r
+  uint32_t n_cap;            // vertex count of the largest graph (sizes the rows)
 };
 
 struct AdsOut {
@@ -22,7 +24,8 @@ struct AdsOut {
   const uint32_t *thr_idx = nullptr;
   uint32_t rounds = 0;
   uint64_t relax_exec = 0;
-  double kernel_ms = 0.0;     // summed device time of the round-kernel launches
+  double kernel_ms = 0.0;     // summed device time of the round-kernel (k_ads_tasks) launches
+  double merge_ms = 0.0;      // summed device time of the split-vertex merge launches
   uint32_t launches = 0;
 };
 

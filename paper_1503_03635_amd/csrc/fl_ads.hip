@@ -45,7 +45,8 @@ constexpr uint32_t LONG_LIST = 24;  // entry lists at least this long are stream
 
 struct AdsArgs {
   uint32_t n, k, cap, W, NS, FW;
-  PermKey rk;
+  const uint32_t *gid;  // graph of each vertex (nullptr: one graph)
+  const SegInfo *seg;   // per-graph rank keys, base, bucket shift
   const uint64_t *row_ptr;
   const uint32_t *col;
   const uint32_t *w;
@@ -61,7 +62,6 @@ struct AdsArgs {
   uint32_t *kept_cnt;  // [slots]
   uint64_t *ctr;       // [64] relax_exec, [64] active vertices this round, [64] survivors, [64] prunes
   uint32_t *status;    // [0] capacity overflow, [1] survivor-buffer overflow
-  uint32_t bshift;     // id bucket = id >> bshift < NBKT
 };
 
 __device__ inline uint64_t pack_info(uint32_t round, uint32_t start, uint32_t count) {
@@ -121,7 +121,7 @@ __global__ __launch_bounds__(256) void k_ads_init(AdsArgs P, int mark) {
   const uint64_t u64 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
   if (u64 >= P.n) return;
   const uint32_t u = (uint32_t)u64;
-  const uint32_t r = perm_fwd(u, P.rk);
+  const uint32_t r = rank_of(u, rank_map(P.seg[seg_of(P.gid, u)]));
   if (lane == 0) {
     P.sk_rank[(size_t)u * P.cap] = r;
     P.sk_dist[(size_t)u * P.cap] = 0;
@@ -195,13 +195,13 @@ __device__ inline uint32_t set_count_below(uint32_t setv, uint32_t r) {
 //   #(running set below r_i) + #(earlier distinct candidates of the chunk below r_i) < k.
 // The running set becomes the k smallest ranks of itself and the chunk.
 // Returns the mask of accepted lanes.
-__device__ inline uint64_t chunk_accept(uint32_t id, uint32_t k, PermKey rk, uint32_t &setv, uint32_t &nset,
-                                        uint32_t &prev, uint32_t *s_r) {
+__device__ inline uint64_t chunk_accept(uint32_t id, uint32_t k, const RankMap &rm, uint32_t &setv,
+                                        uint32_t &nset, uint32_t &prev, uint32_t *s_r) {
   const int lane = lane_id();
   uint32_t left = __shfl_up(id, 1, WAVE);
   if (lane == 0) left = prev;
   bool valid = id != INF32 && id != left;
-  const uint32_t r = valid ? perm_fwd(id, rk) : INF32;
+  const uint32_t r = valid ? rank_of(id, rm) : INF32;
   const uint32_t q = set_count_below(setv, r);
   // a candidate already in the set (same vertex at a shorter distance) is
   // not new; one that dropped out of the set is rejected by the count
@@ -265,8 +265,8 @@ __device__ inline uint64_t chunk_accept(uint32_t id, uint32_t k, PermKey rk, uin
 // k-th smallest rank when the bucket was reached, which no later candidate of
 // that bucket can beat.
 __device__ inline uint32_t prune_level(uint32_t *s_id, uint32_t *s_tmp, uint32_t *s_cnt, uint32_t ns,
-                                       uint32_t bshift, uint32_t k, PermKey rk, uint32_t &setv,
-                                       uint32_t &nset, uint32_t *tbk = nullptr) {
+                                       uint32_t k, const RankMap &rm, uint32_t &setv, uint32_t &nset,
+                                       uint32_t *tbk = nullptr) {
   const int lane = lane_id();
   uint32_t *s_pend = s_cnt;
   uint32_t *s_r = s_cnt + 2 * WAVE;
@@ -274,7 +274,7 @@ __device__ inline uint32_t prune_level(uint32_t *s_id, uint32_t *s_tmp, uint32_t
   if (ns <= (uint32_t)WAVE && !tbk) {
     uint32_t x = (uint32_t)lane < ns ? s_id[lane] : INF32;
     x = wave_sort_reg(x);
-    const uint64_t am = chunk_accept(x, k, rk, setv, nset, prev, s_r);
+    const uint64_t am = chunk_accept(x, k, rm, setv, nset, prev, s_r);
     if ((am >> lane) & 1) s_tmp[lanes_below(am)] = x;
     wave_lds_sync();
     return (uint32_t)__popcll(am);
@@ -282,7 +282,7 @@ __device__ inline uint32_t prune_level(uint32_t *s_id, uint32_t *s_tmp, uint32_t
   // counting sort by id bucket (bucket order is id order)
   s_cnt[lane] = 0;
   wave_lds_sync();
-  for (uint32_t i = lane; i < ns; i += WAVE) atomicAdd(&s_cnt[s_id[i] >> bshift], 1u);
+  for (uint32_t i = lane; i < ns; i += WAVE) atomicAdd(&s_cnt[bucket_of(s_id[i], rm)], 1u);
   wave_lds_sync();
   const uint32_t bc = s_cnt[lane];
   const uint32_t bstart = wave_scan_incl(bc) - bc;
@@ -291,7 +291,7 @@ __device__ inline uint32_t prune_level(uint32_t *s_id, uint32_t *s_tmp, uint32_t
   wave_lds_sync();
   for (uint32_t i = lane; i < ns; i += WAVE) {
     const uint32_t id = s_id[i];
-    s_tmp[atomicAdd(&s_cnt[id >> bshift], 1u)] = id;
+    s_tmp[atomicAdd(&s_cnt[bucket_of(id, rm)], 1u)] = id;
   }
   wave_lds_sync();
   // Buckets are walked in id order.  The survivors of consecutive buckets are
@@ -305,7 +305,7 @@ __device__ inline uint32_t prune_level(uint32_t *s_id, uint32_t *s_tmp, uint32_t
   auto flush = [&]() {
     uint32_t x = (uint32_t)lane < npend ? s_pend[lane] : INF32;
     x = wave_sort_reg(x);
-    const uint64_t am = chunk_accept(x, k, rk, setv, nset, prev, s_r);
+    const uint64_t am = chunk_accept(x, k, rm, setv, nset, prev, s_r);
     if ((am >> lane) & 1) s_tmp[m + lanes_below(am)] = x;
     m += (uint32_t)__popcll(am);
     npend = 0;
@@ -323,7 +323,7 @@ __device__ inline uint32_t prune_level(uint32_t *s_id, uint32_t *s_tmp, uint32_t
       bool pass = false;
       if (j < cb) {
         id = s_tmp[sb + j];
-        pass = open || perm_fwd(id, rk) < Trun;
+        pass = open || rank_of(id, rm) < Trun;
       }
       const uint64_t pm = __ballot(pass);
       if (pass) s_tmp[sb + np + lanes_below(pm)] = id;
@@ -357,7 +357,7 @@ __device__ inline uint32_t prune_level(uint32_t *s_id, uint32_t *s_tmp, uint32_t
       wave_sort_lds(s_id, np);
       for (uint32_t c0 = 0; c0 < np; c0 += WAVE) {
         const uint32_t x = c0 + lane < np ? s_id[c0 + lane] : INF32;
-        const uint64_t am = chunk_accept(x, k, rk, setv, nset, prev, s_r);
+        const uint64_t am = chunk_accept(x, k, rm, setv, nset, prev, s_r);
         if ((am >> lane) & 1) s_tmp[m + lanes_below(am)] = x;
         m += (uint32_t)__popcll(am);
         wave_lds_sync();
@@ -387,6 +387,7 @@ struct Level {
   uint32_t cu;           // entries of u so far
   uint32_t ns;           // buffered candidates
   uint32_t tb;           // lane b < NBKT: rank bound for candidates of id bucket b
+  RankMap rm;            // ranks and id buckets of u's graph
   bool overflow;
   uint32_t nsurv, nprune;  // statistics
 };
@@ -394,6 +395,7 @@ struct Level {
 __device__ inline void level_init(const AdsArgs &P, uint32_t u, Level &L, uint32_t *s_cnt) {
   const int lane = lane_id();
   const uint32_t k = P.k;
+  L.rm = rank_map(P.seg[seg_of(P.gid, u)]);
   L.cu = P.cnt[u];
   L.nset0 = L.cu < k ? L.cu : k;
   L.set0 = (uint32_t)lane < L.nset0 ? P.bk[(size_t)u * k + lane] : INF32;
@@ -428,8 +430,8 @@ __device__ inline void level_offer(const AdsArgs &P, Level &L, bool valid, uint3
   }
   // bucket bound from the last prune: all candidates of earlier id buckets
   // come first, and k of them (or of the set) already rank below it
-  const uint32_t cid = pass ? (have_id ? id : perm_inv(r, P.rk)) : 0u;
-  const uint32_t bnd = __shfl(L.tb, (int)((pass ? cid : 0u) >> P.bshift), WAVE);
+  const uint32_t cid = pass ? (have_id ? id : id_of(r, L.rm)) : L.rm.base;
+  const uint32_t bnd = __shfl(L.tb, (int)bucket_of(cid, L.rm), WAVE);
   if (pass && r >= bnd) pass = false;
   uint64_t msk = __ballot(pass);
   if (!msk) return;
@@ -437,11 +439,11 @@ __device__ inline void level_offer(const AdsArgs &P, Level &L, bool valid, uint3
   if (L.ns + np > ADS_SB) {
     uint32_t tv = L.set0, tn = L.nset0;
     ++L.nprune;
-    L.ns = prune_level(s_id, s_tmp, s_cnt, L.ns, P.bshift, P.k, P.rk, tv, tn, &L.tb);
+    L.ns = prune_level(s_id, s_tmp, s_cnt, L.ns, P.k, L.rm, tv, tn, &L.tb);
     for (uint32_t i = lane; i < L.ns; i += WAVE) s_id[i] = s_tmp[i];
     wave_lds_sync();
     // the new bounds may reject some of this chunk too
-    const uint32_t bnd2 = __shfl(L.tb, (int)((pass ? cid : 0u) >> P.bshift), WAVE);
+    const uint32_t bnd2 = __shfl(L.tb, (int)bucket_of(cid, L.rm), WAVE);
     if (pass && r >= bnd2) pass = false;
     msk = __ballot(pass);
     np = (uint32_t)__popcll(msk);
@@ -531,7 +533,7 @@ __device__ inline void level_commit(const AdsArgs &P, uint32_t u, uint32_t D, Le
   const int lane = lane_id();
   if (L.ns == 0) return;
   uint32_t setv = L.set0, nset = L.nset0;
-  const uint32_t m = prune_level(s_id, s_tmp, s_cnt, L.ns, P.bshift, P.k, P.rk, setv, nset);
+  const uint32_t m = prune_level(s_id, s_tmp, s_cnt, L.ns, P.k, L.rm, setv, nset);
   if (m == 0) return;
   const uint32_t cu = L.cu;
   if (cu + m > P.cap) {
@@ -543,14 +545,14 @@ __device__ inline void level_commit(const AdsArgs &P, uint32_t u, uint32_t D, Le
   // last round (k_ads_canon).
   const size_t base = (size_t)u * P.cap + cu;
   if (m <= (uint32_t)WAVE) {
-    uint32_t x = (uint32_t)lane < m ? perm_fwd(s_tmp[lane], P.rk) : INF32;
+    uint32_t x = (uint32_t)lane < m ? rank_of(s_tmp[lane], L.rm) : INF32;
     x = wave_sort_reg(x);
     if ((uint32_t)lane < m) {
       P.sk_rank[base + lane] = x;
       P.sk_dist[base + lane] = D;
     }
   } else {
-    for (uint32_t i = lane; i < m; i += WAVE) s_id[i] = perm_fwd(s_tmp[i], P.rk);
+    for (uint32_t i = lane; i < m; i += WAVE) s_id[i] = rank_of(s_tmp[i], L.rm);
     wave_sort_lds(s_id, m);  // m <= ADS_SB
     for (uint32_t i = lane; i < m; i += WAVE) {
       P.sk_rank[base + i] = s_id[i];
@@ -613,7 +615,7 @@ __global__ __launch_bounds__(256) void k_ads_tasks(AdsArgs P, uint32_t D, const 
     uint32_t m = 0;
     if (L.ns) {
       uint32_t setv = L.set0, nset = L.nset0;
-      m = prune_level(s_id, s_tmp, s_cnt, L.ns, P.bshift, P.k, P.rk, setv, nset);
+      m = prune_level(s_id, s_tmp, s_cnt, L.ns, P.k, L.rm, setv, nset);
       for (uint32_t i = lane; i < m; i += WAVE) P.kept[(size_t)slot * ADS_SB + i] = s_tmp[i];
     }
     if (lane == 0) P.kept_cnt[slot] = m;
@@ -658,7 +660,7 @@ __global__ __launch_bounds__(256) void k_ads_merge(AdsArgs P, uint32_t D, const 
       uint32_t id = INF32, r = INF32;
       if (valid) {
         id = P.kept[(size_t)(first + g0 + pos) * ADS_SB + (idx - oex)];
-        r = perm_fwd(id, P.rk);
+        r = rank_of(id, L.rm);
       }
       level_offer(P, L, valid, r, true, id, s_id, s_tmp, s_cnt);
     }
@@ -673,14 +675,16 @@ __global__ __launch_bounds__(256) void k_ads_merge(AdsArgs P, uint32_t D, const 
 // Restore (distance, id) order inside each level of every row (levels were
 // stored in increasing rank order while the rounds ran).  One wave per row;
 // a level holds at most ADS_SB entries (the survivor buffer of its commit).
-__global__ __launch_bounds__(256) void k_ads_canon(uint32_t n, uint32_t cap, PermKey rk, const uint32_t *cnt,
-                                                   uint32_t *sk_rank, const uint32_t *sk_dist, uint32_t *status) {
+__global__ __launch_bounds__(256) void k_ads_canon(uint32_t n, uint32_t cap, const uint32_t *gid,
+                                                   const SegInfo *seg, const uint32_t *cnt, uint32_t *sk_rank,
+                                                   const uint32_t *sk_dist, uint32_t *status) {
   __shared__ uint32_t lds[ADS_WPB][ADS_SB];
   const int lane = lane_id();
   const int wv = threadIdx.x / WAVE;
   const uint64_t u64 = (uint64_t)blockIdx.x * ADS_WPB + wv;
   if (u64 >= n) return;
   const uint32_t u = (uint32_t)u64;
+  const RankMap rm = rank_map(seg[seg_of(gid, u)]);
   const uint32_t c = cnt[u];
   uint32_t *rr = sk_rank + (size_t)u * cap;
   const uint32_t *dd = sk_dist + (size_t)u * cap;
@@ -700,13 +704,13 @@ __global__ __launch_bounds__(256) void k_ads_canon(uint32_t n, uint32_t cap, Per
     }
     const uint32_t len = e - pos;
     if (len > 1 && len <= (uint32_t)WAVE) {
-      uint32_t x = (uint32_t)lane < len ? perm_inv(rr[pos + lane], rk) : INF32;
+      uint32_t x = (uint32_t)lane < len ? id_of(rr[pos + lane], rm) : INF32;
       x = wave_sort_reg(x);
-      if ((uint32_t)lane < len) rr[pos + lane] = perm_fwd(x, rk);
+      if ((uint32_t)lane < len) rr[pos + lane] = rank_of(x, rm);
     } else if (len > 1 && len <= ADS_SB) {
-      for (uint32_t i = lane; i < len; i += WAVE) s[i] = perm_inv(rr[pos + i], rk);
+      for (uint32_t i = lane; i < len; i += WAVE) s[i] = id_of(rr[pos + i], rm);
       wave_sort_lds(s, len);
-      for (uint32_t i = lane; i < len; i += WAVE) rr[pos + i] = perm_fwd(s[i], rk);
+      for (uint32_t i = lane; i < len; i += WAVE) rr[pos + i] = rank_of(s[i], rm);
       wave_lds_sync();
     } else if (len > ADS_SB && lane == 0) {
       atomicOr(&status[1], 1u);
@@ -899,7 +903,8 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
   P.W = W;
   P.NS = NS;
   P.FW = FW;
-  P.rk = perm_key(cfg.seed, 1);
+  P.gid = cfg.gid;
+  P.seg = cfg.seg;
   P.row_ptr = g.row_ptr;
   P.col = g.col;
   P.w = g.w;
@@ -913,9 +918,6 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
   P.wl_cnt = c.arena->get<uint32_t>(NS);
   P.ctr = c.arena->get<uint64_t>(256);
   P.status = c.arena->get<uint32_t>(4);
-  uint32_t bits = 0;
-  while (bits < 32 && (1ull << bits) < (uint64_t)n) ++bits;
-  P.bshift = bits > 6 ? bits - 6 : 0;  // NBKT = 64 buckets
   fill_u64(c, P.dinfo, (size_t)NS * n, INF64);
   fill_u32(c, P.flags, (size_t)n * FW, 0);
   fill_u32(c, P.wl_cnt, NS, 0);
@@ -984,17 +986,20 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
     FL_LAUNCH_CHECK();
   }
   bool sparse = mark;  // mode of round 1
-  hipEvent_t e0, e1;
+  hipEvent_t e0, em, e1;
   FL_HIP(hipEventCreate(&e0));
+  FL_HIP(hipEventCreate(&em));
   FL_HIP(hipEventCreate(&e1));
   struct EvDel {
-    hipEvent_t a, b;
+    hipEvent_t a, b, c;
     ~EvDel() {
       (void)hipEventDestroy(a);
       (void)hipEventDestroy(b);
+      (void)hipEventDestroy(c);
     }
-  } evdel{e0, e1};
+  } evdel{e0, em, e1};
   o.kernel_ms = 0.0;
+  o.merge_ms = 0.0;
   o.launches = 0;
   uint64_t active_prev = n;
   uint32_t rounds = 0;
@@ -1022,6 +1027,7 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
         k_ads_tasks<false><<<tb, 256, 0, c.s>>>(P, D, T->task_u, T->task_sub, T->task_slot, T->ntasks,
                                                 sparse ? 1 : 0, mark ? 1 : 0);
       FL_LAUNCH_CHECK();
+      FL_HIP(hipEventRecord(em, c.s));
       if (T->nsplit) {
         const uint32_t mb = (uint32_t)ceil_div(T->nsplit, ADS_WPB);
         if (unit)
@@ -1041,9 +1047,11 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
     FL_HIP(hipMemcpyAsync(hwl.data(), P.wl_cnt, NS * 4, hipMemcpyDeviceToHost, c.s));
     c.sync();
     if (T->ntasks) {
-      float ms = 0.f;
-      FL_HIP(hipEventElapsedTime(&ms, e0, e1));
+      float ms = 0.f, ms2 = 0.f;
+      FL_HIP(hipEventElapsedTime(&ms, e0, em));
+      FL_HIP(hipEventElapsedTime(&ms2, em, e1));
       o.kernel_ms += ms;
+      o.merge_ms += ms2;
       o.launches += 1;
       if (std::getenv("FL_DEBUG")) {
         std::vector<uint64_t> hs(256);
@@ -1092,7 +1100,7 @@ int ads_build(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o) {
   if (cfg.k == 0) return FL_EINVAL;
   if (cfg.k > MAX_K) return FL_ENOTIMPL;
   if (g.w && g.max_w > MAX_W) return FL_ENOTIMPL;
-  uint32_t cap = ads_capacity(g.n, cfg.k);
+  uint32_t cap = ads_capacity(cfg.n_cap ? cfg.n_cap : g.n, cfg.k);
   for (int attempt = 0; attempt < 6; ++attempt) {
     if (cap > MAX_CAP) return FL_ENOTIMPL;
     const size_t mark = c.arena->used();
@@ -1115,7 +1123,7 @@ int ads_build(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o) {
         uint32_t *st = c.arena->get<uint32_t>(4);
         fill_u32(c, st, 4, 0);
         k_ads_canon<<<(uint32_t)ceil_div(g.n, ADS_WPB), ADS_WPB * WAVE, 0, c.s>>>(
-            g.n, cap, perm_key(cfg.seed, 1), o.cnt, o.sk_rank, o.sk_dist, st);
+            g.n, cap, cfg.gid, cfg.seg, o.cnt, o.sk_rank, o.sk_dist, st);
         FL_LAUNCH_CHECK();
         FL_HIP(hipMemcpyAsync(c.h_status, st, 8, hipMemcpyDeviceToHost, c.s));
         c.sync();
@@ -1130,7 +1138,8 @@ int ads_build(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o) {
       return FL_OK;
     }
     uint64_t nc = (uint64_t)cap * 3 / 2 + 16;
-    if (nc > g.n) nc = g.n;
+    const uint32_t nmax = cfg.n_cap ? cfg.n_cap : g.n;
+    if (nc > nmax) nc = nmax;
     if (nc == cap) return FL_ENOMEM;
     c.arena->rewind(mark);
     cap = (uint32_t)nc;

@@ -4,6 +4,7 @@
 //   assignment -> objective.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -86,33 +87,28 @@ __global__ void k_gamma_init(uint32_t n, const uint32_t *fac_cost, uint64_t *lab
     lab[v] = c != FL_NOT_FACILITY ? (((uint64_t)c << 32) | v) : INF64;
   }
 }
-// served clients, gamma, counts.  ctr: [0..63] nC, [64..127] nCeff,
-// [128..191] nUF0, [192..255] max gamma
-__global__ void k_clients(uint32_t n, const uint8_t *is_client, const uint64_t *gl, const uint32_t *fac_cost,
-                          uint8_t *ceff, uint64_t *ctr) {
+// served clients, gamma, counts per graph: fields nC, nCeff, nUF0, max gamma
+enum { CL_NC = 0, CL_NCEFF, CL_NUF0, CL_GMAX, CL_NFIELD };
+__global__ void k_clients(uint32_t n, const uint32_t *gid, const uint8_t *is_client, const uint64_t *gl,
+                          const uint32_t *fac_cost, uint8_t *ceff, uint64_t *ctr, uint32_t stripes) {
   const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = v < n;
   bool cl = false, ce = false, uf = false;
   uint64_t gmax = 0;
-  if (v < n) {
+  uint32_t g = 0;
+  if (valid) {
+    g = seg_of(gid, (uint32_t)v);
     cl = is_client ? is_client[v] != 0 : true;
     ce = cl && gl[v] != INF64;
     uf = ce && fac_cost[v] != FL_NOT_FACILITY;
     ceff[v] = ce ? 1 : 0;
     if (ce) gmax = gl[v] >> 32;
   }
-  const uint64_t a = __popcll(__ballot(cl)), b = __popcll(__ballot(ce)), d = __popcll(__ballot(uf));
-#pragma unroll
-  for (int s = 32; s >= 1; s >>= 1) {
-    const uint64_t o = __shfl_xor(gmax, s, WAVE);
-    gmax = o > gmax ? o : gmax;
-  }
-  if (lane_id() == 0) {
-    const int st = blockIdx.x & 63;
-    atomicAdd((unsigned long long *)&ctr[st], (unsigned long long)a);
-    atomicAdd((unsigned long long *)&ctr[64 + st], (unsigned long long)b);
-    atomicAdd((unsigned long long *)&ctr[128 + st], (unsigned long long)d);
-    atomicMax((unsigned long long *)&ctr[192 + st], (unsigned long long)gmax);
-  }
+  unsigned long long *c = (unsigned long long *)ctr;
+  seg_add(c, valid, g, CL_NC, CL_NFIELD, stripes, cl ? 1 : 0);
+  seg_add(c, valid, g, CL_NCEFF, CL_NFIELD, stripes, ce ? 1 : 0);
+  seg_add(c, valid, g, CL_NUF0, CL_NFIELD, stripes, uf ? 1 : 0);
+  seg_max(c, valid, g, CL_GMAX, CL_NFIELD, stripes, gmax);
 }
 __global__ void k_scatter_q(uint32_t nF, const uint32_t *fac_list, const double *qf, double *q) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -129,17 +125,22 @@ __global__ void k_compact_u32(uint32_t n, const uint32_t *flag, const uint64_t *
   const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v < n && flag[v]) out[pos[v]] = (uint32_t)v;
 }
-// assignment outputs and the objective.  ctr: [0..63] cost, [64..127]
-// n_open, [128..191] n_guard
-__global__ void k_assign_out(uint32_t n, const uint8_t *ceff, const uint64_t *lab, const uint8_t *open,
-                             const uint32_t *fac_cost, const uint32_t *orung, uint32_t *assign,
-                             uint32_t *dist, uint64_t *ctr) {
+// assignment outputs (facility ids local to the graph) and the objective per
+// graph: fields cost, n_open, n_guard
+enum { AO_COST = 0, AO_NOPEN, AO_NGUARD, AO_NFIELD };
+__global__ void k_assign_out(uint32_t n, const uint32_t *gid, const SegInfo *seg, const uint8_t *ceff,
+                             const uint64_t *lab, const uint8_t *open, const uint32_t *fac_cost,
+                             const uint32_t *orung, uint32_t *assign, uint32_t *dist, uint64_t *ctr,
+                             uint32_t stripes) {
   const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = v < n;
   uint64_t cost = 0, no = 0, ng = 0;
-  if (v < n) {
+  uint32_t g = 0;
+  if (valid) {
+    g = seg_of(gid, (uint32_t)v);
     if (ceff[v]) {
       const uint64_t L = lab[v];
-      assign[v] = (uint32_t)(L & 0xFFFFFFFFu);
+      assign[v] = (uint32_t)(L & 0xFFFFFFFFu) - seg[g].base;
       const uint32_t d = (uint32_t)(L >> 32);
       if (dist) dist[v] = d;
       cost += d;
@@ -153,29 +154,67 @@ __global__ void k_assign_out(uint32_t n, const uint8_t *ceff, const uint64_t *la
     }
     if (orung[v] == FL_RUNG_GUARD) ng = 1;
   }
-  cost = wave_sum_u64(cost);
-  no = wave_sum_u64(no);
-  ng = wave_sum_u64(ng);
-  if (lane_id() == 0) {
-    const int st = blockIdx.x & 63;
-    atomicAdd((unsigned long long *)&ctr[st], (unsigned long long)cost);
-    atomicAdd((unsigned long long *)&ctr[64 + st], (unsigned long long)no);
-    atomicAdd((unsigned long long *)&ctr[128 + st], (unsigned long long)ng);
-  }
+  unsigned long long *c = (unsigned long long *)ctr;
+  seg_add(c, valid, g, AO_COST, AO_NFIELD, stripes, cost);
+  seg_add(c, valid, g, AO_NOPEN, AO_NFIELD, stripes, no);
+  seg_add(c, valid, g, AO_NGUARD, AO_NFIELD, stripes, ng);
 }
 
-static void read_u64_fields(Ctx &c, const uint64_t *d, int fields, std::vector<uint64_t> &sum,
-                            bool max_last = false) {
-  std::vector<uint64_t> h((size_t)fields * 64);
-  FL_HIP(hipMemcpyAsync(h.data(), d, h.size() * 8, hipMemcpyDeviceToHost, c.s));
-  c.sync();
-  sum.assign(fields, 0);
-  for (int f = 0; f < fields; ++f)
-    for (int s = 0; s < 64; ++s) {
-      const uint64_t x = h[(size_t)f * 64 + s];
-      if (max_last && f == fields - 1) sum[f] = x > sum[f] ? x : sum[f];
-      else sum[f] += x;
-    }
+// ---- union of several graphs ------------------------------------------------
+struct UnionDesc {
+  const uint64_t *row_ptr;
+  const uint32_t *col, *w, *fac_cost;
+  const uint8_t *is_client;
+  uint32_t n, base;
+  uint64_t m, abase;
+};
+// vertex arrays of the union; grid (x: vertex blocks, y: graph)
+__global__ void k_union_vertices(const UnionDesc *d, uint32_t *gid, uint64_t *row_ptr, uint32_t *fac_cost,
+                                 uint8_t *is_client) {
+  const uint32_t g = blockIdx.y;
+  const UnionDesc D = d[g];
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < D.n; v += gridDim.x * blockDim.x) {
+    const uint32_t u = D.base + v;
+    gid[u] = g;
+    row_ptr[u] = D.abase + D.row_ptr[v];
+    fac_cost[u] = D.fac_cost[v];
+    is_client[u] = D.is_client ? (D.is_client[v] != 0) : 1;
+  }
+}
+// arcs of the union (ids shifted by the graph's base; unit graphs get w = 1)
+__global__ void k_union_arcs(const UnionDesc *d, uint32_t *col, uint32_t *w) {
+  const uint32_t g = blockIdx.y;
+  const UnionDesc D = d[g];
+  for (uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; a < D.m;
+       a += (uint64_t)gridDim.x * blockDim.x) {
+    col[D.abase + a] = D.col[a] + D.base;
+    if (w) w[D.abase + a] = D.w ? D.w[a] : 1u;
+  }
+}
+// per-graph caller outputs from the union arrays; grid (x: vertex blocks, y: graph)
+struct OutDesc {
+  uint8_t *open;
+  uint32_t *assign, *dist, *open_rung, *freeze_rung;
+  double *q;
+  uint32_t n, base;
+};
+__global__ void k_scatter_out(const OutDesc *d, const uint8_t *open, const uint32_t *assign, const uint32_t *dist,
+                              const uint32_t *orung, const uint32_t *frz, const double *q) {
+  const OutDesc D = d[blockIdx.y];
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < D.n; v += gridDim.x * blockDim.x) {
+    const uint32_t u = D.base + v;
+    D.open[v] = open[u];
+    D.assign[v] = assign[u];
+    if (D.dist) D.dist[v] = dist[u];
+    if (D.open_rung) D.open_rung[v] = orung[u];
+    if (D.freeze_rung) D.freeze_rung[v] = frz[u];
+    if (D.q) D.q[v] = q[u];
+  }
+}
+// pos[] at each graph's first vertex and at the end: facility counts per graph
+__global__ void k_pick_u64(const uint64_t *src, const uint32_t *idx, uint32_t cnt, uint64_t *dst) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) dst[i] = src[idx[i]];
 }
 
 static int check_params(const fl_problem *p, const fl_params *prm) {
@@ -199,6 +238,12 @@ static size_t estimate_bytes(uint32_t n, uint64_t m, uint64_t nF, uint32_t k, ui
   b += (size_t)64 << 20;                   // counters, scans
   return b;
 }
+// extra bytes of a union of several graphs: CSR copy, graph ids, inputs and outputs
+static size_t union_bytes(uint32_t G, uint64_t n, uint64_t m, bool weighted) {
+  if (G <= 1) return 0;
+  return (size_t)(n + 1) * 8 + (size_t)m * (weighted ? 8 : 4) + (size_t)n * (4 + 4 + 1) +
+         (size_t)n * (1 + 4 + 4 + 4 + 4 + 8) + (size_t)G * 256 + ((size_t)4 << 20);
+}
 
 static double ms_between(hipEvent_t a, hipEvent_t b) {
   float ms = 0.f;
@@ -206,16 +251,31 @@ static double ms_between(hipEvent_t a, hipEvent_t b) {
   return (double)ms;
 }
 
-static int solve_one(const fl_problem *p, const fl_params *prm, fl_result *out, hipStream_t s,
-                     DeviceCache &dc) {
-  int rc = check_params(p, prm);
-  if (rc) return rc;
-  if (!p->fac_cost || !out || !out->open || !out->assign) return FL_EINVAL;
+// One group of graphs with equal k, eps and flags (already checked by the
+// caller), solved together as a disjoint union: every phase runs once for the
+// whole group.  rc[i] receives each graph's code.
+static void solve_group(const fl_problem *const *ps, const fl_params *const *pr, fl_result *const *outs,
+                        uint32_t G0, hipStream_t s, DeviceCache &dc, std::vector<int> &rc_out, int depth = 0) {
+  rc_out.assign(G0, FL_OK);
   ensure_host_status(dc);
-  const uint32_t n = p->n;
-  const uint32_t cap0 = ads_capacity(n, prm->k);
-  // facilities are counted after validation; reserve for all vertices first
-  dc.arena.reserve(estimate_bytes(n, p->n_arcs, n, prm->k, cap0, 2));
+  const uint32_t k = pr[0]->k;
+  const double eps = pr[0]->eps;
+  const uint32_t flags = pr[0]->flags;
+  uint64_t N0 = 0, M0 = 0;
+  uint32_t nmax0 = 1;
+  bool weighted0 = false;
+  for (uint32_t i = 0; i < G0; ++i) {
+    N0 += ps[i]->n;
+    M0 += ps[i]->n_arcs;
+    nmax0 = std::max(nmax0, ps[i]->n);
+    weighted0 |= ps[i]->w != nullptr;
+  }
+  if (N0 >= 0xFFFFFFFFull) {
+    for (auto &r : rc_out) r = FL_ENOMEM;
+    return;
+  }
+  const uint32_t cap0 = ads_capacity(nmax0, k);
+  dc.arena.reserve(estimate_bytes((uint32_t)N0, M0, N0, k, cap0, 2) + union_bytes(G0, N0, M0, weighted0));
   dc.arena.reset();
   Ctx c;
   c.s = s;
@@ -232,106 +292,225 @@ static int solve_one(const fl_problem *p, const fl_params *prm, fl_result *out, 
   } evg{ev};
   FL_HIP(hipEventRecord(ev[0], s));
 
-  uint32_t max_w = 1, max_c = 0;
-  rc = validate_graph(c, p, &max_w, &max_c);
-  if (rc) return rc;
-  const uint64_t bound = (uint64_t)(n - 1) * (p->w ? max_w : 1u) + max_c;
-  if (bound >= 0xFFFFFFFFull) return FL_ERANGE;
-  if (p->w && max_w > MAX_W) return FL_ENOTIMPL;
-  Graph g{n, p->n_arcs, p->row_ptr, p->col, p->w, p->w ? max_w : 1u};
-  const uint32_t NS = g.max_w + 1;
+  // ---- validation per graph; failing graphs leave the group
+  std::vector<uint32_t> mw(G0, 1), mc(G0, 0);
+  if (G0 == 1) {
+    rc_out[0] = validate_graph(c, ps[0], &mw[0], &mc[0]);
+  } else {
+    validate_graphs(c, ps, G0, rc_out, mw, mc);
+  }
+  std::vector<uint32_t> act;  // indices of the graphs that go on
+  for (uint32_t i = 0; i < G0; ++i) {
+    if (rc_out[i]) continue;
+    const fl_problem *p = ps[i];
+    const uint64_t bound = (uint64_t)(p->n - 1) * (p->w ? mw[i] : 1u) + mc[i];
+    if (bound >= 0xFFFFFFFFull) rc_out[i] = FL_ERANGE;
+    else if (p->w && mw[i] > MAX_W) rc_out[i] = FL_ENOTIMPL;
+    else act.push_back(i);
+  }
+  if (act.empty()) return;
+  if (act.size() < G0) {
+    // solve the valid ones alone: the union must hold valid graphs only
+    std::vector<const fl_problem *> ps2;
+    std::vector<const fl_params *> pr2;
+    std::vector<fl_result *> out2;
+    for (uint32_t i : act) {
+      ps2.push_back(ps[i]);
+      pr2.push_back(pr[i]);
+      out2.push_back(outs[i]);
+    }
+    std::vector<int> rc2;
+    solve_group(ps2.data(), pr2.data(), out2.data(), (uint32_t)act.size(), s, dc, rc2, depth);
+    for (size_t j = 0; j < act.size(); ++j) rc_out[act[j]] = rc2[j];
+    return;
+  }
+  const uint32_t G = G0;
+  const uint32_t n = (uint32_t)N0;
+  uint32_t max_w = 1;
+  for (uint32_t i = 0; i < G; ++i)
+    if (ps[i]->w) max_w = std::max(max_w, mw[i]);
+  const bool weighted = weighted0;
+  const uint32_t NS = (weighted ? max_w : 1u) + 1;
+  if (estimate_bytes(n, M0, n, k, cap0, NS) + union_bytes(G, N0, M0, weighted) > dc.arena.capacity()) {
+    if (depth > 0) {
+      for (auto &r : rc_out) r = FL_ENOMEM;
+      return;
+    }
+    dc.arena.reserve(estimate_bytes(n, M0, n, k, cap0, NS) + union_bytes(G, N0, M0, weighted));
+    return solve_group(ps, pr, outs, G0, s, dc, rc_out, depth + 1);  // restart with the larger arena
+  }
+
+  // ---- the union (one graph: the caller's arrays as they are)
+  std::vector<uint32_t> hbase(G);
+  {
+    uint64_t b = 0;
+    for (uint32_t i = 0; i < G; ++i) {
+      hbase[i] = (uint32_t)b;
+      b += ps[i]->n;
+    }
+  }
+  std::vector<SegInfo> hseg(G);
+  for (uint32_t i = 0; i < G; ++i) hseg[i] = seg_info(hbase[i], ps[i]->n, pr[i]->seed);
+  SegInfo *seg = c.arena->get<SegInfo>(G);
+  FL_HIP(hipMemcpyAsync(seg, hseg.data(), G * sizeof(SegInfo), hipMemcpyHostToDevice, s));
+  const uint32_t *gid = nullptr;
+  const uint32_t *fac_cost = ps[0]->fac_cost;
+  const uint8_t *is_client = ps[0]->is_client;
+  Graph g{n, M0, ps[0]->row_ptr, ps[0]->col, ps[0]->w, weighted ? max_w : 1u};
+  if (G > 1) {
+    std::vector<UnionDesc> hd(G);
+    uint64_t ab = 0;
+    uint32_t mx_blocks = 1;
+    uint64_t mx_m = 1;
+    for (uint32_t i = 0; i < G; ++i) {
+      const fl_problem *p = ps[i];
+      hd[i] = UnionDesc{p->row_ptr, p->col, p->w, p->fac_cost, p->is_client, p->n, hbase[i], p->n_arcs, ab};
+      ab += p->n_arcs;
+      mx_blocks = std::max<uint32_t>(mx_blocks, (uint32_t)ceil_div(p->n, 256));
+      mx_m = std::max<uint64_t>(mx_m, p->n_arcs);
+    }
+    UnionDesc *dd = c.arena->get<UnionDesc>(G);
+    FL_HIP(hipMemcpyAsync(dd, hd.data(), G * sizeof(UnionDesc), hipMemcpyHostToDevice, s));
+    uint32_t *d_gid = c.arena->get<uint32_t>(n);
+    uint64_t *d_rp = c.arena->get<uint64_t>((size_t)n + 1);
+    uint32_t *d_col = c.arena->get<uint32_t>(M0 ? M0 : 1);
+    uint32_t *d_w = weighted ? c.arena->get<uint32_t>(M0 ? M0 : 1) : nullptr;
+    uint32_t *d_fc = c.arena->get<uint32_t>(n);
+    uint8_t *d_cl = c.arena->get<uint8_t>(n);
+    const uint32_t vbx = std::min<uint32_t>(mx_blocks, 1024);
+    k_union_vertices<<<dim3(vbx, G), 256, 0, s>>>(dd, d_gid, d_rp, d_fc, d_cl);
+    FL_LAUNCH_CHECK();
+    fill_u64(c, d_rp + n, 1, M0);
+    const uint32_t abx = (uint32_t)std::min<uint64_t>(ceil_div(mx_m, 256 * 8), 1024);
+    k_union_arcs<<<dim3(abx, G), 256, 0, s>>>(dd, d_col, d_w);
+    FL_LAUNCH_CHECK();
+    c.sync();  // hd is read by the copy above
+    gid = d_gid;
+    fac_cost = d_fc;
+    is_client = d_cl;
+    g = Graph{n, M0, d_rp, d_col, d_w, weighted ? max_w : 1u};
+  }
   FL_HIP(hipEventRecord(ev[1], s));
 
-  // facilities
+  // ---- facilities
   uint32_t *flag = c.arena->get<uint32_t>(n);
   uint64_t *pos = c.arena->get<uint64_t>((size_t)n + 1);
   uint32_t *fac_list = c.arena->get<uint32_t>(n);
   uint32_t *fac_idx = c.arena->get<uint32_t>(n);
   const uint32_t vb = (uint32_t)ceil_div(n, 256);
-  k_fac_flags<<<vb, 256, 0, s>>>(n, p->fac_cost, flag);
+  k_fac_flags<<<vb, 256, 0, s>>>(n, fac_cost, flag);
   FL_LAUNCH_CHECK();
   scan_u32_to_u64(c, flag, pos, n);
   k_fac_index<<<vb, 256, 0, s>>>(n, flag, pos, fac_list, fac_idx);
   FL_LAUNCH_CHECK();
-  FL_HIP(hipMemcpyAsync(c.h_status, pos + n, 8, hipMemcpyDeviceToHost, s));
-  c.sync();
-  const uint32_t nF = (uint32_t)c.h_status[0];
-  // re-reserve now that the sizes are known (keeps what is allocated so far
-  // valid only if no reallocation happens; reserve before any use instead)
-  if (estimate_bytes(n, p->n_arcs, nF, prm->k, cap0, NS) > dc.arena.capacity()) {
-    dc.arena.reserve(estimate_bytes(n, p->n_arcs, nF, prm->k, cap0, NS));
-    return solve_one(p, prm, out, s, dc);  // restart with the larger arena
+  std::vector<uint64_t> nF_g(G);
+  uint32_t nF = 0;
+  {
+    std::vector<uint32_t> hidx(G + 1);
+    for (uint32_t i = 0; i < G; ++i) hidx[i] = hbase[i];
+    hidx[G] = n;
+    uint32_t *didx = c.arena->get<uint32_t>(G + 1);
+    uint64_t *dval = c.arena->get<uint64_t>(G + 1);
+    FL_HIP(hipMemcpyAsync(didx, hidx.data(), (G + 1) * 4, hipMemcpyHostToDevice, s));
+    k_pick_u64<<<(uint32_t)ceil_div(G + 1, 256), 256, 0, s>>>(pos, didx, G + 1, dval);
+    FL_LAUNCH_CHECK();
+    std::vector<uint64_t> hv(G + 1);
+    FL_HIP(hipMemcpyAsync(hv.data(), dval, (G + 1) * 8, hipMemcpyDeviceToHost, s));
+    c.sync();
+    for (uint32_t i = 0; i < G; ++i) nF_g[i] = hv[i + 1] - hv[i];
+    nF = (uint32_t)hv[G];
   }
 
-  // sketches
-  AdsConfig acfg{prm->k, prm->seed, prm->flags, nF, fac_idx, fac_list};
+  // ---- sketches (Sec. 3.3)
+  AdsConfig acfg{k, gid, seg, flags, nF, fac_idx, fac_list, nmax0};
   AdsOut ads;
-  rc = ads_build(c, g, acfg, ads);
-  if (rc) return rc;
-  ads_totals(c, g, ads.cnt, &out->stats.relax_alg, &out->stats.ads_entries);
-  out->stats.ads_rounds = ads.rounds;
-  out->stats.relax_exec = ads.relax_exec;
-  out->stats.ms_ads_kernel = ads.kernel_ms;
-  out->stats.ads_kernel_launches = ads.launches;
+  int rc = ads_build(c, g, acfg, ads);
+  if (rc) {
+    for (auto &r : rc_out) r = rc;
+    return;
+  }
+  std::vector<uint64_t> relax, entries;
+  ads_totals(c, g, gid, G, ads.cnt, relax, entries);
   FL_HIP(hipEventRecord(ev[2], s));
 
-  // gamma (Sec. 4.1) and served clients
+  // ---- gamma (Sec. 4.1) and served clients
+  const uint32_t stripes = G == 1 ? 64 : 1;
   uint64_t *gl = c.arena->get<uint64_t>(n);
   uint8_t *ceff = c.arena->get<uint8_t>(n);
-  uint64_t *ctr = c.arena->get<uint64_t>(256);
-  k_gamma_init<<<vb, 256, 0, s>>>(n, p->fac_cost, gl);
+  uint64_t *ctr = c.arena->get<uint64_t>((size_t)G * 4 * stripes);
+  k_gamma_init<<<vb, 256, 0, s>>>(n, fac_cost, gl);
   FL_LAUNCH_CHECK();
   SsspWork wk;
   sssp_alloc(c, wk, n);
   sssp_run(c, g, gl, fac_list, nF, wk, 0);
-  fill_u64(c, ctr, 256, 0);
-  k_clients<<<vb, 256, 0, s>>>(n, p->is_client, gl, p->fac_cost, ceff, ctr);
+  fill_u64(c, ctr, (size_t)G * CL_NFIELD * stripes, 0);
+  k_clients<<<vb, 256, 0, s>>>(n, gid, is_client, gl, fac_cost, ceff, ctr, stripes);
   FL_LAUNCH_CHECK();
-  std::vector<uint64_t> cs;
-  read_u64_fields(c, ctr, 4, cs, true);
-  const uint64_t nC = cs[0], nCeff = cs[1], nUF0 = cs[2], gamma = cs[3];
-  out->stats.gamma = gamma;
-  out->n_unreachable = (uint32_t)(nC - nCeff);
-  const double one_eps = 1.0 + prm->eps;
-  std::vector<double> lad(1, 0.0);
-  if (nF > 0 && nCeff > 0) {
-    const double M = (double)((uint64_t)nF * nCeff);
-    lad[0] = ((double)gamma / (M * M)) * one_eps;
+  const std::vector<uint64_t> cs = read_seg_ctr(c, ctr, G, CL_NFIELD, stripes, true);
+  const double one_eps = 1.0 + eps;
+  std::vector<std::vector<double>> lad(G);
+  OpenIn oi{&g, G, gid, seg, nF, fac_list, fac_idx, fac_cost, &ads, ceff, nF_g, {}, {}, gl, eps, &lad};
+  oi.nCeff.resize(G);
+  oi.nUF0.resize(G);
+  for (uint32_t i = 0; i < G; ++i) {
+    const uint64_t nC = cs[i * CL_NFIELD + CL_NC], nCeff = cs[i * CL_NFIELD + CL_NCEFF];
+    const uint64_t gamma = cs[i * CL_NFIELD + CL_GMAX];
+    oi.nCeff[i] = nCeff;
+    oi.nUF0[i] = cs[i * CL_NFIELD + CL_NUF0];
+    outs[i]->stats.gamma = gamma;
+    outs[i]->n_unreachable = (uint32_t)(nC - nCeff);
+    lad[i].assign(1, 0.0);
+    if (nF_g[i] > 0 && nCeff > 0) {
+      const double Mq = (double)(nF_g[i] * nCeff);
+      lad[i][0] = ((double)gamma / (Mq * Mq)) * one_eps;
+    }
+    lad[i].push_back(lad[i][0] * one_eps);
+    outs[i]->stats.alpha0 = lad[i][0];
   }
-  lad.push_back(lad[0] * one_eps);
-  out->stats.alpha0 = lad[0];
   FL_HIP(hipEventRecord(ev[3], s));
 
-  // opening loop
-  uint32_t *orung = out->open_rung ? out->open_rung : c.arena->get<uint32_t>(n);
-  uint32_t *frz = out->freeze_rung ? out->freeze_rung : c.arena->get<uint32_t>(n);
+  // ---- outputs: the caller's arrays for one graph, union arrays otherwise
+  fl_result *o0 = outs[0];
+  uint8_t *open_u = G == 1 ? o0->open : c.arena->get<uint8_t>(n);
+  uint32_t *assign_u = G == 1 ? o0->assign : c.arena->get<uint32_t>(n);
+  uint32_t *dist_u = G == 1 ? o0->dist : c.arena->get<uint32_t>(n);
+  uint32_t *orung = (G == 1 && o0->open_rung) ? o0->open_rung : c.arena->get<uint32_t>(n);
+  uint32_t *frz = (G == 1 && o0->freeze_rung) ? o0->freeze_rung : c.arena->get<uint32_t>(n);
+  bool want_q = false;
+  for (uint32_t i = 0; i < G; ++i) want_q |= outs[i]->q != nullptr;
+  double *q_u = nullptr;
+  if (want_q) q_u = G == 1 ? o0->q : c.arena->get<double>(n);
+
+  // ---- opening loop (Alg. 4, Alg. 5)
   double *qf = c.arena->get<double>(nF ? nF : 1);
-  OpenIn oi{&g, nF, fac_list, fac_idx, p->fac_cost, &ads, perm_key(prm->seed, 1), ceff, nCeff, nUF0, gl,
-            prm->eps, &lad};
-  OpenOut oo{orung, frz, qf};
+  OpenOut oo{orung, frz, qf, {}, {}, {}};
   rc = open_phase(c, oi, oo);
-  if (rc) return rc;
-  out->stats.rungs = oo.rungs;
-  if (out->q) {
-    fill_f64(c, out->q, n, 0.0);
+  if (rc) {
+    for (auto &r : rc_out) r = rc;
+    return;
+  }
+  if (q_u) {
+    fill_f64(c, q_u, n, 0.0);
     if (nF) {
-      k_scatter_q<<<(uint32_t)ceil_div(nF, 256), 256, 0, s>>>(nF, fac_list, qf, out->q);
+      k_scatter_q<<<(uint32_t)ceil_div(nF, 256), 256, 0, s>>>(nF, fac_list, qf, q_u);
       FL_LAUNCH_CHECK();
     }
   }
   FL_HIP(hipEventRecord(ev[4], s));
 
-  // MIS per rung
-  MisIn mi{&g, oo.rungs, &lad, prm->eps, orung, frz, perm_key(prm->seed, 2)};
-  uint32_t mis_rounds = 0;
-  rc = mis_phase(c, mi, out->open, &mis_rounds);
-  if (rc) return rc;
-  out->stats.mis_rounds = mis_rounds;
+  // ---- MIS per rung (Sec. 4.3, Alg. 6)
+  MisIn mi{&g, G, gid, seg, oo.rungs, &lad, eps, orung, frz};
+  std::vector<uint32_t> mis_rounds;
+  rc = mis_phase(c, mi, open_u, mis_rounds);
+  if (rc) {
+    for (auto &r : rc_out) r = rc;
+    return;
+  }
   FL_HIP(hipEventRecord(ev[5], s));
 
-  // assignment and objective (Sec. 3.1)
+  // ---- assignment and objective (Sec. 3.1)
   uint64_t *al = c.arena->get<uint64_t>(n);
-  k_assign_init<<<vb, 256, 0, s>>>(n, out->open, al, flag);
+  k_assign_init<<<vb, 256, 0, s>>>(n, open_u, al, flag);
   FL_LAUNCH_CHECK();
   scan_u32_to_u64(c, flag, pos, n);
   uint32_t *slist = c.arena->get<uint32_t>(n);
@@ -341,24 +520,60 @@ static int solve_one(const fl_problem *p, const fl_params *prm, fl_result *out, 
   c.sync();
   const uint32_t nS = (uint32_t)c.h_status[0];
   sssp_run(c, g, al, slist, nS, wk, 0);
-  fill_u64(c, ctr, 256, 0);
-  k_assign_out<<<vb, 256, 0, s>>>(n, ceff, al, out->open, p->fac_cost, orung, out->assign, out->dist, ctr);
+  uint64_t *actr = c.arena->get<uint64_t>((size_t)G * AO_NFIELD * stripes);
+  fill_u64(c, actr, (size_t)G * AO_NFIELD * stripes, 0);
+  k_assign_out<<<vb, 256, 0, s>>>(n, gid, seg, ceff, al, open_u, fac_cost, orung, assign_u, dist_u, actr,
+                                  stripes);
   FL_LAUNCH_CHECK();
-  read_u64_fields(c, ctr, 3, cs);
-  out->total_cost = cs[0];
-  out->n_open = (uint32_t)cs[1];
-  out->stats.n_guard = (uint32_t)cs[2];
+  if (G > 1) {
+    std::vector<OutDesc> hd(G);
+    uint32_t mx_blocks = 1;
+    for (uint32_t i = 0; i < G; ++i) {
+      fl_result *o = outs[i];
+      hd[i] = OutDesc{o->open, o->assign, o->dist, o->open_rung, o->freeze_rung, o->q, ps[i]->n, hbase[i]};
+      mx_blocks = std::max<uint32_t>(mx_blocks, (uint32_t)ceil_div(ps[i]->n, 256));
+    }
+    OutDesc *dd = c.arena->get<OutDesc>(G);
+    FL_HIP(hipMemcpyAsync(dd, hd.data(), G * sizeof(OutDesc), hipMemcpyHostToDevice, s));
+    k_scatter_out<<<dim3(std::min<uint32_t>(mx_blocks, 1024), G), 256, 0, s>>>(dd, open_u, assign_u, dist_u,
+                                                                               orung, frz, q_u);
+    FL_LAUNCH_CHECK();
+    c.sync();  // hd is read by the copy above
+  }
+  const std::vector<uint64_t> ao = read_seg_ctr(c, actr, G, AO_NFIELD, stripes);
   FL_HIP(hipEventRecord(ev[6], s));
   FL_HIP(hipEventSynchronize(ev[6]));
-  out->stats.ms_validate = ms_between(ev[0], ev[1]);
-  out->stats.ms_ads = ms_between(ev[1], ev[2]);
-  out->stats.ms_gamma = ms_between(ev[2], ev[3]);
-  out->stats.ms_open = ms_between(ev[3], ev[4]);
-  out->stats.ms_mis = ms_between(ev[4], ev[5]);
-  out->stats.ms_assign = ms_between(ev[5], ev[6]);
-  out->stats.ms_total = ms_between(ev[0], ev[6]);
-  out->stats.workspace_bytes = c.arena->used();
-  return FL_OK;
+  for (uint32_t i = 0; i < G; ++i) {
+    fl_result *o = outs[i];
+    if (oo.rc[i] != FL_OK) {
+      rc_out[i] = oo.rc[i];
+      o->n_open = 0;
+      continue;
+    }
+    o->total_cost = ao[i * AO_NFIELD + AO_COST];
+    o->n_open = (uint32_t)ao[i * AO_NFIELD + AO_NOPEN];
+    fl_stats &st = o->stats;
+    st.n_guard = (uint32_t)ao[i * AO_NFIELD + AO_NGUARD];
+    st.relax_alg = relax[i];
+    st.ads_entries = entries[i];
+    st.rungs = oo.rungs[i];
+    st.mis_rounds = mis_rounds[i];
+    // group-wide figures: rounds, executed relaxations and times are those of
+    // the whole union
+    st.ads_rounds = ads.rounds;
+    st.relax_exec = ads.relax_exec;
+    st.ms_ads_kernel = ads.kernel_ms;
+    st.ms_ads_merge = ads.merge_ms;
+    st.ads_kernel_launches = ads.launches;
+    st.ms_validate = ms_between(ev[0], ev[1]);
+    st.ms_ads = ms_between(ev[1], ev[2]);
+    st.ms_gamma = ms_between(ev[2], ev[3]);
+    st.ms_open = ms_between(ev[3], ev[4]);
+    st.ms_mis = ms_between(ev[4], ev[5]);
+    st.ms_assign = ms_between(ev[5], ev[6]);
+    st.ms_total = ms_between(ev[0], ev[6]);
+    st.workspace_bytes = c.arena->used();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -379,6 +594,7 @@ extern "C" {
 
 int fl_solve(const fl_problem *p, const fl_params *prm, fl_result *out, void *stream) {
   if (out) out->n_open = 0;
+  if (out) out->status = FL_EINVAL;
   try {
     if (out) std::memset(&out->stats, 0, sizeof(out->stats));
     int pc = fl::check_params(p, prm);
@@ -386,13 +602,18 @@ int fl_solve(const fl_problem *p, const fl_params *prm, fl_result *out, void *st
     if (!p->fac_cost || !out || !out->open || !out->assign) return FL_EINVAL;
     fl::DeviceCache &dc = fl::cache_for_current();
     std::lock_guard<std::mutex> lk(dc.mu);
-    int rc = fl::solve_one(p, prm, out, (hipStream_t)stream, dc);
-    if (rc != FL_OK && out) out->n_open = 0;
-    return rc;
+    std::vector<int> rc;
+    fl::solve_group(&p, &prm, &out, 1, (hipStream_t)stream, dc, rc);
+    if (rc[0] != FL_OK) out->n_open = 0;
+    out->status = rc[0];
+    return rc[0];
   } catch (fl::Error &e) {
     if (out) out->n_open = 0;
+    if (out) out->status = e.code;
     return e.code;
   } catch (std::bad_alloc &) {
+    if (out) out->n_open = 0;
+    if (out) out->status = FL_ENOMEM;
     return FL_ENOMEM;
   }
 }
@@ -400,12 +621,87 @@ int fl_solve(const fl_problem *p, const fl_params *prm, fl_result *out, void *st
 int fl_solve_batch(const fl_problem *ps, const fl_params *prms, fl_result *outs, uint32_t count,
                    void *stream) {
   if (count && (!ps || !prms || !outs)) return FL_EINVAL;
-  int first = FL_OK;
-  for (uint32_t i = 0; i < count; ++i) {
-    int rc = fl_solve(&ps[i], &prms[i], &outs[i], stream);
-    if (rc != FL_OK && first == FL_OK) first = rc;
+  try {
+    std::vector<int> rc(count, FL_OK);
+    std::vector<uint32_t> ok;
+    for (uint32_t i = 0; i < count; ++i) {
+      outs[i].n_open = 0;
+      outs[i].status = FL_EINVAL;
+      std::memset(&outs[i].stats, 0, sizeof(outs[i].stats));
+      int pc = fl::check_params(&ps[i], &prms[i]);
+      if (!pc && (!ps[i].fac_cost || !outs[i].open || !outs[i].assign)) pc = FL_EINVAL;
+      rc[i] = pc;
+      if (!pc) ok.push_back(i);
+    }
+    fl::DeviceCache &dc = fl::cache_for_current();
+    std::lock_guard<std::mutex> lk(dc.mu);
+    // groups: equal (k, eps, flags); largest graphs first; each group within
+    // a byte budget (sketch rows are sized by the group's largest graph)
+    std::sort(ok.begin(), ok.end(), [&](uint32_t a, uint32_t b) {
+      const fl_params &x = prms[a], &y = prms[b];
+      if (x.k != y.k) return x.k < y.k;
+      if (x.eps != y.eps) return x.eps < y.eps;
+      if (x.flags != y.flags) return x.flags < y.flags;
+      if (ps[a].n != ps[b].n) return ps[a].n > ps[b].n;
+      return a < b;
+    });
+    size_t free_b = 0, total_b = 0;
+    FL_HIP(hipMemGetInfo(&free_b, &total_b));
+    const size_t budget = (size_t)((double)(free_b + dc.arena.capacity()) * 0.6);
+    size_t i0 = 0;
+    while (i0 < ok.size()) {
+      const fl_params &P0 = prms[ok[i0]];
+      size_t i1 = i0;
+      uint64_t N = 0, M = 0;
+      uint32_t nmax = 1;
+      bool wt = false;
+      while (i1 < ok.size()) {
+        const uint32_t j = ok[i1];
+        const fl_params &Pj = prms[j];
+        if (Pj.k != P0.k || Pj.eps != P0.eps || Pj.flags != P0.flags) break;
+        const uint64_t N2 = N + ps[j].n, M2 = M + ps[j].n_arcs;
+        const uint32_t nm2 = std::max(nmax, ps[j].n);
+        const bool wt2 = wt || ps[j].w != nullptr;
+        const uint32_t cap = fl::ads_capacity(nm2, P0.k);
+        const size_t need = fl::estimate_bytes((uint32_t)std::min<uint64_t>(N2, 0xFFFFFFFEull), M2, N2, P0.k, cap,
+                                               wt2 ? 256 : 2) +
+                            fl::union_bytes((uint32_t)(i1 - i0 + 1), N2, M2, wt2);
+        if (i1 > i0 && (need > budget || N2 >= 0x7FFFFFFFull || i1 - i0 >= 65535)) break;
+        N = N2;
+        M = M2;
+        nmax = nm2;
+        wt = wt2;
+        ++i1;
+      }
+      std::vector<const fl_problem *> gp;
+      std::vector<const fl_params *> gr;
+      std::vector<fl_result *> go;
+      for (size_t t = i0; t < i1; ++t) {
+        gp.push_back(&ps[ok[t]]);
+        gr.push_back(&prms[ok[t]]);
+        go.push_back(&outs[ok[t]]);
+      }
+      std::vector<int> grc;
+      try {
+        fl::solve_group(gp.data(), gr.data(), go.data(), (uint32_t)gp.size(), (hipStream_t)stream, dc, grc);
+      } catch (fl::Error &e) {
+        grc.assign(gp.size(), e.code);
+      }
+      for (size_t t = i0; t < i1; ++t) rc[ok[t]] = grc[t - i0];
+      i0 = i1;
+    }
+    int first = FL_OK;
+    for (uint32_t i = 0; i < count; ++i) {
+      outs[i].status = rc[i];
+      if (rc[i] != FL_OK) outs[i].n_open = 0;
+      if (rc[i] != FL_OK && first == FL_OK) first = rc[i];
+    }
+    return first;
+  } catch (fl::Error &e) {
+    return e.code;
+  } catch (std::bad_alloc &) {
+    return FL_ENOMEM;
   }
-  return first;
 }
 
 int fl_ads_build(const fl_problem *p, const fl_params *prm, fl_sketch **out, void *stream) {
@@ -441,7 +737,10 @@ int fl_ads_build(const fl_problem *p, const fl_params *prm, fl_sketch **out, voi
       if (rc) return rc;
     }
     fl::Graph g{n, p->n_arcs, p->row_ptr, p->col, p->w, p->w ? max_w : 1u};
-    fl::AdsConfig acfg{prm->k, prm->seed, prm->flags, n, nullptr, nullptr};
+    fl::SegInfo hseg = fl::seg_info(0, n, prm->seed);
+    fl::SegInfo *seg = c.arena->get<fl::SegInfo>(1);
+    FL_HIP(hipMemcpyAsync(seg, &hseg, sizeof(hseg), hipMemcpyHostToDevice, s));
+    fl::AdsConfig acfg{prm->k, nullptr, seg, prm->flags, n, nullptr, nullptr, n};
     fl::AdsOut ads;
     rc = fl::ads_build(c, g, acfg, ads);
     if (rc) return rc;

@@ -99,6 +99,39 @@ __host__ __device__ inline uint32_t perm_inv(uint32_t r, PermKey k) {
 }
 
 // ---------------------------------------------------------------------------
+// Several independent graphs are solved together as one disjoint union:
+// vertex v of graph g is vertex base + v of the union.  Ranks, priorities and
+// the id buckets of the level prune use the local id with the graph's own
+// keys, and local order is union order inside a graph, so every graph gets
+// exactly the result it gets alone.  A single graph is the union of one
+// (gid == nullptr, base 0).
+// ---------------------------------------------------------------------------
+struct SegInfo {
+  uint32_t base, n;
+  PermKey rk, pk;   // rank (stream 1) and MIS-priority (stream 2) keys
+  uint32_t bshift;  // level-prune id bucket: local id >> bshift < 64
+  uint32_t pad;
+};
+
+struct RankMap {
+  PermKey rk;
+  uint32_t base, bshift;
+};
+__host__ __device__ inline uint32_t seg_of(const uint32_t *gid, uint32_t v) { return gid ? gid[v] : 0u; }
+__host__ __device__ inline RankMap rank_map(const SegInfo &s) { return RankMap{s.rk, s.base, s.bshift}; }
+__host__ __device__ inline uint32_t rank_of(uint32_t id, const RankMap &m) { return perm_fwd(id - m.base, m.rk); }
+__host__ __device__ inline uint32_t id_of(uint32_t r, const RankMap &m) { return perm_inv(r, m.rk) + m.base; }
+__host__ __device__ inline uint32_t bucket_of(uint32_t id, const RankMap &m) { return (id - m.base) >> m.bshift; }
+inline uint32_t bucket_shift(uint32_t n) {
+  uint32_t bits = 0;
+  while (bits < 32 && (1ull << bits) < (uint64_t)n) ++bits;
+  return bits > 6 ? bits - 6 : 0;  // 64 buckets
+}
+inline SegInfo seg_info(uint32_t base, uint32_t n, uint64_t seed) {
+  return SegInfo{base, n, perm_key(seed, 1), perm_key(seed, 2), bucket_shift(n), 0};
+}
+
+// ---------------------------------------------------------------------------
 // Exact sums of HIP-estimator weights.  A weight a = fl(2^32 / T) lies in
 // [1, 2^32], so a * 2^52 is an integer below 2^85.  It is split at bit 40 into
 // hi (< 2^45) and lo (< 2^40); sums of fewer than 2^16 such parts fit in 64
@@ -210,6 +243,39 @@ __device__ inline uint32_t lanes_below(uint64_t mask) {
   return (uint32_t)__popcll(mask & ((1ull << lane_id()) - 1ull));
 }
 
+// Per-graph counters: field f of graph g, stripe s at [(g * nf + f) * stripes + s].
+// Every lane of the wave calls; lanes with valid == false add nothing.  One
+// atomic per wave when the valid lanes share a graph, one per lane otherwise.
+__device__ inline void seg_add(unsigned long long *ctr, bool valid, uint32_t g, uint32_t f, uint32_t nf,
+                               uint32_t stripes, uint64_t v) {
+  const uint64_t vm = __ballot(valid);
+  if (!vm) return;
+  const uint32_t g0 = __shfl(g, __ffsll((long long)vm) - 1, WAVE);
+  if (!__ballot(valid && g != g0)) {
+    const uint64_t tot = wave_sum_u64(valid ? v : 0);
+    if (lane_id() == 0 && tot) atomicAdd(&ctr[((size_t)g0 * nf + f) * stripes + blockIdx.x % stripes], tot);
+  } else if (valid && v) {
+    atomicAdd(&ctr[((size_t)g * nf + f) * stripes], (unsigned long long)v);
+  }
+}
+__device__ inline void seg_max(unsigned long long *ctr, bool valid, uint32_t g, uint32_t f, uint32_t nf,
+                               uint32_t stripes, uint64_t v) {
+  const uint64_t vm = __ballot(valid);
+  if (!vm) return;
+  const uint32_t g0 = __shfl(g, __ffsll((long long)vm) - 1, WAVE);
+  if (!__ballot(valid && g != g0)) {
+    uint64_t mx = valid ? v : 0;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      const uint64_t o = __shfl_xor(mx, d, WAVE);
+      mx = o > mx ? o : mx;
+    }
+    if (lane_id() == 0 && mx) atomicMax(&ctr[((size_t)g0 * nf + f) * stripes + blockIdx.x % stripes], mx);
+  } else if (valid && v) {
+    atomicMax(&ctr[((size_t)g * nf + f) * stripes], (unsigned long long)v);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Host-side helpers
 // ---------------------------------------------------------------------------
@@ -275,10 +341,18 @@ void fill_u64(Ctx &c, uint64_t *p, uint64_t n, uint64_t v);
 void fill_u8(Ctx &c, uint8_t *p, uint64_t n, uint8_t v);
 void fill_f64(Ctx &c, double *p, uint64_t n, double v);
 int validate_graph(Ctx &c, const fl_problem *p, uint32_t *max_w_out, uint32_t *max_cost_out);
+// validates G graphs (one launch each, one readback); rc/max_w/max_cost per graph
+void validate_graphs(Ctx &c, const fl_problem *const *ps, uint32_t G, std::vector<int> &rc,
+                     std::vector<uint32_t> &max_w, std::vector<uint32_t> &max_cost);
+// per-graph sums (or, for the last field with max_last, maxima) of striped
+// device counters laid out as [(g * nf + f) * stripes + s]
+std::vector<uint64_t> read_seg_ctr(Ctx &c, const uint64_t *d, uint32_t G, uint32_t nf, uint32_t stripes,
+                                   bool max_last = false);
 // exclusive scan of u32 counts into u64 offsets (out has n+1 entries)
 void scan_u32_to_u64(Ctx &c, const uint32_t *in, uint64_t *out, uint32_t n);
-// sum_v cnt[v] * deg(v) and sum_v cnt[v]
-void ads_totals(Ctx &c, const Graph &g, const uint32_t *cnt, uint64_t *relax_alg, uint64_t *entries);
+// per graph: sum_v cnt[v] * deg(v) and sum_v cnt[v]
+void ads_totals(Ctx &c, const Graph &g, const uint32_t *gid, uint32_t G, const uint32_t *cnt,
+                std::vector<uint64_t> &relax_alg, std::vector<uint64_t> &entries);
 
 // Multi-source Bellman-Ford with packed 64-bit labels (value << 32 | tie).
 // Labels move along arcs by adding w << 32.  `labels` holds the initial
@@ -286,8 +360,9 @@ void ads_totals(Ctx &c, const Graph &g, const uint32_t *cnt, uint64_t *relax_alg
 // vertices whose label was lowered since the last call (the first frontier).
 struct SsspWork {
   uint32_t *front[2];
-  uint32_t *flag;  // n
+  uint32_t *flag;  // n: iteration stamp of the last frontier a vertex joined
   uint64_t *ctr;   // device counters
+  uint32_t stamp = 0;  // stamps grow across calls on this workspace
 };
 void sssp_alloc(Ctx &c, SsspWork &wk, uint32_t n);
 uint32_t sssp_run(Ctx &c, const Graph &g, uint64_t *labels, const uint32_t *seeds, uint32_t nseeds,

@@ -54,7 +54,7 @@ __device__ inline bool find_arc(const uint64_t *row_ptr, const uint32_t *col, ui
 __global__ __launch_bounds__(256) void k_validate(uint32_t n, uint64_t m, const uint64_t *row_ptr,
                                                   const uint32_t *col, const uint32_t *w,
                                                   const uint32_t *fac_cost, uint32_t *err,
-                                                  uint32_t *maxw, uint32_t *maxc) {
+                                                  uint32_t *maxw, uint32_t *maxc, uint32_t stripes) {
   const int lane = lane_id();
   const uint64_t u64 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
   if (u64 >= n) return;
@@ -76,14 +76,14 @@ __global__ __launch_bounds__(256) void k_validate(uint32_t n, uint64_t m, const 
   }
   if (fac_cost && lane == 0) {
     uint32_t cst = fac_cost[u];
-    if (cst != FL_NOT_FACILITY) atomicMax(&maxc[u % NCTR], cst);
+    if (cst != FL_NOT_FACILITY) atomicMax(&maxc[u % stripes], cst);
   }
   uint64_t anybad = __ballot(bad != 0);
   mw = wave_min_u32(~mw);
   mw = ~mw;  // wave max
   if (lane == 0) {
-    if (anybad) atomicOr(&err[u % NCTR], 1u);
-    if (mw) atomicMax(&maxw[u % NCTR], mw);
+    if (anybad) atomicOr(&err[u % stripes], 1u);
+    if (mw) atomicMax(&maxw[u % stripes], mw);
   }
 }
 
@@ -99,7 +99,7 @@ int validate_graph(Ctx &c, const fl_problem *p, uint32_t *max_w_out, uint32_t *m
   fill_u32(c, d, 3 * NCTR, 0);
   uint64_t blocks = ceil_div((uint64_t)n * WAVE, 256);
   k_validate<<<(uint32_t)blocks, 256, 0, c.s>>>(n, p->n_arcs, p->row_ptr, p->col, p->w, p->fac_cost,
-                                                 d, d + NCTR, d + 2 * NCTR);
+                                                 d, d + NCTR, d + 2 * NCTR, NCTR);
   FL_LAUNCH_CHECK();
   std::vector<uint32_t> h(3 * NCTR);
   FL_HIP(hipMemcpyAsync(h.data(), d, 3 * NCTR * 4, hipMemcpyDeviceToHost, c.s));
@@ -114,6 +114,64 @@ int validate_graph(Ctx &c, const fl_problem *p, uint32_t *max_w_out, uint32_t *m
   *max_w_out = mw;
   *max_cost_out = mc;
   return FL_OK;
+}
+
+// row_ptr[0] == 0 and row_ptr[n] == n_arcs of each graph
+struct EndsDesc {
+  const uint64_t *row_ptr;
+  uint32_t n;
+  uint64_t m;
+};
+__global__ void k_check_ends(const EndsDesc *d, uint32_t G, uint32_t *err) {
+  const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < G && (d[g].row_ptr[0] != 0 || d[g].row_ptr[d[g].n] != d[g].m)) err[3 * g] |= 2u;
+}
+
+void validate_graphs(Ctx &c, const fl_problem *const *ps, uint32_t G, std::vector<int> &rc,
+                     std::vector<uint32_t> &max_w, std::vector<uint32_t> &max_cost) {
+  uint32_t *d = c.arena->get<uint32_t>((size_t)3 * G);
+  EndsDesc *ed = c.arena->get<EndsDesc>(G);
+  std::vector<EndsDesc> hd(G);
+  for (uint32_t g = 0; g < G; ++g) hd[g] = EndsDesc{ps[g]->row_ptr, ps[g]->n, ps[g]->n_arcs};
+  fill_u32(c, d, (size_t)3 * G, 0);
+  FL_HIP(hipMemcpyAsync(ed, hd.data(), G * sizeof(EndsDesc), hipMemcpyHostToDevice, c.s));
+  k_check_ends<<<(uint32_t)ceil_div(G, 256), 256, 0, c.s>>>(ed, G, d);
+  FL_LAUNCH_CHECK();
+  // the row checks read row_ptr only inside [0, n_arcs], whatever its values
+  for (uint32_t g = 0; g < G; ++g) {
+    const fl_problem *p = ps[g];
+    const uint64_t blocks = ceil_div((uint64_t)p->n * WAVE, 256);
+    k_validate<<<(uint32_t)blocks, 256, 0, c.s>>>(p->n, p->n_arcs, p->row_ptr, p->col, p->w, p->fac_cost,
+                                                   d + 3 * g, d + 3 * g + 1, d + 3 * g + 2, 1);
+    FL_LAUNCH_CHECK();
+  }
+  std::vector<uint32_t> h((size_t)3 * G);
+  FL_HIP(hipMemcpyAsync(h.data(), d, h.size() * 4, hipMemcpyDeviceToHost, c.s));
+  c.sync();
+  rc.assign(G, FL_OK);
+  max_w.assign(G, 1);
+  max_cost.assign(G, 0);
+  for (uint32_t g = 0; g < G; ++g) {
+    if (h[3 * g]) rc[g] = FL_EINVAL;
+    max_w[g] = h[3 * g + 1] > 1 ? h[3 * g + 1] : 1u;
+    max_cost[g] = h[3 * g + 2];
+  }
+}
+
+std::vector<uint64_t> read_seg_ctr(Ctx &c, const uint64_t *d, uint32_t G, uint32_t nf, uint32_t stripes,
+                                   bool max_last) {
+  std::vector<uint64_t> h((size_t)G * nf * stripes);
+  FL_HIP(hipMemcpyAsync(h.data(), d, h.size() * 8, hipMemcpyDeviceToHost, c.s));
+  c.sync();
+  std::vector<uint64_t> out((size_t)G * nf, 0);
+  for (size_t i = 0; i < out.size(); ++i) {
+    const bool mx = max_last && (i % nf) == nf - 1;
+    for (uint32_t s = 0; s < stripes; ++s) {
+      const uint64_t x = h[i * stripes + s];
+      out[i] = mx ? (x > out[i] ? x : out[i]) : out[i] + x;
+    }
+  }
+  return out;
 }
 
 // ---------------------------------------------------------------------------
@@ -210,36 +268,35 @@ void scan_u32_to_u64(Ctx &c, const uint32_t *in, uint64_t *out, uint32_t n) {
 // ---------------------------------------------------------------------------
 // sum_v cnt[v] * deg(v) and sum_v cnt[v]
 // ---------------------------------------------------------------------------
-__global__ void k_ads_totals(uint32_t n, const uint64_t *row_ptr, const uint32_t *cnt, uint64_t *ctr) {
-  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_ads_totals(uint32_t n, const uint64_t *row_ptr, const uint32_t *cnt, const uint32_t *gid,
+                             uint64_t *ctr, uint32_t stripes) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = i < n;
   uint64_t r = 0, e = 0;
-  if (i < n) {
+  uint32_t g = 0;
+  if (valid) {
     e = cnt[i];
     r = e * (row_ptr[i + 1] - row_ptr[i]);
+    g = seg_of(gid, (uint32_t)i);
   }
-  r = wave_sum_u64(r);
-  e = wave_sum_u64(e);
-  if (lane_id() == 0) {
-    atomicAdd((unsigned long long *)&ctr[2 * (blockIdx.x % NCTR)], (unsigned long long)r);
-    atomicAdd((unsigned long long *)&ctr[2 * (blockIdx.x % NCTR) + 1], (unsigned long long)e);
-  }
+  seg_add((unsigned long long *)ctr, valid, g, 0, 2, stripes, r);
+  seg_add((unsigned long long *)ctr, valid, g, 1, 2, stripes, e);
 }
 
-void ads_totals(Ctx &c, const Graph &g, const uint32_t *cnt, uint64_t *relax_alg, uint64_t *entries) {
-  uint64_t *ctr = c.arena->get<uint64_t>(2 * NCTR);
-  fill_u64(c, ctr, 2 * NCTR, 0);
-  k_ads_totals<<<(uint32_t)ceil_div(g.n, 256), 256, 0, c.s>>>(g.n, g.row_ptr, cnt, ctr);
+void ads_totals(Ctx &c, const Graph &g, const uint32_t *gid, uint32_t G, const uint32_t *cnt,
+                std::vector<uint64_t> &relax_alg, std::vector<uint64_t> &entries) {
+  const uint32_t stripes = G == 1 ? 64 : 1;
+  uint64_t *ctr = c.arena->get<uint64_t>((size_t)2 * G * stripes);
+  fill_u64(c, ctr, (size_t)2 * G * stripes, 0);
+  k_ads_totals<<<(uint32_t)ceil_div(g.n, 256), 256, 0, c.s>>>(g.n, g.row_ptr, cnt, gid, ctr, stripes);
   FL_LAUNCH_CHECK();
-  std::vector<uint64_t> h(2 * NCTR);
-  FL_HIP(hipMemcpyAsync(h.data(), ctr, h.size() * 8, hipMemcpyDeviceToHost, c.s));
-  c.sync();
-  uint64_t r = 0, e = 0;
-  for (int i = 0; i < NCTR; ++i) {
-    r += h[2 * i];
-    e += h[2 * i + 1];
+  const std::vector<uint64_t> h = read_seg_ctr(c, ctr, G, 2, stripes);
+  relax_alg.resize(G);
+  entries.resize(G);
+  for (uint32_t q = 0; q < G; ++q) {
+    relax_alg[q] = h[2 * q];
+    entries[q] = h[2 * q + 1];
   }
-  *relax_alg = r;
-  *entries = e;
 }
 
 // ---------------------------------------------------------------------------
@@ -294,8 +351,7 @@ void sssp_alloc(Ctx &c, SsspWork &wk, uint32_t n) {
 }
 
 // Runs to the fixed point.  Returns the number of iterations.  Stamps grow
-// monotonically across calls (kept in wk.ctr[0] on the host side copy).
-static uint32_t g_stamp_base = 0;
+// monotonically across the calls on one workspace.
 
 uint32_t sssp_run(Ctx &c, const Graph &g, uint64_t *labels, const uint32_t *seeds, uint32_t nseeds,
                   SsspWork &wk, uint64_t) {
@@ -307,7 +363,7 @@ uint32_t sssp_run(Ctx &c, const Graph &g, uint64_t *labels, const uint32_t *seed
   uint32_t iters = 0, cur = 0;
   uint32_t nf = nseeds;
   while (nf) {
-    const uint32_t stamp = ++g_stamp_base;
+    const uint32_t stamp = ++wk.stamp;
     fill_u32(c, &cnt[cur ^ 1], 1, 0);
     uint64_t waves = nf;
     uint64_t blocks = ceil_div(waves * WAVE, 256);

@@ -14,7 +14,10 @@
 //   3. clients within the radius of a joined facility are covered;
 //   4. active facilities within the radius of a covered client retire.
 // Rounds repeat until no facility is active; the result is the greedy MIS in
-// priority order.  A sweep computes, for every vertex x, the minimum label
+// priority order.  In a union of several graphs, each graph walks through its
+// own non-empty rungs: step i runs the i-th one of every graph at once (the
+// graphs share no vertex, so their sweeps do not interact), each with its own
+// radius and priorities.  A sweep computes, for every vertex x, the minimum label
 // over sources within distance R of x.  It runs in distance order (round j
 // settles labels at distance exactly j) with one pending-label array per
 // distance slot modulo max_w + 1, so a label is forwarded only when it
@@ -31,6 +34,8 @@ namespace fl {
 
 struct SweepArgs {
   uint32_t n, NS;
+  const uint32_t *gid;  // graph of each vertex (nullptr: one graph)
+  const uint32_t *Rg;   // [G] radius of each graph in the current step
   const uint64_t *row_ptr;
   const uint32_t *col;
   const uint32_t *w;
@@ -43,7 +48,8 @@ struct SweepArgs {
 };
 
 // push label lab from x (settled at distance j) to its neighbours
-__device__ inline void sweep_push(const SweepArgs &S, uint32_t x, uint32_t lab, uint32_t j, uint32_t R) {
+__device__ inline void sweep_push(const SweepArgs &S, uint32_t x, uint32_t lab, uint32_t j) {
+  const uint32_t R = S.Rg[seg_of(S.gid, x)];
   const int lane = lane_id();
   const uint64_t a0 = S.row_ptr[x], a1 = S.row_ptr[x + 1];
   for (uint64_t b = a0; b < a1; b += WAVE) {
@@ -83,7 +89,7 @@ __device__ inline void sweep_push(const SweepArgs &S, uint32_t x, uint32_t lab, 
 
 // sources: set ml and push at distance 0 (one wave per source)
 __global__ __launch_bounds__(256) void k_sweep_init(SweepArgs S, const uint32_t *src, uint32_t nsrc,
-                                                    const uint32_t *lab, uint32_t R) {
+                                                    const uint32_t *lab) {
   const uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
   if (i >= nsrc) return;
   const uint32_t x = src[i];
@@ -93,10 +99,10 @@ __global__ __launch_bounds__(256) void k_sweep_init(SweepArgs S, const uint32_t 
     const uint32_t p = atomicAdd(S.touched_cnt, 1u);
     S.touched[p] = x;
   }
-  sweep_push(S, x, l, 0, R);
+  sweep_push(S, x, l, 0);
 }
 
-__global__ __launch_bounds__(256) void k_sweep_round(SweepArgs S, uint32_t j, uint32_t R) {
+__global__ __launch_bounds__(256) void k_sweep_round(SweepArgs S, uint32_t j) {
   const uint32_t slot = j % S.NS;
   const uint32_t cnt = S.tl_cnt[slot];
   const uint64_t wid = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
@@ -114,7 +120,7 @@ __global__ __launch_bounds__(256) void k_sweep_round(SweepArgs S, uint32_t j, ui
           S.touched[p] = y;
         }
       }
-      sweep_push(S, y, v, j, R);
+      sweep_push(S, y, v, j);
     }
   }
 }
@@ -142,7 +148,7 @@ struct MisWork {
 static void sweep(Ctx &c, MisWork &M, const uint32_t *src, uint32_t nsrc, uint32_t R) {
   SweepArgs &S = M.S;
   if (nsrc == 0) return;
-  k_sweep_init<<<(uint32_t)ceil_div((uint64_t)nsrc * WAVE, 256), 256, 0, c.s>>>(S, src, nsrc, M.lab, R);
+  k_sweep_init<<<(uint32_t)ceil_div((uint64_t)nsrc * WAVE, 256), 256, 0, c.s>>>(S, src, nsrc, M.lab);
   FL_LAUNCH_CHECK();
   std::vector<uint32_t> h(S.NS);
   for (uint32_t j = 1; j <= R; ++j) {
@@ -155,7 +161,7 @@ static void sweep(Ctx &c, MisWork &M, const uint32_t *src, uint32_t nsrc, uint32
     const uint32_t cnt = h[slot];
     if (cnt) {
       const uint32_t blocks = (uint32_t)std::min<uint64_t>(ceil_div((uint64_t)cnt * WAVE, 256), 8192);
-      k_sweep_round<<<blocks, 256, 0, c.s>>>(S, j, R);
+      k_sweep_round<<<blocks, 256, 0, c.s>>>(S, j);
       FL_LAUNCH_CHECK();
       fill_u32(c, S.tl_cnt + slot, 1, 0);
     }
@@ -169,9 +175,14 @@ static void sweep_reset(Ctx &c, MisWork &M) {
 }
 
 // ---- small per-round kernels -------------------------------------------------
-__global__ void k_set_key_labels(const uint32_t *list, uint32_t cnt, uint32_t *lab, PermKey pk) {
+__device__ inline uint32_t priority_of(uint32_t f, const uint32_t *gid, const SegInfo *seg) {
+  const SegInfo &sg = seg[seg_of(gid, f)];
+  return perm_fwd(f - sg.base, sg.pk);
+}
+__global__ void k_set_key_labels(const uint32_t *list, uint32_t cnt, uint32_t *lab, const uint32_t *gid,
+                                 const SegInfo *seg) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < cnt) lab[list[i]] = perm_fwd(list[i], pk);
+  if (i < cnt) lab[list[i]] = priority_of(list[i], gid, seg);
 }
 __global__ void k_set_const_labels(const uint32_t *list, uint32_t cnt, uint32_t *lab, uint32_t v) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -201,15 +212,16 @@ __global__ void k_take_pmin(const uint32_t *cl, uint32_t ncl, const uint32_t *ml
   }
 }
 // join test: m(f) = ml[f]; join iff no client (INF) or m(f) == pi(f)
-__global__ void k_join(const uint32_t *act, uint32_t na, const uint32_t *ml, PermKey pk, uint8_t *open,
-                       uint32_t *joined, uint32_t *nj, uint32_t *rest, uint32_t *nr) {
+__global__ void k_join(const uint32_t *act, uint32_t na, const uint32_t *ml, const uint32_t *gid,
+                       const SegInfo *seg, uint8_t *open, uint32_t *joined, uint32_t *nj, uint32_t *rest,
+                       uint32_t *nr) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   bool j = false, r = false;
   uint32_t f = 0;
   if (i < na) {
     f = act[i];
     const uint32_t m = ml[f];
-    j = m == INF32 || m >= perm_fwd(f, pk);
+    j = m == INF32 || m >= priority_of(f, gid, seg);
     r = !j;
     if (j) open[f] = 1;
   }
@@ -244,42 +256,62 @@ __global__ void k_collect_hit(const uint32_t *list, uint32_t cnt, const uint32_t
   }
 }
 
-// per-rung lists: counting sort by rung value
-__global__ void k_rung_count(uint32_t n, const uint32_t *rung, uint32_t T, uint32_t *cnt) {
-  const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n) {
-    const uint32_t t = rung[v];
-    if (t >= 1 && t <= T) atomicAdd(&cnt[t], 1u);
-  }
+// per-(graph, rung) lists: counting sort by key koff[g] + t - 1 (t in 1..T[g])
+__device__ inline bool rung_key(uint32_t v, const uint32_t *rung, const uint32_t *gid, const uint32_t *koff,
+                                const uint32_t *Tg, uint32_t *key) {
+  const uint32_t t = rung[v];
+  const uint32_t g = seg_of(gid, v);
+  if (t < 1 || t > Tg[g]) return false;
+  *key = koff[g] + t - 1;
+  return true;
 }
-__global__ void k_rung_scatter(uint32_t n, const uint32_t *rung, uint32_t T, const uint64_t *off,
-                               uint32_t *cur, uint32_t *out) {
+__global__ void k_rung_count(uint32_t n, const uint32_t *rung, const uint32_t *gid, const uint32_t *koff,
+                             const uint32_t *Tg, uint32_t *cnt) {
   const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n) {
-    const uint32_t t = rung[v];
-    if (t >= 1 && t <= T) out[off[t] + atomicAdd(&cur[t], 1u)] = (uint32_t)v;
-  }
+  uint32_t key;
+  if (v < n && rung_key((uint32_t)v, rung, gid, koff, Tg, &key)) atomicAdd(&cnt[key], 1u);
+}
+__global__ void k_rung_scatter(uint32_t n, const uint32_t *rung, const uint32_t *gid, const uint32_t *koff,
+                               const uint32_t *Tg, const uint64_t *off, uint32_t *cur, uint32_t *out) {
+  const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t key;
+  if (v < n && rung_key((uint32_t)v, rung, gid, koff, Tg, &key)) out[off[key] + atomicAdd(&cur[key], 1u)] = (uint32_t)v;
+}
+// concatenate ranges [src + start, src + start + len) of a list; one block per range
+__global__ void k_gather_ranges(const uint32_t *src, const uint64_t *rstart, const uint32_t *rlen,
+                                const uint64_t *rdst, uint32_t *dst) {
+  const uint32_t r = blockIdx.x;
+  const uint64_t s0 = rstart[r], d0 = rdst[r];
+  for (uint32_t i = threadIdx.x; i < rlen[r]; i += blockDim.x) dst[d0 + i] = src[s0 + i];
+}
+// graphs whose facility of list[i] is active this round
+__global__ void k_mark_graphs(const uint32_t *list, uint32_t cnt, const uint32_t *gid, uint32_t *flag) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) flag[seg_of(gid, list[i])] = 1u;
 }
 __global__ void k_guard_open(uint32_t n, const uint32_t *orung, uint8_t *open) {
   const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v < n) open[v] = orung[v] == FL_RUNG_GUARD ? 1 : 0;
 }
-__global__ void k_open_one(const uint32_t *list, uint8_t *open) { open[list[0]] = 1; }
+__global__ void k_open_list(const uint32_t *list, uint32_t cnt, uint8_t *open) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) open[list[i]] = 1;
+}
 
-static void by_rung(Ctx &c, uint32_t n, const uint32_t *rung, uint32_t T, uint32_t *list,
-                    std::vector<uint64_t> &hoff) {
-  uint32_t *cnt = c.arena->get<uint32_t>((size_t)T + 2);
-  uint32_t *cur = c.arena->get<uint32_t>((size_t)T + 2);
-  uint64_t *off = c.arena->get<uint64_t>((size_t)T + 3);
-  fill_u32(c, cnt, T + 2, 0);
-  fill_u32(c, cur, T + 2, 0);
+static void by_rung(Ctx &c, uint32_t n, const uint32_t *rung, const uint32_t *gid, const uint32_t *koff,
+                    const uint32_t *Tg, uint32_t K, uint32_t *list, std::vector<uint64_t> &hoff) {
+  uint32_t *cnt = c.arena->get<uint32_t>((size_t)K + 1);
+  uint32_t *cur = c.arena->get<uint32_t>((size_t)K + 1);
+  uint64_t *off = c.arena->get<uint64_t>((size_t)K + 2);
+  fill_u32(c, cnt, K + 1, 0);
+  fill_u32(c, cur, K + 1, 0);
   const uint32_t vb = (uint32_t)ceil_div(n, 256);
-  k_rung_count<<<vb, 256, 0, c.s>>>(n, rung, T, cnt);
+  k_rung_count<<<vb, 256, 0, c.s>>>(n, rung, gid, koff, Tg, cnt);
   FL_LAUNCH_CHECK();
-  scan_u32_to_u64(c, cnt, off, T + 2);
-  k_rung_scatter<<<vb, 256, 0, c.s>>>(n, rung, T, off, cur, list);
+  scan_u32_to_u64(c, cnt, off, K);
+  k_rung_scatter<<<vb, 256, 0, c.s>>>(n, rung, gid, koff, Tg, off, cur, list);
   FL_LAUNCH_CHECK();
-  hoff.resize((size_t)T + 3);
+  hoff.resize((size_t)K + 1);
   FL_HIP(hipMemcpyAsync(hoff.data(), off, hoff.size() * 8, hipMemcpyDeviceToHost, c.s));
   c.sync();
 }
@@ -290,23 +322,68 @@ static uint32_t read_u32(Ctx &c, const uint32_t *d) {
   return (uint32_t)(c.h_status[0] & 0xFFFFFFFFu);
 }
 
-int mis_phase(Ctx &c, const MisIn &in, uint8_t *open, uint32_t *rounds_out) {
+// Concatenates host-described ranges of `src` into `dst` on the device;
+// returns the total length.
+struct RangeBuf {
+  uint64_t *start, *dst;
+  uint32_t *len;
+};
+static uint32_t gather(Ctx &c, const uint32_t *src, const std::vector<std::pair<uint64_t, uint32_t>> &rs,
+                       RangeBuf &rb, uint32_t *dst) {
+  if (rs.empty()) return 0;
+  const size_t R = rs.size();
+  std::vector<uint64_t> hs(R), hd(R);
+  std::vector<uint32_t> hl(R);
+  uint64_t tot = 0;
+  for (size_t i = 0; i < R; ++i) {
+    hs[i] = rs[i].first;
+    hl[i] = rs[i].second;
+    hd[i] = tot;
+    tot += rs[i].second;
+  }
+  FL_HIP(hipMemcpyAsync(rb.start, hs.data(), R * 8, hipMemcpyHostToDevice, c.s));
+  FL_HIP(hipMemcpyAsync(rb.dst, hd.data(), R * 8, hipMemcpyHostToDevice, c.s));
+  FL_HIP(hipMemcpyAsync(rb.len, hl.data(), R * 4, hipMemcpyHostToDevice, c.s));
+  k_gather_ranges<<<(uint32_t)R, 256, 0, c.s>>>(src, rb.start, rb.len, rb.dst, dst);
+  FL_LAUNCH_CHECK();
+  c.sync();  // the host vectors are released on return
+  return (uint32_t)tot;
+}
+
+int mis_phase(Ctx &c, const MisIn &in, uint8_t *open, std::vector<uint32_t> &rounds_out) {
   const Graph &g = *in.g;
-  const uint32_t n = g.n, T = in.rungs;
+  const uint32_t n = g.n, G = in.G;
   const uint32_t NS = (g.w ? g.max_w : 1u) + 1;
   k_guard_open<<<(uint32_t)ceil_div(n, 256), 256, 0, c.s>>>(n, in.orung, open);
   FL_LAUNCH_CHECK();
-  *rounds_out = 0;
-  if (T == 0) return FL_OK;
+  rounds_out.assign(G, 0);
+  // keys (graph, rung) -> koff[g] + t - 1
+  std::vector<uint32_t> hkoff(G), hT(G);
+  uint64_t K64 = 0;
+  for (uint32_t q = 0; q < G; ++q) {
+    hkoff[q] = (uint32_t)K64;
+    hT[q] = in.rungs[q];
+    K64 += in.rungs[q];
+  }
+  if (K64 == 0) return FL_OK;
+  if (K64 >= 0xFFFFFFF0ull) return FL_ENOMEM;
+  const uint32_t K = (uint32_t)K64;
+  uint32_t *koff = c.arena->get<uint32_t>(G);
+  uint32_t *Tg = c.arena->get<uint32_t>(G);
+  FL_HIP(hipMemcpyAsync(koff, hkoff.data(), G * 4, hipMemcpyHostToDevice, c.s));
+  FL_HIP(hipMemcpyAsync(Tg, hT.data(), G * 4, hipMemcpyHostToDevice, c.s));
   uint32_t *flist = c.arena->get<uint32_t>(n);
   uint32_t *clist = c.arena->get<uint32_t>(n);
   std::vector<uint64_t> foff, coff;
-  by_rung(c, n, in.orung, T, flist, foff);
-  by_rung(c, n, in.frz, T, clist, coff);
+  by_rung(c, n, in.orung, in.gid, koff, Tg, K, flist, foff);
+  by_rung(c, n, in.frz, in.gid, koff, Tg, K, clist, coff);
 
   MisWork M;
   M.S.n = n;
   M.S.NS = NS;
+  M.S.gid = in.gid;
+  uint32_t *d_R = c.arena->get<uint32_t>(G);
+  M.S.Rg = d_R;
   M.S.row_ptr = g.row_ptr;
   M.S.col = g.col;
   M.S.w = g.w;
@@ -324,39 +401,85 @@ int mis_phase(Ctx &c, const MisIn &in, uint8_t *open, uint32_t *rounds_out) {
   M.cov = c.arena->get<uint32_t>(n);
   M.src = c.arena->get<uint32_t>(n);
   M.cnts = c.arena->get<uint32_t>(8);
+  uint32_t *ct_list = c.arena->get<uint32_t>(n);  // clients of the current step
+  uint32_t *gact = c.arena->get<uint32_t>(G);     // graphs active in a round
+  RangeBuf rb;
+  rb.start = c.arena->get<uint64_t>(G);
+  rb.dst = c.arena->get<uint64_t>(G);
+  rb.len = c.arena->get<uint32_t>(G);
   fill_u32(c, M.S.ml, n, INF32);
   fill_u32(c, M.S.pend, (size_t)NS * n, INF32);
   fill_u32(c, M.S.tl_cnt, NS, 0);
   fill_u32(c, M.S.touched_cnt, 1, 0);
 
-  const double one_eps = 1.0 + in.eps;
-  uint32_t total_rounds = 0;
-  for (uint32_t t = 1; t <= T; ++t) {
-    const uint32_t nf = (uint32_t)(foff[t + 1] - foff[t]);
-    if (nf == 0) continue;
-    const uint32_t *Ft = flist + foff[t];
-    if (nf == 1) {
-      k_open_one<<<1, 1, 0, c.s>>>(Ft, open);
-      FL_LAUNCH_CHECK();
-      total_rounds += 1;
-      continue;
+  // each graph's non-empty rungs, in order
+  std::vector<std::vector<uint32_t>> lists(G);
+  size_t steps = 0;
+  for (uint32_t q = 0; q < G; ++q) {
+    for (uint32_t t = 1; t <= hT[q]; ++t) {
+      const uint32_t key = hkoff[q] + t - 1;
+      if (foff[key + 1] > foff[key]) lists[q].push_back(t);
     }
-    const uint32_t ncl = (uint32_t)(coff[t + 1] - coff[t]);
-    const uint32_t *Ct = clist + coff[t];
-    const double rho = one_eps * (*in.lad)[t];
-    // integer radius: d <= rho  <=>  d <= floor(rho)
-    const uint32_t R = rho >= 4294967295.0 ? 0xFFFFFFFEu : (uint32_t)std::floor(rho);
-    FL_HIP(hipMemcpyAsync(M.act, Ft, (size_t)nf * 4, hipMemcpyDeviceToDevice, c.s));
-    uint32_t na = nf;
-    uint32_t guard_rounds = 0;
-    while (na) {
-      // the active facility of smallest priority joins every round
-      if (++guard_rounds > nf + 1) return FL_EHIP;
-      ++total_rounds;
-      // 1. pi_min at the clients of the rung
-      k_set_key_labels<<<(uint32_t)ceil_div(na, 256), 256, 0, c.s>>>(M.act, na, M.lab, in.pk);
+    steps = std::max(steps, lists[q].size());
+  }
+  const double one_eps = 1.0 + in.eps;
+  std::vector<uint32_t> hR(G, 0), hact(G);
+  std::vector<std::pair<uint64_t, uint32_t>> fr, cr, single;
+  for (size_t i = 0; i < steps; ++i) {
+    fr.clear();
+    cr.clear();
+    single.clear();
+    uint32_t Rmax = 0;
+    std::fill(hR.begin(), hR.end(), 0u);
+    for (uint32_t q = 0; q < G; ++q) {
+      if (i >= lists[q].size()) continue;
+      const uint32_t t = lists[q][i];
+      const uint32_t key = hkoff[q] + t - 1;
+      const uint32_t nf = (uint32_t)(foff[key + 1] - foff[key]);
+      if (nf == 1) {
+        single.push_back({foff[key], 1u});
+        rounds_out[q] += 1;
+        continue;
+      }
+      fr.push_back({foff[key], nf});
+      const uint32_t ncl = (uint32_t)(coff[key + 1] - coff[key]);
+      if (ncl) cr.push_back({coff[key], ncl});
+      const double rho = one_eps * (*in.lad)[q][t];
+      // integer radius: d <= rho  <=>  d <= floor(rho)
+      hR[q] = rho >= 4294967295.0 ? 0xFFFFFFFEu : (uint32_t)std::floor(rho);
+      Rmax = std::max(Rmax, hR[q]);
+    }
+    if (!single.empty()) {
+      const uint32_t ns1 = gather(c, flist, single, rb, M.act);
+      k_open_list<<<(uint32_t)ceil_div(ns1, 256), 256, 0, c.s>>>(M.act, ns1, open);
       FL_LAUNCH_CHECK();
-      sweep(c, M, M.act, na, R);
+    }
+    if (fr.empty()) continue;
+    FL_HIP(hipMemcpyAsync(d_R, hR.data(), G * 4, hipMemcpyHostToDevice, c.s));
+    uint32_t na = gather(c, flist, fr, rb, M.act);
+    const uint32_t ncl = gather(c, clist, cr, rb, ct_list);
+    const uint32_t *Ct = ct_list;
+    uint32_t guard_rounds = 0;
+    uint32_t nf_max = 0;
+    for (auto &r : fr) nf_max = std::max(nf_max, r.second);
+    while (na) {
+      // the active facility of smallest priority of each graph joins every round
+      if (++guard_rounds > nf_max + 1) return FL_EHIP;
+      if (G > 1) {
+        fill_u32(c, gact, G, 0);
+        k_mark_graphs<<<(uint32_t)ceil_div(na, 256), 256, 0, c.s>>>(M.act, na, in.gid, gact);
+        FL_LAUNCH_CHECK();
+        FL_HIP(hipMemcpyAsync(hact.data(), gact, G * 4, hipMemcpyDeviceToHost, c.s));
+      }
+      // 1. pi_min at the clients of the rung
+      k_set_key_labels<<<(uint32_t)ceil_div(na, 256), 256, 0, c.s>>>(M.act, na, M.lab, in.gid, in.seg);
+      FL_LAUNCH_CHECK();
+      sweep(c, M, M.act, na, Rmax);
+      if (G > 1) {
+        for (uint32_t q = 0; q < G; ++q) rounds_out[q] += hact[q];
+      } else {
+        rounds_out[0] += 1;
+      }
       fill_u32(c, M.cnts, 8, 0);
       if (ncl) {
         k_take_pmin<<<(uint32_t)ceil_div(ncl, 256), 256, 0, c.s>>>(Ct, ncl, M.S.ml, M.lab, M.src, M.cnts);
@@ -365,8 +488,8 @@ int mis_phase(Ctx &c, const MisIn &in, uint8_t *open, uint32_t *rounds_out) {
       sweep_reset(c, M);
       const uint32_t ns2 = read_u32(c, M.cnts);
       // 2. smallest pi_min around each active facility; joins
-      sweep(c, M, M.src, ns2, R);
-      k_join<<<(uint32_t)ceil_div(na, 256), 256, 0, c.s>>>(M.act, na, M.S.ml, in.pk, open, M.joined,
+      sweep(c, M, M.src, ns2, Rmax);
+      k_join<<<(uint32_t)ceil_div(na, 256), 256, 0, c.s>>>(M.act, na, M.S.ml, in.gid, in.seg, open, M.joined,
                                                            M.cnts + 1, M.act2, M.cnts + 2);
       FL_LAUNCH_CHECK();
       sweep_reset(c, M);
@@ -378,7 +501,7 @@ int mis_phase(Ctx &c, const MisIn &in, uint8_t *open, uint32_t *rounds_out) {
       // 3. clients covered by a joined facility
       k_set_const_labels<<<(uint32_t)ceil_div(nj, 256), 256, 0, c.s>>>(M.joined, nj, M.lab, 0);
       FL_LAUNCH_CHECK();
-      sweep(c, M, M.joined, nj, R);
+      sweep(c, M, M.joined, nj, Rmax);
       if (ncl) {
         k_collect_hit<<<(uint32_t)ceil_div(ncl, 256), 256, 0, c.s>>>(Ct, ncl, M.S.ml, M.cov, M.cnts + 3, 1);
         FL_LAUNCH_CHECK();
@@ -388,14 +511,13 @@ int mis_phase(Ctx &c, const MisIn &in, uint8_t *open, uint32_t *rounds_out) {
       // 4. facilities next to a covered client retire
       k_set_const_labels<<<(uint32_t)ceil_div(ncov ? ncov : 1, 256), 256, 0, c.s>>>(M.cov, ncov, M.lab, 0);
       FL_LAUNCH_CHECK();
-      sweep(c, M, M.cov, ncov, R);
+      sweep(c, M, M.cov, ncov, Rmax);
       k_collect_hit<<<(uint32_t)ceil_div(nr, 256), 256, 0, c.s>>>(M.act2, nr, M.S.ml, M.act, M.cnts + 4, 0);
       FL_LAUNCH_CHECK();
       sweep_reset(c, M);
       na = read_u32(c, M.cnts + 4);
     }
   }
-  *rounds_out = total_rounds;
   return FL_OK;
 }
 

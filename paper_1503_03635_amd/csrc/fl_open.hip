@@ -20,6 +20,9 @@
 //                 opened in this rung.
 //   freeze kernel (thread per vertex): unfrozen served clients within
 //                 (1 + eps) alpha of an open facility freeze at this rung.
+// Several graphs (a disjoint union) run the loop together: rung t is the same
+// for every graph still running, alpha and the counters are per graph, and a
+// graph leaves the loop when its own stopping rule holds.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -29,12 +32,25 @@
 
 namespace fl {
 
-// status counters, 64-way strided: field f of stripe s at [f * 64 + s]
+// status counters per graph: field f of graph g, stripe s at
+// [(g * OC_NFIELD + f) * stripes + s]
 enum { OC_HEAVY = 0, OC_OPENED, OC_FROZEN, OC_FINITE, OC_NUF_DEC, OC_LIVE, OC_NFIELD };
+
+// per-graph parameters of the current rung
+struct RungParam {
+  double alpha, eps_alpha, ae, a0, a1, rho;
+  uint32_t run;      // the graph evaluates this rung
+  uint32_t frz_prev; // some client of the graph froze in the previous rung
+  uint32_t freeze;   // the freeze kernel runs for the graph (it has open facilities)
+  uint32_t stuck;    // the stall check runs for the graph
+};
 
 struct OpenArgs {
   uint32_t n, nF, cap;
-  PermKey rk;
+  uint32_t stripes;
+  const uint32_t *gid;        // graph of each vertex (nullptr: one graph)
+  const SegInfo *seg;
+  const RungParam *rp;        // [G]
   const uint32_t *fac_list;
   const uint32_t *fac_cost;   // vertex-indexed
   uint32_t *sk_rank;          // live region holds client ids
@@ -56,8 +72,8 @@ struct OpenArgs {
   uint32_t *ctr;              // [OC_NFIELD * 64]
 };
 
-__device__ inline void ctr_add(uint32_t *ctr, int field, uint32_t v) {
-  if (v) atomicAdd(&ctr[field * 64 + (blockIdx.x & 63)], v);
+__device__ inline void ctr_add(const OpenArgs &A, uint32_t g, int field, uint32_t v) {
+  if (v) atomicAdd(&A.ctr[((size_t)g * OC_NFIELD + field) * A.stripes + (blockIdx.x % A.stripes)], v);
 }
 
 // wave-aggregated append of x to list (lanes with want)
@@ -94,37 +110,44 @@ __device__ inline bool try_open(const OpenArgs &A, uint32_t fi, uint32_t f, doub
   return false;
 }
 
-__global__ __launch_bounds__(256) void k_open_light(OpenArgs A, uint32_t t, double alpha, double eps_alpha,
-                                                    int any_freeze_prev) {
+__global__ __launch_bounds__(256) void k_open_light(OpenArgs A, uint32_t t) {
   const uint32_t fi = blockIdx.x * blockDim.x + threadIdx.x;
   bool heavy = false, opened = false, nuf = false;
-  uint32_t f = 0;
+  uint32_t f = 0, g = 0;
   if (fi < A.nF && !A.state[fi]) {
     f = A.fac_list[fi];
-    const uint32_t nx = A.nxt[fi];
-    heavy = (any_freeze_prev && A.nlive[fi] > 0) || (nx != INF32 && (double)nx <= alpha);
-    if (!heavy) {
-      // N unchanged: Eq. 3 with the stored estimate (0 when nothing is live;
-      // at the first rung an empty Eq. 2 sum is 0 as well)
-      const double inc = eps_alpha * A.nhat[fi];
-      const double qn = A.q[fi] + inc;
-      A.q[fi] = qn;
-      opened = try_open(A, fi, f, qn, t);
-      nuf = opened && A.ceff[f] && A.frz[f] == FL_RUNG_NONE;
+    g = seg_of(A.gid, f);
+    const RungParam &R = A.rp[g];
+    if (R.run) {
+      const uint32_t nx = A.nxt[fi];
+      heavy = (R.frz_prev && A.nlive[fi] > 0) || (nx != INF32 && (double)nx <= R.alpha);
+      if (!heavy) {
+        // N unchanged: Eq. 3 with the stored estimate (0 when nothing is live;
+        // at the first rung an empty Eq. 2 sum is 0 as well)
+        const double inc = R.eps_alpha * A.nhat[fi];
+        const double qn = A.q[fi] + inc;
+        A.q[fi] = qn;
+        opened = try_open(A, fi, f, qn, t);
+        nuf = opened && A.ceff[f] && A.frz[f] == FL_RUNG_NONE;
+      }
     }
   }
   wave_append(A.heavy, A.heavy_cnt, heavy, fi);
   wave_append(A.opened, A.opened_cnt, opened, f);
-  const uint32_t no = (uint32_t)__popcll(__ballot(opened));
-  const uint32_t nd = (uint32_t)__popcll(__ballot(nuf));
-  if (lane_id() == 0) {
-    ctr_add(A.ctr, OC_OPENED, no);
-    ctr_add(A.ctr, OC_NUF_DEC, nd);
+  if (A.gid) {
+    if (opened) ctr_add(A, g, OC_OPENED, 1);
+    if (nuf) ctr_add(A, g, OC_NUF_DEC, 1);
+  } else {
+    const uint32_t no = (uint32_t)__popcll(__ballot(opened));
+    const uint32_t nd = (uint32_t)__popcll(__ballot(nuf));
+    if (lane_id() == 0) {
+      ctr_add(A, 0, OC_OPENED, no);
+      ctr_add(A, 0, OC_NUF_DEC, nd);
+    }
   }
 }
 
-__global__ __launch_bounds__(256) void k_open_heavy(OpenArgs A, uint32_t t, double alpha, double eps_alpha,
-                                                    double ae, double a0, double a1, int any_freeze_prev) {
+__global__ __launch_bounds__(256) void k_open_heavy(OpenArgs A, uint32_t t) {
   const int lane = lane_id();
   const uint32_t nh = *A.heavy_cnt;
   const uint64_t wid = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
@@ -132,6 +155,11 @@ __global__ __launch_bounds__(256) void k_open_heavy(OpenArgs A, uint32_t t, doub
   for (uint64_t h = wid; h < nh; h += nw) {
     const uint32_t fi = A.heavy[h];
     const uint32_t f = A.fac_list[fi];
+    const uint32_t g = seg_of(A.gid, f);
+    const RungParam &R = A.rp[g];
+    const RankMap rm = rank_map(A.seg[g]);
+    const double alpha = R.alpha;
+    const int any_freeze_prev = R.frz_prev;
     const size_t base = (size_t)f * A.cap;
     const size_t trow = (size_t)fi * A.cap;
     const uint32_t c = A.cnt[f];
@@ -178,7 +206,7 @@ __global__ __launch_bounds__(256) void k_open_heavy(OpenArgs A, uint32_t t, doub
       bool keep = false;
       uint32_t id = 0, T = 0;
       if (cross) {
-        id = perm_inv(A.sk_rank[base + j], A.rk);
+        id = id_of(A.sk_rank[base + j], rm);
         T = A.thr[trow + j];
         keep = A.ceff[id] && A.frz[id] == FL_RUNG_NONE;
       }
@@ -209,13 +237,13 @@ __global__ __launch_bounds__(256) void k_open_heavy(OpenArgs A, uint32_t t, doub
       if (lane == 0) {
         for (uint32_t i = 0; i < nl; ++i) {
           const double dj = (double)A.sk_dist[base + i];
-          const double b = dj <= a0 ? a0 : a1;
-          s = s + hip_weight(A.thr[trow + i]) * (ae - b);
+          const double b = dj <= R.a0 ? R.a0 : R.a1;
+          s = s + hip_weight(A.thr[trow + i]) * (R.ae - b);
         }
       }
       inc = __shfl(s, 0, WAVE);
     } else {
-      inc = eps_alpha * nh_;
+      inc = R.eps_alpha * nh_;
     }
     if (lane == 0) {
       A.shi[fi] = shi;
@@ -229,8 +257,8 @@ __global__ __launch_bounds__(256) void k_open_heavy(OpenArgs A, uint32_t t, doub
       if (try_open(A, fi, f, qn, t)) {
         const uint32_t p = atomicAdd(A.opened_cnt, 1u);
         A.opened[p] = f;
-        ctr_add(A.ctr, OC_OPENED, 1);
-        if (A.ceff[f] && A.frz[f] == FL_RUNG_NONE) ctr_add(A.ctr, OC_NUF_DEC, 1);
+        ctr_add(A, g, OC_OPENED, 1);
+        if (A.ceff[f] && A.frz[f] == FL_RUNG_NONE) ctr_add(A, g, OC_NUF_DEC, 1);
       }
     }
   }
@@ -245,15 +273,16 @@ __global__ void k_seed_opened(const uint32_t *opened, const uint32_t *cnt, uint6
   }
 }
 
-__global__ __launch_bounds__(256) void k_freeze(OpenArgs A, const uint64_t *dlab, uint32_t t, double rho,
+__global__ __launch_bounds__(256) void k_freeze(OpenArgs A, const uint64_t *dlab, uint32_t t,
                                                 const uint32_t *fac_idx) {
   const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool froze = false, finite = false, nuf = false;
-  if (c < A.n && A.ceff[c] && A.frz[c] == FL_RUNG_NONE) {
+  uint32_t g = 0;
+  if (c < A.n && A.ceff[c] && A.frz[c] == FL_RUNG_NONE && A.rp[g = seg_of(A.gid, (uint32_t)c)].freeze) {
     const uint64_t L = dlab[c];
     if (L != INF64) {
       const uint32_t d = (uint32_t)(L >> 32);
-      if ((double)d <= rho) {
+      if ((double)d <= A.rp[g].rho) {
         A.frz[c] = t;
         froze = true;
         const uint32_t fi = fac_idx[c];
@@ -263,13 +292,19 @@ __global__ __launch_bounds__(256) void k_freeze(OpenArgs A, const uint64_t *dlab
       }
     }
   }
-  const uint32_t a = (uint32_t)__popcll(__ballot(froze));
-  const uint32_t b = (uint32_t)__popcll(__ballot(finite));
-  const uint32_t e = (uint32_t)__popcll(__ballot(nuf));
-  if (lane_id() == 0) {
-    ctr_add(A.ctr, OC_FROZEN, a);
-    ctr_add(A.ctr, OC_FINITE, b);
-    ctr_add(A.ctr, OC_NUF_DEC, e);
+  if (A.gid) {
+    if (froze) ctr_add(A, g, OC_FROZEN, 1);
+    if (finite) ctr_add(A, g, OC_FINITE, 1);
+    if (nuf) ctr_add(A, g, OC_NUF_DEC, 1);
+  } else {
+    const uint32_t a = (uint32_t)__popcll(__ballot(froze));
+    const uint32_t b = (uint32_t)__popcll(__ballot(finite));
+    const uint32_t e = (uint32_t)__popcll(__ballot(nuf));
+    if (lane_id() == 0) {
+      ctr_add(A, 0, OC_FROZEN, a);
+      ctr_add(A, 0, OC_FINITE, b);
+      ctr_add(A, 0, OC_NUF_DEC, e);
+    }
   }
 }
 
@@ -281,48 +316,56 @@ __global__ __launch_bounds__(256) void k_stuck_scan(OpenArgs A) {
   const uint64_t fi = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
   if (fi >= A.nF || A.state[fi]) return;
   const uint32_t f = A.fac_list[fi];
+  const uint32_t g = seg_of(A.gid, f);
+  if (!A.rp[g].stuck) return;
+  const RankMap rm = rank_map(A.seg[g]);
   const size_t base = (size_t)f * A.cap;
   const uint32_t nl = A.nlive[fi], cur = A.cursor[fi], c = A.cnt[f];
   bool live = false;
   for (uint32_t i = lane; i < nl; i += WAVE) live |= A.frz[A.sk_rank[base + i]] == FL_RUNG_NONE;
   for (uint32_t j = cur + lane; j < c; j += WAVE) {
-    const uint32_t id = perm_inv(A.sk_rank[base + j], A.rk);
+    const uint32_t id = id_of(A.sk_rank[base + j], rm);
     live |= A.ceff[id] && A.frz[id] == FL_RUNG_NONE;
   }
-  if (__ballot(live) && lane == 0) atomicAdd(&A.ctr[OC_LIVE * 64], 1u);
+  if (__ballot(live) && lane == 0) atomicAdd(&A.ctr[((size_t)g * OC_NFIELD + OC_LIVE) * A.stripes], 1u);
 }
 
-__global__ void k_guard(uint32_t n, const uint8_t *ceff, uint32_t *frz, uint32_t *orung, const uint64_t *gam) {
+// graphs flagged in gflag[g] & 1: stall guard; & 2: end phase
+__global__ void k_guard(uint32_t n, const uint32_t *gid, const uint8_t *gflag, const uint8_t *ceff, uint32_t *frz,
+                        uint32_t *orung, const uint64_t *gam) {
   const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n || !ceff[c] || frz[c] != FL_RUNG_NONE) return;
+  if (c >= n || !(gflag[seg_of(gid, (uint32_t)c)] & 1) || !ceff[c] || frz[c] != FL_RUNG_NONE) return;
   const uint32_t f = (uint32_t)(gam[c] & 0xFFFFFFFFu);
   orung[f] = FL_RUNG_GUARD;
   frz[c] = FL_RUNG_GUARD;
 }
 
-__global__ void k_endphase(uint32_t n, const uint8_t *ceff, uint32_t *frz) {
+__global__ void k_endphase(uint32_t n, const uint32_t *gid, const uint8_t *gflag, const uint8_t *ceff,
+                           uint32_t *frz) {
   const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < n && ceff[c] && frz[c] == FL_RUNG_NONE) frz[c] = FL_RUNG_END;
+  if (c < n && (gflag[seg_of(gid, (uint32_t)c)] & 2) && ceff[c] && frz[c] == FL_RUNG_NONE) frz[c] = FL_RUNG_END;
 }
 
-static void read_ctr(Ctx &c, const uint32_t *d, uint64_t out[OC_NFIELD]) {
-  std::vector<uint32_t> h(OC_NFIELD * 64);
-  FL_HIP(hipMemcpyAsync(h.data(), d, h.size() * 4, hipMemcpyDeviceToHost, c.s));
+// per-graph sums of the striped counters
+static void read_ctr(Ctx &c, const OpenArgs &A, uint32_t G, std::vector<uint64_t> &out) {
+  std::vector<uint32_t> h((size_t)G * OC_NFIELD * A.stripes);
+  FL_HIP(hipMemcpyAsync(h.data(), A.ctr, h.size() * 4, hipMemcpyDeviceToHost, c.s));
   c.sync();
-  for (int f = 0; f < OC_NFIELD; ++f) {
-    out[f] = 0;
-    for (int s = 0; s < 64; ++s) out[f] += h[f * 64 + s];
-  }
+  out.assign((size_t)G * OC_NFIELD, 0);
+  for (size_t i = 0; i < out.size(); ++i)
+    for (uint32_t s = 0; s < A.stripes; ++s) out[i] += h[i * A.stripes + s];
 }
 
 int open_phase(Ctx &c, const OpenIn &in, OpenOut &out) {
   const Graph &g = *in.g;
-  const uint32_t n = g.n, nF = in.nF;
+  const uint32_t n = g.n, nF = in.nF, G = in.G;
   OpenArgs A{};
   A.n = n;
   A.nF = nF;
   A.cap = in.ads->cap;
-  A.rk = in.rk;
+  A.stripes = G == 1 ? 64 : 1;
+  A.gid = in.gid;
+  A.seg = in.seg;
   A.fac_list = in.fac_list;
   A.fac_cost = in.fac_cost;
   A.sk_rank = in.ads->sk_rank;
@@ -345,7 +388,10 @@ int open_phase(Ctx &c, const OpenIn &in, OpenOut &out) {
   uint32_t *cnts = c.arena->get<uint32_t>(2);
   A.heavy_cnt = cnts;
   A.opened_cnt = cnts + 1;
-  A.ctr = c.arena->get<uint32_t>(OC_NFIELD * 64);
+  A.ctr = c.arena->get<uint32_t>((size_t)G * OC_NFIELD * A.stripes);
+  RungParam *d_rp = c.arena->get<RungParam>(G);
+  A.rp = d_rp;
+  uint8_t *d_gflag = c.arena->get<uint8_t>(G);
   uint64_t *dlab = c.arena->get<uint64_t>(n);
   fill_u64(c, dlab, n, INF64);
   fill_u32(c, out.frz, n, FL_RUNG_NONE);
@@ -357,71 +403,126 @@ int open_phase(Ctx &c, const OpenIn &in, OpenOut &out) {
   SsspWork wk;
   sssp_alloc(c, wk, n);
 
-  std::vector<double> &lad = *in.lad;
   const double one_eps = 1.0 + in.eps;
-  uint32_t nO = 0, t = 0, nguard = 0;
-  uint64_t nU = in.nCeff, nUF = in.nUF0, finite_unfrozen = 0;
-  bool any_freeze_prev = false;
+  // host state per graph
+  std::vector<uint64_t> nO(G, 0), nU(in.nCeff), nUF(in.nUF0), finite_unfrozen(G, 0);
+  std::vector<uint8_t> frz_prev(G, 0), done(G, 0), gflag(G, 0);
+  std::vector<RungParam> rp(G);
+  out.rungs.assign(G, 0);
+  out.rc.assign(G, FL_OK);
+  for (uint32_t q = 0; q < G; ++q) done[q] = !(nO[q] < in.nF_g[q] && nU[q] > 0);
+  uint32_t t = 0;
   const uint32_t fblocks = (uint32_t)ceil_div(nF ? nF : 1, 256);
   const uint32_t hblocks = (uint32_t)std::min<uint64_t>(ceil_div((uint64_t)(nF ? nF : 1) * WAVE, 256), 4096);
   const uint32_t vblocks = (uint32_t)ceil_div(n, 256);
-  uint64_t ctr[OC_NFIELD];
-  while (nO < nF && nU > 0) {
-    if (finite_unfrozen == 0 && nUF == 0) {
-      // stall check
-      fill_u32(c, A.ctr, OC_NFIELD * 64, 0);
-      k_stuck_scan<<<(uint32_t)ceil_div((uint64_t)nF * WAVE, 256), 256, 0, c.s>>>(A);
-      FL_LAUNCH_CHECK();
-      read_ctr(c, A.ctr, ctr);
-      if (ctr[OC_LIVE] == 0) {
-        k_guard<<<vblocks, 256, 0, c.s>>>(n, in.ceff, out.frz, out.orung, in.gam_lab);
-        FL_LAUNCH_CHECK();
-        nU = 0;
-        break;
-      }
+  std::vector<uint64_t> ctr;
+  auto upload = [&]() {
+    FL_HIP(hipMemcpyAsync(d_rp, rp.data(), G * sizeof(RungParam), hipMemcpyHostToDevice, c.s));
+  };
+  for (;;) {
+    // stall check for the running graphs with nothing in reach
+    bool any_stuck = false;
+    for (uint32_t q = 0; q < G; ++q) {
+      rp[q] = RungParam{};
+      rp[q].stuck = !done[q] && finite_unfrozen[q] == 0 && nUF[q] == 0;
+      any_stuck |= rp[q].stuck != 0;
     }
+    if (any_stuck) {
+      upload();
+      fill_u32(c, A.ctr, (size_t)G * OC_NFIELD * A.stripes, 0);
+      k_stuck_scan<<<(uint32_t)ceil_div((uint64_t)(nF ? nF : 1) * WAVE, 256), 256, 0, c.s>>>(A);
+      FL_LAUNCH_CHECK();
+      read_ctr(c, A, G, ctr);
+      for (uint32_t q = 0; q < G; ++q)
+        if (rp[q].stuck && ctr[(size_t)q * OC_NFIELD + OC_LIVE] == 0) {
+          gflag[q] |= 1;  // stall guard
+          nU[q] = 0;
+          done[q] = 1;
+        }
+    }
+    bool any = false;
+    for (uint32_t q = 0; q < G; ++q) any |= !done[q];
+    if (!any) break;
     ++t;
-    while (lad.size() <= t) lad.push_back(lad.back() * one_eps);
-    const double alpha = lad[t];
-    if (!std::isfinite(alpha)) return FL_ERANGE;
-    const double eps_alpha = in.eps * alpha;
-    const double ae = one_eps * alpha;
+    for (uint32_t q = 0; q < G; ++q) {
+      RungParam &R = rp[q];
+      R = RungParam{};
+      if (done[q]) continue;
+      std::vector<double> &lad = (*in.lad)[q];
+      while (lad.size() <= t) lad.push_back(lad.back() * one_eps);
+      const double alpha = lad[t];
+      if (!std::isfinite(alpha)) {
+        out.rc[q] = FL_ERANGE;
+        done[q] = 1;
+        continue;
+      }
+      R.alpha = alpha;
+      R.eps_alpha = in.eps * alpha;
+      R.ae = one_eps * alpha;
+      R.a0 = lad[0];
+      R.a1 = lad[1];
+      R.rho = one_eps * alpha;
+      R.run = 1;
+      R.frz_prev = frz_prev[q];
+      out.rungs[q] = t;
+    }
+    upload();
     fill_u32(c, cnts, 2, 0);
-    fill_u32(c, A.ctr, OC_NFIELD * 64, 0);
-    k_open_light<<<fblocks, 256, 0, c.s>>>(A, t, alpha, eps_alpha, any_freeze_prev ? 1 : 0);
+    fill_u32(c, A.ctr, (size_t)G * OC_NFIELD * A.stripes, 0);
+    k_open_light<<<fblocks, 256, 0, c.s>>>(A, t);
     FL_LAUNCH_CHECK();
-    k_open_heavy<<<hblocks, 256, 0, c.s>>>(A, t, alpha, eps_alpha, ae, lad[0], lad[1],
-                                           any_freeze_prev ? 1 : 0);
+    k_open_heavy<<<hblocks, 256, 0, c.s>>>(A, t);
     FL_LAUNCH_CHECK();
-    read_ctr(c, A.ctr, ctr);
-    const uint32_t opened = (uint32_t)ctr[OC_OPENED];
-    nUF -= ctr[OC_NUF_DEC];
+    read_ctr(c, A, G, ctr);
+    uint64_t opened = 0;
+    bool any_freeze = false;
+    for (uint32_t q = 0; q < G; ++q) {
+      if (!rp[q].run) continue;
+      const uint64_t o = ctr[(size_t)q * OC_NFIELD + OC_OPENED];
+      opened += o;
+      nO[q] += o;
+      nUF[q] -= ctr[(size_t)q * OC_NFIELD + OC_NUF_DEC];
+      frz_prev[q] = 0;
+      rp[q].freeze = nO[q] > 0;
+      any_freeze |= rp[q].freeze != 0;
+    }
     if (opened) {
-      nO += opened;
       k_seed_opened<<<(uint32_t)ceil_div(opened, 256), 256, 0, c.s>>>(A.opened, A.opened_cnt, dlab);
       FL_LAUNCH_CHECK();
-      sssp_run(c, g, dlab, A.opened, opened, wk, 0);
+      sssp_run(c, g, dlab, A.opened, (uint32_t)opened, wk, 0);
     }
-    any_freeze_prev = false;
-    if (nO > 0) {
-      const double rho = one_eps * alpha;
-      fill_u32(c, A.ctr, OC_NFIELD * 64, 0);
-      k_freeze<<<vblocks, 256, 0, c.s>>>(A, dlab, t, rho, in.fac_idx);
+    if (any_freeze) {
+      upload();
+      fill_u32(c, A.ctr, (size_t)G * OC_NFIELD * A.stripes, 0);
+      k_freeze<<<vblocks, 256, 0, c.s>>>(A, dlab, t, in.fac_idx);
       FL_LAUNCH_CHECK();
-      read_ctr(c, A.ctr, ctr);
-      nU -= ctr[OC_FROZEN];
-      nUF -= ctr[OC_NUF_DEC];
-      finite_unfrozen = ctr[OC_FINITE];
-      any_freeze_prev = ctr[OC_FROZEN] > 0;
+      read_ctr(c, A, G, ctr);
+      for (uint32_t q = 0; q < G; ++q) {
+        if (!rp[q].freeze) continue;
+        const uint64_t *cq = &ctr[(size_t)q * OC_NFIELD];
+        nU[q] -= cq[OC_FROZEN];
+        nUF[q] -= cq[OC_NUF_DEC];
+        finite_unfrozen[q] = cq[OC_FINITE];
+        frz_prev[q] = cq[OC_FROZEN] > 0;
+      }
     }
+    for (uint32_t q = 0; q < G; ++q)
+      if (rp[q].run && !(nO[q] < in.nF_g[q] && nU[q] > 0)) done[q] = 1;
   }
-  out.rungs = t;
   out.nO = nO;
-  if (nO == nF && nU > 0) {
-    k_endphase<<<vblocks, 256, 0, c.s>>>(n, in.ceff, out.frz);
-    FL_LAUNCH_CHECK();
+  bool any_flag = false;
+  for (uint32_t q = 0; q < G; ++q) {
+    if (nO[q] == in.nF_g[q] && nU[q] > 0 && out.rc[q] == FL_OK) gflag[q] |= 2;  // end phase
+    any_flag |= gflag[q] != 0;
   }
-  (void)nguard;
+  if (any_flag) {
+    FL_HIP(hipMemcpyAsync(d_gflag, gflag.data(), G, hipMemcpyHostToDevice, c.s));
+    k_guard<<<vblocks, 256, 0, c.s>>>(n, in.gid, d_gflag, in.ceff, out.frz, out.orung, in.gam_lab);
+    FL_LAUNCH_CHECK();
+    k_endphase<<<vblocks, 256, 0, c.s>>>(n, in.gid, d_gflag, in.ceff, out.frz);
+    FL_LAUNCH_CHECK();
+    c.sync();  // gflag is read by the copy above
+  }
   // q by vertex for the caller's diagnostics is scattered later
   return FL_OK;
 }
