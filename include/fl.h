@@ -79,6 +79,12 @@ typedef struct {
 } fl_params;
 
 #define FL_FLAG_NO_DENSE 1u  /* always use frontier worklists in the ADS rounds */
+#define FL_FLAG_LUBY_MIS 2u  /* Luby's MIS variant (the baseline the paper compares
+                                against, Sec. 5.4): the same rounds as Alg. 6, but
+                                round r of a rung draws fresh priorities, a
+                                bijection of the local id keyed by
+                                SplitMix64(seed ^ (3 + 256 r)).  A maximal
+                                independent set, in general not the greedy one. */
 
 /* ---- statistics ---------------------------------------------------------- */
 typedef struct {
@@ -142,6 +148,39 @@ int fl_solve(const fl_problem *p, const fl_params *prm, fl_result *out, void *st
  */
 int fl_solve_batch(const fl_problem *ps, const fl_params *prms, fl_result *outs, uint32_t count,
                    void *stream);
+
+/* ---- serving: continuous batching ------------------------------------------
+ * A server solves requests as they arrive.  It owns `slots` workers on the
+ * current device, each with its own stream and workspace.  A free worker takes
+ * the oldest waiting request together with later waiting ones of equal k, eps
+ * and flags, as many as fit the device-memory budget, and solves them as one
+ * group (the disjoint union of fl_solve_batch).  Requests that arrive while
+ * others are on the GPU wait until a worker and memory free up; work of
+ * different workers overlaps on the device.  Every result equals fl_solve of
+ * the same request alone.
+ *
+ * The caller keeps each request's problem, params and result (and the device
+ * buffers they point to) alive until fl_server_poll reports it finished or
+ * fl_server_wait returns for it.  The server keeps no pointer afterwards.
+ */
+typedef struct fl_server fl_server;
+
+/* hbm_budget_bytes: device memory the workers' workspaces may hold together
+ * (0 = 60% of the free memory); slots: workers (0 = 3).  FL_EINVAL if a
+ * request alone can never fit is reported per request at submission. */
+int fl_server_create(uint64_t hbm_budget_bytes, uint32_t slots, fl_server **out);
+/* Queues one request; *ticket identifies it.  FL_EINVAL for bad arguments,
+ * FL_ENOMEM if the request alone exceeds the budget, FL_EBUSY if the server is
+ * shutting down. */
+int fl_server_submit(fl_server *s, const fl_problem *p, const fl_params *prm, fl_result *out, uint64_t *ticket);
+/* FL_OK with *status = the request's code when it has finished (the ticket is
+ * then retired), FL_EBUSY while it is queued or running, FL_EINVAL for an
+ * unknown ticket. */
+int fl_server_poll(fl_server *s, uint64_t ticket, int *status);
+/* Blocks until the request finishes; then as fl_server_poll. */
+int fl_server_wait(fl_server *s, uint64_t ticket, int *status);
+/* Finishes every queued and running request, then frees the server. */
+void fl_server_destroy(fl_server *s);
 
 /* ---- sketches (Sec. 3.3) --------------------------------------------------- */
 typedef struct fl_sketch fl_sketch;

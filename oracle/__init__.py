@@ -84,6 +84,7 @@ def _setup(L):
     L.orc_prune.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32]
     L.orc_hipest.argtypes = [C.POINTER(_Sketch), C.c_uint32, C.c_uint32, C.c_void_p, C.c_void_p]
     L.orc_solve.argtypes = [C.POINTER(_Graph), C.c_uint32, C.c_uint64, C.c_double, C.POINTER(_Result)]
+    L.orc_solve_luby.argtypes = [C.POINTER(_Graph), C.c_uint32, C.c_uint64, C.c_double, C.POINTER(_Result)]
     L.orc_opt_exhaustive.argtypes = [C.POINTER(_Graph), C.POINTER(C.c_uint64)]
     L.orc_sssp.argtypes = [C.POINTER(_Graph), C.c_uint32, C.c_void_p]
     L.orc_ladder.argtypes = [C.c_double, C.c_double, C.c_uint32, C.c_void_p]
@@ -229,8 +230,9 @@ def hipest(sk, k):
     return T[:tot], a[:tot]
 
 
-def solve(g, k, seed, eps=0.1):
-    """Full facility-location solve.  Returns (rc, dict)."""
+def solve(g, k, seed, eps=0.1, luby=False):
+    """Full facility-location solve (luby=True: Luby's MIS variant with
+    priorities redrawn every round).  Returns (rc, dict)."""
     n = g.n
     h = _Held(g)
     res = {
@@ -240,7 +242,8 @@ def solve(g, k, seed, eps=0.1):
     }
     r = _Result(_ptr(res["open"]), _ptr(res["assign"]), _ptr(res["dist"]),
                 _ptr(res["open_rung"]), _ptr(res["freeze_rung"]), _ptr(res["q"]))
-    rc = int(lib().orc_solve(C.byref(h.s), k, seed, eps, C.byref(r)))
+    fn = lib().orc_solve_luby if luby else lib().orc_solve
+    rc = int(fn(C.byref(h.s), k, seed, eps, C.byref(r)))
     for name in ("total_cost", "n_open", "n_unreachable", "n_rungs", "mis_rounds", "n_guard",
                  "relax_alg", "ads_entries", "gamma", "alpha0", "one_eps"):
         res[name] = getattr(r, name)

@@ -707,7 +707,21 @@ static int ball(const orc_graph *g, uint32_t s, double rho, uint64_t *dist, uint
   return ORC_OK;
 }
 
+/* Luby's variant of the MIS (the baseline of Sec. 5.4): the same rounds, but
+ * round r of a rung (r = 1, 2, ...) draws fresh priorities, a bijection keyed
+ * by SplitMix64(seed ^ (3 + 256 r)). */
+static uint64_t luby_key(uint64_t seed, uint32_t r) { return orc_splitmix64(seed ^ (3ull + 256ull * r)); }
+
+static int solve_impl(const orc_graph *g, uint32_t k, uint64_t seed, double eps, int luby, orc_result *r);
+
 int orc_solve(const orc_graph *g, uint32_t k, uint64_t seed, double eps, orc_result *r) {
+  return solve_impl(g, k, seed, eps, 0, r);
+}
+int orc_solve_luby(const orc_graph *g, uint32_t k, uint64_t seed, double eps, orc_result *r) {
+  return solve_impl(g, k, seed, eps, 1, r);
+}
+
+static int solve_impl(const orc_graph *g, uint32_t k, uint64_t seed, double eps, int luby, orc_result *r) {
   int rc = orc_validate(g, k, eps);
   if (r) r->n_open = 0;
   if (rc != ORC_OK) return rc;
@@ -955,20 +969,23 @@ int orc_solve(const orc_graph *g, uint32_t k, uint64_t seed, double eps, orc_res
         if (gsel[j] && adj[(size_t)i * m + j]) ok = 0;
       gsel[i] = (uint8_t)ok;
     }
-    /* fixed-priority parallel rounds: an active facility joins when no active
-     * neighbour has a smaller priority; joined facilities retire their
-     * neighbours */
+    /* parallel rounds: an active facility joins when no active neighbour
+     * has a smaller priority (this round's priority for Luby's variant);
+     * joined facilities retire their neighbours */
     uint8_t *act = (uint8_t *)malloc(m), *psel = (uint8_t *)calloc(m, 1), *join = (uint8_t *)malloc(m);
+    uint32_t *pr = (uint32_t *)malloc((size_t)m * sizeof(uint32_t));
     memset(act, 1, m);
     uint32_t nact = m, rounds = 0;
     while (nact) {
       rounds++;
+      for (uint32_t i = 0; i < m; i++)
+        pr[i] = luby ? orc_perm(fac[i], luby_key(seed, rounds)) : prio[fac[i]];
       for (uint32_t i = 0; i < m; i++) {
         join[i] = 0;
         if (!act[i]) continue;
         int mn = 1;
-        for (uint32_t j = 0; j < i && mn; j++) /* fac sorted by priority */
-          if (act[j] && adj[(size_t)i * m + j]) mn = 0;
+        for (uint32_t j = 0; j < m && mn; j++)
+          if (j != i && act[j] && adj[(size_t)i * m + j] && pr[j] < pr[i]) mn = 0;
         join[i] = (uint8_t)mn;
       }
       for (uint32_t i = 0; i < m; i++)
@@ -981,11 +998,12 @@ int orc_solve(const orc_graph *g, uint32_t k, uint64_t seed, double eps, orc_res
     }
     mis_rounds += rounds;
     for (uint32_t i = 0; i < m; i++) {
-      if (gsel[i] != psel[i]) return ORC_EINTERNAL;
-      if (gsel[i]) inS[fac[i]] = 1;
+      /* fixed priorities: the rounds give the greedy set (checked) */
+      if (!luby && gsel[i] != psel[i]) return ORC_EINTERNAL;
+      if (psel[i]) inS[fac[i]] = 1;
     }
     for (uint32_t i = 0; i < m; i++) free(cl[i]);
-    free(cl); free(ncl); free(adj); free(gsel); free(act); free(psel); free(join); free(fac);
+    free(cl); free(ncl); free(adj); free(gsel); free(act); free(psel); free(join); free(fac); free(pr);
   }
   r->mis_rounds = mis_rounds;
   for (uint32_t f = 0; f < n; f++)

@@ -13,12 +13,12 @@ from typing import Optional
 import torch
 
 from . import _lib
-from ._lib import (FL_FLAG_NO_DENSE, FL_NONE, FL_NOT_FACILITY, FL_RUNG_END, FL_RUNG_GUARD,
+from ._lib import (FL_FLAG_LUBY_MIS, FL_FLAG_NO_DENSE, FL_NONE, FL_NOT_FACILITY, FL_RUNG_END, FL_RUNG_GUARD,
                    FL_RUNG_NONE, FlError, lib)
 
-__all__ = ["DeviceGraph", "to_device", "solve", "solve_batch", "ads_build", "rank_of", "priority_of",
+__all__ = ["DeviceGraph", "to_device", "solve", "solve_batch", "Server", "ads_build", "rank_of", "priority_of",
            "FlError", "FL_NONE", "FL_NOT_FACILITY", "FL_RUNG_NONE", "FL_RUNG_GUARD", "FL_RUNG_END",
-           "FL_FLAG_NO_DENSE", "lib"]
+           "FL_FLAG_NO_DENSE", "FL_FLAG_LUBY_MIS", "lib"]
 
 
 @dataclass
@@ -143,6 +143,74 @@ def solve_batch(dgs, k, seed, eps=0.1, flags=0, diagnostics=False, stream=None, 
     if rc != _lib.FL_OK and check:
         raise FlError(rc, "fl_solve_batch")
     return outs
+
+
+class Server:
+    """Continuous-batching solve server (fl_server_*): submit() queues a
+    request and returns a ticket; wait()/poll() return the result dict.  The
+    request's structs and output tensors are kept alive here until then."""
+
+    def __init__(self, hbm_budget_bytes: int = 0, slots: int = 0):
+        h = C.c_void_p()
+        rc = lib().fl_server_create(hbm_budget_bytes, slots, C.byref(h))
+        if rc != _lib.FL_OK:
+            raise FlError(rc, "fl_server_create")
+        self._h = h
+        self._live = {}
+        import threading
+        self._lock = threading.Lock()
+
+    def submit(self, dg: DeviceGraph, k: int, seed: int, eps: float = 0.1, flags: int = 0,
+               diagnostics: bool = False, outputs=None) -> int:
+        device = dg.col.device if dg.n_arcs else dg.row_ptr.device
+        out = outputs if outputs is not None else _alloc_outputs(dg.n, device, diagnostics)
+        torch.cuda.synchronize(device)  # inputs and outputs ready before another stream reads them
+        prob = _problem(dg)
+        prm = _lib.FlParams(k, seed, eps, flags)
+        res = _result_struct(out)
+        t = C.c_uint64()
+        rc = lib().fl_server_submit(self._h, C.byref(prob), C.byref(prm), C.byref(res), C.byref(t))
+        if rc != _lib.FL_OK:
+            raise FlError(rc, "fl_server_submit")
+        with self._lock:
+            self._live[t.value] = (dg, prob, prm, res, out)
+        return t.value
+
+    def _finish(self, ticket, st):
+        with self._lock:
+            dg, prob, prm, res, out = self._live.pop(ticket)
+        out["rc"] = st
+        _collect(res, out)
+        return out
+
+    def wait(self, ticket: int):
+        st = C.c_int()
+        rc = lib().fl_server_wait(self._h, ticket, C.byref(st))
+        if rc != _lib.FL_OK:
+            raise FlError(rc, "fl_server_wait")
+        return self._finish(ticket, st.value)
+
+    def poll(self, ticket: int):
+        """The result dict when finished, else None."""
+        st = C.c_int()
+        rc = lib().fl_server_poll(self._h, ticket, C.byref(st))
+        if rc == _lib.FL_EBUSY:
+            return None
+        if rc != _lib.FL_OK:
+            raise FlError(rc, "fl_server_poll")
+        return self._finish(ticket, st.value)
+
+    def close(self):
+        if self._h:
+            lib().fl_server_destroy(self._h)
+            self._h = None
+            self._live.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
 
 
 def ads_build(dg: DeviceGraph, k: int, seed: int, flags: int = 0, stream=None):

@@ -18,6 +18,7 @@ FL_RUNG_NONE = 0xFFFFFFFF
 FL_RUNG_GUARD = 0xFFFFFFFE
 FL_RUNG_END = 0xFFFFFFFD
 FL_FLAG_NO_DENSE = 1
+FL_FLAG_LUBY_MIS = 2
 
 
 class FlProblem(C.Structure):
@@ -65,6 +66,12 @@ SIGNATURES = {
     "fl_strerror": (C.c_char_p, [C.c_int]),
     "fl_last_hip_error": (C.c_int, []),
     "fl_release_workspace": (None, []),
+    "fl_server_create": (C.c_int, [C.c_uint64, C.c_uint32, C.POINTER(C.c_void_p)]),
+    "fl_server_submit": (C.c_int, [C.c_void_p, C.POINTER(FlProblem), C.POINTER(FlParams), C.POINTER(FlResult),
+                                   C.POINTER(C.c_uint64)]),
+    "fl_server_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_int)]),
+    "fl_server_wait": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_int)]),
+    "fl_server_destroy": (None, [C.c_void_p]),
 }
 
 _lib = None

@@ -7,6 +7,10 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <thread>
+#include <unordered_map>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -47,6 +51,11 @@ struct DeviceCache {
   std::mutex mu;
   Arena arena;
   uint64_t *h_status = nullptr;
+  void release_all() {
+    arena.release();
+    if (h_status) (void)hipHostFree(h_status);
+    h_status = nullptr;
+  }
 };
 static DeviceCache g_cache[64];
 
@@ -499,7 +508,7 @@ static void solve_group(const fl_problem *const *ps, const fl_params *const *pr,
   FL_HIP(hipEventRecord(ev[4], s));
 
   // ---- MIS per rung (Sec. 4.3, Alg. 6)
-  MisIn mi{&g, G, gid, seg, oo.rungs, &lad, eps, orung, frz};
+  MisIn mi{&g, G, gid, seg, oo.rungs, &lad, eps, orung, frz, (flags & FL_FLAG_LUBY_MIS) != 0};
   std::vector<uint32_t> mis_rounds;
   rc = mis_phase(c, mi, open_u, mis_rounds);
   if (rc) {
@@ -575,6 +584,171 @@ static void solve_group(const fl_problem *const *ps, const fl_params *const *pr,
     st.workspace_bytes = c.arena->used();
   }
 }
+
+// ---------------------------------------------------------------------------
+// serving: continuous batching over worker slots
+// ---------------------------------------------------------------------------
+struct Request {
+  const fl_problem *p;
+  const fl_params *prm;
+  fl_result *out;
+  uint64_t ticket;
+  size_t bytes;  // workspace of this request alone
+  int status = FL_EBUSY;
+  bool done = false;
+};
+
+struct Server;
+struct Slot {
+  Server *srv = nullptr;
+  DeviceCache dc;
+  hipStream_t stream = nullptr;
+  size_t cap = 0;  // workspace bytes this slot holds
+  bool busy = false;
+  std::thread th;
+};
+
+struct Server {
+  int device = 0;
+  size_t budget = 0;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Request *> queue;
+  std::unordered_map<uint64_t, Request *> reqs;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  std::vector<Slot *> slots;
+};
+
+static size_t group_bytes(const std::vector<Request *> &b) {
+  uint64_t N = 0, M = 0;
+  uint32_t nmax = 1;
+  bool wt = false;
+  for (const Request *r : b) {
+    N += r->p->n;
+    M += r->p->n_arcs;
+    nmax = std::max(nmax, r->p->n);
+    wt |= r->p->w != nullptr;
+  }
+  const uint32_t k = b[0]->prm->k;
+  return estimate_bytes((uint32_t)std::min<uint64_t>(N, 0xFFFFFFFEull), M, N, k, ads_capacity(nmax, k),
+                        wt ? MAX_W + 1 : 2) +
+         union_bytes((uint32_t)b.size(), N, M, wt);
+}
+
+static bool same_group(const Request *a, const Request *b) {
+  return a->prm->k == b->prm->k && a->prm->eps == b->prm->eps && a->prm->flags == b->prm->flags;
+}
+
+static void slot_main(Slot *sl) {
+  Server &S = *sl->srv;
+  (void)hipSetDevice(S.device);
+  for (;;) {
+    std::vector<Request *> batch;
+    size_t need = 0;
+    {
+      std::unique_lock<std::mutex> lk(S.mu);
+      for (;;) {
+        if (S.queue.empty()) {
+          if (S.stop) return;
+          S.cv_work.wait(lk);
+          continue;
+        }
+        // the oldest request, then later ones of the same group while the
+        // budget allows.  Workspaces of running slots count against the
+        // budget; idle slots give theirs up when the room is needed.
+        Request *head = S.queue.front();
+        batch.assign(1, head);
+        need = group_bytes(batch);
+        size_t running = 0;
+        for (Slot *x : S.slots)
+          if (x != sl && x->busy) running += x->cap;
+        if (running + need > S.budget && running > 0) {
+          S.cv_work.wait(lk);  // wait for a running slot to finish
+          continue;
+        }
+        for (size_t i = 1; i < S.queue.size() && batch.size() < 4096; ++i) {
+          Request *r = S.queue[i];
+          if (!same_group(head, r)) continue;
+          batch.push_back(r);
+          const size_t nb = group_bytes(batch);
+          if (running + nb > S.budget) {
+            batch.pop_back();
+            continue;
+          }
+          need = nb;
+        }
+        for (Request *r : batch)
+          for (auto it = S.queue.begin(); it != S.queue.end(); ++it)
+            if (*it == r) {
+              S.queue.erase(it);
+              break;
+            }
+        // make room: this slot's workspace grows to `need` (or is dropped
+        // and rebuilt), idle slots release theirs while the total is over
+        size_t total = running + std::max(need, sl->cap);
+        for (Slot *x : S.slots) {
+          if (total <= S.budget) break;
+          if (x == sl || x->busy || x->cap == 0) continue;
+          std::lock_guard<std::mutex> xl(x->dc.mu);
+          x->dc.arena.release();
+          total -= x->cap;
+          x->cap = 0;
+        }
+        if (total > S.budget && sl->cap > need) {
+          sl->dc.arena.release();
+          sl->cap = 0;
+        }
+        sl->busy = true;
+        sl->cap = std::max(need, sl->cap);
+        break;
+      }
+    }
+    std::vector<const fl_problem *> ps;
+    std::vector<const fl_params *> pr;
+    std::vector<fl_result *> os;
+    for (Request *r : batch) {
+      ps.push_back(r->p);
+      pr.push_back(r->prm);
+      os.push_back(r->out);
+      r->out->n_open = 0;
+      std::memset(&r->out->stats, 0, sizeof(r->out->stats));
+    }
+    std::vector<int> rc;
+    try {
+      std::lock_guard<std::mutex> lk(sl->dc.mu);
+      sl->dc.arena.reserve(need);
+      solve_group(ps.data(), pr.data(), os.data(), (uint32_t)batch.size(), sl->stream, sl->dc, rc);
+    } catch (Error &e) {
+      rc.assign(batch.size(), e.code);
+    } catch (std::bad_alloc &) {
+      rc.assign(batch.size(), FL_ENOMEM);
+    }
+    {
+      std::lock_guard<std::mutex> lk(S.mu);
+      // the workspace may have grown past the estimate
+      sl->cap = sl->dc.arena.capacity();
+      sl->busy = false;
+      for (size_t i = 0; i < batch.size(); ++i) {
+        Request *r = batch[i];
+        r->status = rc[i];
+        r->out->status = rc[i];
+        if (rc[i] != FL_OK) r->out->n_open = 0;
+        r->done = true;
+      }
+    }
+    S.cv_done.notify_all();
+    S.cv_work.notify_all();
+  }
+}
+
+}  // namespace fl
+
+struct fl_server {
+  fl::Server s;
+};
+
+namespace fl {
 
 // ---------------------------------------------------------------------------
 // sketches for export
@@ -812,6 +986,111 @@ const char *fl_strerror(int code) {
 }
 
 int fl_last_hip_error(void) { return fl::g_last_hip.load(); }
+
+int fl_server_create(uint64_t hbm_budget_bytes, uint32_t slots, fl_server **out) {
+  if (!out) return FL_EINVAL;
+  *out = nullptr;
+  try {
+    fl_server *sv = new fl_server();
+    fl::Server &S = sv->s;
+    FL_HIP(hipGetDevice(&S.device));
+    if (hbm_budget_bytes == 0) {
+      size_t fr = 0, tot = 0;
+      FL_HIP(hipMemGetInfo(&fr, &tot));
+      hbm_budget_bytes = (uint64_t)((double)fr * 0.6);
+    }
+    S.budget = (size_t)hbm_budget_bytes;
+    const uint32_t ns = slots ? slots : 3u;
+    for (uint32_t i = 0; i < ns; ++i) {
+      fl::Slot *sl = new fl::Slot();
+      sl->srv = &S;
+      FL_HIP(hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking));
+      fl::ensure_host_status(sl->dc);
+      S.slots.push_back(sl);
+    }
+    for (fl::Slot *sl : S.slots) sl->th = std::thread(fl::slot_main, sl);
+    *out = sv;
+    return FL_OK;
+  } catch (fl::Error &e) {
+    return e.code;
+  } catch (std::bad_alloc &) {
+    return FL_ENOMEM;
+  }
+}
+
+int fl_server_submit(fl_server *sv, const fl_problem *p, const fl_params *prm, fl_result *out, uint64_t *ticket) {
+  if (!sv || !ticket) return FL_EINVAL;
+  int pc = fl::check_params(p, prm);
+  if (pc) return pc;
+  if (!p->fac_cost || !out || !out->open || !out->assign) return FL_EINVAL;
+  fl::Server &S = sv->s;
+  fl::Request *r = new fl::Request();
+  r->p = p;
+  r->prm = prm;
+  r->out = out;
+  std::vector<fl::Request *> one(1, r);
+  r->bytes = fl::group_bytes(one);
+  if (r->bytes > S.budget) {
+    delete r;
+    return FL_ENOMEM;
+  }
+  {
+    std::lock_guard<std::mutex> lk(S.mu);
+    if (S.stop) {
+      delete r;
+      return FL_EBUSY;
+    }
+    r->ticket = S.next_ticket++;
+    S.reqs[r->ticket] = r;
+    S.queue.push_back(r);
+    *ticket = r->ticket;
+  }
+  S.cv_work.notify_one();
+  return FL_OK;
+}
+
+static int server_finish(fl::Server &S, uint64_t ticket, int *status, bool block) {
+  std::unique_lock<std::mutex> lk(S.mu);
+  auto it = S.reqs.find(ticket);
+  if (it == S.reqs.end()) return FL_EINVAL;
+  fl::Request *r = it->second;
+  while (!r->done) {
+    if (!block) return FL_EBUSY;
+    S.cv_done.wait(lk);
+  }
+  if (status) *status = r->status;
+  S.reqs.erase(it);
+  delete r;
+  return FL_OK;
+}
+
+int fl_server_poll(fl_server *sv, uint64_t ticket, int *status) {
+  if (!sv) return FL_EINVAL;
+  return server_finish(sv->s, ticket, status, false);
+}
+
+int fl_server_wait(fl_server *sv, uint64_t ticket, int *status) {
+  if (!sv) return FL_EINVAL;
+  return server_finish(sv->s, ticket, status, true);
+}
+
+void fl_server_destroy(fl_server *sv) {
+  if (!sv) return;
+  fl::Server &S = sv->s;
+  {
+    std::lock_guard<std::mutex> lk(S.mu);
+    S.stop = true;
+  }
+  S.cv_work.notify_all();
+  for (fl::Slot *sl : S.slots) {
+    if (sl->th.joinable()) sl->th.join();
+    (void)hipStreamDestroy(sl->stream);
+    sl->dc.release_all();
+    delete sl;
+  }
+  for (auto &kv : S.reqs) delete kv.second;
+  delete sv;
+}
 
 void fl_release_workspace(void) {
   try {

@@ -111,6 +111,7 @@ struct SegInfo {
   PermKey rk, pk;   // rank (stream 1) and MIS-priority (stream 2) keys
   uint32_t bshift;  // level-prune id bucket: local id >> bshift < 64
   uint32_t pad;
+  uint64_t seed;    // the graph's seed (Luby's MIS draws per-round keys from it)
 };
 
 struct RankMap {
@@ -128,7 +129,7 @@ inline uint32_t bucket_shift(uint32_t n) {
   return bits > 6 ? bits - 6 : 0;  // 64 buckets
 }
 inline SegInfo seg_info(uint32_t base, uint32_t n, uint64_t seed) {
-  return SegInfo{base, n, perm_key(seed, 1), perm_key(seed, 2), bucket_shift(n), 0};
+  return SegInfo{base, n, perm_key(seed, 1), perm_key(seed, 2), bucket_shift(n), 0, seed};
 }
 
 // ---------------------------------------------------------------------------
@@ -257,6 +258,25 @@ __device__ inline void seg_add(unsigned long long *ctr, bool valid, uint32_t g, 
   } else if (valid && v) {
     atomicAdd(&ctr[((size_t)g * nf + f) * stripes], (unsigned long long)v);
   }
+}
+__device__ inline void seg_add32(uint32_t *ctr, bool valid, uint32_t g, uint32_t f, uint32_t nf, uint32_t stripes,
+                                 uint32_t v) {
+  const uint64_t vm = __ballot(valid);
+  if (!vm) return;
+  const uint32_t g0 = __shfl(g, __ffsll((long long)vm) - 1, WAVE);
+  if (!__ballot(valid && g != g0)) {
+    const uint32_t tot = (uint32_t)wave_sum_u64(valid ? v : 0);
+    if (lane_id() == 0 && tot) atomicAdd(&ctr[((size_t)g0 * nf + f) * stripes + blockIdx.x % stripes], tot);
+  } else if (valid && v) {
+    atomicAdd(&ctr[((size_t)g * nf + f) * stripes], v);
+  }
+}
+__device__ inline uint32_t wave_max_u32(uint32_t x) { return ~wave_min_u32(~x); }
+// rows up to this many arcs are walked by their own lane; longer rows by the whole wave
+constexpr uint32_t LIGHT_DEG = 16;
+__device__ inline uint64_t shfl_u64(uint64_t x, int src) {
+  const uint32_t lo = __shfl((uint32_t)x, src, WAVE), hi = __shfl((uint32_t)(x >> 32), src, WAVE);
+  return ((uint64_t)hi << 32) | lo;
 }
 __device__ inline void seg_max(unsigned long long *ctr, bool valid, uint32_t g, uint32_t f, uint32_t nf,
                                uint32_t stripes, uint64_t v) {

@@ -307,36 +307,60 @@ void ads_totals(Ctx &c, const Graph &g, const uint32_t *gid, uint32_t G, const u
 // the iteration number).  The fixed point is the lexicographic minimum over
 // sources of (init value + distance, tie).
 // ---------------------------------------------------------------------------
+// one arc step (every lane calls, converged): relax arc a with label L
+__device__ inline void sssp_arc(const uint32_t *col, const uint32_t *w, uint64_t *labels, bool valid, uint64_t a,
+                                uint64_t L, uint32_t *next, uint32_t *nnext, uint32_t *stamp, uint32_t iter) {
+  bool add = false;
+  uint32_t y = 0;
+  if (valid) {
+    y = col[a];
+    const uint64_t nl = L + ((uint64_t)(w ? w[a] : 1u) << 32);
+    if (nl < __hip_atomic_load(&labels[y], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+      const uint64_t old = atomicMin((unsigned long long *)&labels[y], (unsigned long long)nl);
+      if (nl < old) add = atomicMax(&stamp[y], iter) < iter;
+    }
+  }
+  const uint64_t mask = __ballot(add);
+  if (mask) {
+    uint32_t base = 0;
+    if (lane_id() == 0) base = atomicAdd(nnext, (uint32_t)__popcll(mask));
+    base = __shfl(base, 0, WAVE);
+    if (add) next[base + lanes_below(mask)] = y;
+  }
+}
+
+// One lane per frontier vertex; short rows are walked lane-parallel (step i
+// takes the i-th arc of every short row), long rows by the whole wave.
 __global__ __launch_bounds__(256) void k_sssp_push(const uint64_t *row_ptr, const uint32_t *col,
                                                    const uint32_t *w, uint64_t *labels,
                                                    const uint32_t *front, const uint32_t *nfront,
                                                    uint32_t *next, uint32_t *nnext, uint32_t *stamp,
                                                    uint32_t iter) {
   const int lane = lane_id();
-  const uint64_t wid = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
-  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / WAVE;
   const uint32_t nf = *nfront;
-  for (uint64_t i = wid; i < nf; i += nwaves) {
-    const uint32_t v = front[i];
-    const uint64_t L = __hip_atomic_load(&labels[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint64_t a0 = row_ptr[v], a1 = row_ptr[v + 1];
-    for (uint64_t b = a0; b < a1; b += WAVE) {
-      const uint64_t a = b + lane;
-      bool add = false;
-      uint32_t y = 0;
-      if (a < a1) {
-        y = col[a];
-        const uint64_t nl = L + ((uint64_t)(w ? w[a] : 1u) << 32);
-        const uint64_t old = atomicMin((unsigned long long *)&labels[y], (unsigned long long)nl);
-        if (nl < old) add = atomicMax(&stamp[y], iter) < iter;
-      }
-      const uint64_t mask = __ballot(add);
-      if (mask) {
-        uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(nnext, (uint32_t)__popcll(mask));
-        base = __shfl(base, 0, WAVE);
-        if (add) next[base + lanes_below(mask)] = y;
-      }
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x; b < nf; b += stride) {
+    const uint64_t i = b + threadIdx.x;
+    const bool want = i < nf;
+    uint64_t a0 = 0, a1 = 0, L = 0;
+    if (want) {
+      const uint32_t v = front[i];
+      L = __hip_atomic_load(&labels[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      a0 = row_ptr[v];
+      a1 = row_ptr[v + 1];
+    }
+    const uint64_t deg = a1 - a0;
+    const bool light = want && deg <= LIGHT_DEG;
+    const uint32_t dmax = wave_max_u32(light ? (uint32_t)deg : 0u);
+    for (uint32_t k = 0; k < dmax; ++k)
+      sssp_arc(col, w, labels, light && k < deg, a0 + k, L, next, nnext, stamp, iter);
+    uint64_t hm = __ballot(want && !light);
+    while (hm) {
+      const int h = __ffsll((long long)hm) - 1;
+      hm &= hm - 1;
+      const uint64_t b0 = shfl_u64(a0, h), b1 = shfl_u64(a1, h), Lh = shfl_u64(L, h);
+      for (uint64_t c = b0; c < b1; c += WAVE)
+        sssp_arc(col, w, labels, c + lane < b1, c + lane, Lh, next, nnext, stamp, iter);
     }
   }
 }
@@ -363,19 +387,24 @@ uint32_t sssp_run(Ctx &c, const Graph &g, uint64_t *labels, const uint32_t *seed
   uint32_t iters = 0, cur = 0;
   uint32_t nf = nseeds;
   while (nf) {
-    const uint32_t stamp = ++wk.stamp;
-    fill_u32(c, &cnt[cur ^ 1], 1, 0);
-    uint64_t waves = nf;
-    uint64_t blocks = ceil_div(waves * WAVE, 256);
+    // The kernel reads the frontier size on the device, so small frontiers
+    // run several iterations per host check (an empty frontier costs one
+    // short launch); large ones are checked after every iteration.
+    const uint32_t burst = nf > 65536 ? 1u : 8u;
+    uint64_t blocks = ceil_div((uint64_t)nf * (burst > 1 ? 4 : 1), 256);
     if (blocks > 16384) blocks = 16384;
-    k_sssp_push<<<(uint32_t)blocks, 256, 0, c.s>>>(g.row_ptr, g.col, g.w, labels, wk.front[cur], &cnt[cur],
-                                                    wk.front[cur ^ 1], &cnt[cur ^ 1], wk.flag, stamp);
-    FL_LAUNCH_CHECK();
-    FL_HIP(hipMemcpyAsync(c.h_status, &cnt[cur ^ 1], 4, hipMemcpyDeviceToHost, c.s));
+    for (uint32_t b = 0; b < burst; ++b) {
+      const uint32_t stamp = ++wk.stamp;
+      fill_u32(c, &cnt[cur ^ 1], 1, 0);
+      k_sssp_push<<<(uint32_t)blocks, 256, 0, c.s>>>(g.row_ptr, g.col, g.w, labels, wk.front[cur], &cnt[cur],
+                                                      wk.front[cur ^ 1], &cnt[cur ^ 1], wk.flag, stamp);
+      FL_LAUNCH_CHECK();
+      cur ^= 1;
+      ++iters;
+    }
+    FL_HIP(hipMemcpyAsync(c.h_status, &cnt[cur], 4, hipMemcpyDeviceToHost, c.s));
     c.sync();
     nf = (uint32_t)(c.h_status[0] & 0xFFFFFFFFu);
-    cur ^= 1;
-    ++iters;
   }
   return iters;
 }

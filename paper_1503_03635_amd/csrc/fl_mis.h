@@ -16,6 +16,7 @@ struct MisIn {
   double eps;
   const uint32_t *orung;  // [n]
   const uint32_t *frz;    // [n]
+  bool luby;              // Luby's variant: priorities redrawn every round
 };
 
 // rounds_out[g]: MIS rounds of graph g, summed over its rungs

@@ -47,16 +47,15 @@ struct SweepArgs {
   uint32_t *touched_cnt;
 };
 
-// push label lab from x (settled at distance j) to its neighbours
-__device__ inline void sweep_push(const SweepArgs &S, uint32_t x, uint32_t lab, uint32_t j) {
-  const uint32_t R = S.Rg[seg_of(S.gid, x)];
+// One arc step of a push (every lane calls, converged; lanes with valid ==
+// false have no arc this step): lower the pending label of the arc's head at
+// distance j + w when that is within R, and queue the head once per slot.
+__device__ inline void sweep_arc(const SweepArgs &S, bool valid, uint64_t a, uint32_t lab, uint32_t j, uint32_t R) {
   const int lane = lane_id();
-  const uint64_t a0 = S.row_ptr[x], a1 = S.row_ptr[x + 1];
-  for (uint64_t b = a0; b < a1; b += WAVE) {
-    const uint64_t a = b + lane;
+  {
     bool add = false;
     uint32_t y = 0, s = 0;
-    if (a < a1) {
+    if (valid) {
       y = S.col[a];
       const uint32_t wv = S.w ? S.w[a] : 1u;
       if ((uint64_t)j + wv <= R) {
@@ -87,41 +86,81 @@ __device__ inline void sweep_push(const SweepArgs &S, uint32_t x, uint32_t lab, 
   }
 }
 
-// sources: set ml and push at distance 0 (one wave per source)
-__global__ __launch_bounds__(256) void k_sweep_init(SweepArgs S, const uint32_t *src, uint32_t nsrc,
-                                                    const uint32_t *lab) {
-  const uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
-  if (i >= nsrc) return;
-  const uint32_t x = src[i];
-  const uint32_t l = lab[x];
-  if (lane_id() == 0 && l != INF32) {
-    S.ml[x] = l;
-    const uint32_t p = atomicAdd(S.touched_cnt, 1u);
-    S.touched[p] = x;
+// Push the label of each lane's vertex (want) from distance j.  Short rows:
+// step i takes the i-th arc of every short row; long rows: the whole wave
+// walks one row at a time.
+__device__ inline void sweep_push_lanes(const SweepArgs &S, bool want, uint32_t x, uint32_t lab, uint32_t j) {
+  const int lane = lane_id();
+  uint64_t a0 = 0, a1 = 0;
+  uint32_t R = 0;
+  if (want) {
+    a0 = S.row_ptr[x];
+    a1 = S.row_ptr[x + 1];
+    R = S.Rg[seg_of(S.gid, x)];
   }
-  sweep_push(S, x, l, 0);
+  const uint64_t deg = a1 - a0;
+  const bool light = want && deg <= LIGHT_DEG;
+  const uint32_t dmax = wave_max_u32(light ? (uint32_t)deg : 0u);
+  for (uint32_t i = 0; i < dmax; ++i) sweep_arc(S, light && i < deg, a0 + i, lab, j, R);
+  uint64_t hm = __ballot(want && !light);
+  while (hm) {
+    const int h = __ffsll((long long)hm) - 1;
+    hm &= hm - 1;
+    const uint64_t b0 = shfl_u64(a0, h), b1 = shfl_u64(a1, h);
+    const uint32_t lb = __shfl(lab, h, WAVE), Rb = __shfl(R, h, WAVE);
+    for (uint64_t b = b0; b < b1; b += WAVE) sweep_arc(S, b + lane < b1, b + lane, lb, j, Rb);
+  }
 }
 
+// vertices whose ml was set for the first time -> touched (one atomic per wave)
+__device__ inline void touch(const SweepArgs &S, bool first, uint32_t x) {
+  const uint64_t m = __ballot(first);
+  if (!m) return;
+  const int lead = __ffsll((long long)m) - 1;
+  uint32_t base = 0;
+  if (lane_id() == lead) base = atomicAdd(S.touched_cnt, (uint32_t)__popcll(m));
+  base = __shfl(base, lead, WAVE);
+  if (first) S.touched[base + lanes_below(m)] = x;
+}
+
+// sources: set ml and push at distance 0 (one lane per source)
+__global__ __launch_bounds__(256) void k_sweep_init(SweepArgs S, const uint32_t *src, uint32_t nsrc,
+                                                    const uint32_t *lab) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool want = false;
+  uint32_t x = 0, l = INF32;
+  if (i < nsrc) {
+    x = src[i];
+    l = lab[x];
+    want = l != INF32;
+    if (want) S.ml[x] = l;
+  }
+  touch(S, want, x);
+  sweep_push_lanes(S, want, x, l, 0);
+}
+
+// distance j: settle the pending labels of slot j (one lane per vertex)
 __global__ __launch_bounds__(256) void k_sweep_round(SweepArgs S, uint32_t j) {
   const uint32_t slot = j % S.NS;
   const uint32_t cnt = S.tl_cnt[slot];
-  const uint64_t wid = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
-  const uint64_t nw = ((uint64_t)gridDim.x * blockDim.x) / WAVE;
-  for (uint64_t i = wid; i < cnt; i += nw) {
-    const uint32_t y = S.tl[(size_t)slot * S.n + i];
-    const uint32_t v = S.pend[(size_t)slot * S.n + y];
-    const uint32_t cur = S.ml[y];
-    if (lane_id() == 0) S.pend[(size_t)slot * S.n + y] = INF32;
-    if (v < cur) {
-      if (lane_id() == 0) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x; b < cnt; b += stride) {
+    const uint64_t i = b + threadIdx.x;
+    bool want = false, first = false;
+    uint32_t y = 0, v = INF32;
+    if (i < cnt) {
+      y = S.tl[(size_t)slot * S.n + i];
+      v = S.pend[(size_t)slot * S.n + y];
+      const uint32_t cur = S.ml[y];
+      S.pend[(size_t)slot * S.n + y] = INF32;
+      if (v < cur) {
         S.ml[y] = v;
-        if (cur == INF32) {
-          const uint32_t p = atomicAdd(S.touched_cnt, 1u);
-          S.touched[p] = y;
-        }
+        want = true;
+        first = cur == INF32;
       }
-      sweep_push(S, y, v, j);
     }
+    touch(S, first, y);
+    sweep_push_lanes(S, want, y, v, j);
   }
 }
 
@@ -148,22 +187,29 @@ struct MisWork {
 static void sweep(Ctx &c, MisWork &M, const uint32_t *src, uint32_t nsrc, uint32_t R) {
   SweepArgs &S = M.S;
   if (nsrc == 0) return;
-  k_sweep_init<<<(uint32_t)ceil_div((uint64_t)nsrc * WAVE, 256), 256, 0, c.s>>>(S, src, nsrc, M.lab);
+  k_sweep_init<<<(uint32_t)ceil_div((uint64_t)nsrc, 256), 256, 0, c.s>>>(S, src, nsrc, M.lab);
   FL_LAUNCH_CHECK();
   std::vector<uint32_t> h(S.NS);
-  for (uint32_t j = 1; j <= R; ++j) {
+  uint32_t j = 1;
+  while (j <= R) {
     FL_HIP(hipMemcpyAsync(h.data(), S.tl_cnt, S.NS * 4, hipMemcpyDeviceToHost, c.s));
     c.sync();
     uint64_t pending = 0;
-    for (uint32_t s = 0; s < S.NS; ++s) pending += h[s];
+    uint32_t hmax = 0;
+    for (uint32_t s = 0; s < S.NS; ++s) {
+      pending += h[s];
+      hmax = std::max(hmax, h[s]);
+    }
     if (!pending) break;
-    const uint32_t slot = j % S.NS;
-    const uint32_t cnt = h[slot];
-    if (cnt) {
-      const uint32_t blocks = (uint32_t)std::min<uint64_t>(ceil_div((uint64_t)cnt * WAVE, 256), 8192);
+    // k_sweep_round reads its slot's count on the device: small rounds run
+    // several distances per host check
+    const uint32_t burst = hmax > 65536 ? 1u : 8u;
+    const uint32_t blocks =
+        (uint32_t)std::min<uint64_t>(std::max<uint64_t>(ceil_div((uint64_t)hmax * 2, 256), 4), 8192);
+    for (uint32_t b = 0; b < burst && j <= R; ++b, ++j) {
       k_sweep_round<<<blocks, 256, 0, c.s>>>(S, j);
       FL_LAUNCH_CHECK();
-      fill_u32(c, S.tl_cnt + slot, 1, 0);
+      fill_u32(c, S.tl_cnt + j % S.NS, 1, 0);
     }
   }
 }
@@ -175,14 +221,18 @@ static void sweep_reset(Ctx &c, MisWork &M) {
 }
 
 // ---- small per-round kernels -------------------------------------------------
-__device__ inline uint32_t priority_of(uint32_t f, const uint32_t *gid, const SegInfo *seg) {
+// Priority of facility f: the fixed one (luby_round == 0), or for Luby's
+// variant the one drawn for round r of the rung, a bijection keyed by
+// SplitMix64(seed ^ (3 + 256 r)).
+__device__ inline uint32_t priority_of(uint32_t f, const uint32_t *gid, const SegInfo *seg, uint32_t luby_round) {
   const SegInfo &sg = seg[seg_of(gid, f)];
-  return perm_fwd(f - sg.base, sg.pk);
+  const PermKey key = luby_round ? perm_key(sg.seed, 3ull + 256ull * luby_round) : sg.pk;
+  return perm_fwd(f - sg.base, key);
 }
 __global__ void k_set_key_labels(const uint32_t *list, uint32_t cnt, uint32_t *lab, const uint32_t *gid,
-                                 const SegInfo *seg) {
+                                 const SegInfo *seg, uint32_t luby_round) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < cnt) lab[list[i]] = priority_of(list[i], gid, seg);
+  if (i < cnt) lab[list[i]] = priority_of(list[i], gid, seg, luby_round);
 }
 __global__ void k_set_const_labels(const uint32_t *list, uint32_t cnt, uint32_t *lab, uint32_t v) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -213,15 +263,15 @@ __global__ void k_take_pmin(const uint32_t *cl, uint32_t ncl, const uint32_t *ml
 }
 // join test: m(f) = ml[f]; join iff no client (INF) or m(f) == pi(f)
 __global__ void k_join(const uint32_t *act, uint32_t na, const uint32_t *ml, const uint32_t *gid,
-                       const SegInfo *seg, uint8_t *open, uint32_t *joined, uint32_t *nj, uint32_t *rest,
-                       uint32_t *nr) {
+                       const SegInfo *seg, uint32_t luby_round, uint8_t *open, uint32_t *joined, uint32_t *nj,
+                       uint32_t *rest, uint32_t *nr) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   bool j = false, r = false;
   uint32_t f = 0;
   if (i < na) {
     f = act[i];
     const uint32_t m = ml[f];
-    j = m == INF32 || m >= priority_of(f, gid, seg);
+    j = m == INF32 || m >= priority_of(f, gid, seg, luby_round);
     r = !j;
     if (j) open[f] = 1;
   }
@@ -459,12 +509,13 @@ int mis_phase(Ctx &c, const MisIn &in, uint8_t *open, std::vector<uint32_t> &rou
     uint32_t na = gather(c, flist, fr, rb, M.act);
     const uint32_t ncl = gather(c, clist, cr, rb, ct_list);
     const uint32_t *Ct = ct_list;
-    uint32_t guard_rounds = 0;
+    uint32_t guard_rounds = 0, step_round = 0;
     uint32_t nf_max = 0;
     for (auto &r : fr) nf_max = std::max(nf_max, r.second);
     while (na) {
       // the active facility of smallest priority of each graph joins every round
       if (++guard_rounds > nf_max + 1) return FL_EHIP;
+      const uint32_t luby_round = in.luby ? ++step_round : 0u;
       if (G > 1) {
         fill_u32(c, gact, G, 0);
         k_mark_graphs<<<(uint32_t)ceil_div(na, 256), 256, 0, c.s>>>(M.act, na, in.gid, gact);
@@ -472,7 +523,8 @@ int mis_phase(Ctx &c, const MisIn &in, uint8_t *open, std::vector<uint32_t> &rou
         FL_HIP(hipMemcpyAsync(hact.data(), gact, G * 4, hipMemcpyDeviceToHost, c.s));
       }
       // 1. pi_min at the clients of the rung
-      k_set_key_labels<<<(uint32_t)ceil_div(na, 256), 256, 0, c.s>>>(M.act, na, M.lab, in.gid, in.seg);
+      k_set_key_labels<<<(uint32_t)ceil_div(na, 256), 256, 0, c.s>>>(M.act, na, M.lab, in.gid, in.seg,
+                                                                     luby_round);
       FL_LAUNCH_CHECK();
       sweep(c, M, M.act, na, Rmax);
       if (G > 1) {
@@ -489,8 +541,8 @@ int mis_phase(Ctx &c, const MisIn &in, uint8_t *open, std::vector<uint32_t> &rou
       const uint32_t ns2 = read_u32(c, M.cnts);
       // 2. smallest pi_min around each active facility; joins
       sweep(c, M, M.src, ns2, Rmax);
-      k_join<<<(uint32_t)ceil_div(na, 256), 256, 0, c.s>>>(M.act, na, M.S.ml, in.gid, in.seg, open, M.joined,
-                                                           M.cnts + 1, M.act2, M.cnts + 2);
+      k_join<<<(uint32_t)ceil_div(na, 256), 256, 0, c.s>>>(M.act, na, M.S.ml, in.gid, in.seg, luby_round, open,
+                                                           M.joined, M.cnts + 1, M.act2, M.cnts + 2);
       FL_LAUNCH_CHECK();
       sweep_reset(c, M);
       FL_HIP(hipMemcpyAsync(c.h_status, M.cnts, 16, hipMemcpyDeviceToHost, c.s));

@@ -293,9 +293,11 @@ __global__ __launch_bounds__(256) void k_freeze(OpenArgs A, const uint64_t *dlab
     }
   }
   if (A.gid) {
-    if (froze) ctr_add(A, g, OC_FROZEN, 1);
-    if (finite) ctr_add(A, g, OC_FINITE, 1);
-    if (nuf) ctr_add(A, g, OC_NUF_DEC, 1);
+    const bool valid = c < A.n;
+    if (valid) g = seg_of(A.gid, (uint32_t)c);
+    seg_add32(A.ctr, valid, g, OC_FROZEN, OC_NFIELD, A.stripes, froze ? 1u : 0u);
+    seg_add32(A.ctr, valid, g, OC_FINITE, OC_NFIELD, A.stripes, finite ? 1u : 0u);
+    seg_add32(A.ctr, valid, g, OC_NUF_DEC, OC_NFIELD, A.stripes, nuf ? 1u : 0u);
   } else {
     const uint32_t a = (uint32_t)__popcll(__ballot(froze));
     const uint32_t b = (uint32_t)__popcll(__ballot(finite));

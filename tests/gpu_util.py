@@ -52,7 +52,7 @@ def assert_solve_equal(g, k, seed, eps=0.1, flags=0):
     distances, rungs and the double-precision q bit for bit (the 1e-12
     relative tolerance is met with error 0), cost and counts."""
     got = gpu_solve(g, k, seed, eps, flags)
-    rc, want = O.solve(g, k, seed, eps)
+    rc, want = O.solve(g, k, seed, eps, luby=bool(flags & fl.FL_FLAG_LUBY_MIS))
     assert rc == 0
     for key in ("open_rung", "freeze_rung"):
         bad = np.nonzero(got[key] != want[key])[0]

@@ -96,6 +96,14 @@ def test_solve_other_eps(eps):
     assert_solve_equal(g, 8, 3, eps=eps)
 
 
+@pytest.mark.parametrize("name,make,k", SOLVE_CASES, ids=[c[0] for c in SOLVE_CASES])
+def test_solve_luby_mis_bit_exact(name, make, k):
+    """Luby's MIS variant (priorities redrawn every round) against the oracle's."""
+    g = make()
+    print(f"[solve luby] {name} k={k}", flush=True)
+    assert_solve_equal(g, k, 2, flags=fl.FL_FLAG_LUBY_MIS)
+
+
 def test_solve_tiny_exhaustive_graphs():
     for seed in range(8):
         n = 8 + seed % 5

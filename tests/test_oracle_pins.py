@@ -431,6 +431,62 @@ def test_mis_is_greedy_maximal_independent(pi):
     assert np.array_equal(opened[outside], orung[outside] == O.RUNG_GUARD)
 
 
+def _luby_prio(fac, seed, r):
+    """Round r priorities of Luby's variant: the seeded bijection keyed by
+    SplitMix64(seed ^ (3 + 256 r))."""
+    key = O.splitmix64(seed ^ (3 + 256 * r))
+    return np.array([O.perm(int(f), key) for f in fac], np.uint64)
+
+
+@pytest.mark.parametrize("pi", range(len(PROBLEMS)))
+def test_luby_mis_rounds_on_explicit_hbar(pi):
+    """Luby's variant (Sec. 4.3, the baseline of Sec. 5.4): the opening phase
+    is unchanged; per rung the rounds, simulated here on the explicit H-bar_t
+    from scipy distances with fresh priorities each round, give the oracle's
+    set and round count, and the set is independent and maximal."""
+    g = PROBLEMS[pi]
+    eps, seed = 0.1, 6
+    fixed = _solve(g, 8, seed, eps)
+    rc, r = O.solve(g, 8, seed, eps, luby=True)
+    assert rc == 0
+    assert np.array_equal(r["open_rung"], fixed["open_rung"])
+    assert np.array_equal(r["freeze_rung"], fixed["freeze_rung"])
+    T = r["n_rungs"]
+    lad = O.ladder(r["alpha0"], eps, T + 2)
+    D = apsp(g)
+    orung, frung, opened = r["open_rung"], r["freeze_rung"], r["open"].astype(bool)
+    total_rounds = 0
+    for t in np.unique(orung[(orung >= 1) & (orung <= T)]):
+        Ft = np.nonzero(orung == t)[0]
+        Ct = np.nonzero(frung == t)[0]
+        rho = (1.0 + eps) * lad[t]
+        H = D[np.ix_(Ft, Ct)] <= rho
+        conf = (H.astype(np.int64) @ H.T.astype(np.int64)) > 0
+        np.fill_diagonal(conf, False)
+        active = np.ones(len(Ft), bool)
+        chosen = np.zeros(len(Ft), bool)
+        rounds = 0
+        while active.any():
+            rounds += 1
+            pr = _luby_prio(Ft, seed, rounds)
+            join = np.zeros(len(Ft), bool)
+            for i in np.nonzero(active)[0]:
+                nb = np.nonzero(conf[i] & active)[0]
+                join[i] = not (pr[nb] < pr[i]).any()
+            chosen |= join
+            active &= ~join
+            for i in np.nonzero(active)[0]:
+                if (conf[i] & join).any():
+                    active[i] = False
+        total_rounds += rounds
+        assert np.array_equal(opened[Ft], chosen)
+        sel = np.nonzero(chosen)[0]
+        assert not conf[np.ix_(sel, sel)].any()          # independent
+        for i in range(len(Ft)):                          # maximal
+            assert chosen[i] or (conf[i] & chosen).any()
+    assert total_rounds == r["mis_rounds"]
+
+
 @pytest.mark.parametrize("pi", range(len(PROBLEMS)))
 def test_assignment_and_cost_brute_force(pi):
     """P11 (part): assignment = nearest facility of S with smaller id on ties,
