@@ -107,6 +107,90 @@ def write_traffic(fetch_dir, write_dir):
     print(json.dumps(out))
 
 
+def batch_bench(count, plain_count, seed):
+    """Batched vs plain on power-law graphs: count Chung-Lu graphs (exponent
+    2.2, average degree 10, weights 1..20, n log-uniform in [500, 200000]),
+    k = 32.  Batched: one fl_solve_batch over all of them (after one untimed
+    call); plain: fl_solve one after another on the first plain_count."""
+    import torch
+    import graphgen as gg
+    import paper_1503_03635_amd as fl
+    t0 = time.perf_counter()
+    graphs = gg.powerlaw_batch(count, seed)
+    dgs = [fl.to_device(g, "cuda:0") for g in graphs]
+    torch.cuda.synchronize()
+    log(f"[bench] batch: {count} graphs, sum n {sum(g.n for g in graphs)} in {time.perf_counter() - t0:.1f}s")
+    fl.solve(dgs[0], 32, seed, 0.1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for d in dgs[:plain_count]:
+        fl.solve(d, 32, seed, 0.1)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    fl.solve_batch(dgs, 32, seed, 0.1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = fl.solve_batch(dgs, 32, seed, 0.1)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    relax = sum(o["stats"]["relax_alg"] for o in outs)
+    plain_sps = plain_count / t_plain
+    batch_sps = count / t_batch
+    log(f"[bench] batch: plain {plain_sps:.2f} solves/s, batched {batch_sps:.2f} solves/s")
+    return {"workload": f"powerlaw_batch{count}_k32", "graphs": count,
+            "n_total": int(sum(g.n for g in graphs)), "arcs_total": int(sum(g.n_arcs for g in graphs)),
+            "n_range": [500, 200000], "degree": "Chung-Lu exponent 2.2, average 10", "weights": "1..20",
+            "batched_solves_per_s": round(batch_sps, 3), "plain_solves_per_s": round(plain_sps, 3),
+            "plain_sample": plain_count, "speedup": round(batch_sps / plain_sps, 2),
+            "batched_relax_per_s": round(relax / t_batch, 1), "batched_s": round(t_batch, 3)}
+
+
+def serve_bench(count, seed, rate, slots):
+    """Continuous batching: a Poisson stream of count requests at `rate`
+    requests/s (Chung-Lu graphs, exponent 2.2, average degree 12, weights
+    1..50, n log-uniform in [1000, 500000], k = 32) submitted to a server with
+    a 200 GB budget; latency from submission to completion."""
+    import numpy as np
+    import torch
+    import graphgen as gg
+    import paper_1503_03635_amd as fl
+    t0 = time.perf_counter()
+    arrivals, graphs = gg.poisson_requests(count, seed, rate=rate)
+    dgs = [fl.to_device(g, "cuda:0") for g in graphs]
+    torch.cuda.synchronize()
+    log(f"[bench] serve: {count} requests, sum n {sum(g.n for g in graphs)} in {time.perf_counter() - t0:.1f}s")
+    with fl.Server(hbm_budget_bytes=200 << 30, slots=slots) as srv:
+        srv.wait(srv.submit(dgs[0], 32, seed, 0.1))
+        t_sub = np.zeros(count)
+        t_done = np.zeros(count)
+        tickets = []
+        pending = {}
+        t0 = time.perf_counter()
+        i = 0
+        while i < count or pending:
+            now = time.perf_counter() - t0
+            while i < count and arrivals[i] <= now:
+                t_sub[i] = time.perf_counter() - t0
+                pending[srv.submit(dgs[i], 32, seed + i, 0.1)] = i
+                i += 1
+            for t in list(pending):
+                r = srv.poll(t)
+                if r is not None:
+                    j = pending.pop(t)
+                    t_done[j] = time.perf_counter() - t0
+                    assert r["status"] == 0, f"request {j} failed: {r['status']}"
+            time.sleep(0.0005)
+    lat = (t_done - t_sub) * 1e3
+    span = t_done.max() - t_sub.min()
+    log(f"[bench] serve: p50 {np.percentile(lat, 50):.0f} ms, p99 {np.percentile(lat, 99):.0f} ms, "
+        f"{count / span:.2f} solves/s")
+    return {"workload": f"poisson{int(rate)}_requests{count}_k32", "requests": count, "rate_per_s": rate,
+            "n_range": [1000, 500000], "degree": "Chung-Lu exponent 2.2, average 12", "weights": "1..50",
+            "hbm_budget_gb": 200, "slots": slots,
+            "p50_ms": round(float(np.percentile(lat, 50)), 1), "p99_ms": round(float(np.percentile(lat, 99)), 1),
+            "solves_per_s": round(count / span, 3), "offered_per_s": rate}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +203,11 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-sources", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=128, help="graphs of the batched measurement (0: skip)")
+    ap.add_argument("--batch-plain", type=int, default=32, help="of them solved one by one for the plain rate")
+    ap.add_argument("--serve-count", type=int, default=64, help="requests of the serving measurement (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-slots", type=int, default=3)
     ap.add_argument("--pmc-calibration", action="store_true",
                     help="run a 1 GiB device copy first (counter calibration)")
     ap.add_argument("--traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -212,6 +301,10 @@ def main():
                      for p in ("validate", "ads", "gamma", "open", "mis", "assign", "total")},
         "roofline": roof,
     }
+    if args.batch_count:
+        out["batched"] = batch_bench(args.batch_count, min(args.batch_plain, args.batch_count), args.seed)
+    if args.serve_count:
+        out["serving"] = serve_bench(args.serve_count, args.seed, args.serve_rate, args.serve_slots)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(g, args.k, args.seed, args.cpu_sources)
