@@ -272,11 +272,46 @@ __device__ inline void seg_add32(uint32_t *ctr, bool valid, uint32_t g, uint32_t
   }
 }
 __device__ inline uint32_t wave_max_u32(uint32_t x) { return ~wave_min_u32(~x); }
-// rows up to this many arcs are walked by their own lane; longer rows by the whole wave
-constexpr uint32_t LIGHT_DEG = 16;
 __device__ inline uint64_t shfl_u64(uint64_t x, int src) {
   const uint32_t lo = __shfl((uint32_t)x, src, WAVE), hi = __shfl((uint32_t)(x >> 32), src, WAVE);
   return ((uint64_t)hi << 32) | lo;
+}
+// wave-aggregated append of x to list (lanes with want)
+__device__ inline void wave_push(uint32_t *list, uint32_t *count, bool want, uint32_t x) {
+  const uint64_t m = __ballot(want);
+  if (!m) return;
+  const int lead = __ffsll((long long)m) - 1;
+  uint32_t base = 0;
+  if (lane_id() == lead) base = atomicAdd(count, (uint32_t)__popcll(m));
+  base = __shfl(base, lead, WAVE);
+  if (want) list[base + lanes_below(m)] = x;
+}
+// Frontier expansion: rows up to FLAT_MAX arcs are flattened over the wave
+// (step c takes arcs c*64 .. c*64+63 of the concatenated rows, each lane
+// finding its row by binary search over the running degree sum); longer rows
+// go to a queue that a second kernel walks one row per wave.
+constexpr uint32_t FLAT_MAX = 256;
+// f(valid, arc, owner_lane) is called by every lane of the wave, converged.
+template <class F>
+__device__ inline void flat_arcs(bool light, uint64_t a0, uint64_t deg, F &&f) {
+  const int lane = lane_id();
+  const uint32_t d = light ? (uint32_t)deg : 0u;
+  const uint32_t incl = wave_scan_incl(d);
+  const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
+  const uint32_t excl = incl - d;
+  for (uint32_t c0 = 0; c0 < total; c0 += WAVE) {
+    const uint32_t idx = c0 + lane;
+    uint32_t pos = 0;  // first lane whose inclusive sum exceeds idx
+#pragma unroll
+    for (uint32_t s = 32; s >= 1; s >>= 1) {
+      const uint32_t val = __shfl(incl, (int)(pos + s - 1), WAVE);
+      if (val <= idx) pos += s;
+    }
+    const bool valid = idx < total;
+    const uint64_t oa = shfl_u64(a0, (int)(valid ? pos : 0));
+    const uint32_t oe = __shfl(excl, (int)(valid ? pos : 0), WAVE);
+    f(valid, oa + (idx - oe), (int)(valid ? pos : 0));
+  }
 }
 __device__ inline void seg_max(unsigned long long *ctr, bool valid, uint32_t g, uint32_t f, uint32_t nf,
                                uint32_t stripes, uint64_t v) {
@@ -381,7 +416,8 @@ void ads_totals(Ctx &c, const Graph &g, const uint32_t *gid, uint32_t G, const u
 struct SsspWork {
   uint32_t *front[2];
   uint32_t *flag;  // n: iteration stamp of the last frontier a vertex joined
-  uint64_t *ctr;   // device counters
+  uint32_t *heavy; // n: long rows of the current iteration
+  uint64_t *ctr;   // device counters: u32 [0], [1] frontier sizes, [2] long rows
   uint32_t stamp = 0;  // stamps grow across calls on this workspace
 };
 void sssp_alloc(Ctx &c, SsspWork &wk, uint32_t n);

@@ -329,39 +329,54 @@ __device__ inline void sssp_arc(const uint32_t *col, const uint32_t *w, uint64_t
   }
 }
 
-// One lane per frontier vertex; short rows are walked lane-parallel (step i
-// takes the i-th arc of every short row), long rows by the whole wave.
+// One lane per frontier vertex: short rows flattened over the wave, long rows
+// queued for k_sssp_heavy (one wave per row).
 __global__ __launch_bounds__(256) void k_sssp_push(const uint64_t *row_ptr, const uint32_t *col,
                                                    const uint32_t *w, uint64_t *labels,
                                                    const uint32_t *front, const uint32_t *nfront,
                                                    uint32_t *next, uint32_t *nnext, uint32_t *stamp,
-                                                   uint32_t iter) {
-  const int lane = lane_id();
+                                                   uint32_t iter, uint32_t *heavy, uint32_t *nheavy) {
   const uint32_t nf = *nfront;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x; b < nf; b += stride) {
     const uint64_t i = b + threadIdx.x;
     const bool want = i < nf;
-    uint64_t a0 = 0, a1 = 0, L = 0;
+    uint32_t v = 0;
+    uint64_t a0 = 0, deg = 0, L = 0;
     if (want) {
-      const uint32_t v = front[i];
+      v = front[i];
       L = __hip_atomic_load(&labels[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       a0 = row_ptr[v];
-      a1 = row_ptr[v + 1];
+      deg = row_ptr[v + 1] - a0;
     }
-    const uint64_t deg = a1 - a0;
-    const bool light = want && deg <= LIGHT_DEG;
-    const uint32_t dmax = wave_max_u32(light ? (uint32_t)deg : 0u);
-    for (uint32_t k = 0; k < dmax; ++k)
-      sssp_arc(col, w, labels, light && k < deg, a0 + k, L, next, nnext, stamp, iter);
-    uint64_t hm = __ballot(want && !light);
-    while (hm) {
-      const int h = __ffsll((long long)hm) - 1;
-      hm &= hm - 1;
-      const uint64_t b0 = shfl_u64(a0, h), b1 = shfl_u64(a1, h), Lh = shfl_u64(L, h);
-      for (uint64_t c = b0; c < b1; c += WAVE)
-        sssp_arc(col, w, labels, c + lane < b1, c + lane, Lh, next, nnext, stamp, iter);
-    }
+    const bool hv = want && deg > FLAT_MAX;
+    wave_push(heavy, nheavy + (iter & 1), hv, v);
+    flat_arcs(want && !hv, a0, deg, [&](bool valid, uint64_t a, int o) {
+      sssp_arc(col, w, labels, valid, a, shfl_u64(L, o), next, nnext, stamp, iter);
+    });
+  }
+}
+
+// Long rows of iteration iter, one wave per row.  Also clears the count of
+// the frontier iteration iter consumed (it receives the frontier after next)
+// and the long-row counter of iteration iter + 1.
+__global__ __launch_bounds__(256) void k_sssp_heavy(const uint64_t *row_ptr, const uint32_t *col, const uint32_t *w,
+                                                    uint64_t *labels, uint32_t *next, uint32_t *nnext,
+                                                    uint32_t *stamp, uint32_t iter, const uint32_t *heavy,
+                                                    uint32_t *nheavy, uint32_t *nconsumed) {
+  const int lane = lane_id();
+  const uint32_t cnt = nheavy[iter & 1];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *nconsumed = 0;
+    nheavy[(iter + 1) & 1] = 0;
+  }
+  const uint64_t nw = ((uint64_t)gridDim.x * blockDim.x) / WAVE;
+  for (uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE; i < cnt; i += nw) {
+    const uint32_t v = heavy[i];
+    const uint64_t L = __hip_atomic_load(&labels[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t a0 = row_ptr[v], a1 = row_ptr[v + 1];
+    for (uint64_t c = a0; c < a1; c += WAVE)
+      sssp_arc(col, w, labels, c + lane < a1, c + lane, L, next, nnext, stamp, iter);
   }
 }
 
@@ -369,6 +384,7 @@ void sssp_alloc(Ctx &c, SsspWork &wk, uint32_t n) {
   wk.front[0] = c.arena->get<uint32_t>(n + 1);
   wk.front[1] = c.arena->get<uint32_t>(n + 1);
   wk.flag = c.arena->get<uint32_t>(n);
+  wk.heavy = c.arena->get<uint32_t>(n);
   wk.ctr = c.arena->get<uint64_t>(4);
   fill_u32(c, wk.flag, n, 0);
   fill_u64(c, wk.ctr, 4, 0);
@@ -382,8 +398,8 @@ uint32_t sssp_run(Ctx &c, const Graph &g, uint64_t *labels, const uint32_t *seed
   if (nseeds == 0) return 0;
   uint32_t *cnt = reinterpret_cast<uint32_t *>(wk.ctr);  // cnt[0], cnt[1]: frontier sizes
   FL_HIP(hipMemcpyAsync(wk.front[0], seeds, (size_t)nseeds * 4, hipMemcpyDeviceToDevice, c.s));
-  uint32_t h = nseeds;
-  FL_HIP(hipMemcpyAsync(&cnt[0], &h, 4, hipMemcpyHostToDevice, c.s));
+  fill_u32(c, cnt, 4, 0);
+  fill_u32(c, &cnt[0], 1, nseeds);
   uint32_t iters = 0, cur = 0;
   uint32_t nf = nseeds;
   while (nf) {
@@ -394,10 +410,15 @@ uint32_t sssp_run(Ctx &c, const Graph &g, uint64_t *labels, const uint32_t *seed
     uint64_t blocks = ceil_div((uint64_t)nf * (burst > 1 ? 4 : 1), 256);
     if (blocks > 16384) blocks = 16384;
     for (uint32_t b = 0; b < burst; ++b) {
+      // cnt[cur ^ 1] (the next frontier's count) is zero: cleared at the
+      // start or by the previous iteration's k_sssp_heavy
       const uint32_t stamp = ++wk.stamp;
-      fill_u32(c, &cnt[cur ^ 1], 1, 0);
       k_sssp_push<<<(uint32_t)blocks, 256, 0, c.s>>>(g.row_ptr, g.col, g.w, labels, wk.front[cur], &cnt[cur],
-                                                      wk.front[cur ^ 1], &cnt[cur ^ 1], wk.flag, stamp);
+                                                      wk.front[cur ^ 1], &cnt[cur ^ 1], wk.flag, stamp,
+                                                      wk.heavy, &cnt[2]);
+      FL_LAUNCH_CHECK();
+      k_sssp_heavy<<<256, 256, 0, c.s>>>(g.row_ptr, g.col, g.w, labels, wk.front[cur ^ 1], &cnt[cur ^ 1],
+                                         wk.flag, stamp, wk.heavy, &cnt[2], &cnt[cur]);
       FL_LAUNCH_CHECK();
       cur ^= 1;
       ++iters;

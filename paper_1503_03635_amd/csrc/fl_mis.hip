@@ -45,6 +45,8 @@ struct SweepArgs {
   uint32_t *tl_cnt;   // [NS]
   uint32_t *touched;  // [n] vertices whose ml was set
   uint32_t *touched_cnt;
+  uint32_t *heavy;    // [n] long rows queued in the current distance
+  uint32_t *heavy_cnt;  // [2] by distance parity
 };
 
 // One arc step of a push (every lane calls, converged; lanes with valid ==
@@ -86,41 +88,26 @@ __device__ inline void sweep_arc(const SweepArgs &S, bool valid, uint64_t a, uin
   }
 }
 
-// Push the label of each lane's vertex (want) from distance j.  Short rows:
-// step i takes the i-th arc of every short row; long rows: the whole wave
-// walks one row at a time.
+// Push the labels of the lanes' vertices (want) from distance j: short rows
+// flattened over the wave, long rows queued for k_sweep_heavy.
 __device__ inline void sweep_push_lanes(const SweepArgs &S, bool want, uint32_t x, uint32_t lab, uint32_t j) {
-  const int lane = lane_id();
-  uint64_t a0 = 0, a1 = 0;
+  uint64_t a0 = 0, deg = 0;
   uint32_t R = 0;
   if (want) {
     a0 = S.row_ptr[x];
-    a1 = S.row_ptr[x + 1];
+    deg = S.row_ptr[x + 1] - a0;
     R = S.Rg[seg_of(S.gid, x)];
   }
-  const uint64_t deg = a1 - a0;
-  const bool light = want && deg <= LIGHT_DEG;
-  const uint32_t dmax = wave_max_u32(light ? (uint32_t)deg : 0u);
-  for (uint32_t i = 0; i < dmax; ++i) sweep_arc(S, light && i < deg, a0 + i, lab, j, R);
-  uint64_t hm = __ballot(want && !light);
-  while (hm) {
-    const int h = __ffsll((long long)hm) - 1;
-    hm &= hm - 1;
-    const uint64_t b0 = shfl_u64(a0, h), b1 = shfl_u64(a1, h);
-    const uint32_t lb = __shfl(lab, h, WAVE), Rb = __shfl(R, h, WAVE);
-    for (uint64_t b = b0; b < b1; b += WAVE) sweep_arc(S, b + lane < b1, b + lane, lb, j, Rb);
-  }
+  const bool heavy = want && deg > FLAT_MAX;
+  wave_push(S.heavy, S.heavy_cnt + (j & 1), heavy, x);
+  flat_arcs(want && !heavy, a0, deg, [&](bool valid, uint64_t a, int o) {
+    sweep_arc(S, valid, a, __shfl(lab, o, WAVE), j, __shfl(R, o, WAVE));
+  });
 }
 
 // vertices whose ml was set for the first time -> touched (one atomic per wave)
 __device__ inline void touch(const SweepArgs &S, bool first, uint32_t x) {
-  const uint64_t m = __ballot(first);
-  if (!m) return;
-  const int lead = __ffsll((long long)m) - 1;
-  uint32_t base = 0;
-  if (lane_id() == lead) base = atomicAdd(S.touched_cnt, (uint32_t)__popcll(m));
-  base = __shfl(base, lead, WAVE);
-  if (first) S.touched[base + lanes_below(m)] = x;
+  wave_push(S.touched, S.touched_cnt, first, x);
 }
 
 // sources: set ml and push at distance 0 (one lane per source)
@@ -164,6 +151,27 @@ __global__ __launch_bounds__(256) void k_sweep_round(SweepArgs S, uint32_t j) {
   }
 }
 
+// the long rows queued at distance j: one wave per row; the label is the
+// vertex's own (settled at j, unchanged until the next distance).  Also
+// clears slot j (consumed) and the long-row counter of distance j + 1 (its
+// last use, distance j - 1, is over).
+__global__ __launch_bounds__(256) void k_sweep_heavy(SweepArgs S, uint32_t j) {
+  const int lane = lane_id();
+  const uint32_t cnt = S.heavy_cnt[j & 1];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    S.tl_cnt[j % S.NS] = 0;
+    S.heavy_cnt[(j + 1) & 1] = 0;
+  }
+  const uint64_t nw = ((uint64_t)gridDim.x * blockDim.x) / WAVE;
+  for (uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE; i < cnt; i += nw) {
+    const uint32_t x = S.heavy[i];
+    const uint32_t lab = S.ml[x];
+    const uint32_t R = S.Rg[seg_of(S.gid, x)];
+    const uint64_t a0 = S.row_ptr[x], a1 = S.row_ptr[x + 1];
+    for (uint64_t b = a0; b < a1; b += WAVE) sweep_arc(S, b + lane < a1, b + lane, lab, j, R);
+  }
+}
+
 __global__ void k_sweep_reset(SweepArgs S) {
   const uint32_t cnt = *S.touched_cnt;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
@@ -189,6 +197,8 @@ static void sweep(Ctx &c, MisWork &M, const uint32_t *src, uint32_t nsrc, uint32
   if (nsrc == 0) return;
   k_sweep_init<<<(uint32_t)ceil_div((uint64_t)nsrc, 256), 256, 0, c.s>>>(S, src, nsrc, M.lab);
   FL_LAUNCH_CHECK();
+  k_sweep_heavy<<<256, 256, 0, c.s>>>(S, 0);
+  FL_LAUNCH_CHECK();
   std::vector<uint32_t> h(S.NS);
   uint32_t j = 1;
   while (j <= R) {
@@ -209,9 +219,11 @@ static void sweep(Ctx &c, MisWork &M, const uint32_t *src, uint32_t nsrc, uint32
     for (uint32_t b = 0; b < burst && j <= R; ++b, ++j) {
       k_sweep_round<<<blocks, 256, 0, c.s>>>(S, j);
       FL_LAUNCH_CHECK();
-      fill_u32(c, S.tl_cnt + j % S.NS, 1, 0);
+      k_sweep_heavy<<<256, 256, 0, c.s>>>(S, j);
+      FL_LAUNCH_CHECK();
     }
   }
+  fill_u32(c, S.heavy_cnt, 2, 0);  // the last distance's long-row count
 }
 
 static void sweep_reset(Ctx &c, MisWork &M) {
@@ -443,6 +455,8 @@ int mis_phase(Ctx &c, const MisIn &in, uint8_t *open, std::vector<uint32_t> &rou
   M.S.tl_cnt = c.arena->get<uint32_t>(NS);
   M.S.touched = c.arena->get<uint32_t>(n);
   M.S.touched_cnt = c.arena->get<uint32_t>(1);
+  M.S.heavy = c.arena->get<uint32_t>(n);
+  M.S.heavy_cnt = c.arena->get<uint32_t>(2);
   M.lab = c.arena->get<uint32_t>(n);
   M.pm = c.arena->get<uint32_t>(n);
   M.act = c.arena->get<uint32_t>(n);
@@ -461,6 +475,7 @@ int mis_phase(Ctx &c, const MisIn &in, uint8_t *open, std::vector<uint32_t> &rou
   fill_u32(c, M.S.pend, (size_t)NS * n, INF32);
   fill_u32(c, M.S.tl_cnt, NS, 0);
   fill_u32(c, M.S.touched_cnt, 1, 0);
+  fill_u32(c, M.S.heavy_cnt, 2, 0);
 
   // each graph's non-empty rungs, in order
   std::vector<std::vector<uint32_t>> lists(G);
