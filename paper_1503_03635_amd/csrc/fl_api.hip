@@ -242,7 +242,7 @@ static size_t estimate_bytes(uint32_t n, uint64_t m, uint64_t nF, uint32_t k, ui
   b += (size_t)nF * cap * 4;               // HIP thresholds
   b += (size_t)n * 32;                     // outputs kept while the sketches are built
   const size_t ads = ads_scratch_bytes(n, m, k, NS);
-  const size_t later = (size_t)NS * n * 8 + (size_t)n * 160 + (size_t)nF * 96;  // opening loop, MIS, assignment
+  const size_t later = (size_t)NS * n * 8 + (size_t)n * 200 + (size_t)m / 64 + (size_t)nF * 96;  // opening loop, MIS, assignment
   b += ads > later ? ads : later;
   b += (size_t)64 << 20;                   // counters, scans
   return b;
@@ -450,7 +450,7 @@ static void solve_group(const fl_problem *const *ps, const fl_params *const *pr,
   k_gamma_init<<<vb, 256, 0, s>>>(n, fac_cost, gl);
   FL_LAUNCH_CHECK();
   SsspWork wk;
-  sssp_alloc(c, wk, n);
+  sssp_alloc(c, wk, n, g.m);
   sssp_run(c, g, gl, fac_list, nF, wk, 0);
   fill_u64(c, ctr, (size_t)G * CL_NFIELD * stripes, 0);
   k_clients<<<vb, 256, 0, s>>>(n, gid, is_client, gl, fac_cost, ceff, ctr, stripes);

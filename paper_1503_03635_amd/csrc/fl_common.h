@@ -416,11 +416,11 @@ void ads_totals(Ctx &c, const Graph &g, const uint32_t *gid, uint32_t G, const u
 struct SsspWork {
   uint32_t *front[2];
   uint32_t *flag;  // n: iteration stamp of the last frontier a vertex joined
-  uint32_t *heavy; // n: long rows of the current iteration
+  uint64_t *heavy; // pieces of the long rows of the current iteration
   uint64_t *ctr;   // device counters: u32 [0], [1] frontier sizes, [2] long rows
   uint32_t stamp = 0;  // stamps grow across calls on this workspace
 };
-void sssp_alloc(Ctx &c, SsspWork &wk, uint32_t n);
+void sssp_alloc(Ctx &c, SsspWork &wk, uint32_t n, uint64_t m);
 uint32_t sssp_run(Ctx &c, const Graph &g, uint64_t *labels, const uint32_t *seeds, uint32_t nseeds,
                   SsspWork &wk, uint64_t cap_value);
 

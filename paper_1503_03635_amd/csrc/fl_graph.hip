@@ -7,6 +7,7 @@
 #include <mutex>
 
 #include "fl_common.h"
+#include "fl_frontier.h"
 
 namespace fl {
 
@@ -335,7 +336,7 @@ __global__ __launch_bounds__(256) void k_sssp_push(const uint64_t *row_ptr, cons
                                                    const uint32_t *w, uint64_t *labels,
                                                    const uint32_t *front, const uint32_t *nfront,
                                                    uint32_t *next, uint32_t *nnext, uint32_t *stamp,
-                                                   uint32_t iter, uint32_t *heavy, uint32_t *nheavy) {
+                                                   uint32_t iter, uint64_t *heavy, uint32_t *nheavy) {
   const uint32_t nf = *nfront;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x; b < nf; b += stride) {
@@ -350,7 +351,7 @@ __global__ __launch_bounds__(256) void k_sssp_push(const uint64_t *row_ptr, cons
       deg = row_ptr[v + 1] - a0;
     }
     const bool hv = want && deg > FLAT_MAX;
-    wave_push(heavy, nheavy + (iter & 1), hv, v);
+    push_pieces(heavy, nheavy + (iter & 1), hv, v, deg);
     flat_arcs(want && !hv, a0, deg, [&](bool valid, uint64_t a, int o) {
       sssp_arc(col, w, labels, valid, a, shfl_u64(L, o), next, nnext, stamp, iter);
     });
@@ -362,7 +363,7 @@ __global__ __launch_bounds__(256) void k_sssp_push(const uint64_t *row_ptr, cons
 // and the long-row counter of iteration iter + 1.
 __global__ __launch_bounds__(256) void k_sssp_heavy(const uint64_t *row_ptr, const uint32_t *col, const uint32_t *w,
                                                     uint64_t *labels, uint32_t *next, uint32_t *nnext,
-                                                    uint32_t *stamp, uint32_t iter, const uint32_t *heavy,
+                                                    uint32_t *stamp, uint32_t iter, const uint64_t *heavy,
                                                     uint32_t *nheavy, uint32_t *nconsumed) {
   const int lane = lane_id();
   const uint32_t cnt = nheavy[iter & 1];
@@ -372,19 +373,19 @@ __global__ __launch_bounds__(256) void k_sssp_heavy(const uint64_t *row_ptr, con
   }
   const uint64_t nw = ((uint64_t)gridDim.x * blockDim.x) / WAVE;
   for (uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE; i < cnt; i += nw) {
-    const uint32_t v = heavy[i];
+    uint64_t a0, a1;
+    const uint32_t v = piece_arcs(heavy[i], row_ptr, &a0, &a1);
     const uint64_t L = __hip_atomic_load(&labels[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint64_t a0 = row_ptr[v], a1 = row_ptr[v + 1];
     for (uint64_t c = a0; c < a1; c += WAVE)
       sssp_arc(col, w, labels, c + lane < a1, c + lane, L, next, nnext, stamp, iter);
   }
 }
 
-void sssp_alloc(Ctx &c, SsspWork &wk, uint32_t n) {
+void sssp_alloc(Ctx &c, SsspWork &wk, uint32_t n, uint64_t m) {
   wk.front[0] = c.arena->get<uint32_t>(n + 1);
   wk.front[1] = c.arena->get<uint32_t>(n + 1);
   wk.flag = c.arena->get<uint32_t>(n);
-  wk.heavy = c.arena->get<uint32_t>(n);
+  wk.heavy = c.arena->get<uint64_t>(piece_capacity(n, m));
   wk.ctr = c.arena->get<uint64_t>(4);
   fill_u32(c, wk.flag, n, 0);
   fill_u64(c, wk.ctr, 4, 0);

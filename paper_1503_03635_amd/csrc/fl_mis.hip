@@ -28,6 +28,7 @@
 #include <cmath>
 
 #include "fl_common.h"
+#include "fl_frontier.h"
 #include "fl_mis.h"
 
 namespace fl {
@@ -45,7 +46,7 @@ struct SweepArgs {
   uint32_t *tl_cnt;   // [NS]
   uint32_t *touched;  // [n] vertices whose ml was set
   uint32_t *touched_cnt;
-  uint32_t *heavy;    // [n] long rows queued in the current distance
+  uint64_t *heavy;    // pieces of the long rows queued in the current distance
   uint32_t *heavy_cnt;  // [2] by distance parity
 };
 
@@ -99,7 +100,7 @@ __device__ inline void sweep_push_lanes(const SweepArgs &S, bool want, uint32_t 
     R = S.Rg[seg_of(S.gid, x)];
   }
   const bool heavy = want && deg > FLAT_MAX;
-  wave_push(S.heavy, S.heavy_cnt + (j & 1), heavy, x);
+  push_pieces(S.heavy, S.heavy_cnt + (j & 1), heavy, x, deg);
   flat_arcs(want && !heavy, a0, deg, [&](bool valid, uint64_t a, int o) {
     sweep_arc(S, valid, a, __shfl(lab, o, WAVE), j, __shfl(R, o, WAVE));
   });
@@ -151,8 +152,8 @@ __global__ __launch_bounds__(256) void k_sweep_round(SweepArgs S, uint32_t j) {
   }
 }
 
-// the long rows queued at distance j: one wave per row; the label is the
-// vertex's own (settled at j, unchanged until the next distance).  Also
+// the pieces of long rows queued at distance j: one wave per piece; the label
+// is the vertex's own (settled at j, unchanged until the next distance).  Also
 // clears slot j (consumed) and the long-row counter of distance j + 1 (its
 // last use, distance j - 1, is over).
 __global__ __launch_bounds__(256) void k_sweep_heavy(SweepArgs S, uint32_t j) {
@@ -164,10 +165,10 @@ __global__ __launch_bounds__(256) void k_sweep_heavy(SweepArgs S, uint32_t j) {
   }
   const uint64_t nw = ((uint64_t)gridDim.x * blockDim.x) / WAVE;
   for (uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE; i < cnt; i += nw) {
-    const uint32_t x = S.heavy[i];
+    uint64_t a0, a1;
+    const uint32_t x = piece_arcs(S.heavy[i], S.row_ptr, &a0, &a1);
     const uint32_t lab = S.ml[x];
     const uint32_t R = S.Rg[seg_of(S.gid, x)];
-    const uint64_t a0 = S.row_ptr[x], a1 = S.row_ptr[x + 1];
     for (uint64_t b = a0; b < a1; b += WAVE) sweep_arc(S, b + lane < a1, b + lane, lab, j, R);
   }
 }
@@ -455,7 +456,7 @@ int mis_phase(Ctx &c, const MisIn &in, uint8_t *open, std::vector<uint32_t> &rou
   M.S.tl_cnt = c.arena->get<uint32_t>(NS);
   M.S.touched = c.arena->get<uint32_t>(n);
   M.S.touched_cnt = c.arena->get<uint32_t>(1);
-  M.S.heavy = c.arena->get<uint32_t>(n);
+  M.S.heavy = c.arena->get<uint64_t>(piece_capacity(n, g.m));
   M.S.heavy_cnt = c.arena->get<uint32_t>(2);
   M.lab = c.arena->get<uint32_t>(n);
   M.pm = c.arena->get<uint32_t>(n);

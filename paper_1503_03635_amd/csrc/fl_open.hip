@@ -403,7 +403,7 @@ int open_phase(Ctx &c, const OpenIn &in, OpenOut &out) {
     FL_LAUNCH_CHECK();
   }
   SsspWork wk;
-  sssp_alloc(c, wk, n);
+  sssp_alloc(c, wk, n, g.m);
 
   const double one_eps = 1.0 + in.eps;
   // host state per graph
