@@ -37,7 +37,9 @@
 
 namespace fl {
 
-constexpr int ADS_WPB = 4;          // waves per block
+constexpr int ADS_WPB = 4;          // waves per block (canonical-order pass)
+constexpr int TASK_WPB = 1;         // waves per block of the round kernels: a block's LDS is
+                                    // freed when its own task ends (task lengths vary widely)
 constexpr uint32_t ADS_SB = 1024;   // survivor ids per wave: one level of one sketch plus a chunk
 constexpr uint32_t TASK_ARCS = 256; // arcs per task of a split vertex
 constexpr uint32_t NBKT = 64;       // id buckets of the level prune (one per lane)
@@ -571,15 +573,15 @@ __device__ inline void level_commit(const AdsArgs &P, uint32_t u, uint32_t D, Le
 // One wave per task.  task_slot == INF32: the task is the whole vertex and
 // commits; otherwise it leaves its kept set in scratch slot task_slot.
 template <bool UNITW>
-__global__ __launch_bounds__(256) void k_ads_tasks(AdsArgs P, uint32_t D, const uint32_t *task_u,
+__global__ __launch_bounds__(TASK_WPB * WAVE) void k_ads_tasks(AdsArgs P, uint32_t D, const uint32_t *task_u,
                                                    const uint32_t *task_sub, const uint32_t *task_slot,
                                                    uint32_t ntasks, int sparse, int mark) {
-  __shared__ uint32_t lds_id[ADS_WPB][ADS_SB];
-  __shared__ uint32_t lds_tmp[ADS_WPB][ADS_SB];
-  __shared__ __align__(16) uint32_t lds_cnt[ADS_WPB][3 * WAVE];
+  __shared__ uint32_t lds_id[TASK_WPB][ADS_SB];
+  __shared__ uint32_t lds_tmp[TASK_WPB][ADS_SB];
+  __shared__ __align__(16) uint32_t lds_cnt[TASK_WPB][3 * WAVE];
   const int lane = lane_id();
   const int wv = threadIdx.x / WAVE;
-  const uint64_t item = (uint64_t)blockIdx.x * ADS_WPB + wv;
+  const uint64_t item = (uint64_t)blockIdx.x * TASK_WPB + wv;
   if (item >= ntasks) return;
   uint32_t *s_id = lds_id[wv];
   uint32_t *s_tmp = lds_tmp[wv];
@@ -624,15 +626,15 @@ __global__ __launch_bounds__(256) void k_ads_tasks(AdsArgs P, uint32_t D, const 
 
 // One wave per split vertex: prune the union of its tasks' kept sets, commit.
 template <bool UNITW>
-__global__ __launch_bounds__(256) void k_ads_merge(AdsArgs P, uint32_t D, const uint32_t *split_u,
+__global__ __launch_bounds__(TASK_WPB * WAVE) void k_ads_merge(AdsArgs P, uint32_t D, const uint32_t *split_u,
                                                    const uint32_t *split_first, const uint32_t *split_nt,
                                                    uint32_t nsplit, int mark) {
-  __shared__ uint32_t lds_id[ADS_WPB][ADS_SB];
-  __shared__ uint32_t lds_tmp[ADS_WPB][ADS_SB];
-  __shared__ __align__(16) uint32_t lds_cnt[ADS_WPB][3 * WAVE];
+  __shared__ uint32_t lds_id[TASK_WPB][ADS_SB];
+  __shared__ uint32_t lds_tmp[TASK_WPB][ADS_SB];
+  __shared__ __align__(16) uint32_t lds_cnt[TASK_WPB][3 * WAVE];
   const int lane = lane_id();
   const int wv = threadIdx.x / WAVE;
-  const uint64_t item = (uint64_t)blockIdx.x * ADS_WPB + wv;
+  const uint64_t item = (uint64_t)blockIdx.x * TASK_WPB + wv;
   if (item >= nsplit) return;
   uint32_t *s_id = lds_id[wv];
   uint32_t *s_tmp = lds_tmp[wv];
@@ -1019,22 +1021,22 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
     fill_u64(c, P.ctr + 64, 64, 0);
     if (T->ntasks) {
       FL_HIP(hipEventRecord(e0, c.s));
-      const uint32_t tb = (uint32_t)ceil_div(T->ntasks, ADS_WPB);
+      const uint32_t tb = (uint32_t)ceil_div(T->ntasks, TASK_WPB);
       if (unit)
-        k_ads_tasks<true><<<tb, 256, 0, c.s>>>(P, D, T->task_u, T->task_sub, T->task_slot, T->ntasks,
+        k_ads_tasks<true><<<tb, TASK_WPB * WAVE, 0, c.s>>>(P, D, T->task_u, T->task_sub, T->task_slot, T->ntasks,
                                                sparse ? 1 : 0, mark ? 1 : 0);
       else
-        k_ads_tasks<false><<<tb, 256, 0, c.s>>>(P, D, T->task_u, T->task_sub, T->task_slot, T->ntasks,
+        k_ads_tasks<false><<<tb, TASK_WPB * WAVE, 0, c.s>>>(P, D, T->task_u, T->task_sub, T->task_slot, T->ntasks,
                                                 sparse ? 1 : 0, mark ? 1 : 0);
       FL_LAUNCH_CHECK();
       FL_HIP(hipEventRecord(em, c.s));
       if (T->nsplit) {
-        const uint32_t mb = (uint32_t)ceil_div(T->nsplit, ADS_WPB);
+        const uint32_t mb = (uint32_t)ceil_div(T->nsplit, TASK_WPB);
         if (unit)
-          k_ads_merge<true><<<mb, 256, 0, c.s>>>(P, D, T->split_u, T->split_first, T->split_nt, T->nsplit,
+          k_ads_merge<true><<<mb, TASK_WPB * WAVE, 0, c.s>>>(P, D, T->split_u, T->split_first, T->split_nt, T->nsplit,
                                                  mark ? 1 : 0);
         else
-          k_ads_merge<false><<<mb, 256, 0, c.s>>>(P, D, T->split_u, T->split_first, T->split_nt, T->nsplit,
+          k_ads_merge<false><<<mb, TASK_WPB * WAVE, 0, c.s>>>(P, D, T->split_u, T->split_first, T->split_nt, T->nsplit,
                                                   mark ? 1 : 0);
         FL_LAUNCH_CHECK();
       }
