@@ -41,6 +41,7 @@ constexpr int ADS_WPB = 4;          // waves per block (canonical-order pass)
 constexpr int TASK_WPB = 1;         // waves per block of the round kernels: a block's LDS is
                                     // freed when its own task ends (task lengths vary widely)
 constexpr uint32_t ADS_SB = 1024;   // survivor ids per wave: one level of one sketch plus a chunk
+static_assert((ADS_SB & (ADS_SB - 1)) == 0, "wave_sort_lds pads to a power of two inside the buffer");
 constexpr uint32_t TASK_ARCS = 256; // arcs per task of a split vertex
 constexpr uint32_t NBKT = 64;       // id buckets of the level prune (one per lane)
 constexpr uint32_t LONG_LIST = 24;  // entry lists at least this long are streamed one arc at a time
