@@ -264,6 +264,84 @@ __global__ __launch_bounds__(256) void k_open_heavy(OpenArgs A, uint32_t t) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Quiet rungs.  When no client froze in the previous rung, a rung in which no
+// facility crosses its next sketch entry, none reaches its cost and no client
+// comes within (1 + eps) alpha of the open set changes nothing but q:
+// q += (eps alpha_t) N for every unopened facility, with N fixed.  The next
+// rung with an event is found on the device and the quiet rungs before it
+// are applied in one pass, in the same floating-point order as rung by rung.
+// ---------------------------------------------------------------------------
+constexpr uint32_t FF_WIN = 256;  // ladder rungs held on the device per look-ahead
+
+struct FFArgs {
+  const double *lw;     // [G * FF_WIN] a_g[t0 + i] of running graphs
+  const uint8_t *run;   // [G] the graph is still in the loop
+  uint32_t t0, nw;      // rungs t0 .. t0 + nw - 1
+  double eps, one_eps;
+  uint32_t *tev;        // earliest event rung (atomic min), t0 + nw if none
+};
+
+__global__ __launch_bounds__(256) void k_ff_scan_fac(OpenArgs A, FFArgs F) {
+  const uint32_t fi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (fi >= A.nF || A.state[fi]) return;
+  const uint32_t f = A.fac_list[fi];
+  const uint32_t g = seg_of(A.gid, f);
+  if (!F.run[g]) return;
+  const double *a = F.lw + (size_t)g * FF_WIN;
+  uint32_t ev = F.nw;
+  const uint32_t nx = A.nxt[fi];
+  if (nx != INF32)
+    for (uint32_t i = 0; i < F.nw; ++i)
+      if ((double)nx <= a[i]) {
+        ev = i;
+        break;
+      }
+  double q = A.q[fi];
+  const double nh = A.nhat[fi], c = (double)A.fac_cost[f];
+  for (uint32_t i = 0; i < ev; ++i) {
+    const double ea = F.eps * a[i];
+    q = q + ea * nh;
+    if (q >= c) {
+      ev = i;
+      break;
+    }
+  }
+  if (ev < F.nw) atomicMin(F.tev, F.t0 + ev);
+}
+
+__global__ __launch_bounds__(256) void k_ff_scan_cli(OpenArgs A, FFArgs F, const uint64_t *dlab) {
+  const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= A.n || !A.ceff[c] || A.frz[c] != FL_RUNG_NONE) return;
+  const uint32_t g = seg_of(A.gid, (uint32_t)c);
+  if (!F.run[g]) return;
+  const uint64_t L = dlab[c];
+  if (L == INF64) return;
+  const double d = (double)(uint32_t)(L >> 32);
+  const double *a = F.lw + (size_t)g * FF_WIN;
+  for (uint32_t i = 0; i < F.nw; ++i)
+    if (d <= F.one_eps * a[i]) {
+      atomicMin(F.tev, F.t0 + i);
+      return;
+    }
+}
+
+// the quiet rungs t0 .. t0 + nr - 1
+__global__ __launch_bounds__(256) void k_ff_apply(OpenArgs A, FFArgs F, uint32_t nr) {
+  const uint32_t fi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (fi >= A.nF || A.state[fi]) return;
+  const uint32_t g = seg_of(A.gid, A.fac_list[fi]);
+  if (!F.run[g]) return;
+  const double *a = F.lw + (size_t)g * FF_WIN;
+  double q = A.q[fi];
+  const double nh = A.nhat[fi];
+  for (uint32_t i = 0; i < nr; ++i) {
+    const double ea = F.eps * a[i];
+    q = q + ea * nh;
+  }
+  A.q[fi] = q;
+}
+
 // opened facilities become sources at distance 0 (tie = own id)
 __global__ void k_seed_opened(const uint32_t *opened, const uint32_t *cnt, uint64_t *lab) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -394,6 +472,11 @@ int open_phase(Ctx &c, const OpenIn &in, OpenOut &out) {
   RungParam *d_rp = c.arena->get<RungParam>(G);
   A.rp = d_rp;
   uint8_t *d_gflag = c.arena->get<uint8_t>(G);
+  double *d_lw = c.arena->get<double>((size_t)G * FF_WIN);
+  uint8_t *d_run = c.arena->get<uint8_t>(G);
+  uint32_t *d_tev = c.arena->get<uint32_t>(1);
+  std::vector<double> h_lw((size_t)G * FF_WIN);
+  std::vector<uint8_t> h_run(G);
   uint64_t *dlab = c.arena->get<uint64_t>(n);
   fill_u64(c, dlab, n, INF64);
   fill_u32(c, out.frz, n, FL_RUNG_NONE);
@@ -445,6 +528,51 @@ int open_phase(Ctx &c, const OpenIn &in, OpenOut &out) {
     bool any = false;
     for (uint32_t q = 0; q < G; ++q) any |= !done[q];
     if (!any) break;
+    // skip the quiet rungs before the next event (not the first rung, which
+    // uses Eq. 2, and not right after a freeze, which changes N)
+    bool can_ff = t >= 1 && nF > 0;
+    bool any_open = false;
+    for (uint32_t q = 0; q < G && can_ff; ++q) {
+      if (done[q]) continue;
+      can_ff = !frz_prev[q];
+      any_open |= nO[q] > 0;
+    }
+    if (can_ff) {
+      const uint32_t t0 = t + 1;
+      for (uint32_t q = 0; q < G && can_ff; ++q) {
+        h_run[q] = !done[q];
+        std::vector<double> &lad = (*in.lad)[q];
+        if (!h_run[q]) continue;
+        while (lad.size() < (size_t)t0 + FF_WIN) lad.push_back(lad.back() * one_eps);
+        for (uint32_t i = 0; i < FF_WIN; ++i) {
+          const double a = lad[t0 + i];
+          if (!std::isfinite(a)) can_ff = false;  // the rung loop reports the overflow
+          h_lw[(size_t)q * FF_WIN + i] = a;
+        }
+      }
+      if (can_ff) {
+        FL_HIP(hipMemcpyAsync(d_lw, h_lw.data(), h_lw.size() * 8, hipMemcpyHostToDevice, c.s));
+        FL_HIP(hipMemcpyAsync(d_run, h_run.data(), G, hipMemcpyHostToDevice, c.s));
+        fill_u32(c, d_tev, 1, t0 + FF_WIN);
+        FFArgs F{d_lw, d_run, t0, FF_WIN, in.eps, one_eps, d_tev};
+        k_ff_scan_fac<<<fblocks, 256, 0, c.s>>>(A, F);
+        FL_LAUNCH_CHECK();
+        if (any_open) {
+          k_ff_scan_cli<<<vblocks, 256, 0, c.s>>>(A, F, dlab);
+          FL_LAUNCH_CHECK();
+        }
+        FL_HIP(hipMemcpyAsync(c.h_status, d_tev, 4, hipMemcpyDeviceToHost, c.s));
+        c.sync();
+        const uint32_t tev = (uint32_t)(c.h_status[0] & 0xFFFFFFFFu);
+        if (tev > t0) {
+          k_ff_apply<<<fblocks, 256, 0, c.s>>>(A, F, tev - t0);
+          FL_LAUNCH_CHECK();
+          t = tev - 1;
+          for (uint32_t q = 0; q < G; ++q)
+            if (!done[q]) out.rungs[q] = t;
+        }
+      }
+    }
     ++t;
     for (uint32_t q = 0; q < G; ++q) {
       RungParam &R = rp[q];
