@@ -191,6 +191,57 @@ def serve_bench(count, seed, rate, slots):
             "solves_per_s": round(count / span, 3), "offered_per_s": rate}
 
 
+def accuracy_experiment(ks, samples, seed):
+    """HIP-estimator accuracy (the protocol of Sec. 5.1): for sampled vertices
+    v and distances d, the relative error |N(v,d) - |B(v,d)|| / |B(v,d)| of the
+    estimate from the GPU sketches, against exact ball sizes from scipy's
+    Dijkstra.  Unweighted graphs use d = 1..20, weighted (1..100) graphs
+    d = 100..2000 step 100, as in the paper's figures."""
+    import numpy as np
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import dijkstra
+    import torch
+    import graphgen as gg
+    import paper_1503_03635_amd as fl
+    cases = [("rmat14_unit", lambda: gg.rmat(14, 16 << 14, seed), list(range(1, 21))),
+             ("rmat14_w1..100", lambda: gg.rmat(14, 16 << 14, seed, wmax=100), list(range(100, 2001, 100))),
+             ("forestfire8k_unit", lambda: gg.forest_fire(8000, seed), list(range(1, 21))),
+             ("forestfire8k_w1..100", lambda: gg.forest_fire(8000, seed, wmax=100), list(range(100, 2001, 100)))]
+    out = {}
+    rng = np.random.Generator(np.random.PCG64(seed))
+    for name, make, dists in cases:
+        g = make()
+        w = g.w if g.w is not None else np.ones(g.n_arcs, np.uint32)
+        A = sp.csr_matrix((w.astype(np.float64), g.col.astype(np.int64), g.row_ptr.astype(np.int64)),
+                          shape=(g.n, g.n))
+        deg = g.degrees()
+        cand = np.nonzero(deg > 0)[0]
+        vs = rng.choice(cand, size=min(samples, len(cand)), replace=False)
+        D = dijkstra(A, directed=True, indices=vs)
+        exact = np.array([[np.count_nonzero(D[i] <= d) for d in dists] for i in range(len(vs))], np.float64)
+        dg = fl.to_device(g, "cuda:0")
+        res = {}
+        for k in ks:
+            s = fl.ads_build(dg, k, seed)
+            torch.cuda.synchronize()
+            off = s["off"].cpu().numpy().view(np.uint64).astype(np.int64)
+            dist = s["dist"].cpu().numpy().view(np.uint32).astype(np.float64)
+            thr = s["thresh"].cpu().numpy().view(np.uint32).astype(np.float64)
+            a = np.where(thr == 0, 1.0, 4294967296.0 / np.maximum(thr, 1.0))
+            est = np.zeros_like(exact)
+            for i, v in enumerate(vs):
+                dv, av = dist[off[v]:off[v + 1]], a[off[v]:off[v + 1]]
+                for j, d in enumerate(dists):
+                    est[i, j] = av[dv <= d].sum()
+            rel = np.abs(est - exact) / exact
+            res[f"k{k}"] = {"mean_rel_err": round(float(rel.mean()), 4),
+                            "max_rel_err": round(float(rel.max()), 4),
+                            "mean_rel_err_by_d": [round(float(x), 4) for x in rel.mean(axis=0)]}
+            log(f"[accuracy] {name} k={k}: mean relative error {rel.mean():.4f}")
+        out[name] = {"n": g.n, "arcs": g.n_arcs, "samples": int(len(vs)), "distances": dists, "by_k": res}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -208,6 +259,8 @@ def main():
     ap.add_argument("--serve-count", type=int, default=64, help="requests of the serving measurement (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=3)
+    ap.add_argument("--accuracy", action="store_true",
+                    help="run the HIP-estimator accuracy experiment instead and print its JSON")
     ap.add_argument("--pmc-calibration", action="store_true",
                     help="run a 1 GiB device copy first (counter calibration)")
     ap.add_argument("--traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -215,6 +268,9 @@ def main():
     args = ap.parse_args()
     if args.traffic:
         write_traffic(*args.traffic)
+        return
+    if args.accuracy:
+        print(json.dumps({"accuracy": accuracy_experiment([4, 8, 16, 32, 64], 100, args.seed)}), flush=True)
         return
 
     if args.gpus != 1:

@@ -11,6 +11,8 @@ uniform weights in 1..100; the workloads below stand in for them):
 * ``er``        Erdos-Renyi G(n, p), sampled by geometric skips over vertex pairs.
 * ``rmat``      R-MAT edge sampling (Chakrabarti et al.), seeded vertex relabelling.
 * ``chung_lu``  power-law expected-degree graphs (Chung-Lu), degree cap sqrt(sum w).
+* ``forest_fire`` the Forest Fire growth model (Leskovec, Kleinberg, Faloutsos),
+                symmetrised.
 * small structured graphs (path, star, clique, grid, tree, disjoint unions).
 
 Every generator draws from ``numpy.random.Generator(PCG64(seed))`` only, so
@@ -172,6 +174,57 @@ def rmat(scale: int, n_samples: int, seed: int, abcd=(0.57, 0.19, 0.19, 0.05),
     u = perm[u]
     v = perm[v]
     return from_edges(n, u, v, wmax, rng, name=f"rmat_s{scale}_m{n_samples}")
+
+
+def forest_fire(n: int, seed: int, p_fwd: float = 0.3, p_bwd: float = 0.4,
+                wmax: Optional[int] = None, max_burn: int = 4096) -> Graph:
+    """Forest Fire (Leskovec, Kleinberg, Faloutsos, KDD 2005): vertex v links
+    to a uniformly chosen earlier ambassador, then spreads from each newly
+    reached vertex x to Geometric(mean p/(1-p)) of x's unvisited out-neighbours
+    (forward burning p_fwd) and in-neighbours (backward burning p_bwd),
+    linking to each; at most max_burn vertices per arrival.  The directed
+    links are symmetrised.  Pure Python: meant for n up to about 10^5."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out_adj = [[] for _ in range(n)]
+    in_adj = [[] for _ in range(n)]
+    us, vs = [], []
+
+    def pick(cands, count):
+        if count <= 0 or not cands:
+            return []
+        if count >= len(cands):
+            return cands
+        idx = rng.choice(len(cands), size=count, replace=False)
+        return [cands[i] for i in idx]
+
+    for v in range(1, n):
+        amb = int(rng.integers(0, v))
+        visited = {v, amb}
+        frontier = [amb]
+        linked = [amb]
+        while frontier and len(linked) < max_burn:
+            nxt = []
+            for x in frontier:
+                nf = int(rng.geometric(1.0 - p_fwd)) - 1
+                nb = int(rng.geometric(1.0 - p_bwd)) - 1
+                chosen = pick([y for y in out_adj[x] if y not in visited], nf)
+                chosen += pick([y for y in in_adj[x] if y not in visited and y not in chosen], nb)
+                for y in chosen:
+                    if len(linked) >= max_burn:
+                        break
+                    visited.add(y)
+                    linked.append(y)
+                    nxt.append(y)
+            frontier = nxt
+        for y in linked:
+            out_adj[v].append(y)
+            in_adj[y].append(v)
+            us.append(v)
+            vs.append(y)
+    u = np.asarray(us, np.uint32)
+    w_ = np.asarray(vs, np.uint32)
+    perm = rng.permutation(n).astype(np.uint32)
+    return from_edges(n, perm[u], perm[w_], wmax, rng, name=f"ff_n{n}_p{p_fwd}_{p_bwd}")
 
 
 def chung_lu(n: int, seed: int, exponent: float = 2.2, avg_deg: float = 10.0,

@@ -328,17 +328,64 @@ __device__ inline bool rung_key(uint32_t v, const uint32_t *rung, const uint32_t
   *key = koff[g] + t - 1;
   return true;
 }
-__global__ void k_rung_count(uint32_t n, const uint32_t *rung, const uint32_t *gid, const uint32_t *koff,
-                             const uint32_t *Tg, uint32_t *cnt) {
-  const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// With few keys (K <= RK_LDS) a block counts in LDS first and adds one
+// global atomic per key it saw: the per-rung counters are otherwise hit by
+// every vertex of the rung.
+constexpr uint32_t RK_LDS = 4096;
+constexpr uint32_t RK_ITEMS = 16;  // vertices per thread in the LDS path
+__global__ __launch_bounds__(256) void k_rung_count(uint32_t n, const uint32_t *rung, const uint32_t *gid,
+                                                    const uint32_t *koff, const uint32_t *Tg, uint32_t K,
+                                                    uint32_t *cnt) {
+  __shared__ uint32_t lc[RK_LDS];
   uint32_t key;
-  if (v < n && rung_key((uint32_t)v, rung, gid, koff, Tg, &key)) atomicAdd(&cnt[key], 1u);
+  if (K > RK_LDS) {
+    const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n && rung_key((uint32_t)v, rung, gid, koff, Tg, &key)) atomicAdd(&cnt[key], 1u);
+    return;
+  }
+  for (uint32_t i = threadIdx.x; i < K; i += blockDim.x) lc[i] = 0;
+  __syncthreads();
+  const uint64_t v0 = (uint64_t)blockIdx.x * blockDim.x * RK_ITEMS;
+  for (uint32_t it = 0; it < RK_ITEMS; ++it) {
+    const uint64_t v = v0 + (uint64_t)it * blockDim.x + threadIdx.x;
+    if (v < n && rung_key((uint32_t)v, rung, gid, koff, Tg, &key)) atomicAdd(&lc[key], 1u);
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < K; i += blockDim.x)
+    if (lc[i]) atomicAdd(&cnt[i], lc[i]);
 }
-__global__ void k_rung_scatter(uint32_t n, const uint32_t *rung, const uint32_t *gid, const uint32_t *koff,
-                               const uint32_t *Tg, const uint64_t *off, uint32_t *cur, uint32_t *out) {
-  const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_rung_scatter(uint32_t n, const uint32_t *rung, const uint32_t *gid,
+                                                      const uint32_t *koff, const uint32_t *Tg, uint32_t K,
+                                                      const uint64_t *off, uint32_t *cur, uint32_t *out) {
+  __shared__ uint32_t lc[RK_LDS];
   uint32_t key;
-  if (v < n && rung_key((uint32_t)v, rung, gid, koff, Tg, &key)) out[off[key] + atomicAdd(&cur[key], 1u)] = (uint32_t)v;
+  if (K > RK_LDS) {
+    const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n && rung_key((uint32_t)v, rung, gid, koff, Tg, &key))
+      out[off[key] + atomicAdd(&cur[key], 1u)] = (uint32_t)v;
+    return;
+  }
+  // local positions, then one reservation per key, then the writes
+  for (uint32_t i = threadIdx.x; i < K; i += blockDim.x) lc[i] = 0;
+  __syncthreads();
+  const uint64_t v0 = (uint64_t)blockIdx.x * blockDim.x * RK_ITEMS;
+  uint32_t lpos[RK_ITEMS], keys[RK_ITEMS];
+  for (uint32_t it = 0; it < RK_ITEMS; ++it) {
+    const uint64_t v = v0 + (uint64_t)it * blockDim.x + threadIdx.x;
+    keys[it] = INF32;
+    if (v < n && rung_key((uint32_t)v, rung, gid, koff, Tg, &key)) {
+      keys[it] = key;
+      lpos[it] = atomicAdd(&lc[key], 1u);
+    }
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < K; i += blockDim.x)
+    if (lc[i]) lc[i] = atomicAdd(&cur[i], lc[i]);
+  __syncthreads();
+  for (uint32_t it = 0; it < RK_ITEMS; ++it) {
+    const uint64_t v = v0 + (uint64_t)it * blockDim.x + threadIdx.x;
+    if (keys[it] != INF32) out[off[keys[it]] + lc[keys[it]] + lpos[it]] = (uint32_t)v;
+  }
 }
 // concatenate ranges [src + start, src + start + len) of a list; one block per range
 __global__ void k_gather_ranges(const uint32_t *src, const uint64_t *rstart, const uint32_t *rlen,
@@ -368,11 +415,11 @@ static void by_rung(Ctx &c, uint32_t n, const uint32_t *rung, const uint32_t *gi
   uint64_t *off = c.arena->get<uint64_t>((size_t)K + 2);
   fill_u32(c, cnt, K + 1, 0);
   fill_u32(c, cur, K + 1, 0);
-  const uint32_t vb = (uint32_t)ceil_div(n, 256);
-  k_rung_count<<<vb, 256, 0, c.s>>>(n, rung, gid, koff, Tg, cnt);
+  const uint32_t vb = (uint32_t)(K > RK_LDS ? ceil_div(n, 256) : ceil_div(n, 256 * RK_ITEMS));
+  k_rung_count<<<vb, 256, 0, c.s>>>(n, rung, gid, koff, Tg, K, cnt);
   FL_LAUNCH_CHECK();
   scan_u32_to_u64(c, cnt, off, K);
-  k_rung_scatter<<<vb, 256, 0, c.s>>>(n, rung, gid, koff, Tg, off, cur, list);
+  k_rung_scatter<<<vb, 256, 0, c.s>>>(n, rung, gid, koff, Tg, K, off, cur, list);
   FL_LAUNCH_CHECK();
   hoff.resize((size_t)K + 1);
   FL_HIP(hipMemcpyAsync(hoff.data(), off, hoff.size() * 8, hipMemcpyDeviceToHost, c.s));
