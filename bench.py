@@ -242,6 +242,47 @@ def accuracy_experiment(ks, samples, seed):
     return out
 
 
+def sweep_experiment(seed):
+    """Time vs k and vs eps (the paper's Fig. 3 and Fig. 4 on synthetic
+    graphs): full solves of R-MAT 2^20 (16 edge samples per vertex, unit
+    weights, costs 1..1000) for k in {16, 32, 64} at eps = 0.1 and for eps in
+    {0.01, 0.1, 1} at k = 32, and the same eps sweep on a Forest Fire graph
+    (n = 20,000, weights 1..100).  Each point: one untimed solve, then the
+    median of three."""
+    import torch
+    import graphgen as gg
+    import paper_1503_03635_amd as fl
+
+    def point(dg, k, eps):
+        fl.solve(dg, k, seed, eps)
+        torch.cuda.synchronize()
+        runs = []
+        for _ in range(3):
+            r = fl.solve(dg, k, seed, eps)
+            torch.cuda.synchronize()
+            runs.append(r)
+        runs.sort(key=lambda r: r["stats"]["ms_total"])
+        st = runs[1]["stats"]
+        return {"k": k, "eps": eps, "ms_total": round(st["ms_total"], 1), "ms_ads": round(st["ms_ads"], 1),
+                "ms_open": round(st["ms_open"], 1), "ms_mis": round(st["ms_mis"], 1), "rungs": st["rungs"],
+                "mis_rounds": st["mis_rounds"], "n_open": runs[1]["n_open"], "cost": runs[1]["total_cost"],
+                "ads_entries": st["ads_entries"], "relax_alg": st["relax_alg"]}
+
+    out = {}
+    g = gg.rmat_unit(20, 16, seed)
+    dg = fl.to_device(g, "cuda:0")
+    out["rmat20_unit"] = {"n": g.n, "arcs": g.n_arcs,
+                          "k_sweep": [point(dg, k, 0.1) for k in (16, 32, 64)],
+                          "eps_sweep": [point(dg, 32, e) for e in (0.01, 0.1, 1.0)]}
+    log(f"[sweep] rmat20: {out['rmat20_unit']}")
+    g = gg.with_problem(gg.forest_fire(20000, seed, wmax=100), seed, cost="uniform")
+    dg = fl.to_device(g, "cuda:0")
+    out["forestfire20k_w1..100"] = {"n": g.n, "arcs": g.n_arcs,
+                                    "eps_sweep": [point(dg, 32, e) for e in (0.01, 0.1, 1.0)]}
+    log(f"[sweep] forest fire: {out['forestfire20k_w1..100']}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -259,6 +300,8 @@ def main():
     ap.add_argument("--serve-count", type=int, default=64, help="requests of the serving measurement (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=3)
+    ap.add_argument("--sweep", action="store_true",
+                    help="run the k and eps sweeps instead and print their JSON")
     ap.add_argument("--accuracy", action="store_true",
                     help="run the HIP-estimator accuracy experiment instead and print its JSON")
     ap.add_argument("--pmc-calibration", action="store_true",
@@ -268,6 +311,9 @@ def main():
     args = ap.parse_args()
     if args.traffic:
         write_traffic(*args.traffic)
+        return
+    if args.sweep:
+        print(json.dumps({"sweep": sweep_experiment(args.seed)}), flush=True)
         return
     if args.accuracy:
         print(json.dumps({"accuracy": accuracy_experiment([4, 8, 16, 32, 64], 100, args.seed)}), flush=True)
