@@ -59,6 +59,16 @@ struct DeviceCache {
 };
 static DeviceCache g_cache[64];
 
+// Workers of fl_solve_batch: a group is split into up to BATCH_WORKERS
+// sub-unions solved at once on their own streams, so that one sub-union's
+// host synchronisations and small launches overlap another's kernels.
+constexpr int BATCH_WORKERS = 3;
+struct BatchPool {
+  DeviceCache dc[BATCH_WORKERS];
+  hipStream_t st[BATCH_WORKERS] = {};
+};
+static BatchPool g_pool[64];
+
 static DeviceCache &cache_for_current() {
   int dev = 0;
   FL_HIP(hipGetDevice(&dev));
@@ -821,7 +831,11 @@ int fl_solve_batch(const fl_problem *ps, const fl_params *prms, fl_result *outs,
     });
     size_t free_b = 0, total_b = 0;
     FL_HIP(hipMemGetInfo(&free_b, &total_b));
-    const size_t budget = (size_t)((double)(free_b + dc.arena.capacity()) * 0.6);
+    int devb = 0;
+    FL_HIP(hipGetDevice(&devb));
+    size_t held = dc.arena.capacity();
+    for (int w = 0; w < fl::BATCH_WORKERS; ++w) held += fl::g_pool[devb].dc[w].arena.capacity();
+    const size_t budget = (size_t)((double)(free_b + held) * 0.6);
     size_t i0 = 0;
     while (i0 < ok.size()) {
       const fl_params &P0 = prms[ok[i0]];
@@ -855,11 +869,58 @@ int fl_solve_batch(const fl_problem *ps, const fl_params *prms, fl_result *outs,
         gr.push_back(&prms[ok[t]]);
         go.push_back(&outs[ok[t]]);
       }
-      std::vector<int> grc;
-      try {
-        fl::solve_group(gp.data(), gr.data(), go.data(), (uint32_t)gp.size(), (hipStream_t)stream, dc, grc);
-      } catch (fl::Error &e) {
-        grc.assign(gp.size(), e.code);
+      std::vector<int> grc(gp.size(), FL_OK);
+      const int P = (int)std::min<size_t>(fl::BATCH_WORKERS, gp.size());
+      if (P <= 1) {
+        try {
+          fl::solve_group(gp.data(), gr.data(), go.data(), (uint32_t)gp.size(), (hipStream_t)stream, dc, grc);
+        } catch (fl::Error &e) {
+          grc.assign(gp.size(), e.code);
+        }
+      } else {
+        // largest first onto the least loaded worker (elements are in
+        // decreasing n already); each worker keeps its elements in order
+        std::vector<std::vector<size_t>> part(P);
+        std::vector<uint64_t> load(P, 0);
+        for (size_t t = 0; t < gp.size(); ++t) {
+          const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+          part[w].push_back(t);
+          load[w] += (uint64_t)gp[t]->n + gp[t]->n_arcs / 8;
+        }
+        int dev = 0;
+        FL_HIP(hipGetDevice(&dev));
+        fl::BatchPool &pool = fl::g_pool[dev];
+        hipEvent_t ready;
+        FL_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+        FL_HIP(hipEventRecord(ready, (hipStream_t)stream));  // inputs written on the caller's stream
+        std::vector<std::thread> th;
+        for (int w = 0; w < P; ++w) {
+          th.emplace_back([&, w]() {
+            std::vector<const fl_problem *> sp;
+            std::vector<const fl_params *> sr;
+            std::vector<fl_result *> so;
+            for (size_t t : part[w]) {
+              sp.push_back(gp[t]);
+              sr.push_back(gr[t]);
+              so.push_back(go[t]);
+            }
+            std::vector<int> src;
+            try {
+              FL_HIP(hipSetDevice(dev));
+              std::lock_guard<std::mutex> wl(pool.dc[w].mu);
+              if (!pool.st[w]) FL_HIP(hipStreamCreateWithFlags(&pool.st[w], hipStreamNonBlocking));
+              FL_HIP(hipStreamWaitEvent(pool.st[w], ready, 0));
+              fl::solve_group(sp.data(), sr.data(), so.data(), (uint32_t)sp.size(), pool.st[w], pool.dc[w], src);
+            } catch (fl::Error &e) {
+              src.assign(sp.size(), e.code);
+            } catch (std::bad_alloc &) {
+              src.assign(sp.size(), FL_ENOMEM);
+            }
+            for (size_t j = 0; j < part[w].size(); ++j) grc[part[w][j]] = src[j];
+          });
+        }
+        for (auto &t : th) t.join();
+        (void)hipEventDestroy(ready);
       }
       for (size_t t = i0; t < i1; ++t) rc[ok[t]] = grc[t - i0];
       i0 = i1;
@@ -1097,6 +1158,12 @@ void fl_release_workspace(void) {
     fl::DeviceCache &dc = fl::cache_for_current();
     std::lock_guard<std::mutex> lk(dc.mu);
     dc.arena.release();
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64)
+      for (int w = 0; w < fl::BATCH_WORKERS; ++w) {
+        std::lock_guard<std::mutex> wl(fl::g_pool[dev].dc[w].mu);
+        fl::g_pool[dev].dc[w].arena.release();
+      }
   } catch (...) {
   }
 }
