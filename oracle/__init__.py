@@ -84,6 +84,8 @@ def _setup(L):
     L.orc_prune.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32]
     L.orc_hipest.argtypes = [C.POINTER(_Sketch), C.c_uint32, C.c_uint32, C.c_void_p, C.c_void_p]
     L.orc_solve.argtypes = [C.POINTER(_Graph), C.c_uint32, C.c_uint64, C.c_double, C.POINTER(_Result)]
+    L.orc_ads_one.argtypes = [C.POINTER(_Graph), C.c_void_p, C.c_uint32, C.c_uint32, C.c_void_p, C.c_void_p,
+                              C.c_uint32, C.POINTER(C.c_uint32)]
     L.orc_solve_luby.argtypes = [C.POINTER(_Graph), C.c_uint32, C.c_uint64, C.c_double, C.POINTER(_Result)]
     L.orc_opt_exhaustive.argtypes = [C.POINTER(_Graph), C.POINTER(C.c_uint64)]
     L.orc_sssp.argtypes = [C.POINTER(_Graph), C.c_uint32, C.c_void_p]
@@ -189,6 +191,23 @@ def ads_pruned_timed(g, k, seed, max_sources):
     if rc != OK:
         raise RuntimeError(f"oracle ADS failed: {rc}")
     return int(cnt.value)
+
+
+def ads_one(g, k, seed, v, rank=None, cap=1 << 16):
+    """The sketch of vertex v alone (Alg. 1 with the (distance, id) order):
+    (ranks, distances) in sketch order."""
+    h = _Held(g)
+    if rank is None:
+        rank, _ = ranks(g.n, seed)
+    rank = np.ascontiguousarray(rank, np.uint32)
+    out_r = np.zeros(cap, np.uint32)
+    out_d = np.zeros(cap, np.uint32)
+    cnt = C.c_uint32(0)
+    rc = lib().orc_ads_one(C.byref(h.s), _ptr(rank), k, v, _ptr(out_r), _ptr(out_d), cap, C.byref(cnt))
+    if rc != OK:
+        raise RuntimeError(f"orc_ads_one failed: {rc}")
+    m = int(cnt.value)
+    return out_r[:m].copy(), out_d[:m].copy()
 
 
 def ads_rounds(g, k, seed=None, rank=None):

@@ -409,6 +409,40 @@ int orc_ads_brute(const orc_graph *g, const uint32_t *rank, uint32_t k, orc_sket
   return rc;
 }
 
+/* The sketch of one vertex v by the definition (Alg. 1 with the (distance,
+ * id) order): Dijkstra from v, vertices in that order, each inserted iff fewer
+ * than k earlier ones have a smaller rank.  Entries (rank, distance) in
+ * sketch order into out_rank/out_dist (capacity cap); *count receives the
+ * size (ORC_ENOMEM if it exceeds cap).  Used to check single sketches of
+ * graphs too large for the all-vertex builders. */
+int orc_ads_one(const orc_graph *g, const uint32_t *rank, uint32_t k, uint32_t v, uint32_t *out_rank,
+                uint32_t *out_dist, uint32_t cap, uint32_t *count) {
+  uint32_t n = g->n;
+  uint64_t *dist = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
+  uint32_t *order = (uint32_t *)malloc((size_t)n * sizeof(uint32_t));
+  uint32_t *bkv = (uint32_t *)malloc((size_t)k * sizeof(uint32_t));
+  if (!dist || !order || !bkv) return ORC_ENOMEM;
+  uint32_t cnt;
+  int rc = dijkstra(g, v, dist, order, &cnt);
+  bottomk b = {bkv, 0, k};
+  uint32_t m = 0;
+  for (uint32_t i = 0; i < cnt && rc == ORC_OK; i++) {
+    uint32_t u = order[i];
+    if (bk_count_below(&b, rank[u]) < k) {
+      if (m == cap) rc = ORC_ENOMEM;
+      else {
+        out_rank[m] = rank[u];
+        out_dist[m] = (uint32_t)dist[u];
+        m++;
+      }
+    }
+    bk_insert(&b, rank[u]);
+  }
+  *count = m;
+  free(dist); free(order); free(bkv);
+  return rc;
+}
+
 /* (ii) Pruned Dijkstra: sources in increasing rank; a search from u that
  * settles x at distance d is pruned at x when the sketch of x already holds k
  * entries that come before (d, id(u)) -- all of them have a smaller rank,

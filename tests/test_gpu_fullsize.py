@@ -1,0 +1,77 @@
+"""GPU parity at the full size of the benchmark workload (R-MAT 2^22, 64M edge
+samples, unit weights, k = 64, eps = 0.1), in the launch configuration
+bench.py times.  The oracle cannot build all 4M sketches, so sampled outputs
+are checked one by one against it, and the solve against properties that hold
+at any size."""
+import numpy as np
+import pytest
+import torch
+
+import graphgen as gg
+import oracle as O
+import paper_1503_03635_amd as fl
+
+pytestmark = pytest.mark.gpu
+
+K, SEED, EPS = 64, 1, 0.1
+
+
+@pytest.fixture(scope="module")
+def big():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    print("[fullsize] generating R-MAT 2^22", flush=True)
+    g = gg.rmat_unit(22, 16, SEED)
+    return g, fl.to_device(g, "cuda:0")
+
+
+def test_sampled_sketches_equal_definition(big):
+    """Sketches of sampled vertices (ranks, distances, HIP thresholds) equal the
+    oracle's sketch of that vertex by the definition (Alg. 1, (distance, id)
+    order)."""
+    g, dg = big
+    s = fl.ads_build(dg, K, SEED)
+    torch.cuda.synchronize()
+    off = s["off"].cpu().numpy().view(np.uint64)
+    rank = s["rank"].cpu().numpy().view(np.uint32)
+    dist = s["dist"].cpu().numpy().view(np.uint32)
+    thr = s["thresh"].cpu().numpy().view(np.uint32)
+    rk, _ = O.ranks(g.n, SEED)
+    deg = g.degrees()
+    rng = np.random.Generator(np.random.PCG64(11))
+    hubs = np.argsort(deg)[-1:]                                # the largest hub
+    sample = np.concatenate([hubs, rng.choice(np.nonzero(deg > 0)[0], 3, replace=False)])
+    for v in sample:
+        print(f"[fullsize] vertex {v} (degree {deg[v]})", flush=True)
+        r_want, d_want = O.ads_one(g, K, SEED, int(v), rank=rk)
+        o0, o1 = int(off[v]), int(off[v + 1])
+        assert np.array_equal(rank[o0:o1], r_want), f"ranks of {v}"
+        assert np.array_equal(dist[o0:o1], d_want), f"distances of {v}"
+        # HIP thresholds: k-th smallest rank among the earlier entries
+        want_t = np.zeros(len(r_want), np.uint32)
+        for j in range(K, len(r_want)):
+            want_t[j] = np.partition(r_want[:j], K - 1)[K - 1]
+        assert np.array_equal(thr[o0:o1], want_t), f"thresholds of {v}"
+
+
+def test_solve_properties(big):
+    """One solve as bench.py runs it: the objective equals its definition from
+    the outputs (Sec. 3.1), and sampled clients are assigned to their nearest
+    open facility (ties: smaller id) at the exact distance."""
+    g, dg = big
+    r = fl.solve(dg, K, SEED, EPS, diagnostics=True)
+    torch.cuda.synchronize()
+    opened = r["open"].cpu().numpy().astype(bool)
+    assign = r["assign"].cpu().numpy().view(np.uint32)
+    dist = r["dist"].cpu().numpy().view(np.uint32)
+    served = assign != fl.FL_NONE
+    cost = int(g.fac_cost[opened].astype(np.uint64).sum()) + int(dist[served].astype(np.uint64).sum())
+    assert cost == r["total_cost"]
+    assert int(opened.sum()) == r["n_open"]
+    assert opened[assign[served]].all()
+    rng = np.random.Generator(np.random.PCG64(12))
+    for c in rng.choice(np.nonzero(served)[0], 2, replace=False):
+        d = O.sssp(g, int(c))
+        fac = np.nonzero(opened)[0]
+        best = fac[np.lexsort((fac, d[fac]))[0]]
+        print(f"[fullsize] client {c}: nearest open {best} at {d[best]}", flush=True)
+        assert assign[c] == best and dist[c] == d[best]

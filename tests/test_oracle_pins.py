@@ -118,6 +118,21 @@ def test_ads_three_ways_agree(gi, k):
         assert np.array_equal(a[key], c[key]), key
 
 
+def test_ads_one_vertex_equals_full_builders():
+    """The single-vertex sketch (used at sizes the all-vertex builders cannot
+    reach) equals the brute-force and pruned builders row by row."""
+    for g, k, seed in ((gg.rmat(11, 16 << 11, 4), 16, 2), (gg.er(400, 6, 3, wmax=9), 8, 5),
+                       (gg.grid(12, 12), 4, 1)):
+        brute = O.ads_brute(g, k, seed=seed)
+        pruned = O.ads_pruned(g, k, seed=seed)
+        for v in range(0, g.n, max(1, g.n // 25)):
+            r, d = O.ads_one(g, k, seed, v)
+            o0, o1 = brute["off"][v], brute["off"][v + 1]
+            assert np.array_equal(r, brute["rank"][o0:o1]) and np.array_equal(d, brute["dist"][o0:o1])
+            p0, p1 = pruned["off"][v], pruned["off"][v + 1]
+            assert np.array_equal(r, pruned["rank"][p0:p1])
+
+
 @pytest.mark.parametrize("gi", [0, 2, 3, 6])
 def test_ads_k_at_least_n_is_exact_ball(gi):
     """P2: with k >= n every reachable vertex is in the sketch at its exact
