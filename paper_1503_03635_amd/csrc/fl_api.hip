@@ -677,7 +677,11 @@ static void slot_main(Slot *sl) {
           S.cv_work.wait(lk);  // wait for a running slot to finish
           continue;
         }
-        for (size_t i = 1; i < S.queue.size() && batch.size() < 4096; ++i) {
+        // share the waiting requests among the idle workers (this one included)
+        size_t idle = 0;
+        for (Slot *x : S.slots) idle += x->busy ? 0 : 1;
+        const size_t take = std::max<size_t>(1, (S.queue.size() + idle - 1) / std::max<size_t>(idle, 1));
+        for (size_t i = 1; i < S.queue.size() && batch.size() < std::min<size_t>(take, 4096); ++i) {
           Request *r = S.queue[i];
           if (!same_group(head, r)) continue;
           batch.push_back(r);
