@@ -1,7 +1,8 @@
 """Seeded synthetic inputs for sketch-based facility location.
 
 This module only builds inputs: undirected graphs as symmetric CSR arrays,
-edge weights, facility opening costs and client sets.  It holds none of the
+directed graphs as CSR arrays of out-arcs, edge weights, facility opening
+costs and client sets.  It holds none of the
 method's arithmetic, and both the HIP library's tests and the CPU oracle take
 their inputs from here.
 
@@ -14,6 +15,10 @@ uniform weights in 1..100; the workloads below stand in for them):
 * ``forest_fire`` the Forest Fire growth model (Leskovec, Kleinberg, Faloutsos),
                 symmetrised.
 * small structured graphs (path, star, clique, grid, tree, disjoint unions).
+
+Directed variants (``directed=True`` on ``rmat``, ``forest_fire``, ``er``,
+``chung_lu``, ``path`` and ``cycle``) keep the sampled arcs as they are:
+self loops and repeated arcs are dropped, and every arc draws its own weight.
 
 Every generator draws from ``numpy.random.Generator(PCG64(seed))`` only, so
 the same seed gives the same arrays on every machine.
@@ -36,6 +41,7 @@ class Graph:
     is_client: Optional[np.ndarray] = None  # uint8 [n] or None (every vertex a client)
     name: str = ""
     meta: dict = field(default_factory=dict)
+    directed: bool = False              # rows are out-arcs of a directed graph
 
     @property
     def n_arcs(self) -> int:
@@ -99,6 +105,51 @@ def from_edges(n: int, u: np.ndarray, v: np.ndarray, wmax: Optional[int] = None,
                  meta={"edges": int(m)})
 
 
+def from_arcs(n: int, u: np.ndarray, v: np.ndarray, wmax: Optional[int] = None,
+              rng: Optional[np.random.Generator] = None, name: str = "") -> Graph:
+    """Directed simple graph from an arc list u -> v: self loops and repeated
+    arcs are dropped, then every arc gets a weight uniform in 1..wmax (None:
+    unit weights), drawn in sorted arc order.  Rows hold out-arcs."""
+    u = np.asarray(u, dtype=np.uint64)
+    v = np.asarray(v, dtype=np.uint64)
+    keep = u != v
+    keys = _sort_keys((u[keep] << np.uint64(32)) | v[keep])
+    src = (keys >> np.uint64(32)).astype(np.uint32)
+    col = (keys & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+    m = src.shape[0]
+    w = None
+    if wmax is not None:
+        if rng is None:
+            raise ValueError("weights need a generator")
+        w = rng.integers(1, wmax + 1, size=m, dtype=np.uint32)
+    counts = np.bincount(src, minlength=n).astype(np.uint64)
+    row_ptr = np.zeros(n + 1, np.uint64)
+    np.cumsum(counts, out=row_ptr[1:])
+    return Graph(n=n, row_ptr=row_ptr, col=np.ascontiguousarray(col, np.uint32),
+                 w=None if w is None else np.ascontiguousarray(w, np.uint32), name=name,
+                 meta={"arcs": int(m)}, directed=True)
+
+
+def _build(directed, n, u, v, wmax, rng, name):
+    if directed:
+        return from_arcs(n, u, v, wmax, rng, name="d" + name)
+    return from_edges(n, u, v, wmax, rng, name=name)
+
+
+def reverse(g: Graph) -> Graph:
+    """The graph with every arc turned around (weights kept), rows sorted."""
+    src = np.repeat(np.arange(g.n, dtype=np.uint64), np.diff(g.row_ptr.astype(np.int64)))
+    keys = (g.col.astype(np.uint64) << np.uint64(32)) | src
+    order = _argsort_u64(keys)
+    col = src[order].astype(np.uint32)
+    counts = np.bincount(g.col, minlength=g.n).astype(np.uint64)
+    row_ptr = np.zeros(g.n + 1, np.uint64)
+    np.cumsum(counts, out=row_ptr[1:])
+    w = None if g.w is None else np.ascontiguousarray(g.w[order], np.uint32)
+    return Graph(n=g.n, row_ptr=row_ptr, col=np.ascontiguousarray(col), w=w, fac_cost=g.fac_cost,
+                 is_client=g.is_client, name="rev_" + g.name, directed=g.directed)
+
+
 def _argsort_u64(keys: np.ndarray) -> np.ndarray:
     if keys.shape[0] > (1 << 22):
         try:
@@ -113,11 +164,20 @@ def _argsort_u64(keys: np.ndarray) -> np.ndarray:
 # --------------------------------------------------------------------------
 # graph families
 # --------------------------------------------------------------------------
-def er(n: int, avg_deg: float, seed: int, wmax: Optional[int] = None) -> Graph:
+def er(n: int, avg_deg: float, seed: int, wmax: Optional[int] = None, directed: bool = False) -> Graph:
     """G(n, p) with p = avg_deg / (n - 1): geometric skips over the pairs
-    i < j in row-major order."""
+    i < j in row-major order.  Directed: each of the n(n-1) ordered pairs is
+    an arc with probability p (avg_deg is then the mean out-degree)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     p = avg_deg / (n - 1)
+    if directed:
+        nord = n * (n - 1)
+        cnt = int(rng.binomial(nord, p))
+        idx = np.sort(rng.choice(nord, size=cnt, replace=False)).astype(np.int64)
+        i = idx // (n - 1)
+        j = idx % (n - 1)
+        j = j + (j >= i)                            # skip the diagonal
+        return from_arcs(n, i, j, wmax, rng, name=f"der_n{n}_d{avg_deg}")
     npairs = n * (n - 1) // 2
     pos = []
     cur = -1
@@ -145,10 +205,11 @@ def er(n: int, avg_deg: float, seed: int, wmax: Optional[int] = None) -> Graph:
 
 
 def rmat(scale: int, n_samples: int, seed: int, abcd=(0.57, 0.19, 0.19, 0.05),
-         wmax: Optional[int] = None, chunk: int = 1 << 24) -> Graph:
+         wmax: Optional[int] = None, chunk: int = 1 << 24, directed: bool = False) -> Graph:
     """R-MAT: each sample picks one quadrant per level with probabilities
     (a, b, c, d); vertices are relabelled by a seeded permutation; self loops
-    and duplicates are dropped and the graph is symmetrised."""
+    and duplicates are dropped and the graph is symmetrised (directed: each
+    sample is an arc, row -> column)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     a, b, c, _ = abcd
     n = 1 << scale
@@ -173,17 +234,18 @@ def rmat(scale: int, n_samples: int, seed: int, abcd=(0.57, 0.19, 0.19, 0.05),
     perm = rng.permutation(n).astype(np.uint32)
     u = perm[u]
     v = perm[v]
-    return from_edges(n, u, v, wmax, rng, name=f"rmat_s{scale}_m{n_samples}")
+    return _build(directed, n, u, v, wmax, rng, f"rmat_s{scale}_m{n_samples}")
 
 
 def forest_fire(n: int, seed: int, p_fwd: float = 0.3, p_bwd: float = 0.4,
-                wmax: Optional[int] = None, max_burn: int = 4096) -> Graph:
+                wmax: Optional[int] = None, max_burn: int = 4096, directed: bool = False) -> Graph:
     """Forest Fire (Leskovec, Kleinberg, Faloutsos, KDD 2005): vertex v links
     to a uniformly chosen earlier ambassador, then spreads from each newly
     reached vertex x to Geometric(mean p/(1-p)) of x's unvisited out-neighbours
     (forward burning p_fwd) and in-neighbours (backward burning p_bwd),
-    linking to each; at most max_burn vertices per arrival.  The directed
-    links are symmetrised.  Pure Python: meant for n up to about 10^5."""
+    linking to each; at most max_burn vertices per arrival.  The links point
+    from the new vertex to the earlier ones; they are symmetrised unless
+    directed.  Pure Python: meant for n up to about 10^5."""
     rng = np.random.Generator(np.random.PCG64(seed))
     out_adj = [[] for _ in range(n)]
     in_adj = [[] for _ in range(n)]
@@ -224,11 +286,11 @@ def forest_fire(n: int, seed: int, p_fwd: float = 0.3, p_bwd: float = 0.4,
     u = np.asarray(us, np.uint32)
     w_ = np.asarray(vs, np.uint32)
     perm = rng.permutation(n).astype(np.uint32)
-    return from_edges(n, perm[u], perm[w_], wmax, rng, name=f"ff_n{n}_p{p_fwd}_{p_bwd}")
+    return _build(directed, n, perm[u], perm[w_], wmax, rng, f"ff_n{n}_p{p_fwd}_{p_bwd}")
 
 
 def chung_lu(n: int, seed: int, exponent: float = 2.2, avg_deg: float = 10.0,
-             wmax: Optional[int] = None) -> Graph:
+             wmax: Optional[int] = None, directed: bool = False) -> Graph:
     """Chung-Lu power law: expected degrees w_i proportional to
     (i + 1)^(-1/(exponent-1)), scaled to the average degree and capped at
     sqrt(sum w); n*avg/2 endpoint pairs drawn proportionally to w, then
@@ -248,19 +310,19 @@ def chung_lu(n: int, seed: int, exponent: float = 2.2, avg_deg: float = 10.0,
     u = np.minimum(u, n - 1)
     v = np.minimum(v, n - 1)
     perm = rng.permutation(n).astype(np.uint32)
-    return from_edges(n, perm[u], perm[v], wmax, rng, name=f"cl_n{n}_d{avg_deg}")
+    return _build(directed, n, perm[u], perm[v], wmax, rng, f"cl_n{n}_d{avg_deg}")
 
 
-def path(n, wmax=None, seed=0):
+def path(n, wmax=None, seed=0, directed=False):
     rng = np.random.Generator(np.random.PCG64(seed))
     i = np.arange(n - 1)
-    return from_edges(n, i, i + 1, wmax, rng, name=f"path{n}")
+    return _build(directed, n, i, i + 1, wmax, rng, f"path{n}")
 
 
-def cycle(n, wmax=None, seed=0):
+def cycle(n, wmax=None, seed=0, directed=False):
     rng = np.random.Generator(np.random.PCG64(seed))
     i = np.arange(n)
-    return from_edges(n, i, (i + 1) % n, wmax, rng, name=f"cycle{n}")
+    return _build(directed, n, i, (i + 1) % n, wmax, rng, f"cycle{n}")
 
 
 def star(n, wmax=None, seed=0):
@@ -289,11 +351,15 @@ def random_tree(n, seed, wmax=None):
     return from_edges(n, np.arange(1, n), parent, wmax, rng, name=f"tree{n}")
 
 
-def empty(n):
-    return Graph(n=n, row_ptr=np.zeros(n + 1, np.uint64), col=np.zeros(0, np.uint32), name=f"empty{n}")
+def empty(n, directed=False):
+    return Graph(n=n, row_ptr=np.zeros(n + 1, np.uint64), col=np.zeros(0, np.uint32), name=f"empty{n}",
+                 directed=directed)
 
 
 def disjoint_union(*gs: Graph) -> Graph:
+    """Side-by-side union; the parts must be all directed or all undirected."""
+    if len({bool(g.directed) for g in gs}) > 1:
+        raise ValueError("mixing directed and undirected parts")
     n = sum(g.n for g in gs)
     rp = [np.zeros(1, np.uint64)]
     cols, ws = [], []
@@ -309,7 +375,7 @@ def disjoint_union(*gs: Graph) -> Graph:
         ao += g.n_arcs
     return Graph(n=n, row_ptr=np.concatenate(rp), col=np.concatenate(cols).astype(np.uint32),
                  w=np.concatenate(ws).astype(np.uint32) if weighted else None,
-                 name="+".join(g.name for g in gs))
+                 name="+".join(g.name for g in gs), directed=bool(gs[0].directed) if gs else False)
 
 
 # --------------------------------------------------------------------------

@@ -40,7 +40,7 @@ def lib():
 class _Graph(C.Structure):
     _fields_ = [("n", C.c_uint32), ("n_arcs", C.c_uint64),
                 ("row_ptr", C.c_void_p), ("col", C.c_void_p), ("w", C.c_void_p),
-                ("fac_cost", C.c_void_p), ("is_client", C.c_void_p)]
+                ("fac_cost", C.c_void_p), ("is_client", C.c_void_p), ("directed", C.c_uint32)]
 
 
 class _Sketch(C.Structure):
@@ -108,7 +108,8 @@ class _Held:
         ic = getattr(g, "is_client", None)
         self.is_client = None if ic is None else np.ascontiguousarray(ic, dtype=np.uint8)
         self.s = _Graph(int(g.n), int(self.col.shape[0]), _ptr(self.row_ptr), _ptr(self.col),
-                        _ptr(self.w), _ptr(self.fac_cost), _ptr(self.is_client))
+                        _ptr(self.w), _ptr(self.fac_cost), _ptr(self.is_client),
+                        1 if getattr(g, "directed", False) else 0)
 
 
 def _sketch_to_numpy(sk, n):

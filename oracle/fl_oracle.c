@@ -29,6 +29,15 @@
  *                  objective (Sec. 3.1)
  *   exhaustive ... OPT over all non-empty facility subsets (tiny n only)
  *
+ * Directed graphs (Sec. 3.2 considers them; the algorithm is adapted to them
+ * without the guarantee, Sec. 4.4): d(u, v) is the shortest path along arcs
+ * from u to v.  Entries travel along arcs (Alg. 2 sends (u, d + e(u,v)) to
+ * the out-neighbours), so the sketch of v holds vertices u that reach v, at
+ * d(u, v); a facility's estimate counts the clients that can reach it; a
+ * client is served by, frozen by and in conflict through facilities it can
+ * reach, at d(c, f).  Searches for distances into a vertex run on the
+ * reversed arcs.  On an undirected graph both directions coincide.
+ *
  * Readings of passages that are silent or ambiguous are listed in the design
  * notes; the short form of each is repeated at the point of use.
  */
@@ -61,6 +70,8 @@ typedef struct {
   const uint32_t *w;       /* [n_arcs] or NULL = unit weights */
   const uint32_t *fac_cost;/* [n], NOT_FACILITY marks non-facilities; may be NULL for ADS-only calls */
   const uint8_t *is_client;/* [n] or NULL = every vertex is a client */
+  uint32_t directed;       /* 0: symmetric CSR of an undirected graph;
+                              1: rows are the out-arcs of a directed graph */
 } orc_graph;
 
 typedef struct {
@@ -71,6 +82,40 @@ typedef struct {
 } orc_sketch;
 
 static inline uint32_t arcw(const orc_graph *g, uint64_t i) { return g->w ? g->w[i] : 1u; }
+
+/* The graph with every arc turned around: row v lists the u with an arc
+ * u -> v (increasing u), with that arc's weight.  A search from s over it
+ * yields d(u, s), the distance INTO s.  An undirected graph is its own
+ * reverse; then nothing is allocated. */
+typedef struct { orc_graph g; uint64_t *rp; uint32_t *col, *w; } orc_rev;
+
+static int reverse_graph(const orc_graph *g, orc_rev *r) {
+  r->g = *g;
+  r->rp = NULL; r->col = NULL; r->w = NULL;
+  if (!g->directed) return 0;
+  uint32_t n = g->n;
+  uint64_t m = g->n_arcs;
+  r->rp = (uint64_t *)calloc((size_t)n + 1, sizeof(uint64_t));
+  r->col = (uint32_t *)malloc((size_t)(m ? m : 1) * sizeof(uint32_t));
+  r->w = g->w ? (uint32_t *)malloc((size_t)(m ? m : 1) * sizeof(uint32_t)) : NULL;
+  uint64_t *fill = (uint64_t *)malloc((size_t)(n ? n : 1) * sizeof(uint64_t));
+  if (!r->rp || !r->col || (g->w && !r->w) || !fill) return 1;
+  for (uint64_t i = 0; i < m; i++) r->rp[g->col[i] + 1]++;
+  for (uint32_t v = 0; v < n; v++) r->rp[v + 1] += r->rp[v];
+  for (uint32_t v = 0; v < n; v++) fill[v] = r->rp[v];
+  for (uint32_t u = 0; u < n; u++)
+    for (uint64_t i = g->row_ptr[u]; i < g->row_ptr[u + 1]; i++) {
+      uint64_t p = fill[g->col[i]]++;
+      r->col[p] = u;
+      if (r->w) r->w[p] = g->w[i];
+    }
+  free(fill);
+  r->g.row_ptr = r->rp;
+  r->g.col = r->col;
+  r->g.w = r->w;
+  return 0;
+}
+static void reverse_free(orc_rev *r) { free(r->rp); free(r->col); free(r->w); }
 
 /* ------------------------------------------------------------------------ */
 /* Ranks: a seeded bijection on 32-bit integers.                             */
@@ -160,7 +205,9 @@ int orc_perm_check_range(uint64_t key, uint32_t lo, uint64_t count) {
 /* weights).  Reading: a simple undirected graph given as a symmetric CSR     */
 /* with strictly increasing neighbour ids per row, integer weights >= 1, no   */
 /* self loops.  A bound keeps every distance and every cost+distance below    */
-/* 2^32 - 1: (n-1)*max_w + max_cost < 2^32 - 1, else ERANGE.                  */
+/* 2^32 - 1: (n-1)*max_w + max_cost < 2^32 - 1, else ERANGE.  A directed      */
+/* graph (Sec. 3.2) gives its out-arcs per row, with the same rules except    */
+/* symmetry.                                                                   */
 /* ------------------------------------------------------------------------ */
 static int find_arc(const orc_graph *g, uint32_t u, uint32_t v, uint64_t *pos) {
   uint64_t lo = g->row_ptr[u], hi = g->row_ptr[u + 1];
@@ -192,7 +239,8 @@ int orc_validate(const orc_graph *g, uint32_t k, double eps) {
       if (wi > maxw) maxw = wi;
     }
   }
-  for (uint32_t u = 0; u < n; u++) {
+  /* symmetry (same arc both ways, same weight) only for undirected input */
+  for (uint32_t u = 0; u < n && !g->directed; u++) {
     for (uint64_t i = g->row_ptr[u]; i < g->row_ptr[u + 1]; i++) {
       uint64_t back;
       if (!find_arc(g, g->col[i], u, &back)) return ORC_EINVAL;
@@ -283,9 +331,10 @@ int orc_sssp(const orc_graph *g, uint32_t s, uint64_t *dist) { return dijkstra(g
 
 /* Multi-source Dijkstra with lexicographic labels (value, tie).  Each source
  * s carries an initial label (init_val[s], init_tie[s]); a label moves along an
- * arc by adding the arc weight to its value.  Result: for every v the minimum
- * over sources of (init_val[s] + d(v,s), init_tie[s]).  Sources are the v with
- * init_val[v] != ORC_INF64. */
+ * arc of the given graph by adding the arc weight to its value.  Result: for
+ * every v the minimum over sources of (init_val[s] + d'(s,v), init_tie[s]),
+ * d' measured along the given rows; on the reversed graph d'(s,v) = d(v,s).
+ * Sources are the v with init_val[v] != ORC_INF64. */
 static int msdijkstra(const orc_graph *g, const uint64_t *init_val, const uint32_t *init_tie,
                       uint64_t *val, uint32_t *tie) {
   heap h = {0};
@@ -384,6 +433,8 @@ static void bk_insert(bottomk *b, uint32_t r) {
  * have a smaller rank; every listed vertex then enters the bottom-k set. */
 int orc_ads_brute(const orc_graph *g, const uint32_t *rank, uint32_t k, orc_sketch *out) {
   uint32_t n = g->n;
+  orc_rev rv;
+  if (reverse_graph(g, &rv)) return ORC_ENOMEM;
   uint64_t *dist = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
   uint32_t *order = (uint32_t *)malloc((size_t)n * sizeof(uint32_t));
   uint32_t *bkv = (uint32_t *)malloc((size_t)k * sizeof(uint32_t));
@@ -392,7 +443,7 @@ int orc_ads_brute(const orc_graph *g, const uint32_t *rank, uint32_t k, orc_sket
   int rc = ORC_OK;
   for (uint32_t v = 0; v < n && rc == ORC_OK; v++) {
     uint32_t cnt;
-    rc = dijkstra(g, v, dist, order, &cnt);
+    rc = dijkstra(&rv.g, v, dist, order, &cnt); /* d(u, v) for every u */
     bottomk b = {bkv, 0, k};
     for (uint32_t i = 0; i < cnt && rc == ORC_OK; i++) {
       uint32_t u = order[i];
@@ -406,6 +457,7 @@ int orc_ads_brute(const orc_graph *g, const uint32_t *rank, uint32_t k, orc_sket
   if (rc == ORC_OK) rc = sketch_from_vecs(n, vecs, out);
   for (uint32_t v = 0; v < n; v++) free(vecs[v].a);
   free(vecs); free(dist); free(order); free(bkv);
+  reverse_free(&rv);
   return rc;
 }
 
@@ -421,9 +473,10 @@ int orc_ads_one(const orc_graph *g, const uint32_t *rank, uint32_t k, uint32_t v
   uint64_t *dist = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
   uint32_t *order = (uint32_t *)malloc((size_t)n * sizeof(uint32_t));
   uint32_t *bkv = (uint32_t *)malloc((size_t)k * sizeof(uint32_t));
-  if (!dist || !order || !bkv) return ORC_ENOMEM;
+  orc_rev rv;
+  if (!dist || !order || !bkv || reverse_graph(g, &rv)) return ORC_ENOMEM;
   uint32_t cnt;
-  int rc = dijkstra(g, v, dist, order, &cnt);
+  int rc = dijkstra(&rv.g, v, dist, order, &cnt); /* d(u, v) for every u */
   bottomk b = {bkv, 0, k};
   uint32_t m = 0;
   for (uint32_t i = 0; i < cnt && rc == ORC_OK; i++) {
@@ -440,11 +493,12 @@ int orc_ads_one(const orc_graph *g, const uint32_t *rank, uint32_t k, uint32_t v
   }
   *count = m;
   free(dist); free(order); free(bkv);
+  reverse_free(&rv);
   return rc;
 }
 
-/* (ii) Pruned Dijkstra: sources in increasing rank; a search from u that
- * settles x at distance d is pruned at x when the sketch of x already holds k
+/* (ii) Pruned Dijkstra: sources in increasing rank; a search from u along
+ * the arcs (so d = d(u, x)) that settles x at distance d is pruned at x when the sketch of x already holds k
  * entries that come before (d, id(u)) -- all of them have a smaller rank,
  * since sources are taken by increasing rank.  Otherwise (r(u), d) is inserted
  * at its sorted place and the search continues past x.  relax_count (may be
@@ -577,7 +631,7 @@ uint32_t orc_prune(uint64_t *d, uint32_t *id, uint32_t *rank, uint32_t m, uint32
 }
 
 /* (iii) Alg. 2 as synchronous supersteps.  Each vertex receives the entries
- * its neighbours changed in the previous superstep, shifted by the arc
+ * its in-neighbours changed in the previous superstep, shifted by the arc
  * weight; it merges them into its sketch and runs CleanUp on the whole sketch
  * (the per-distance bottom-k rule, applied every superstep here), then sends
  * the entries that are new or got shorter.  Stops when no vertex sends. */
@@ -588,7 +642,9 @@ int orc_ads_rounds(const orc_graph *g, const uint32_t *rank, uint32_t k, orc_ske
   entvec *delta = (entvec *)calloc(n, sizeof(entvec));
   entvec *ndelta = (entvec *)calloc(n, sizeof(entvec));
   uint32_t *bk = (uint32_t *)malloc((size_t)k * sizeof(uint32_t));
-  if (!sk || !delta || !ndelta || !bk) return ORC_ENOMEM;
+  orc_rev rv; /* a vertex receives along its in-arcs */
+  if (!sk || !delta || !ndelta || !bk || reverse_graph(g, &rv)) return ORC_ENOMEM;
+  const orc_graph *gin = &rv.g;
   int rc = ORC_OK;
   for (uint32_t v = 0; v < n; v++) {
     ent e = {0, v, rank[v]};
@@ -604,11 +660,11 @@ int orc_ads_rounds(const orc_graph *g, const uint32_t *rank, uint32_t k, orc_ske
     for (uint32_t u = 0; u < n && rc == ORC_OK; u++) {
       buf.n = 0;
       int got = 0;
-      for (uint64_t i = g->row_ptr[u]; i < g->row_ptr[u + 1]; i++) {
-        uint32_t v = g->col[i];
+      for (uint64_t i = gin->row_ptr[u]; i < gin->row_ptr[u + 1]; i++) {
+        uint32_t v = gin->col[i];
         for (uint32_t j = 0; j < delta[v].n; j++) {
           ent e = delta[v].a[j];
-          e.d += arcw(g, i);
+          e.d += arcw(gin, i);
           if (!ev_push(&buf, e)) { rc = ORC_ENOMEM; break; }
           got = 1;
         }
@@ -637,6 +693,7 @@ int orc_ads_rounds(const orc_graph *g, const uint32_t *rank, uint32_t k, orc_ske
   if (rc == ORC_OK) rc = sketch_from_vecs(n, sk, out);
   for (uint32_t v = 0; v < n; v++) { free(sk[v].a); free(delta[v].a); free(ndelta[v].a); }
   free(sk); free(delta); free(ndelta); free(bk); free(buf.a);
+  reverse_free(&rv);
   return rc;
 }
 
@@ -708,7 +765,8 @@ static double lad_beta(ladder *L, uint64_t d) {
 /* exact value a * 2^52 of a weight a >= 1 (every such double is a multiple of 2^-52) */
 static __int128 fixed52(double a) { return (__int128)ldexp(a, 52); }
 
-/* Bounded search: all vertices within distance <= rho (as doubles) of s. */
+/* Bounded search: all vertices within distance <= rho (as doubles) of s,
+ * along the given rows (on the reversed graph: all c with d(c, s) <= rho). */
 static int ball(const orc_graph *g, uint32_t s, double rho, uint64_t *dist, uint32_t *list, uint32_t *cnt) {
   heap h = {0};
   uint32_t m = 0;
@@ -765,6 +823,11 @@ static int solve_impl(const orc_graph *g, uint32_t k, uint64_t seed, double eps,
   uint32_t *prio = (uint32_t *)malloc((size_t)n * sizeof(uint32_t));
   if (!rank || !prio) return ORC_ENOMEM;
   orc_ranks(n, seed, rank, prio);
+  /* distances from clients to facilities, d(c, f), come from searches that
+   * start at facilities and follow the arcs backwards */
+  orc_rev rv;
+  if (reverse_graph(g, &rv)) return ORC_ENOMEM;
+  const orc_graph *gb = &rv.g;
 
   /* Phase (i): neighbourhood sketching */
   orc_sketch sk = {0};
@@ -776,6 +839,7 @@ static int solve_impl(const orc_graph *g, uint32_t k, uint64_t seed, double eps,
   orc_hipest(&sk, n, k, NULL, aw);
   r->ads_entries = total;
   r->relax_alg = 0;
+  /* every entry of v is sent once along each arc out of v */
   for (uint32_t v = 0; v < n; v++)
     r->relax_alg += (sk.off[v + 1] - sk.off[v]) * (g->row_ptr[v + 1] - g->row_ptr[v]);
 
@@ -806,7 +870,7 @@ static int solve_impl(const orc_graph *g, uint32_t k, uint64_t seed, double eps,
     r->assign[v] = ORC_NONE;
     r->dist[v] = ORC_NONE;
   }
-  rc = msdijkstra(g, ival, itie, gam, fstar);
+  rc = msdijkstra(gb, ival, itie, gam, fstar);
   if (rc != ORC_OK) return rc;
   uint64_t gamma = 0;
   uint32_t nU = 0, unreach = 0;
@@ -913,7 +977,7 @@ static int solve_impl(const orc_graph *g, uint32_t k, uint64_t seed, double eps,
     }
     if (nnew) {
       for (uint32_t v = 0; v < n; v++) { ival[v] = inO[v] ? 0 : ORC_INF64; itie[v] = 0; }
-      rc = msdijkstra(g, ival, itie, dO, tmpt);
+      rc = msdijkstra(gb, ival, itie, dO, tmpt);
       if (rc != ORC_OK) return rc;
     }
     /* Freeze (reading: Alg. 3's rule -- any open facility within
@@ -974,7 +1038,7 @@ static int solve_impl(const orc_graph *g, uint32_t k, uint64_t seed, double eps,
     uint32_t *ncl = (uint32_t *)calloc(m, sizeof(uint32_t));
     for (uint32_t i = 0; i < m; i++) {
       uint32_t cnt;
-      rc = ball(g, fac[i], rho, bdist, blist, &cnt);
+      rc = ball(gb, fac[i], rho, bdist, blist, &cnt); /* d(c, f) <= rho */
       if (rc != ORC_OK) return rc;
       cl[i] = (uint32_t *)malloc((size_t)(cnt ? cnt : 1) * sizeof(uint32_t));
       for (uint32_t z = 0; z < cnt; z++)
@@ -1047,7 +1111,7 @@ static int solve_impl(const orc_graph *g, uint32_t k, uint64_t seed, double eps,
    * nearest facility of S (ties: smaller id); cost = sum of opening costs of
    * S plus the sum of client distances. */
   for (uint32_t v = 0; v < n; v++) { ival[v] = inS[v] ? 0 : ORC_INF64; itie[v] = v; }
-  rc = msdijkstra(g, ival, itie, dO, tmpt);
+  rc = msdijkstra(gb, ival, itie, dO, tmpt);
   if (rc != ORC_OK) return rc;
   uint64_t cost = 0;
   uint32_t nopen = 0;
@@ -1068,6 +1132,7 @@ static int solve_impl(const orc_graph *g, uint32_t k, uint64_t seed, double eps,
   free(aw); free(rank); free(prio); free(ival); free(itie); free(gam); free(fstar);
   free(isF); free(isC); free(inU); free(inO); free(inS); free(dO); free(tmpt);
   free(cursor); free(newly); free(bdist); free(blist); free(rcount); free(L.a);
+  reverse_free(&rv);
   return ORC_OK;
 }
 
@@ -1093,8 +1158,10 @@ int orc_opt_exhaustive(const orc_graph *g, uint64_t *best_cost) {
     }
   if (nF == 0) { *best_cost = 0; return ORC_OK; }
   uint64_t *D = (uint64_t *)malloc((size_t)nF * n * sizeof(uint64_t));
-  if (!D) return ORC_ENOMEM;
-  for (uint32_t i = 0; i < nF; i++) dijkstra(g, F[i], D + (size_t)i * n, NULL, NULL);
+  orc_rev rv;
+  if (!D || reverse_graph(g, &rv)) return ORC_ENOMEM;
+  /* D[i][c] = d(c, F[i]) */
+  for (uint32_t i = 0; i < nF; i++) dijkstra(&rv.g, F[i], D + (size_t)i * n, NULL, NULL);
   uint64_t best = ORC_INF64;
   for (uint64_t mask = 1; mask < (1ull << nF); mask++) {
     uint64_t cost = 0;
@@ -1117,6 +1184,7 @@ int orc_opt_exhaustive(const orc_graph *g, uint64_t *best_cost) {
     if (ok && cost < best) best = cost;
   }
   free(D);
+  reverse_free(&rv);
   *best_cost = best;
   return ORC_OK;
 }

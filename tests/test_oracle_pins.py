@@ -4,6 +4,11 @@ Every check here compares the oracle with something independent of its code:
 hand-worked fixtures from the sketch definition, published reference values,
 library shortest paths (scipy), closed forms derived from the paper's
 equations, brute force, and statistical properties of the estimator.
+
+Directed graphs run through the same pins.  D[u, v] below is the scipy
+distance along arcs from u to v; the sketch of v holds the vertices that
+reach v (column v of D), and clients reach facilities (D[c, f]).  On an
+undirected graph both read the same.
 """
 import itertools
 import math
@@ -27,7 +32,14 @@ def csr_matrix(g):
 
 
 def apsp(g):
+    """D[u, v] = d(u, v) along the arcs (scipy Dijkstra)."""
     return sp_dijkstra(csr_matrix(g), directed=True)
+
+
+def dist_into(g):
+    """Din[v, u] = d(u, v): row v lists the distances into v, which are the
+    distances a sketch of v records."""
+    return apsp(g).T
 
 
 ZOO = [
@@ -40,7 +52,12 @@ ZOO = [
     lambda: gg.disjoint_union(gg.path(25), gg.star(15, wmax=5), gg.empty(3)),
     lambda: gg.random_tree(120, 5, wmax=4),
     lambda: gg.cycle(31),
+    lambda: gg.er(150, 4, 1, wmax=10, directed=True),
+    lambda: gg.rmat(8, 1500, 3, directed=True),     # many vertices with no in- or out-arcs
+    lambda: gg.forest_fire(200, 5, wmax=7, directed=True),
+    lambda: gg.disjoint_union(gg.path(20, directed=True), gg.cycle(17, wmax=3, directed=True)),
 ]
+DIRECTED_ZOO = [i for i in range(len(ZOO)) if ZOO[i]().directed]
 
 
 # ---------------------------------------------------------------- ranks
@@ -133,14 +150,15 @@ def test_ads_one_vertex_equals_full_builders():
             assert np.array_equal(r, pruned["rank"][p0:p1])
 
 
-@pytest.mark.parametrize("gi", [0, 2, 3, 6])
+@pytest.mark.parametrize("gi", [0, 2, 3, 6] + DIRECTED_ZOO)
 def test_ads_k_at_least_n_is_exact_ball(gi):
-    """P2: with k >= n every reachable vertex is in the sketch at its exact
-    shortest-path distance (scipy Dijkstra), and every HIP weight is 1."""
+    """P2: with k >= n every vertex that reaches v is in the sketch of v at
+    its exact shortest-path distance (scipy Dijkstra), and every HIP weight
+    is 1."""
     g = ZOO[gi]()
     k = g.n
     sk = O.ads_pruned(g, k, seed=3)
-    D = apsp(g)
+    D = dist_into(g)
     T, a = O.hipest(sk, k)
     assert np.all(a == 1.0)
     rank, _ = O.ranks(g.n, 3)
@@ -154,7 +172,7 @@ def test_ads_k_at_least_n_is_exact_ball(gi):
         assert np.array_equal(sk["rank"][lo:hi], rank[ids])
 
 
-@pytest.mark.parametrize("gi", [0, 1, 3, 4, 7])
+@pytest.mark.parametrize("gi", [0, 1, 3, 4, 7] + DIRECTED_ZOO)
 @pytest.mark.parametrize("k", [1, 4, 8])
 def test_ads_bottomk_of_every_ball(gi, k):
     """P3: for every v and radius D, the k smallest ranks among sketch entries
@@ -165,7 +183,7 @@ def test_ads_bottomk_of_every_ball(gi, k):
     seed = 5
     sk = O.ads_pruned(g, k, seed=seed)
     rank, _ = O.ranks(g.n, seed)
-    D = apsp(g)
+    D = dist_into(g)
     for v in range(0, g.n, 3):
         lo, hi = sk["off"][v], sk["off"][v + 1]
         ids, dist, rk = sk["id"][lo:hi], sk["dist"][lo:hi].astype(np.int64), sk["rank"][lo:hi]
@@ -184,8 +202,12 @@ def test_ads_bottomk_of_every_ball(gi, k):
 def test_ads_mean_size_matches_expectation():
     """P4: with a rank-independent order the i-th listed vertex enters with
     probability min(1, k/i), so E|ADS(v)| = sum_{i<=reach(v)} min(1, k/i)."""
-    g = gg.er(400, 8, 21)
-    D = apsp(g)
+    for g in (gg.er(400, 8, 21), gg.er(400, 3, 22, directed=True)):
+        _mean_size_check(g)
+
+
+def _mean_size_check(g):
+    D = dist_into(g)
     reach = np.isfinite(D).sum(axis=1)
     for k in (2, 8):
         expect = sum(sum(min(1.0, k / i) for i in range(1, r + 1)) for r in reach)
@@ -218,11 +240,12 @@ def test_prune_is_associative():
             assert np.array_equal(x, y)
 
 
-def test_hip_estimator_unbiased():
+@pytest.mark.parametrize("directed", [False, True])
+def test_hip_estimator_unbiased(directed):
     """P6: over many seeds the HIP estimate of |B(v, d)| averages to the
-    true size (within 4 standard errors)."""
-    g = gg.er(60, 4, 3, wmax=3)
-    D = apsp(g)
+    true size (within 4 standard errors); directed: the in-ball of v."""
+    g = gg.er(60, 4, 3, wmax=3, directed=directed)
+    D = dist_into(g)
     k = 2
     queries = [(0, 2.0), (0, 4.0), (7, 3.0), (13, 6.0)]
     est = {q: [] for q in queries}
@@ -250,6 +273,11 @@ def _problems():
     out.append(gg.with_problem(gg.rmat(9, 3000, 8), 8, cost="uniform", cost_lo=1, cost_hi=1000))
     out.append(gg.with_problem(gg.rmat(9, 3000, 9, wmax=100), 9, cost="lognormal", fac_frac=0.1))
     out.append(gg.with_problem(gg.grid(12, 12, wmax=4), 4, cost="uniform", cost_lo=1, cost_hi=60))
+    # directed: clients reach facilities along arcs
+    out.append(gg.with_problem(gg.er(300, 4, 7, wmax=10, directed=True), 7, cost="uniform", cost_hi=200))
+    out.append(gg.with_problem(gg.rmat(9, 3000, 8, directed=True), 8, cost="uniform", fac_frac=0.3))
+    out.append(gg.with_problem(gg.forest_fire(250, 3, wmax=20, directed=True), 3, cost="lognormal",
+                               fac_frac=0.5, client_frac=0.7))
     return out
 
 
@@ -334,8 +362,8 @@ def _alg3_exact(g, eps, lad, T):
         alpha = lad[t]
         for f in np.nonzero(isF & (opn < 0))[0]:
             lhs = Fr(0)
-            for c in np.nonzero(served & np.isfinite(D[f]))[0]:
-                d = float(D[f, c])
+            for c in np.nonzero(served & np.isfinite(D[:, f]))[0]:
+                d = float(D[c, f])
                 if not d <= lad[T]:
                     continue                  # beyond every evaluated rung
                 if d not in jb:
@@ -361,12 +389,13 @@ def _alg3_exact(g, eps, lad, T):
     return opn, frz, near
 
 
-@pytest.mark.parametrize("seed", [1, 2])
-def test_exact_alg3_when_k_covers_graph(seed):
+@pytest.mark.parametrize("seed,directed", [(1, False), (2, False), (3, True), (4, True)])
+def test_exact_alg3_when_k_covers_graph(seed, directed):
     """P8: with k >= n the sketches are exact balls, and the opening phase is
     Alg. 3 evaluated on exact distances (bucketed); decisions agree except at
     flagged near-ties."""
-    g = gg.with_problem(gg.er(40, 4, seed, wmax=4), seed, cost="uniform", cost_lo=1, cost_hi=30)
+    g = gg.with_problem(gg.er(40, 4, seed, wmax=4, directed=directed), seed, cost="uniform", cost_lo=1,
+                        cost_hi=30)
     eps = 0.1
     r = _solve(g, g.n, seed, eps)
     T = r["n_rungs"]
@@ -428,7 +457,7 @@ def test_mis_is_greedy_maximal_independent(pi):
         Ft = np.nonzero(orung == t)[0]
         Ct = np.nonzero(frung == t)[0]
         rho = (1.0 + eps) * lad[t]
-        H = D[np.ix_(Ft, Ct)] <= rho
+        H = D[np.ix_(Ct, Ft)].T <= rho                    # H[i, j]: d(client j, facility i)
         conf = (H.astype(np.int64) @ H.T.astype(np.int64)) > 0
         np.fill_diagonal(conf, False)
         order = np.argsort(prio[Ft])
@@ -475,7 +504,7 @@ def test_luby_mis_rounds_on_explicit_hbar(pi):
         Ft = np.nonzero(orung == t)[0]
         Ct = np.nonzero(frung == t)[0]
         rho = (1.0 + eps) * lad[t]
-        H = D[np.ix_(Ft, Ct)] <= rho
+        H = D[np.ix_(Ct, Ft)].T <= rho
         conf = (H.astype(np.int64) @ H.T.astype(np.int64)) > 0
         np.fill_diagonal(conf, False)
         active = np.ones(len(Ft), bool)
@@ -544,13 +573,14 @@ def _opt_python(g):
     return best
 
 
-@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("seed", range(9))
 def test_cost_vs_exhaustive_opt(seed):
     """P11: cost >= OPT (exhaustive over facility subsets, n <= 12).  The
     (3+eps) bound is logged, not asserted: same-rung H edges and sketch
-    estimates fall outside the theorems' proofs."""
+    estimates fall outside the theorems' proofs (seeds 6..8: directed)."""
     n = 8 + seed % 5
-    g = gg.with_problem(gg.er(n, 3, seed, wmax=6), seed, cost="uniform", cost_lo=1, cost_hi=25)
+    g = gg.with_problem(gg.er(n, 3, seed, wmax=6, directed=seed >= 6), seed, cost="uniform", cost_lo=1,
+                        cost_hi=25)
     opt = _opt_python(g)
     assert O.opt_exhaustive(g) == opt
     for k in (1, 4, n):
@@ -618,3 +648,75 @@ def test_validation_errors():
     huge.w = np.full(huge.n_arcs, 0x7FFFFFFF, np.uint32)
     huge.fac_cost = np.array([1, 1, 1], np.uint32)
     assert O.validate(huge, 1, 0.1) == O.ERANGE
+
+
+# ---------------------------------------------------------------- directed graphs
+def _as_directed(g):
+    h = gg.Graph(g.n, g.row_ptr, g.col, g.w, g.fac_cost, g.is_client, name="d" + g.name, directed=True)
+    return h
+
+
+@pytest.mark.parametrize("pi", [0, 1, 3, 4])
+def test_directed_reading_of_symmetric_input_is_undirected(pi):
+    """A symmetric arc set read as directed is the undirected graph: the same
+    sketches and the same solve, bit for bit (every search direction
+    coincides)."""
+    g = PROBLEMS[pi]
+    h = _as_directed(g)
+    a, b = O.ads_brute(g, 4, seed=2), O.ads_pruned(h, 4, seed=2)
+    for key in ("off", "rank", "dist", "id"):
+        assert np.array_equal(a[key], b[key]), key
+    ra, rb = _solve(g, 8, 5), _solve(h, 8, 5)
+    for key in ("open", "assign", "dist", "open_rung", "freeze_rung"):
+        assert np.array_equal(ra[key], rb[key]), key
+    assert np.array_equal(ra["q"].view(np.uint64), rb["q"].view(np.uint64))
+    for key in ("total_cost", "n_rungs", "mis_rounds", "relax_alg", "ads_entries"):
+        assert ra[key] == rb[key], key
+
+
+def _star_arcs(n, inward):
+    leaves = np.arange(1, n)
+    hub = np.zeros(n - 1, np.int64)
+    u, v = (leaves, hub) if inward else (hub, leaves)
+    g = gg.from_arcs(n, u, v, None, None, name="instar" if inward else "outstar")
+    g.fac_cost = np.array([7] + [gg.NOT_FACILITY] * (n - 1), np.uint32)
+    g.is_client = None
+    return g
+
+
+def test_directed_stars_serve_along_arcs():
+    """Facility only at the hub.  Arcs into the hub: every leaf reaches it at
+    distance 1, so cost = c(hub) + (n - 1).  Arcs out of the hub: no leaf can
+    reach a facility; they are unreachable and only the hub is served."""
+    n = 9
+    for seed in (1, 2, 3):
+        r = _solve(_star_arcs(n, True), 2, seed)
+        assert r["n_unreachable"] == 0 and r["n_open"] == 1 and r["open"][0] == 1
+        assert np.all(r["assign"] == 0) and np.all(r["dist"][1:] == 1)
+        assert r["total_cost"] == 7 + (n - 1)
+        r = _solve(_star_arcs(n, False), 2, seed)
+        assert r["n_unreachable"] == n - 1 and r["n_open"] == 1
+        assert r["assign"][0] == 0 and np.all(r["assign"][1:] == O.NONE)
+        assert r["total_cost"] == 7
+        # relaxations: every sketch entry of the hub goes out on n - 1 arcs
+        sk = O.ads_pruned(_star_arcs(n, False), 2, seed=seed)
+        assert r["relax_alg"] == (sk["off"][1] - sk["off"][0]) * (n - 1)
+
+
+def test_directed_validation():
+    """A directed graph needs no reverse arcs; the same arrays read as
+    undirected are rejected."""
+    g = gg.with_problem(gg.er(40, 3, 2, wmax=5, directed=True), 2)
+    assert O.validate(g, 4, 0.1) == O.OK
+    assert O.validate(_as_undirected(g), 4, 0.1) == O.EINVAL
+    bad = gg.Graph(g.n, g.row_ptr.copy(), g.col.copy(), g.w.copy(), g.fac_cost, directed=True)
+    bad.w[0] = 0
+    assert O.validate(bad, 4, 0.1) == O.EINVAL
+    bad = gg.Graph(g.n, g.row_ptr.copy(), g.col.copy(), g.w.copy(), g.fac_cost, directed=True)
+    r0 = int(np.nonzero(np.diff(g.row_ptr.astype(np.int64)) > 0)[0][0])
+    bad.col[g.row_ptr[r0]] = r0                       # self loop
+    assert O.validate(bad, 4, 0.1) == O.EINVAL
+
+
+def _as_undirected(g):
+    return gg.Graph(g.n, g.row_ptr, g.col, g.w, g.fac_cost, g.is_client, name=g.name, directed=False)
