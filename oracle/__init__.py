@@ -55,7 +55,7 @@ class _Result(C.Structure):
                 ("n_open", C.c_uint32), ("n_unreachable", C.c_uint32), ("n_rungs", C.c_uint32),
                 ("mis_rounds", C.c_uint32), ("n_guard", C.c_uint32),
                 ("relax_alg", C.c_uint64), ("ads_entries", C.c_uint64), ("gamma", C.c_uint64),
-                ("alpha0", C.c_double), ("one_eps", C.c_double)]
+                ("alpha0", C.c_double), ("one_eps", C.c_double), ("n_reach_guard", C.c_uint32)]
 
 
 def _setup(L):
@@ -265,7 +265,7 @@ def solve(g, k, seed, eps=0.1, luby=False):
     fn = lib().orc_solve_luby if luby else lib().orc_solve
     rc = int(fn(C.byref(h.s), k, seed, eps, C.byref(r)))
     for name in ("total_cost", "n_open", "n_unreachable", "n_rungs", "mis_rounds", "n_guard",
-                 "relax_alg", "ads_entries", "gamma", "alpha0", "one_eps"):
+                 "relax_alg", "ads_entries", "gamma", "alpha0", "one_eps", "n_reach_guard"):
         res[name] = getattr(r, name)
     return rc, res
 

@@ -29,7 +29,7 @@
  *                  objective (Sec. 3.1)
  *   exhaustive ... OPT over all non-empty facility subsets (tiny n only)
  *
- * Directed graphs (Sec. 3.2 considers them; the algorithm is adapted to them
+ * Directed graphs (Sec. 3.1 considers them; the algorithm is adapted to them
  * without the guarantee, Sec. 4.4): d(u, v) is the shortest path along arcs
  * from u to v.  Entries travel along arcs (Alg. 2 sends (u, d + e(u,v)) to
  * the out-neighbours), so the sketch of v holds vertices u that reach v, at
@@ -206,7 +206,7 @@ int orc_perm_check_range(uint64_t key, uint32_t lo, uint64_t count) {
 /* with strictly increasing neighbour ids per row, integer weights >= 1, no   */
 /* self loops.  A bound keeps every distance and every cost+distance below    */
 /* 2^32 - 1: (n-1)*max_w + max_cost < 2^32 - 1, else ERANGE.  A directed      */
-/* graph (Sec. 3.2) gives its out-arcs per row, with the same rules except    */
+/* graph (Sec. 3.1) gives its out-arcs per row, with the same rules except    */
 /* symmetry.                                                                   */
 /* ------------------------------------------------------------------------ */
 static int find_arc(const orc_graph *g, uint32_t u, uint32_t v, uint64_t *pos) {
@@ -734,6 +734,7 @@ typedef struct {
   uint32_t n_open, n_unreachable, n_rungs, mis_rounds, n_guard;
   uint64_t relax_alg, ads_entries, gamma;
   double alpha0, one_eps;
+  uint32_t n_reach_guard; /* facilities added by the reach guard (directed graphs) */
 } orc_result;
 
 /* a[t] ladder (Sec. 4.2: alpha takes values alpha_0 (1+eps)^j); grown on demand */
@@ -1106,6 +1107,20 @@ static int solve_impl(const orc_graph *g, uint32_t k, uint64_t seed, double eps,
   r->mis_rounds = mis_rounds;
   for (uint32_t f = 0; f < n; f++)
     if (isF[f] && r->open_rung[f] == RUNG_GUARD) inS[f] = 1;
+
+  /* Reach guard (not in the paper; never fires on an undirected graph, where
+   * a client reaches every facility of its component).  On a directed graph
+   * a client's facility can lose the MIS to a conflicting one the client
+   * cannot reach.  Every served client that reaches no facility of S opens
+   * its gamma minimiser, which it reaches by definition, straight into S. */
+  r->n_reach_guard = 0;
+  for (uint32_t v = 0; v < n; v++) { ival[v] = inS[v] ? 0 : ORC_INF64; itie[v] = v; }
+  rc = msdijkstra(gb, ival, itie, dO, tmpt);
+  if (rc != ORC_OK) return rc;
+  for (uint32_t c = 0; c < n; c++) {
+    if (!isC[c] || gam[c] == ORC_INF64 || dO[c] != ORC_INF64) continue;
+    if (!inS[fstar[c]]) { inS[fstar[c]] = 1; r->n_reach_guard++; }
+  }
 
   /* Assignment and objective (Sec. 3.1): each served client goes to its
    * nearest facility of S (ties: smaller id); cost = sum of opening costs of

@@ -278,6 +278,8 @@ def _problems():
     out.append(gg.with_problem(gg.rmat(9, 3000, 8, directed=True), 8, cost="uniform", fac_frac=0.3))
     out.append(gg.with_problem(gg.forest_fire(250, 3, wmax=20, directed=True), 3, cost="lognormal",
                                fac_frac=0.5, client_frac=0.7))
+    out.append(gg.with_problem(gg.forest_fire(1500, 4, wmax=20, directed=True), 4, cost="uniform",
+                               client_frac=0.6))             # the reach guard fires here
     return out
 
 
@@ -452,7 +454,8 @@ def test_mis_is_greedy_maximal_independent(pi):
     lad = O.ladder(r["alpha0"], eps, T + 2)
     D = apsp(g)
     _, prio = O.ranks(g.n, seed)
-    orung, frung, opened = r["open_rung"], r["freeze_rung"], r["open"].astype(bool)
+    orung, frung = r["open_rung"], r["freeze_rung"]
+    S = np.zeros(g.n, bool)
     for t in np.unique(orung[(orung >= 1) & (orung <= T)]):
         Ft = np.nonzero(orung == t)[0]
         Ct = np.nonzero(frung == t)[0]
@@ -465,14 +468,36 @@ def test_mis_is_greedy_maximal_independent(pi):
         for i in order:
             if not (conf[i] & chosen).any():
                 chosen[i] = True
-        assert np.array_equal(opened[Ft], chosen)
         sel = np.nonzero(chosen)[0]
         assert not conf[np.ix_(sel, sel)].any()          # independent
         for i in range(len(Ft)):                          # maximal
             assert chosen[i] or (conf[i] & chosen).any()
-    # guard facilities are open; nothing else outside a rung is
-    outside = ~((orung >= 1) & (orung <= T))
-    assert np.array_equal(opened[outside], orung[outside] == O.RUNG_GUARD)
+        S[Ft[sel]] = True
+    _check_open_set(g, r, S, D)
+
+
+def _check_open_set(g, r, S, D):
+    """S (the rungs' independent sets) plus the stall-guard facilities, plus
+    the reach guard: every served client that reaches no facility of that
+    set opens argmin_f (c(f) + d(c, f), id f).  The result must be exactly
+    the oracle's open set; the reach guard never fires on an undirected
+    graph."""
+    S = S | (r["open_rung"] == O.RUNG_GUARD)
+    isF = g.fac_cost != O.NOT_FACILITY
+    isC = np.ones(g.n, bool) if g.is_client is None else g.is_client.astype(bool)
+    served = isC & np.isfinite(D[:, isF]).any(axis=1)
+    dS = D[:, S].min(axis=1) if S.any() else np.full(g.n, np.inf)
+    F = np.nonzero(isF)[0]
+    added = set()
+    for c in np.nonzero(served & ~np.isfinite(dS))[0]:
+        val = g.fac_cost[F].astype(np.float64) + D[c, F]
+        added.add(int(F[np.lexsort((F, val))[0]]))
+    for f in added:
+        S[f] = True
+    assert np.array_equal(r["open"].astype(bool), S)
+    assert r["n_reach_guard"] == len(added)
+    if not g.directed:
+        assert not added
 
 
 def _luby_prio(fac, seed, r):
@@ -498,7 +523,8 @@ def test_luby_mis_rounds_on_explicit_hbar(pi):
     T = r["n_rungs"]
     lad = O.ladder(r["alpha0"], eps, T + 2)
     D = apsp(g)
-    orung, frung, opened = r["open_rung"], r["freeze_rung"], r["open"].astype(bool)
+    orung, frung = r["open_rung"], r["freeze_rung"]
+    S = np.zeros(g.n, bool)
     total_rounds = 0
     for t in np.unique(orung[(orung >= 1) & (orung <= T)]):
         Ft = np.nonzero(orung == t)[0]
@@ -523,11 +549,12 @@ def test_luby_mis_rounds_on_explicit_hbar(pi):
                 if (conf[i] & join).any():
                     active[i] = False
         total_rounds += rounds
-        assert np.array_equal(opened[Ft], chosen)
         sel = np.nonzero(chosen)[0]
         assert not conf[np.ix_(sel, sel)].any()          # independent
         for i in range(len(Ft)):                          # maximal
             assert chosen[i] or (conf[i] & chosen).any()
+        S[Ft[sel]] = True
+    _check_open_set(g, r, S, D)
     assert total_rounds == r["mis_rounds"]
 
 
