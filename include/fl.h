@@ -56,9 +56,11 @@ extern "C" {
 #define FL_RUNG_END 0xFFFFFFFDu     /* frozen in the end phase (all facilities open) */
 
 /* ---- problem: graph in symmetric CSR, costs, clients (Sec. 3.1) ---------- */
+/* With FL_FLAG_DIRECTED the rows are out-arcs and the symmetry rules below
+ * do not apply; every other rule does. */
 typedef struct {
   uint32_t n;               /* |V|, 1 <= n < 2^32-1 */
-  uint64_t n_arcs;          /* 2|E| */
+  uint64_t n_arcs;          /* 2|E| (directed: the number of arcs) */
   const uint64_t *row_ptr;  /* [n+1], row_ptr[0] = 0, row_ptr[n] = n_arcs */
   const uint32_t *col;      /* [n_arcs], strictly increasing within each row,
                                no self loops; (u,v) present iff (v,u) present */
@@ -85,6 +87,20 @@ typedef struct {
                                 bijection of the local id keyed by
                                 SplitMix64(seed ^ (3 + 256 r)).  A maximal
                                 independent set, in general not the greedy one. */
+#define FL_FLAG_DIRECTED 4u  /* the CSR holds the out-arcs of a directed graph
+                                (Sec. 3.1 considers both kinds; Sec. 4.4: the
+                                method carries over, without its guarantee).
+                                No reverse arcs are required.  d(u, v) is then the
+                                shortest path along arcs from u to v; the sketch
+                                of v holds the vertices that reach v, at d(u, v)
+                                (entries travel along arcs, Alg. 2); clients are
+                                counted by, frozen by, in conflict through and
+                                assigned to facilities they can reach, at d(c, f);
+                                gamma and unreachable clients likewise.  On a
+                                symmetric CSR the result equals the undirected
+                                one.  Costs an in-arc copy of the graph in the
+                                workspace (8(n+1) + 4 n_arcs bytes, 8 n_arcs when
+                                weighted). */
 
 /* ---- statistics ---------------------------------------------------------- */
 typedef struct {
@@ -92,7 +108,7 @@ typedef struct {
   uint32_t rungs;       /* radius-ladder rungs evaluated by the opening loop */
   uint32_t mis_rounds;  /* parallel MIS rounds, summed over rungs */
   uint32_t n_guard;     /* facilities opened by the stall guard */
-  uint64_t relax_alg;   /* sum_v |ADS(v)| * deg(v) */
+  uint64_t relax_alg;   /* sum_v |ADS(v)| * deg(v) (directed: out-degree) */
   uint64_t relax_exec;  /* candidate entries read by the sketch rounds */
   uint64_t ads_entries; /* sum_v |ADS(v)| */
   uint64_t gamma;       /* max over served clients of min_f c(f) + d(c,f) */
@@ -103,6 +119,10 @@ typedef struct {
   double ms_ads_merge;           /* summed device time of the merges of split hub vertices */
   uint32_t ads_kernel_launches;  /* number of sketch-round kernel launches */
   uint64_t workspace_bytes;
+  uint32_t n_reach_guard;  /* facilities added because a served client reached no
+                              facility of S (directed graphs only: each such client
+                              opens its gamma minimiser, argmin_f c(f) + d(c,f),
+                              ties by id); always 0 on an undirected graph */
 } fl_stats;
 
 /* ---- result -------------------------------------------------------------- */

@@ -13,12 +13,12 @@ from typing import Optional
 import torch
 
 from . import _lib
-from ._lib import (FL_FLAG_LUBY_MIS, FL_FLAG_NO_DENSE, FL_NONE, FL_NOT_FACILITY, FL_RUNG_END, FL_RUNG_GUARD,
+from ._lib import (FL_FLAG_DIRECTED, FL_FLAG_LUBY_MIS, FL_FLAG_NO_DENSE, FL_NONE, FL_NOT_FACILITY, FL_RUNG_END, FL_RUNG_GUARD,
                    FL_RUNG_NONE, FlError, lib)
 
 __all__ = ["DeviceGraph", "to_device", "solve", "solve_batch", "Server", "ads_build", "rank_of", "priority_of",
            "FlError", "FL_NONE", "FL_NOT_FACILITY", "FL_RUNG_NONE", "FL_RUNG_GUARD", "FL_RUNG_END",
-           "FL_FLAG_NO_DENSE", "FL_FLAG_LUBY_MIS", "lib"]
+           "FL_FLAG_NO_DENSE", "FL_FLAG_LUBY_MIS", "FL_FLAG_DIRECTED", "lib"]
 
 
 @dataclass
@@ -29,6 +29,7 @@ class DeviceGraph:
     w: Optional[torch.Tensor] = None      # int32 [m]
     fac_cost: Optional[torch.Tensor] = None   # int32 [n] (read as uint32)
     is_client: Optional[torch.Tensor] = None  # uint8 [n]
+    directed: bool = False                # rows are out-arcs: FL_FLAG_DIRECTED is added to the flags
 
     @property
     def n_arcs(self):
@@ -56,7 +57,12 @@ def to_device(g, device="cuda") -> DeviceGraph:
         _t(np.asarray(g.fac_cost, np.uint32), np.int32, device),
         is_client=None if getattr(g, "is_client", None) is None else
         _t(np.asarray(g.is_client, np.uint8), np.uint8, device),
+        directed=bool(getattr(g, "directed", False)),
     )
+
+
+def _flags(dg: DeviceGraph, flags: int) -> int:
+    return flags | (_lib.FL_FLAG_DIRECTED if dg.directed else 0)
 
 
 def _ptr(t):
@@ -110,7 +116,7 @@ def solve(dg: DeviceGraph, k: int, seed: int, eps: float = 0.1, flags: int = 0,
     device = dg.col.device if dg.n_arcs else dg.row_ptr.device
     out = outputs if outputs is not None else _alloc_outputs(dg.n, device, diagnostics)
     prob = _problem(dg)
-    prm = _lib.FlParams(k, seed, eps, flags)
+    prm = _lib.FlParams(k, seed, eps, _flags(dg, flags))
     res = _result_struct(out)
     rc = lib().fl_solve(C.byref(prob), C.byref(prm), C.byref(res), C.c_void_p(_stream_ptr(stream)))
     out["rc"] = rc
@@ -132,7 +138,8 @@ def solve_batch(dgs, k, seed, eps=0.1, flags=0, diagnostics=False, stream=None, 
         return list(x) if isinstance(x, (list, tuple)) else [x] * count
     ks, seeds, epss, flagss = per(k), per(seed), per(eps), per(flags)
     probs = (_lib.FlProblem * count)(*[_problem(d) for d in dgs])
-    prms = (_lib.FlParams * count)(*[_lib.FlParams(ks[i], seeds[i], epss[i], flagss[i]) for i in range(count)])
+    prms = (_lib.FlParams * count)(*[_lib.FlParams(ks[i], seeds[i], epss[i], _flags(dgs[i], flagss[i]))
+                                     for i in range(count)])
     outs = outputs if outputs is not None else [
         _alloc_outputs(d.n, d.col.device if d.n_arcs else d.row_ptr.device, diagnostics) for d in dgs]
     ress = (_lib.FlResult * count)(*[_result_struct(o) for o in outs])
@@ -166,7 +173,7 @@ class Server:
         out = outputs if outputs is not None else _alloc_outputs(dg.n, device, diagnostics)
         torch.cuda.synchronize(device)  # inputs and outputs ready before another stream reads them
         prob = _problem(dg)
-        prm = _lib.FlParams(k, seed, eps, flags)
+        prm = _lib.FlParams(k, seed, eps, _flags(dg, flags))
         res = _result_struct(out)
         t = C.c_uint64()
         rc = lib().fl_server_submit(self._h, C.byref(prob), C.byref(prm), C.byref(res), C.byref(t))
@@ -217,7 +224,7 @@ def ads_build(dg: DeviceGraph, k: int, seed: int, flags: int = 0, stream=None):
     """Bottom-k sketches of every vertex (fl_ads_build), copied into fresh
     device tensors: off int64 [n+1], rank/dist/thresh int32 [total]."""
     prob = _problem(dg)
-    prm = _lib.FlParams(k, seed, 0.1, flags)
+    prm = _lib.FlParams(k, seed, 0.1, _flags(dg, flags))
     h = C.c_void_p()
     rc = lib().fl_ads_build(C.byref(prob), C.byref(prm), C.byref(h), C.c_void_p(_stream_ptr(stream)))
     if rc != _lib.FL_OK:

@@ -19,6 +19,7 @@ FL_RUNG_GUARD = 0xFFFFFFFE
 FL_RUNG_END = 0xFFFFFFFD
 FL_FLAG_NO_DENSE = 1
 FL_FLAG_LUBY_MIS = 2
+FL_FLAG_DIRECTED = 4
 
 
 class FlProblem(C.Structure):
@@ -38,7 +39,8 @@ class FlStats(C.Structure):
                 ("ms_validate", C.c_double), ("ms_ads", C.c_double), ("ms_gamma", C.c_double),
                 ("ms_open", C.c_double), ("ms_mis", C.c_double), ("ms_assign", C.c_double),
                 ("ms_total", C.c_double), ("ms_ads_kernel", C.c_double), ("ms_ads_merge", C.c_double),
-                ("ads_kernel_launches", C.c_uint32), ("workspace_bytes", C.c_uint64)]
+                ("ads_kernel_launches", C.c_uint32), ("workspace_bytes", C.c_uint64),
+                ("n_reach_guard", C.c_uint32)]
 
 
 class FlResult(C.Structure):

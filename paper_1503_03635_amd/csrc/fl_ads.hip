@@ -2,11 +2,13 @@
 // edge relaxation on the GPU.
 //
 // Schedule.  Round D settles every sketch entry at distance exactly D (integer
-// weights >= 1).  A candidate (r, D) reaches u from a neighbour v over an arc
-// of weight w only if v inserted r in round D - w, so all entries at smaller
+// weights >= 1).  A candidate (r, D) reaches u from an in-neighbour v over an
+// arc v -> u of weight w only if v inserted r in round D - w, so all entries at smaller
 // distances are final when round D runs: sketches grow append-only, already in
 // (distance, id) order, and no entry is ever evicted (the CleanUp of Alg. 2 is
 // never needed).  With unit weights this is the superstep order of Alg. 2.
+// Entries move along arcs, so on a directed graph the sketch of u holds the
+// vertices that reach u, at d(v, u) (an undirected graph is read as both arcs).
 //
 // Work items.  A vertex with at most TASK_ARCS arcs is one task; a larger one
 // is split into tasks of TASK_ARCS arcs.  Each task (one wave64) streams the
@@ -50,9 +52,15 @@ struct AdsArgs {
   uint32_t n, k, cap, W, NS, FW;
   const uint32_t *gid;  // graph of each vertex (nullptr: one graph)
   const SegInfo *seg;   // per-graph rank keys, base, bucket shift
-  const uint64_t *row_ptr;
+  // entries travel along arcs: a vertex gathers over its in-arcs and, when
+  // its sketch changes, marks the heads of its out-arcs (one CSR twice when
+  // the graph is undirected)
+  const uint64_t *row_ptr;  // in-arcs
   const uint32_t *col;
   const uint32_t *w;
+  const uint64_t *out_ptr;  // out-arcs
+  const uint32_t *out_col;
+  const uint32_t *out_w;
   uint32_t *sk_rank;
   uint32_t *sk_dist;
   uint32_t *bk;
@@ -103,14 +111,14 @@ __device__ inline void mark_targets(const AdsArgs &P, bool want, uint32_t y, uin
 template <bool UNITW>
 __device__ inline void mark_neighbours(const AdsArgs &P, uint32_t u, uint32_t D) {
   const int lane = lane_id();
-  const uint64_t a0 = P.row_ptr[u], a1 = P.row_ptr[u + 1];
+  const uint64_t a0 = P.out_ptr[u], a1 = P.out_ptr[u + 1];
   for (uint64_t b = a0; b < a1; b += WAVE) {
     const uint64_t a = b + lane;
     const bool valid = a < a1;
     uint32_t y = 0, s = 0;
     if (valid) {
-      y = P.col[a];
-      const uint32_t wv = UNITW ? 1u : P.w[a];
+      y = P.out_col[a];
+      const uint32_t wv = UNITW ? 1u : P.out_w[a];
       s = (D + wv) % P.NS;
     }
     mark_targets<UNITW>(P, valid, y, s);
@@ -810,7 +818,7 @@ static void build_tasks(Ctx &c, const Graph &g, const uint32_t *list, uint32_t c
   tl.ntasks = tl.nsplit = tl.nslots = 0;
   if (count == 0) return;
   const uint32_t blocks = (uint32_t)ceil_div(count, 256);
-  k_task_count<<<blocks, 256, 0, c.s>>>(list, count, g.row_ptr, ts.ntask, ts.nslot, ts.isplit);
+  k_task_count<<<blocks, 256, 0, c.s>>>(list, count, g.in_ptr, ts.ntask, ts.nslot, ts.isplit);
   FL_LAUNCH_CHECK();
   scan_u32_to_u64(c, ts.ntask, ts.toff, count);
   scan_u32_to_u64(c, ts.nslot, ts.soff, count);
@@ -828,7 +836,7 @@ static void build_tasks(Ctx &c, const Graph &g, const uint32_t *list, uint32_t c
   tl.nsplit = (uint32_t)h[2];
 }
 
-// list of vertices with at least one arc
+// list of vertices with at least one in-arc
 __global__ void k_nonisolated_flags(uint32_t n, const uint64_t *row_ptr, uint32_t *flag) {
   uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) flag[i] = row_ptr[i + 1] > row_ptr[i] ? 1u : 0u;
@@ -908,9 +916,12 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
   P.FW = FW;
   P.gid = cfg.gid;
   P.seg = cfg.seg;
-  P.row_ptr = g.row_ptr;
-  P.col = g.col;
-  P.w = g.w;
+  P.row_ptr = g.in_ptr;
+  P.col = g.in_col;
+  P.w = g.in_w;
+  P.out_ptr = g.row_ptr;
+  P.out_col = g.col;
+  P.out_w = g.w;
   P.sk_rank = o.sk_rank;
   P.sk_dist = o.sk_dist;
   P.bk = c.arena->get<uint32_t>((size_t)n * k);
@@ -931,7 +942,7 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
   {
     uint32_t *need = c.arena->get<uint32_t>(n);
     uint64_t *noff = c.arena->get<uint64_t>((size_t)n + 1);
-    k_slot_need<<<(uint32_t)ceil_div(n, 256), 256, 0, c.s>>>(n, g.row_ptr, need);
+    k_slot_need<<<(uint32_t)ceil_div(n, 256), 256, 0, c.s>>>(n, g.in_ptr, need);
     FL_LAUNCH_CHECK();
     scan_u32_to_u64(c, need, noff, n);
     FL_HIP(hipMemcpyAsync(c.h_status, noff + n, 8, hipMemcpyDeviceToHost, c.s));
@@ -967,7 +978,7 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
     uint32_t *fl = c.arena->get<uint32_t>(n);
     uint64_t *pos = c.arena->get<uint64_t>((size_t)n + 1);
     uint32_t *dense = c.arena->get<uint32_t>(n);
-    k_nonisolated_flags<<<(uint32_t)ceil_div(n, 256), 256, 0, c.s>>>(n, g.row_ptr, fl);
+    k_nonisolated_flags<<<(uint32_t)ceil_div(n, 256), 256, 0, c.s>>>(n, g.in_ptr, fl);
     FL_LAUNCH_CHECK();
     scan_u32_to_u64(c, fl, pos, n);
     k_compact<<<(uint32_t)ceil_div(n, 256), 256, 0, c.s>>>(n, fl, pos, dense);
@@ -1103,6 +1114,7 @@ int ads_build(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o) {
   if (cfg.k == 0) return FL_EINVAL;
   if (cfg.k > MAX_K) return FL_ENOTIMPL;
   if (g.w && g.max_w > MAX_W) return FL_ENOTIMPL;
+  if (!g.in_ptr) return FL_EINVAL;  // the in-arc view is set by set_in_arcs
   uint32_t cap = ads_capacity(cfg.n_cap ? cfg.n_cap : g.n, cfg.k);
   for (int attempt = 0; attempt < 6; ++attempt) {
     if (cap > MAX_CAP) return FL_ENOTIMPL;

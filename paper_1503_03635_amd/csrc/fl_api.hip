@@ -144,16 +144,29 @@ __global__ void k_compact_u32(uint32_t n, const uint32_t *flag, const uint64_t *
   const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v < n && flag[v]) out[pos[v]] = (uint32_t)v;
 }
+// Reach guard (directed graphs; never fires on an undirected one): a served
+// client that reaches no facility of S opens its gamma minimiser (low half of
+// its gamma label), which it reaches by definition.  Such a facility was
+// closed (it would be in reach otherwise): it is marked 2 and counted once
+// by the kernel below, which writes it back as 1.
+__global__ void k_reach_guard(uint32_t n, const uint8_t *ceff, const uint64_t *lab, const uint64_t *gam_lab,
+                              uint8_t *open, uint32_t *cnt) {
+  const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n && ceff[v] && lab[v] == INF64) {
+    open[(uint32_t)(gam_lab[v] & 0xFFFFFFFFu)] = 2;
+    atomicAdd(cnt, 1u);
+  }
+}
 // assignment outputs (facility ids local to the graph) and the objective per
-// graph: fields cost, n_open, n_guard
-enum { AO_COST = 0, AO_NOPEN, AO_NGUARD, AO_NFIELD };
+// graph: fields cost, n_open, n_guard, n_reach_guard
+enum { AO_COST = 0, AO_NOPEN, AO_NGUARD, AO_NREACH, AO_NFIELD };
 __global__ void k_assign_out(uint32_t n, const uint32_t *gid, const SegInfo *seg, const uint8_t *ceff,
-                             const uint64_t *lab, const uint8_t *open, const uint32_t *fac_cost,
+                             const uint64_t *lab, uint8_t *open, const uint32_t *fac_cost,
                              const uint32_t *orung, uint32_t *assign, uint32_t *dist, uint64_t *ctr,
                              uint32_t stripes) {
   const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = v < n;
-  uint64_t cost = 0, no = 0, ng = 0;
+  uint64_t cost = 0, no = 0, ng = 0, nr = 0;
   uint32_t g = 0;
   if (valid) {
     g = seg_of(gid, (uint32_t)v);
@@ -170,6 +183,10 @@ __global__ void k_assign_out(uint32_t n, const uint32_t *gid, const SegInfo *seg
     if (open[v]) {
       cost += fac_cost[v];
       no = 1;
+      if (open[v] == 2) {
+        nr = 1;
+        open[v] = 1;
+      }
     }
     if (orung[v] == FL_RUNG_GUARD) ng = 1;
   }
@@ -177,6 +194,7 @@ __global__ void k_assign_out(uint32_t n, const uint32_t *gid, const SegInfo *seg
   seg_add(c, valid, g, AO_COST, AO_NFIELD, stripes, cost);
   seg_add(c, valid, g, AO_NOPEN, AO_NFIELD, stripes, no);
   seg_add(c, valid, g, AO_NGUARD, AO_NFIELD, stripes, ng);
+  seg_add(c, valid, g, AO_NREACH, AO_NFIELD, stripes, nr);
 }
 
 // ---- union of several graphs ------------------------------------------------
@@ -280,6 +298,7 @@ static void solve_group(const fl_problem *const *ps, const fl_params *const *pr,
   const uint32_t k = pr[0]->k;
   const double eps = pr[0]->eps;
   const uint32_t flags = pr[0]->flags;
+  const bool directed = (flags & FL_FLAG_DIRECTED) != 0;
   uint64_t N0 = 0, M0 = 0;
   uint32_t nmax0 = 1;
   bool weighted0 = false;
@@ -294,7 +313,8 @@ static void solve_group(const fl_problem *const *ps, const fl_params *const *pr,
     return;
   }
   const uint32_t cap0 = ads_capacity(nmax0, k);
-  dc.arena.reserve(estimate_bytes((uint32_t)N0, M0, N0, k, cap0, 2) + union_bytes(G0, N0, M0, weighted0));
+  const size_t tr0 = directed ? transpose_bytes((uint32_t)N0, M0, weighted0) : 0;
+  dc.arena.reserve(estimate_bytes((uint32_t)N0, M0, N0, k, cap0, 2) + union_bytes(G0, N0, M0, weighted0) + tr0);
   dc.arena.reset();
   Ctx c;
   c.s = s;
@@ -314,9 +334,9 @@ static void solve_group(const fl_problem *const *ps, const fl_params *const *pr,
   // ---- validation per graph; failing graphs leave the group
   std::vector<uint32_t> mw(G0, 1), mc(G0, 0);
   if (G0 == 1) {
-    rc_out[0] = validate_graph(c, ps[0], &mw[0], &mc[0]);
+    rc_out[0] = validate_graph(c, ps[0], directed, &mw[0], &mc[0]);
   } else {
-    validate_graphs(c, ps, G0, rc_out, mw, mc);
+    validate_graphs(c, ps, G0, directed, rc_out, mw, mc);
   }
   std::vector<uint32_t> act;  // indices of the graphs that go on
   for (uint32_t i = 0; i < G0; ++i) {
@@ -350,12 +370,13 @@ static void solve_group(const fl_problem *const *ps, const fl_params *const *pr,
     if (ps[i]->w) max_w = std::max(max_w, mw[i]);
   const bool weighted = weighted0;
   const uint32_t NS = (weighted ? max_w : 1u) + 1;
-  if (estimate_bytes(n, M0, n, k, cap0, NS) + union_bytes(G, N0, M0, weighted) > dc.arena.capacity()) {
+  const size_t need = estimate_bytes(n, M0, n, k, cap0, NS) + union_bytes(G, N0, M0, weighted) + tr0;
+  if (need > dc.arena.capacity()) {
     if (depth > 0) {
       for (auto &r : rc_out) r = FL_ENOMEM;
       return;
     }
-    dc.arena.reserve(estimate_bytes(n, M0, n, k, cap0, NS) + union_bytes(G, N0, M0, weighted));
+    dc.arena.reserve(need);
     return solve_group(ps, pr, outs, G0, s, dc, rc_out, depth + 1);  // restart with the larger arena
   }
 
@@ -409,6 +430,7 @@ static void solve_group(const fl_problem *const *ps, const fl_params *const *pr,
     is_client = d_cl;
     g = Graph{n, M0, d_rp, d_col, d_w, weighted ? max_w : 1u};
   }
+  set_in_arcs(c, g, directed);
   FL_HIP(hipEventRecord(ev[1], s));
 
   // ---- facilities
@@ -529,16 +551,26 @@ static void solve_group(const fl_problem *const *ps, const fl_params *const *pr,
 
   // ---- assignment and objective (Sec. 3.1)
   uint64_t *al = c.arena->get<uint64_t>(n);
-  k_assign_init<<<vb, 256, 0, s>>>(n, open_u, al, flag);
-  FL_LAUNCH_CHECK();
-  scan_u32_to_u64(c, flag, pos, n);
   uint32_t *slist = c.arena->get<uint32_t>(n);
-  k_compact_u32<<<vb, 256, 0, s>>>(n, flag, pos, slist);
-  FL_LAUNCH_CHECK();
-  FL_HIP(hipMemcpyAsync(c.h_status, pos + n, 8, hipMemcpyDeviceToHost, s));
-  c.sync();
-  const uint32_t nS = (uint32_t)c.h_status[0];
-  sssp_run(c, g, al, slist, nS, wk, 0);
+  uint32_t *rgc = c.arena->get<uint32_t>(1);
+  for (int pass = 0; pass < 2; ++pass) {
+    k_assign_init<<<vb, 256, 0, s>>>(n, open_u, al, flag);
+    FL_LAUNCH_CHECK();
+    scan_u32_to_u64(c, flag, pos, n);
+    k_compact_u32<<<vb, 256, 0, s>>>(n, flag, pos, slist);
+    FL_LAUNCH_CHECK();
+    FL_HIP(hipMemcpyAsync(c.h_status, pos + n, 8, hipMemcpyDeviceToHost, s));
+    c.sync();
+    const uint32_t nS = (uint32_t)c.h_status[0];
+    sssp_run(c, g, al, slist, nS, wk, 0);
+    if (!directed || pass == 1) break;
+    fill_u32(c, rgc, 1, 0);
+    k_reach_guard<<<vb, 256, 0, s>>>(n, ceff, al, gl, open_u, rgc);
+    FL_LAUNCH_CHECK();
+    FL_HIP(hipMemcpyAsync(c.h_status, rgc, 4, hipMemcpyDeviceToHost, s));
+    c.sync();
+    if ((c.h_status[0] & 0xFFFFFFFFu) == 0) break;  // every served client reaches S
+  }
   uint64_t *actr = c.arena->get<uint64_t>((size_t)G * AO_NFIELD * stripes);
   fill_u64(c, actr, (size_t)G * AO_NFIELD * stripes, 0);
   k_assign_out<<<vb, 256, 0, s>>>(n, gid, seg, ceff, al, open_u, fac_cost, orung, assign_u, dist_u, actr,
@@ -573,6 +605,7 @@ static void solve_group(const fl_problem *const *ps, const fl_params *const *pr,
     o->n_open = (uint32_t)ao[i * AO_NFIELD + AO_NOPEN];
     fl_stats &st = o->stats;
     st.n_guard = (uint32_t)ao[i * AO_NFIELD + AO_NGUARD];
+    st.n_reach_guard = (uint32_t)ao[i * AO_NFIELD + AO_NREACH];
     st.relax_alg = relax[i];
     st.ads_entries = entries[i];
     st.rungs = oo.rungs[i];
@@ -641,9 +674,10 @@ static size_t group_bytes(const std::vector<Request *> &b) {
     wt |= r->p->w != nullptr;
   }
   const uint32_t k = b[0]->prm->k;
-  return estimate_bytes((uint32_t)std::min<uint64_t>(N, 0xFFFFFFFEull), M, N, k, ads_capacity(nmax, k),
-                        wt ? MAX_W + 1 : 2) +
-         union_bytes((uint32_t)b.size(), N, M, wt);
+  const uint32_t N32 = (uint32_t)std::min<uint64_t>(N, 0xFFFFFFFEull);
+  return estimate_bytes(N32, M, N, k, ads_capacity(nmax, k), wt ? MAX_W + 1 : 2) +
+         union_bytes((uint32_t)b.size(), N, M, wt) +
+         ((b[0]->prm->flags & FL_FLAG_DIRECTED) ? transpose_bytes(N32, M, wt) : 0);
 }
 
 static bool same_group(const Request *a, const Request *b) {
@@ -857,7 +891,10 @@ int fl_solve_batch(const fl_problem *ps, const fl_params *prms, fl_result *outs,
         const uint32_t cap = fl::ads_capacity(nm2, P0.k);
         const size_t need = fl::estimate_bytes((uint32_t)std::min<uint64_t>(N2, 0xFFFFFFFEull), M2, N2, P0.k, cap,
                                                wt2 ? 256 : 2) +
-                            fl::union_bytes((uint32_t)(i1 - i0 + 1), N2, M2, wt2);
+                            fl::union_bytes((uint32_t)(i1 - i0 + 1), N2, M2, wt2) +
+                            ((P0.flags & FL_FLAG_DIRECTED) ? fl::transpose_bytes((uint32_t)std::min<uint64_t>(
+                                                                 N2, 0xFFFFFFFEull), M2, wt2)
+                                                           : 0);
         if (i1 > i0 && (need > budget || N2 >= 0x7FFFFFFFull || i1 - i0 >= 65535)) break;
         N = N2;
         M = M2;
@@ -955,7 +992,9 @@ int fl_ads_build(const fl_problem *p, const fl_params *prm, fl_sketch **out, voi
     hipStream_t s = (hipStream_t)stream;
     const uint32_t n = p->n;
     const uint32_t cap0 = fl::ads_capacity(n, prm->k);
-    dc.arena.reserve(fl::estimate_bytes(n, p->n_arcs, n, prm->k, cap0, 2));
+    const bool directed = (prm->flags & FL_FLAG_DIRECTED) != 0;
+    const size_t tr = directed ? fl::transpose_bytes(n, p->n_arcs, p->w != nullptr) : 0;
+    dc.arena.reserve(fl::estimate_bytes(n, p->n_arcs, n, prm->k, cap0, 2) + tr);
     dc.arena.reset();
     fl::Ctx c;
     c.s = s;
@@ -964,18 +1003,19 @@ int fl_ads_build(const fl_problem *p, const fl_params *prm, fl_sketch **out, voi
     uint32_t max_w = 1, max_c = 0;
     fl_problem q = *p;
     q.fac_cost = nullptr;
-    rc = fl::validate_graph(c, &q, &max_w, &max_c);
+    rc = fl::validate_graph(c, &q, directed, &max_w, &max_c);
     if (rc) return rc;
     if ((uint64_t)(n - 1) * (p->w ? max_w : 1u) >= 0xFFFFFFFFull) return FL_ERANGE;
     if (p->w && max_w > fl::MAX_W) return FL_ENOTIMPL;
     const uint32_t NS = (p->w ? max_w : 1u) + 1;
-    if (fl::estimate_bytes(n, p->n_arcs, n, prm->k, cap0, NS) > dc.arena.capacity()) {
-      dc.arena.reserve(fl::estimate_bytes(n, p->n_arcs, n, prm->k, cap0, NS));
+    if (fl::estimate_bytes(n, p->n_arcs, n, prm->k, cap0, NS) + tr > dc.arena.capacity()) {
+      dc.arena.reserve(fl::estimate_bytes(n, p->n_arcs, n, prm->k, cap0, NS) + tr);
       dc.arena.reset();
-      rc = fl::validate_graph(c, &q, &max_w, &max_c);
+      rc = fl::validate_graph(c, &q, directed, &max_w, &max_c);
       if (rc) return rc;
     }
     fl::Graph g{n, p->n_arcs, p->row_ptr, p->col, p->w, p->w ? max_w : 1u};
+    fl::set_in_arcs(c, g, directed);
     fl::SegInfo hseg = fl::seg_info(0, n, prm->seed);
     fl::SegInfo *seg = c.arena->get<fl::SegInfo>(1);
     FL_HIP(hipMemcpyAsync(seg, &hseg, sizeof(hseg), hipMemcpyHostToDevice, s));

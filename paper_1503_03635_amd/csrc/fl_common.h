@@ -381,6 +381,12 @@ struct Ctx {
 // ---------------------------------------------------------------------------
 // Validated graph description used by every phase (device pointers).
 // ---------------------------------------------------------------------------
+// row_ptr/col/w: the arcs out of each vertex (the caller's CSR).  in_*: the
+// arcs into each vertex (row v lists the u with an arc u -> v, with its
+// weight); the same arrays when the graph is undirected.  Work that moves
+// along arcs reads the out-arcs when it pushes from a vertex and the in-arcs
+// when it pulls into one; a search for distances TO a set of vertices pushes
+// over the in-arcs.
 struct Graph {
   uint32_t n;
   uint64_t m;
@@ -388,6 +394,9 @@ struct Graph {
   const uint32_t *col;
   const uint32_t *w;  // nullptr = unit weights
   uint32_t max_w;
+  const uint64_t *in_ptr = nullptr;
+  const uint32_t *in_col = nullptr;
+  const uint32_t *in_w = nullptr;
 };
 
 // fill / utility launches (fl_graph.hip)
@@ -395,9 +404,13 @@ void fill_u32(Ctx &c, uint32_t *p, uint64_t n, uint32_t v);
 void fill_u64(Ctx &c, uint64_t *p, uint64_t n, uint64_t v);
 void fill_u8(Ctx &c, uint8_t *p, uint64_t n, uint8_t v);
 void fill_f64(Ctx &c, double *p, uint64_t n, double v);
-int validate_graph(Ctx &c, const fl_problem *p, uint32_t *max_w_out, uint32_t *max_cost_out);
+int validate_graph(Ctx &c, const fl_problem *p, bool directed, uint32_t *max_w_out, uint32_t *max_cost_out);
+// Sets g's in-arc view: the out-arc arrays themselves (undirected), or their
+// transpose built in the arena (directed; g must be validated).
+void set_in_arcs(Ctx &c, Graph &g, bool directed);
+size_t transpose_bytes(uint32_t n, uint64_t m, bool weighted);
 // validates G graphs (one launch each, one readback); rc/max_w/max_cost per graph
-void validate_graphs(Ctx &c, const fl_problem *const *ps, uint32_t G, std::vector<int> &rc,
+void validate_graphs(Ctx &c, const fl_problem *const *ps, uint32_t G, bool directed, std::vector<int> &rc,
                      std::vector<uint32_t> &max_w, std::vector<uint32_t> &max_cost);
 // per-graph sums (or, for the last field with max_last, maxima) of striped
 // device counters laid out as [(g * nf + f) * stripes + s]

@@ -34,9 +34,10 @@ void fill_u8(Ctx &c, uint8_t *p, uint64_t n, uint8_t v) { fill_t(c, p, n, v); }
 void fill_f64(Ctx &c, double *p, uint64_t n, double v) { fill_t(c, p, n, v); }
 
 // ---------------------------------------------------------------------------
-// Validation (a simple undirected graph as a symmetric CSR, Sec. 3.1).  One
-// wave per vertex; lanes walk the row.  err bits: 1 = structural error.
-// Also reduces max weight and max facility cost.
+// Validation (a simple undirected graph as a symmetric CSR, Sec. 3.1; a
+// directed graph gives its out-arcs and skips the symmetry test).  One wave
+// per vertex; lanes walk the row.  err bits: 1 = structural error.  Also
+// reduces max weight and max facility cost.
 // ---------------------------------------------------------------------------
 __device__ inline bool find_arc(const uint64_t *row_ptr, const uint32_t *col, uint64_t m, uint32_t u,
                                 uint32_t v, uint64_t *pos) {
@@ -55,7 +56,8 @@ __device__ inline bool find_arc(const uint64_t *row_ptr, const uint32_t *col, ui
 __global__ __launch_bounds__(256) void k_validate(uint32_t n, uint64_t m, const uint64_t *row_ptr,
                                                   const uint32_t *col, const uint32_t *w,
                                                   const uint32_t *fac_cost, uint32_t *err,
-                                                  uint32_t *maxw, uint32_t *maxc, uint32_t stripes) {
+                                                  uint32_t *maxw, uint32_t *maxc, uint32_t stripes,
+                                                  uint32_t directed) {
   const int lane = lane_id();
   const uint64_t u64 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
   if (u64 >= n) return;
@@ -69,9 +71,11 @@ __global__ __launch_bounds__(256) void k_validate(uint32_t n, uint64_t m, const 
       uint32_t wv = w ? w[a] : 1u;
       if (v >= n || v == u || wv == 0) { bad = 1; continue; }
       if (a > a0 && col[a - 1] >= v) { bad = 1; continue; }
-      uint64_t back;
-      if (!find_arc(row_ptr, col, m, v, u, &back)) { bad = 1; continue; }
-      if ((w ? w[back] : 1u) != wv) bad = 1;
+      if (!directed) {
+        uint64_t back;
+        if (!find_arc(row_ptr, col, m, v, u, &back)) { bad = 1; continue; }
+        if ((w ? w[back] : 1u) != wv) bad = 1;
+      }
       mw = wv > mw ? wv : mw;
     }
   }
@@ -88,7 +92,7 @@ __global__ __launch_bounds__(256) void k_validate(uint32_t n, uint64_t m, const 
   }
 }
 
-int validate_graph(Ctx &c, const fl_problem *p, uint32_t *max_w_out, uint32_t *max_cost_out) {
+int validate_graph(Ctx &c, const fl_problem *p, bool directed, uint32_t *max_w_out, uint32_t *max_cost_out) {
   const uint32_t n = p->n;
   // row_ptr[0] and row_ptr[n]
   uint64_t ends[2];
@@ -100,7 +104,7 @@ int validate_graph(Ctx &c, const fl_problem *p, uint32_t *max_w_out, uint32_t *m
   fill_u32(c, d, 3 * NCTR, 0);
   uint64_t blocks = ceil_div((uint64_t)n * WAVE, 256);
   k_validate<<<(uint32_t)blocks, 256, 0, c.s>>>(n, p->n_arcs, p->row_ptr, p->col, p->w, p->fac_cost,
-                                                 d, d + NCTR, d + 2 * NCTR, NCTR);
+                                                 d, d + NCTR, d + 2 * NCTR, NCTR, directed ? 1u : 0u);
   FL_LAUNCH_CHECK();
   std::vector<uint32_t> h(3 * NCTR);
   FL_HIP(hipMemcpyAsync(h.data(), d, 3 * NCTR * 4, hipMemcpyDeviceToHost, c.s));
@@ -128,7 +132,7 @@ __global__ void k_check_ends(const EndsDesc *d, uint32_t G, uint32_t *err) {
   if (g < G && (d[g].row_ptr[0] != 0 || d[g].row_ptr[d[g].n] != d[g].m)) err[3 * g] |= 2u;
 }
 
-void validate_graphs(Ctx &c, const fl_problem *const *ps, uint32_t G, std::vector<int> &rc,
+void validate_graphs(Ctx &c, const fl_problem *const *ps, uint32_t G, bool directed, std::vector<int> &rc,
                      std::vector<uint32_t> &max_w, std::vector<uint32_t> &max_cost) {
   uint32_t *d = c.arena->get<uint32_t>((size_t)3 * G);
   EndsDesc *ed = c.arena->get<EndsDesc>(G);
@@ -143,7 +147,7 @@ void validate_graphs(Ctx &c, const fl_problem *const *ps, uint32_t G, std::vecto
     const fl_problem *p = ps[g];
     const uint64_t blocks = ceil_div((uint64_t)p->n * WAVE, 256);
     k_validate<<<(uint32_t)blocks, 256, 0, c.s>>>(p->n, p->n_arcs, p->row_ptr, p->col, p->w, p->fac_cost,
-                                                   d + 3 * g, d + 3 * g + 1, d + 3 * g + 2, 1);
+                                                   d + 3 * g, d + 3 * g + 1, d + 3 * g + 2, 1, directed ? 1u : 0u);
     FL_LAUNCH_CHECK();
   }
   std::vector<uint32_t> h((size_t)3 * G);
@@ -264,6 +268,71 @@ void scan_u32_to_u64(Ctx &c, const uint32_t *in, uint64_t *out, uint32_t n) {
   FL_LAUNCH_CHECK();
   k_scan_add<<<tiles, SCAN_BLOCK, 0, c.s>>>(out, n, sums);
   FL_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// In-arcs of a directed graph (Sec. 3.1 admits directed graphs): a counting
+// sort of the arcs by head.  Within a row the order is that of the atomic
+// cursor; nothing downstream depends on it (sketches, labels and sweeps are
+// minima over the row).
+// ---------------------------------------------------------------------------
+__global__ void k_in_degree(uint64_t m, const uint32_t *col, uint32_t *deg) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; a < m; a += stride) atomicAdd(&deg[col[a]], 1u);
+}
+
+// row_ptr is validated: row_ptr[0] = 0, non-decreasing, row_ptr[n] = m, and
+// every col < n, so the tail search stays in [0, n) and p < in_ptr[v + 1].
+__global__ void k_in_scatter(uint32_t n, uint64_t m, const uint64_t *row_ptr, const uint32_t *col,
+                             const uint32_t *w, const uint64_t *in_ptr, uint32_t *cur, uint32_t *in_col,
+                             uint32_t *in_w) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; a < m; a += stride) {
+    uint32_t lo = 0, hi = n;  // row_ptr[lo] <= a < row_ptr[hi]
+    while (hi - lo > 1) {
+      const uint32_t mid = lo + ((hi - lo) >> 1);
+      if (row_ptr[mid] <= a) lo = mid;
+      else hi = mid;
+    }
+    const uint32_t v = col[a];
+    const uint64_t p = in_ptr[v] + atomicAdd(&cur[v], 1u);
+    in_col[p] = lo;
+    if (w) in_w[p] = w[a];
+  }
+}
+
+size_t transpose_bytes(uint32_t n, uint64_t m, bool weighted) {
+  return (size_t)(n + 1) * 8 + (size_t)n * 4 + (size_t)m * (weighted ? 8 : 4) + ((size_t)1 << 20);
+}
+
+void set_in_arcs(Ctx &c, Graph &g, bool directed) {
+  if (!directed) {
+    g.in_ptr = g.row_ptr;
+    g.in_col = g.col;
+    g.in_w = g.w;
+    return;
+  }
+  const uint32_t n = g.n;
+  const uint64_t m = g.m;
+  uint32_t *deg = c.arena->get<uint32_t>(n);
+  uint64_t *ip = c.arena->get<uint64_t>((size_t)n + 1);
+  uint32_t *ic = c.arena->get<uint32_t>(m ? m : 1);
+  uint32_t *iw = g.w ? c.arena->get<uint32_t>(m ? m : 1) : nullptr;
+  fill_u32(c, deg, n, 0);
+  const uint32_t blocks = (uint32_t)std::min<uint64_t>(ceil_div(m ? m : 1, 256), 16384);
+  if (m) {
+    k_in_degree<<<blocks, 256, 0, c.s>>>(m, g.col, deg);
+    FL_LAUNCH_CHECK();
+  }
+  scan_u32_to_u64(c, deg, ip, n);
+  fill_u32(c, deg, n, 0);  // now the per-row cursor
+  if (m) {
+    k_in_scatter<<<blocks, 256, 0, c.s>>>(n, m, g.row_ptr, g.col, g.w, ip, deg, ic, iw);
+    FL_LAUNCH_CHECK();
+  }
+  g.in_ptr = ip;
+  g.in_col = ic;
+  g.in_w = iw;
 }
 
 // ---------------------------------------------------------------------------
@@ -392,7 +461,9 @@ void sssp_alloc(Ctx &c, SsspWork &wk, uint32_t n, uint64_t m) {
 }
 
 // Runs to the fixed point.  Returns the number of iterations.  Stamps grow
-// monotonically across the calls on one workspace.
+// monotonically across the calls on one workspace.  Labels travel against
+// the arcs (over the in-arcs), so each vertex ends with the best label of the
+// seeds it can reach: distances from every vertex TO the seed set.
 
 uint32_t sssp_run(Ctx &c, const Graph &g, uint64_t *labels, const uint32_t *seeds, uint32_t nseeds,
                   SsspWork &wk, uint64_t) {
@@ -414,11 +485,11 @@ uint32_t sssp_run(Ctx &c, const Graph &g, uint64_t *labels, const uint32_t *seed
       // cnt[cur ^ 1] (the next frontier's count) is zero: cleared at the
       // start or by the previous iteration's k_sssp_heavy
       const uint32_t stamp = ++wk.stamp;
-      k_sssp_push<<<(uint32_t)blocks, 256, 0, c.s>>>(g.row_ptr, g.col, g.w, labels, wk.front[cur], &cnt[cur],
+      k_sssp_push<<<(uint32_t)blocks, 256, 0, c.s>>>(g.in_ptr, g.in_col, g.in_w, labels, wk.front[cur], &cnt[cur],
                                                       wk.front[cur ^ 1], &cnt[cur ^ 1], wk.flag, stamp,
                                                       wk.heavy, &cnt[2]);
       FL_LAUNCH_CHECK();
-      k_sssp_heavy<<<256, 256, 0, c.s>>>(g.row_ptr, g.col, g.w, labels, wk.front[cur ^ 1], &cnt[cur ^ 1],
+      k_sssp_heavy<<<256, 256, 0, c.s>>>(g.in_ptr, g.in_col, g.in_w, labels, wk.front[cur ^ 1], &cnt[cur ^ 1],
                                          wk.flag, stamp, wk.heavy, &cnt[2], &cnt[cur]);
       FL_LAUNCH_CHECK();
       cur ^= 1;

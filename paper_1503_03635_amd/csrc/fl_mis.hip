@@ -14,7 +14,10 @@
 //   3. clients within the radius of a joined facility are covered;
 //   4. active facilities within the radius of a covered client retire.
 // Rounds repeat until no facility is active; the result is the greedy MIS in
-// priority order.  In a union of several graphs, each graph walks through its
+// priority order.  The radius is measured from client to facility, d(c, f):
+// sweeps 1 and 3 start at facilities and push over the in-arcs, sweeps 2 and
+// 4 start at clients and push over the out-arcs (the same arcs when the graph
+// is undirected).  In a union of several graphs, each graph walks through its
 // own non-empty rungs: step i runs the i-th one of every graph at once (the
 // graphs share no vertex, so their sweeps do not interact), each with its own
 // radius and priorities.  A sweep computes, for every vertex x, the minimum label
@@ -182,6 +185,7 @@ __global__ void k_sweep_reset(SweepArgs S) {
 
 struct MisWork {
   SweepArgs S;
+  const Graph *g;
   uint32_t *lab;     // [n] source labels
   uint32_t *pm;      // [n] pi_min of clients
   uint32_t *act;     // [n] list of active facilities
@@ -192,10 +196,18 @@ struct MisWork {
   uint32_t *cnts;    // [8] device counters
 };
 
-// run one sweep to completion; results in S.ml (caller resets afterwards)
-static void sweep(Ctx &c, MisWork &M, const uint32_t *src, uint32_t nsrc, uint32_t R) {
+enum class Toward { clients, facilities };
+
+// run one sweep to completion; results in S.ml (caller resets afterwards).
+// Toward::clients: from facilities f to every x with d(x, f) <= R (in-arcs);
+// Toward::facilities: from clients c to every x with d(c, x) <= R (out-arcs).
+static void sweep(Ctx &c, MisWork &M, const uint32_t *src, uint32_t nsrc, uint32_t R, Toward dir) {
   SweepArgs &S = M.S;
   if (nsrc == 0) return;
+  const bool in = dir == Toward::clients;
+  S.row_ptr = in ? M.g->in_ptr : M.g->row_ptr;
+  S.col = in ? M.g->in_col : M.g->col;
+  S.w = in ? M.g->in_w : M.g->w;
   k_sweep_init<<<(uint32_t)ceil_div((uint64_t)nsrc, 256), 256, 0, c.s>>>(S, src, nsrc, M.lab);
   FL_LAUNCH_CHECK();
   k_sweep_heavy<<<256, 256, 0, c.s>>>(S, 0);
@@ -494,9 +506,7 @@ int mis_phase(Ctx &c, const MisIn &in, uint8_t *open, std::vector<uint32_t> &rou
   M.S.gid = in.gid;
   uint32_t *d_R = c.arena->get<uint32_t>(G);
   M.S.Rg = d_R;
-  M.S.row_ptr = g.row_ptr;
-  M.S.col = g.col;
-  M.S.w = g.w;
+  M.g = &g;
   M.S.ml = c.arena->get<uint32_t>(n);
   M.S.pend = c.arena->get<uint32_t>((size_t)NS * n);
   M.S.tl = c.arena->get<uint32_t>((size_t)NS * n);
@@ -589,7 +599,7 @@ int mis_phase(Ctx &c, const MisIn &in, uint8_t *open, std::vector<uint32_t> &rou
       k_set_key_labels<<<(uint32_t)ceil_div(na, 256), 256, 0, c.s>>>(M.act, na, M.lab, in.gid, in.seg,
                                                                      luby_round);
       FL_LAUNCH_CHECK();
-      sweep(c, M, M.act, na, Rmax);
+      sweep(c, M, M.act, na, Rmax, Toward::clients);
       if (G > 1) {
         for (uint32_t q = 0; q < G; ++q) rounds_out[q] += hact[q];
       } else {
@@ -603,7 +613,7 @@ int mis_phase(Ctx &c, const MisIn &in, uint8_t *open, std::vector<uint32_t> &rou
       sweep_reset(c, M);
       const uint32_t ns2 = read_u32(c, M.cnts);
       // 2. smallest pi_min around each active facility; joins
-      sweep(c, M, M.src, ns2, Rmax);
+      sweep(c, M, M.src, ns2, Rmax, Toward::facilities);
       k_join<<<(uint32_t)ceil_div(na, 256), 256, 0, c.s>>>(M.act, na, M.S.ml, in.gid, in.seg, luby_round, open,
                                                            M.joined, M.cnts + 1, M.act2, M.cnts + 2);
       FL_LAUNCH_CHECK();
@@ -616,7 +626,7 @@ int mis_phase(Ctx &c, const MisIn &in, uint8_t *open, std::vector<uint32_t> &rou
       // 3. clients covered by a joined facility
       k_set_const_labels<<<(uint32_t)ceil_div(nj, 256), 256, 0, c.s>>>(M.joined, nj, M.lab, 0);
       FL_LAUNCH_CHECK();
-      sweep(c, M, M.joined, nj, Rmax);
+      sweep(c, M, M.joined, nj, Rmax, Toward::clients);
       if (ncl) {
         k_collect_hit<<<(uint32_t)ceil_div(ncl, 256), 256, 0, c.s>>>(Ct, ncl, M.S.ml, M.cov, M.cnts + 3, 1);
         FL_LAUNCH_CHECK();
@@ -626,7 +636,7 @@ int mis_phase(Ctx &c, const MisIn &in, uint8_t *open, std::vector<uint32_t> &rou
       // 4. facilities next to a covered client retire
       k_set_const_labels<<<(uint32_t)ceil_div(ncov ? ncov : 1, 256), 256, 0, c.s>>>(M.cov, ncov, M.lab, 0);
       FL_LAUNCH_CHECK();
-      sweep(c, M, M.cov, ncov, Rmax);
+      sweep(c, M, M.cov, ncov, Rmax, Toward::facilities);
       k_collect_hit<<<(uint32_t)ceil_div(nr, 256), 256, 0, c.s>>>(M.act2, nr, M.S.ml, M.act, M.cnts + 4, 0);
       FL_LAUNCH_CHECK();
       sweep_reset(c, M);

@@ -74,5 +74,6 @@ def assert_solve_equal(g, k, seed, eps=0.1, flags=0):
     assert st["ads_entries"] == want["ads_entries"]
     assert st["gamma"] == want["gamma"]
     assert st["n_guard"] == want["n_guard"]
+    assert st["n_reach_guard"] == want["n_reach_guard"]
     assert st["alpha0"] == want["alpha0"]
     return got, want

@@ -51,3 +51,28 @@ def test_strerror_and_param_errors_without_gpu():
     assert L.fl_solve(C.byref(prob), C.byref(prm), C.byref(res), None) == _lib.FL_EINVAL
     assert L.fl_solve(None, C.byref(prm), C.byref(res), None) == _lib.FL_EINVAL
     assert res.n_open == 0
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every field of the ctypes structs sits at the offset the C compiler
+    gives it from include/fl.h (a mismatch would corrupt results silently)."""
+    import subprocess
+    from paper_1503_03635_amd import _lib
+    structs = {"fl_problem": _lib.FlProblem, "fl_params": _lib.FlParams, "fl_stats": _lib.FlStats,
+               "fl_result": _lib.FlResult}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "fl.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
