@@ -145,6 +145,43 @@ def batch_bench(count, plain_count, seed):
             "batched_relax_per_s": round(relax / t_batch, 1), "batched_s": round(t_batch, 3)}
 
 
+def directed_bench(scale, edge_factor, k, seed, steps):
+    """The directed reading (FL_FLAG_DIRECTED): the R-MAT samples of the main
+    workload kept as arcs, unit weights, k and costs as there.  One untimed
+    solve, then `steps` timed ones."""
+    import torch
+    import graphgen as gg
+    import paper_1503_03635_amd as fl
+    t0 = time.perf_counter()
+    g = gg.rmat_unit_directed(scale, edge_factor, seed)
+    dg = fl.to_device(g, "cuda:0")
+    torch.cuda.synchronize()
+    log(f"[bench] directed R-MAT 2^{scale}: n={g.n} arcs={g.n_arcs} in {time.perf_counter() - t0:.1f}s")
+    outputs = fl._alloc_outputs(g.n, dg.col.device, False)
+    r = fl.solve(dg, k, seed, 0.1, outputs=outputs)
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = fl.solve(dg, k, seed, 0.1, outputs=outputs)
+        stats.append(dict(r["stats"], total_cost=r["total_cost"], n_open=r["n_open"],
+                          n_unreachable=r["n_unreachable"]))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    s0 = stats[0]
+    log(f"[bench] directed: {elapsed / steps * 1e3:.1f} ms per solve, open={s0['n_open']} "
+        f"unreachable={s0['n_unreachable']} reach_guard={s0['n_reach_guard']}")
+    return {"workload": f"rmat{scale}_directed_unit_k{k}", "n": g.n, "arcs": g.n_arcs,
+            "edge_samples": edge_factor << scale, "steps": steps,
+            "ms_per_solve": round(elapsed / steps * 1e3, 2),
+            "relax_per_s": round(sum(x["relax_alg"] for x in stats) / elapsed, 1),
+            "relax_alg_per_solve": s0["relax_alg"], "ads_entries_per_solve": s0["ads_entries"],
+            "phase_ms": {p: round(sum(x[f"ms_{p}"] for x in stats) / steps, 2)
+                         for p in ("validate", "ads", "gamma", "open", "mis", "assign", "total")},
+            "n_open": s0["n_open"], "n_unreachable": s0["n_unreachable"],
+            "n_reach_guard": s0["n_reach_guard"]}
+
+
 def serve_bench(count, seed, rate, slots):
     """Continuous batching: a Poisson stream of count requests at `rate`
     requests/s (Chung-Lu graphs, exponent 2.2, average degree 12, weights
@@ -300,6 +337,8 @@ def main():
     ap.add_argument("--serve-count", type=int, default=64, help="requests of the serving measurement (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=3)
+    ap.add_argument("--directed-steps", type=int, default=2,
+                    help="timed solves of the directed reading of the same R-MAT samples (0: skip)")
     ap.add_argument("--sweep", action="store_true",
                     help="run the k and eps sweeps instead and print their JSON")
     ap.add_argument("--accuracy", action="store_true",
@@ -407,6 +446,10 @@ def main():
         out["batched"] = batch_bench(args.batch_count, min(args.batch_plain, args.batch_count), args.seed)
     if args.serve_count:
         out["serving"] = serve_bench(args.serve_count, args.seed, args.serve_rate, args.serve_slots)
+    if args.directed_steps:
+        del dg, outputs
+        torch.cuda.empty_cache()
+        out["directed"] = directed_bench(args.scale, args.edge_factor, args.k, args.seed, args.directed_steps)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(g, args.k, args.seed, args.cpu_sources)

@@ -433,6 +433,14 @@ def rmat_unit(scale: int = 22, edge_factor: int = 16, seed: int = 1) -> Graph:
     return with_problem(g, seed, cost="uniform", cost_lo=1, cost_hi=1000)
 
 
+def rmat_unit_directed(scale: int = 22, edge_factor: int = 16, seed: int = 1) -> Graph:
+    """The same R-MAT samples kept as arcs (row -> column; self loops and
+    repeats dropped), unit weights, all vertices clients and facilities,
+    costs uniform 1..1000."""
+    g = rmat(scale, edge_factor << scale, seed, directed=True)
+    return with_problem(g, seed, cost="uniform", cost_lo=1, cost_hi=1000)
+
+
 def rmat_weighted(scale: int = 24, avg_deg: int = 32, seed: int = 1) -> Graph:
     """R-MAT (0.57, 0.19, 0.19, 0.05), 2^scale vertices, avg_deg/2 * 2^scale
     edge samples, weights 1..100, 10% facilities (seeded) with lognormal(5, 1)

@@ -75,3 +75,61 @@ def test_solve_properties(big):
         best = fac[np.lexsort((fac, d[fac]))[0]]
         print(f"[fullsize] client {c}: nearest open {best} at {d[best]}", flush=True)
         assert assign[c] == best and dist[c] == d[best]
+
+
+@pytest.fixture(scope="module")
+def bigd():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    print("[fullsize] generating directed R-MAT 2^22", flush=True)
+    g = gg.rmat_unit_directed(22, 16, SEED)
+    return g, fl.to_device(g, "cuda:0")
+
+
+def test_directed_sampled_sketches_equal_definition(bigd):
+    """Directed reading of the same samples, as bench.py times it: sketches of
+    the vertices with the most in-arcs and out-arcs and of random ones equal
+    the definition (the vertices that reach v, by (d(u, v), id) order)."""
+    g, dg = bigd
+    s = fl.ads_build(dg, K, SEED)
+    torch.cuda.synchronize()
+    off = s["off"].cpu().numpy().view(np.uint64)
+    rank = s["rank"].cpu().numpy().view(np.uint32)
+    dist = s["dist"].cpu().numpy().view(np.uint32)
+    rk, _ = O.ranks(g.n, SEED)
+    indeg = np.bincount(g.col, minlength=g.n)
+    outdeg = g.degrees()
+    rng = np.random.Generator(np.random.PCG64(13))
+    sample = [int(np.argmax(indeg)), int(np.argmax(outdeg))]
+    sample += [int(v) for v in rng.choice(np.nonzero(indeg > 0)[0], 2, replace=False)]
+    for v in sample:
+        print(f"[fullsize] directed vertex {v} (in {indeg[v]}, out {outdeg[v]})", flush=True)
+        r_want, d_want = O.ads_one(g, K, SEED, v, rank=rk)
+        o0, o1 = int(off[v]), int(off[v + 1])
+        assert np.array_equal(rank[o0:o1], r_want), f"ranks of {v}"
+        assert np.array_equal(dist[o0:o1], d_want), f"distances of {v}"
+
+
+def test_directed_solve_properties(bigd):
+    """Directed solve: the objective equals its definition from the outputs,
+    every served client is assigned to an open facility it reaches, and
+    sampled clients go to their nearest open facility along arcs."""
+    g, dg = bigd
+    r = fl.solve(dg, K, SEED, EPS, diagnostics=True)
+    torch.cuda.synchronize()
+    opened = r["open"].cpu().numpy().astype(bool)
+    assign = r["assign"].cpu().numpy().view(np.uint32)
+    dist = r["dist"].cpu().numpy().view(np.uint32)
+    served = assign != fl.FL_NONE
+    assert r["n_unreachable"] == 0 and served.all()          # every vertex is a facility
+    cost = int(g.fac_cost[opened].astype(np.uint64).sum()) + int(dist[served].astype(np.uint64).sum())
+    assert cost == r["total_cost"]
+    assert int(opened.sum()) == r["n_open"]
+    assert opened[assign[served]].all()
+    print(f"[fullsize] directed: open {r['n_open']}, reach guard {r['stats']['n_reach_guard']}", flush=True)
+    rng = np.random.Generator(np.random.PCG64(14))
+    fac = np.nonzero(opened)[0]
+    for c in rng.choice(np.nonzero(g.degrees() > 0)[0], 2, replace=False):
+        d = O.sssp(g, int(c))                                   # d(c, .) along arcs
+        best = fac[np.lexsort((fac, d[fac]))[0]]
+        print(f"[fullsize] client {c}: nearest open {best} at {d[best]}", flush=True)
+        assert assign[c] == best and dist[c] == d[best]
