@@ -478,8 +478,11 @@ uint32_t sssp_run(Ctx &c, const Graph &g, uint64_t *labels, const uint32_t *seed
     // The kernel reads the frontier size on the device, so small frontiers
     // run several iterations per host check (an empty frontier costs one
     // short launch); large ones are checked after every iteration.
+    // A frontier can grow by orders of magnitude within a burst: burst
+    // launches get a grid for any frontier (blocks past the count exit).
     const uint32_t burst = nf > 65536 ? 1u : 8u;
-    uint64_t blocks = ceil_div((uint64_t)nf * (burst > 1 ? 4 : 1), 256);
+    uint64_t blocks = ceil_div((uint64_t)nf, 256);
+    if (burst > 1) blocks = std::max<uint64_t>(blocks, std::min<uint64_t>(ceil_div(g.n, 256), 2048));
     if (blocks > 16384) blocks = 16384;
     for (uint32_t b = 0; b < burst; ++b) {
       // cnt[cur ^ 1] (the next frontier's count) is zero: cleared at the
