@@ -9,6 +9,10 @@
 namespace fl {
 
 constexpr uint32_t HCHUNK = 2048;  // arcs per queued piece
+// blocks (of 256 threads) of a long-row kernel: it walks a device-side count
+// with one wave per piece, so it needs many waves per CU to hide the random
+// accesses of hub rows (16 per CU on 256 CUs); idle blocks exit at once
+constexpr uint32_t HEAVY_BLOCKS = 1024;
 
 // queue entries needed for n vertices and m arcs at most
 inline uint64_t piece_capacity(uint64_t n, uint64_t m) { return n + m / HCHUNK + 64; }

@@ -492,7 +492,7 @@ uint32_t sssp_run(Ctx &c, const Graph &g, uint64_t *labels, const uint32_t *seed
                                                       wk.front[cur ^ 1], &cnt[cur ^ 1], wk.flag, stamp,
                                                       wk.heavy, &cnt[2]);
       FL_LAUNCH_CHECK();
-      k_sssp_heavy<<<256, 256, 0, c.s>>>(g.in_ptr, g.in_col, g.in_w, labels, wk.front[cur ^ 1], &cnt[cur ^ 1],
+      k_sssp_heavy<<<HEAVY_BLOCKS, 256, 0, c.s>>>(g.in_ptr, g.in_col, g.in_w, labels, wk.front[cur ^ 1], &cnt[cur ^ 1],
                                          wk.flag, stamp, wk.heavy, &cnt[2], &cnt[cur]);
       FL_LAUNCH_CHECK();
       cur ^= 1;

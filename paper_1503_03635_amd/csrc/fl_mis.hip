@@ -210,7 +210,7 @@ static void sweep(Ctx &c, MisWork &M, const uint32_t *src, uint32_t nsrc, uint32
   S.w = in ? M.g->in_w : M.g->w;
   k_sweep_init<<<(uint32_t)ceil_div((uint64_t)nsrc, 256), 256, 0, c.s>>>(S, src, nsrc, M.lab);
   FL_LAUNCH_CHECK();
-  k_sweep_heavy<<<256, 256, 0, c.s>>>(S, 0);
+  k_sweep_heavy<<<HEAVY_BLOCKS, 256, 0, c.s>>>(S, 0);
   FL_LAUNCH_CHECK();
   std::vector<uint32_t> h(S.NS);
   uint32_t j = 1;
@@ -235,7 +235,7 @@ static void sweep(Ctx &c, MisWork &M, const uint32_t *src, uint32_t nsrc, uint32
     for (uint32_t b = 0; b < burst && j <= R; ++b, ++j) {
       k_sweep_round<<<blocks, 256, 0, c.s>>>(S, j);
       FL_LAUNCH_CHECK();
-      k_sweep_heavy<<<256, 256, 0, c.s>>>(S, j);
+      k_sweep_heavy<<<HEAVY_BLOCKS, 256, 0, c.s>>>(S, j);
       FL_LAUNCH_CHECK();
     }
   }
