@@ -26,8 +26,12 @@
 // order, filtered in parallel against the running k-th smallest rank, and
 // the survivors of a bucket are decided 64 at a time by one parallel count
 // (set elements below + earlier candidates of the chunk below < k).
-// The HIP thresholds T_j (k-th smallest rank before entry j) are computed
-// afterwards for the rows that need them.
+// Levels are stored in increasing rank order while the rounds run (a
+// neighbour reads one only up to its threshold); the rows that need the
+// canonical order (those with a HIP-threshold row) also receive each level in
+// id order, in their threshold row, at commit.  A last pass moves that order
+// into the sketch row and computes the HIP thresholds T_j (k-th smallest
+// rank before entry j) in its place.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -39,7 +43,6 @@
 
 namespace fl {
 
-constexpr int ADS_WPB = 4;          // waves per block (canonical-order pass)
 constexpr int TASK_WPB = 1;         // waves per block of the round kernels: a block's LDS is
                                     // freed when its own task ends (task lengths vary widely)
 constexpr uint32_t ADS_SB = 1024;   // survivor ids per wave: one level of one sketch plus a chunk
@@ -73,7 +76,13 @@ struct AdsArgs {
   uint32_t *kept_cnt;  // [slots]
   uint64_t *ctr;       // [64] relax_exec, [64] active vertices this round, [64] survivors, [64] prunes
   uint32_t *status;    // [0] capacity overflow, [1] survivor-buffer overflow
+  uint32_t *thr;             // [rows * cap] threshold rows: canonical-order ranks until the last pass
+  const uint32_t *thr_idx;   // [n] threshold row of each vertex (INF32 = none); nullptr = row u
 };
+
+__device__ inline uint32_t thr_row(const AdsArgs &P, uint32_t u) {
+  return P.thr ? (P.thr_idx ? P.thr_idx[u] : u) : INF32;
+}
 
 __device__ inline uint64_t pack_info(uint32_t round, uint32_t start, uint32_t count) {
   return ((uint64_t)round << 32) | ((uint64_t)start << 16) | (uint64_t)count;
@@ -136,6 +145,8 @@ __global__ __launch_bounds__(256) void k_ads_init(AdsArgs P, int mark) {
   if (lane == 0) {
     P.sk_rank[(size_t)u * P.cap] = r;
     P.sk_dist[(size_t)u * P.cap] = 0;
+    const uint32_t tr = thr_row(P, u);
+    if (tr != INF32) P.thr[(size_t)tr * P.cap] = r;
     P.bk[(size_t)u * P.k] = r;
     P.cnt[u] = 1;
     P.dinfo[u] = pack_info(0, 0, 1);  // slot 0
@@ -552,8 +563,13 @@ __device__ inline void level_commit(const AdsArgs &P, uint32_t u, uint32_t D, Le
     return;
   }
   // The level is stored in increasing rank order, so that a neighbour reads
-  // it only up to its own threshold; rows get (distance, id) order after the
-  // last round (k_ads_canon).
+  // it only up to its own threshold.  A row with a threshold row also gets the
+  // level in id order (the order of s_tmp) there, for the last pass.
+  const uint32_t tr = thr_row(P, u);
+  if (tr != INF32) {
+    uint32_t *trow = P.thr + (size_t)tr * P.cap + cu;
+    for (uint32_t i = lane; i < m; i += WAVE) trow[i] = rank_of(s_tmp[i], L.rm);
+  }
   const size_t base = (size_t)u * P.cap + cu;
   if (m <= (uint32_t)WAVE) {
     uint32_t x = (uint32_t)lane < m ? rank_of(s_tmp[lane], L.rm) : INF32;
@@ -683,84 +699,67 @@ __global__ __launch_bounds__(TASK_WPB * WAVE) void k_ads_merge(AdsArgs P, uint32
   level_commit<UNITW>(P, u, D, L, mark, s_id, s_tmp, s_cnt);
 }
 
-// Restore (distance, id) order inside each level of every row (levels were
-// stored in increasing rank order while the rounds ran).  One wave per row;
-// a level holds at most ADS_SB entries (the survivor buffer of its commit).
-__global__ __launch_bounds__(256) void k_ads_canon(uint32_t n, uint32_t cap, const uint32_t *gid,
-                                                   const SegInfo *seg, const uint32_t *cnt, uint32_t *sk_rank,
-                                                   const uint32_t *sk_dist, uint32_t *status) {
-  __shared__ uint32_t lds[ADS_WPB][ADS_SB];
-  const int lane = lane_id();
-  const int wv = threadIdx.x / WAVE;
-  const uint64_t u64 = (uint64_t)blockIdx.x * ADS_WPB + wv;
-  if (u64 >= n) return;
-  const uint32_t u = (uint32_t)u64;
-  const RankMap rm = rank_map(seg[seg_of(gid, u)]);
-  const uint32_t c = cnt[u];
-  uint32_t *rr = sk_rank + (size_t)u * cap;
-  const uint32_t *dd = sk_dist + (size_t)u * cap;
-  uint32_t *s = lds[wv];
-  uint32_t pos = 1;  // entry 0 is u itself, alone at distance 0
-  while (pos < c) {
-    const uint32_t d0 = dd[pos];
-    uint32_t e = pos;
-    for (;;) {
-      const uint32_t i = e + lane;
-      const uint64_t other = __ballot(!(i < c && dd[i] == d0));
-      if (other) {
-        e += (uint32_t)(__ffsll((long long)other) - 1);
-        break;
-      }
-      e += WAVE;
-    }
-    const uint32_t len = e - pos;
-    if (len > 1 && len <= (uint32_t)WAVE) {
-      uint32_t x = (uint32_t)lane < len ? id_of(rr[pos + lane], rm) : INF32;
-      x = wave_sort_reg(x);
-      if ((uint32_t)lane < len) rr[pos + lane] = rank_of(x, rm);
-    } else if (len > 1 && len <= ADS_SB) {
-      for (uint32_t i = lane; i < len; i += WAVE) s[i] = id_of(rr[pos + i], rm);
-      wave_sort_lds(s, len);
-      for (uint32_t i = lane; i < len; i += WAVE) rr[pos + i] = rank_of(s[i], rm);
-      wave_lds_sync();
-    } else if (len > ADS_SB && lane == 0) {
-      atomicOr(&status[1], 1u);
-    }
-    pos = e;
-  }
-}
 
 // HIP thresholds of the sketch rows that need them: T_j = k-th smallest rank
 // among entries 0..j-1 of the row (0 encodes 2^32 while fewer than k).  One
 // wave per row, the running bottom-k in registers.
-__global__ __launch_bounds__(256) void k_hip_thresholds(uint32_t rows, const uint32_t *row_vertex, uint32_t cap,
-                                                        uint32_t k, const uint32_t *cnt, const uint32_t *sk_rank,
-                                                        uint32_t *thr) {
+// Merge of a bitonic sequence held one value per lane into ascending
+// (desc = false) or descending order.
+__device__ inline uint32_t wave_bitonic_merge(uint32_t x, bool desc) {
   const int lane = lane_id();
+#pragma unroll
+  for (int j = 32; j >= 1; j >>= 1) {
+    const uint32_t y = __shfl_xor(x, j, WAVE);
+    const bool lo = ((lane & j) == 0) != desc;
+    x = lo ? (x < y ? x : y) : (x > y ? x : y);
+  }
+  return x;
+}
+
+// Last pass over the rows with a threshold row (one wave per row): the row
+// holds the sketch in canonical (distance, id) order (written at commit); it
+// is copied into the sketch row, and entry j of the threshold row becomes
+// T_j = the k-th smallest rank of entries 0..j-1 (0 for j < k, meaning 2^32).  Every later entry ranks below its T_j (that is what membership of
+// the sketch means), so each one enters the running bottom-k set and evicts
+// its maximum, and no later entry is above that maximum.  Hence for a chunk
+// C of up to 64 entries after a full set S, the threshold of the chunk's
+// i-th entry is the (i+1)-th largest of S and C together, and the next S is
+// the k smallest of them: one sort and two bitonic merges per chunk.
+__global__ __launch_bounds__(256) void k_hip_thresholds(uint32_t rows, const uint32_t *row_vertex, uint32_t cap,
+                                                        uint32_t k, const uint32_t *cnt, uint32_t *sk_rank,
+                                                        uint32_t *thr) {
+  const uint32_t lane = (uint32_t)lane_id();
   const uint64_t row = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
   if (row >= rows) return;
   const uint32_t u = row_vertex ? row_vertex[row] : (uint32_t)row;
   const uint32_t c = cnt[u];
-  const uint32_t *rk = sk_rank + (size_t)u * cap;
-  uint32_t *out = thr + (size_t)row * cap;
-  uint32_t setv = INF32, nset = 0;
-  for (uint32_t j0 = 0; j0 < c; j0 += WAVE) {
-    const uint32_t mine = j0 + lane < c ? rk[j0 + lane] : INF32;
-    uint32_t tout = 0;
-    const uint32_t lim = c - j0 < (uint32_t)WAVE ? c - j0 : (uint32_t)WAVE;
-    for (uint32_t i = 0; i < lim; ++i) {
-      const uint32_t r = __shfl(mine, (int)i, WAVE);
-      const uint32_t T = nset < k ? 0u : __shfl(setv, (int)k - 1, WAVE);
-      if ((uint32_t)lane == i) tout = T;
-      const uint32_t below = (uint32_t)__popcll(__ballot(setv < r));
-      if (below < k) {
-        const uint32_t up = __shfl_up(setv, 1, WAVE);
-        if ((uint32_t)lane > below && (uint32_t)lane < k) setv = up;
-        if ((uint32_t)lane == below) setv = r;
-        if (nset < k) ++nset;
-      }
-    }
-    if (j0 + lane < c) out[j0 + lane] = tout;
+  uint32_t *rk = sk_rank + (size_t)u * cap;
+  uint32_t *out = thr + (size_t)row * cap;  // canonical ranks in, thresholds out (each lane its own slots)
+  const uint32_t k0 = c < k ? c : k;  // k <= WAVE
+  const uint32_t first = lane < k0 ? out[lane] : INF32;
+  if (lane < k0) {
+    rk[lane] = first;
+    out[lane] = 0;
+  }
+  if (c <= k) return;
+  uint32_t S = wave_sort_reg(lane < k ? first : INF32);  // ascending, INF32 above k
+  for (uint32_t j0 = k; j0 < c; j0 += WAVE) {
+    const uint32_t m = c - j0 < (uint32_t)WAVE ? c - j0 : (uint32_t)WAVE;
+    const uint32_t mine = lane < m ? out[j0 + lane] : INF32;
+    if (lane < m) rk[j0 + lane] = mine;
+    const uint32_t ca = wave_sort_reg(mine);  // chunk ascending, INF32 above m
+    // the 64 largest: S descending (0 above k) against C ascending (0 below 64 - m)
+    const uint32_t sd = __shfl(S, (int)(lane < k ? k - 1 - lane : 0), WAVE);
+    const uint32_t cs = __shfl(ca, (int)(lane >= WAVE - m ? lane - (WAVE - m) : 0), WAVE);
+    uint32_t top = (lane < k ? sd : 0u) > (lane >= WAVE - m ? cs : 0u) ? (lane < k ? sd : 0u)
+                                                                        : (lane >= WAVE - m ? cs : 0u);
+    top = wave_bitonic_merge(top, true);  // lane i: the (i+1)-th largest
+    if (lane < m) out[j0 + lane] = top;
+    // the k smallest: S ascending (INF32 above k) against C descending (INF32 first)
+    const uint32_t cd = __shfl(ca, (int)(WAVE - 1 - lane), WAVE);
+    uint32_t bot = S < cd ? S : cd;
+    bot = wave_bitonic_merge(bot, false);
+    S = lane < k ? bot : INF32;
   }
 }
 
@@ -932,6 +931,8 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
   P.wl_cnt = c.arena->get<uint32_t>(NS);
   P.ctr = c.arena->get<uint64_t>(256);
   P.status = c.arena->get<uint32_t>(4);
+  P.thr = o.thr;
+  P.thr_idx = o.thr ? cfg.thr_idx : nullptr;
   fill_u64(c, P.dinfo, (size_t)NS * n, INF64);
   fill_u32(c, P.flags, (size_t)n * FW, 0);
   fill_u32(c, P.wl_cnt, NS, 0);
@@ -989,7 +990,9 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
     alloc_list(tl_dense);
     build_tasks(c, g, dense, n_dense, ts, tl_dense);
   }
-  const uint64_t dense_threshold = (uint64_t)n_dense / 32;
+  // a round marks (so that the next one runs on worklists) once the previous
+  // round changed at most a quarter of the dense list
+  const uint64_t dense_threshold = (uint64_t)n_dense / 4;
 
   // round 0
   bool mark = !dense_ok || n_dense <= dense_threshold;
@@ -1076,8 +1079,12 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
           sv += hs[128 + i];
           pr += hs[192 + i];
         }
-        std::fprintf(stderr, "[fl] round %u: %u tasks, %u split, %.2f ms, examined(cum) %.3fG survivors(cum) %.3fG prunes(cum) %.3fM\n",
-                     D, T->ntasks, T->nsplit, ms, ex / 1e9, sv / 1e9, pr / 1e6);
+        uint64_t act = 0;
+        for (int i = 0; i < 64; ++i) act += hs[64 + i];
+        std::fprintf(stderr, "[fl] round %u: %s, %u tasks, %u split, %llu changed, %.2f ms, examined(cum) %.3fG "
+                     "survivors(cum) %.3fG prunes(cum) %.3fM\n",
+                     D, sparse ? "sparse" : "dense", T->ntasks, T->nsplit, (unsigned long long)act, ms, ex / 1e9,
+                     sv / 1e9, pr / 1e6);
       }
     }
     const uint32_t st0 = (uint32_t)(c.h_status[0] & 0xFFFFFFFFu);
@@ -1134,17 +1141,8 @@ int ads_build(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o) {
     if (std::getenv("FL_DEBUG"))
       std::fprintf(stderr, "[fl] sketches: cap %u rounds %u overflow %d\n", cap, o.rounds, (int)more);
     if (!more) {
-      {
-        uint32_t *st = c.arena->get<uint32_t>(4);
-        fill_u32(c, st, 4, 0);
-        k_ads_canon<<<(uint32_t)ceil_div(g.n, ADS_WPB), ADS_WPB * WAVE, 0, c.s>>>(
-            g.n, cap, cfg.gid, cfg.seg, o.cnt, o.sk_rank, o.sk_dist, st);
-        FL_LAUNCH_CHECK();
-        FL_HIP(hipMemcpyAsync(c.h_status, st, 8, hipMemcpyDeviceToHost, c.s));
-        c.sync();
-        c.arena->rewind(after_out);
-        if (c.h_status[0] >> 32) return FL_EHIP;
-      }
+      // rows without a threshold row keep rank order within a level: only
+      // the rows of facilities (every row for fl_ads_build) are read later
       if (o.thr && thr_rows) {
         k_hip_thresholds<<<(uint32_t)ceil_div((uint64_t)thr_rows * WAVE, 256), 256, 0, c.s>>>(
             thr_rows, cfg.thr_rows_vertex, cap, cfg.k, o.cnt, o.sk_rank, o.thr);

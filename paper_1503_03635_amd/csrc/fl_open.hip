@@ -87,6 +87,31 @@ __device__ inline void wave_append(uint32_t *list, uint32_t *count, bool want, u
   if (want) list[base + lanes_below(m)] = x;
 }
 
+// Block-aggregated append (every thread of a 256-thread block calls it, in
+// uniform control flow): one global atomic per block.  Used where most waves
+// append, so that the waves do not queue on one counter.
+__device__ inline void block_append(uint32_t *list, uint32_t *count, bool want, uint32_t x) {
+  __shared__ uint32_t s_off[256 / WAVE];
+  __shared__ uint32_t s_base;
+  const int lane = lane_id();
+  const int wv = threadIdx.x / WAVE;
+  const uint64_t m = __ballot(want);
+  if (lane == 0) s_off[wv] = (uint32_t)__popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t tot = 0;
+    for (int i = 0; i < 256 / WAVE; ++i) {
+      const uint32_t cw = s_off[i];
+      s_off[i] = tot;
+      tot += cw;
+    }
+    s_base = tot ? atomicAdd(count, tot) : 0u;
+  }
+  __syncthreads();
+  if (want) list[s_base + s_off[wv] + lanes_below(m)] = x;
+  __syncthreads();  // s_off and s_base may be reused
+}
+
 __global__ void k_fac_init(OpenArgs A) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= A.nF) return;
@@ -110,6 +135,7 @@ __device__ inline bool try_open(const OpenArgs &A, uint32_t fi, uint32_t f, doub
   return false;
 }
 
+// 256 threads per block (block_append)
 __global__ __launch_bounds__(256) void k_open_light(OpenArgs A, uint32_t t) {
   const uint32_t fi = blockIdx.x * blockDim.x + threadIdx.x;
   bool heavy = false, opened = false, nuf = false;
@@ -132,7 +158,7 @@ __global__ __launch_bounds__(256) void k_open_light(OpenArgs A, uint32_t t) {
       }
     }
   }
-  wave_append(A.heavy, A.heavy_cnt, heavy, fi);
+  block_append(A.heavy, A.heavy_cnt, heavy, fi);
   wave_append(A.opened, A.opened_cnt, opened, f);
   if (A.gid) {
     if (opened) ctr_add(A, g, OC_OPENED, 1);
