@@ -402,12 +402,15 @@ __global__ __launch_bounds__(256) void k_rung_scatter(uint32_t n, const uint32_t
     if (keys[it] != INF32) out[off[keys[it]] + lc[keys[it]] + lpos[it]] = (uint32_t)v;
   }
 }
-// concatenate ranges [src + start, src + start + len) of a list; one block per range
+// concatenate ranges [src + start, src + start + len) of a list; blockIdx.x
+// picks the range, the blocks along y split it
 __global__ void k_gather_ranges(const uint32_t *src, const uint64_t *rstart, const uint32_t *rlen,
                                 const uint64_t *rdst, uint32_t *dst) {
   const uint32_t r = blockIdx.x;
   const uint64_t s0 = rstart[r], d0 = rdst[r];
-  for (uint32_t i = threadIdx.x; i < rlen[r]; i += blockDim.x) dst[d0 + i] = src[s0 + i];
+  const uint32_t len = rlen[r];
+  const uint64_t stride = (uint64_t)gridDim.y * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.y * blockDim.x + threadIdx.x; i < len; i += stride) dst[d0 + i] = src[s0 + i];
 }
 // graphs whose facility of list[i] is active this round
 __global__ void k_mark_graphs(const uint32_t *list, uint32_t cnt, const uint32_t *gid, uint32_t *flag) {
@@ -469,7 +472,10 @@ static uint32_t gather(Ctx &c, const uint32_t *src, const std::vector<std::pair<
   FL_HIP(hipMemcpyAsync(rb.start, hs.data(), R * 8, hipMemcpyHostToDevice, c.s));
   FL_HIP(hipMemcpyAsync(rb.dst, hd.data(), R * 8, hipMemcpyHostToDevice, c.s));
   FL_HIP(hipMemcpyAsync(rb.len, hl.data(), R * 4, hipMemcpyHostToDevice, c.s));
-  k_gather_ranges<<<(uint32_t)R, 256, 0, c.s>>>(src, rb.start, rb.len, rb.dst, dst);
+  uint32_t maxlen = 1;
+  for (size_t i = 0; i < R; ++i) maxlen = std::max(maxlen, hl[i]);
+  const uint32_t cy = (uint32_t)std::min<uint64_t>(ceil_div(maxlen, 1024), 1024);
+  k_gather_ranges<<<dim3((uint32_t)R, cy), 256, 0, c.s>>>(src, rb.start, rb.len, rb.dst, dst);
   FL_LAUNCH_CHECK();
   c.sync();  // the host vectors are released on return
   return (uint32_t)tot;

@@ -191,29 +191,34 @@ __global__ __launch_bounds__(256) void k_open_heavy(OpenArgs A, uint32_t t) {
     const uint32_t c = A.cnt[f];
     uint32_t nl = A.nlive[fi];
     uint32_t cur = A.cursor[fi];
-    uint64_t lhi = 0, llo = 0;
+    uint64_t lhi = 0, llo = 0;  // weight added (crossed entries)
+    uint64_t rhi = 0, rlo = 0;  // weight removed (clients that froze)
     const bool rescan = any_freeze_prev && nl > 0;
     if (rescan) {
+      // drop the clients that froze: subtract their weights from the exact
+      // sum and close the gaps (entries before the first gap stay in place)
       uint32_t wpos = 0;
       for (uint32_t b = 0; b < nl; b += WAVE) {
         const uint32_t i = b + lane;
         const bool valid = i < nl;
-        uint32_t id = 0, T = 0, d = 0;
-        if (valid) {
-          id = A.sk_rank[base + i];
-          T = A.thr[trow + i];
-          d = A.sk_dist[base + i];
-        }
-        const bool keep = valid && A.frz[id] == FL_RUNG_NONE;
+        const uint32_t id = valid ? A.sk_rank[base + i] : 0u;
+        const bool gone = valid && A.frz[id] != FL_RUNG_NONE;
+        const bool keep = valid && !gone;
         const uint64_t mk = __ballot(keep);
-        if (keep) {
-          const uint32_t p = wpos + lanes_below(mk);
+        const uint32_t p = wpos + lanes_below(mk);
+        const bool move = keep && p != i;
+        uint32_t T = 0, d = 0;
+        if (gone || move) T = A.thr[trow + i];
+        if (move) d = A.sk_dist[base + i];
+        if (gone) {
+          const Fix52 x = fix52_of(hip_weight(T));
+          rhi += x.hi;
+          rlo += x.lo;
+        }
+        if (move) {
           A.sk_rank[base + p] = id;
           A.thr[trow + p] = T;
           A.sk_dist[base + p] = d;
-          const Fix52 x = fix52_of(hip_weight(T));
-          lhi += x.hi;
-          llo += x.lo;
         }
         wpos += (uint32_t)__popcll(mk);
       }
@@ -252,8 +257,12 @@ __global__ __launch_bounds__(256) void k_open_heavy(OpenArgs A, uint32_t t) {
     }
     lhi = wave_sum_u64(lhi);
     llo = wave_sum_u64(llo);
-    uint64_t shi = rescan ? lhi : A.shi[fi] + lhi;
-    uint64_t slo = rescan ? llo : A.slo[fi] + llo;
+    rhi = wave_sum_u64(rhi);
+    rlo = wave_sum_u64(rlo);
+    // each word is a sum over the live entries, so removing a subset keeps it
+    // exact (no word goes below zero)
+    uint64_t shi = A.shi[fi] - rhi + lhi;
+    uint64_t slo = A.slo[fi] - rlo + llo;
     const double nh_ = fix52_to_double(shi, slo);
     double inc;
     if (t == 1) {
