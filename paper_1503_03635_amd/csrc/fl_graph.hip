@@ -38,6 +38,14 @@ void fill_f64(Ctx &c, double *p, uint64_t n, double v) { fill_t(c, p, n, v); }
 // directed graph gives its out-arcs and skips the symmetry test).  One wave
 // per vertex; lanes walk the row.  err bits: 1 = structural error.  Also
 // reduces max weight and max facility cost.
+//
+// Symmetry: an arc u -> v is "leading" when u has the larger degree (ties:
+// the larger id).  Only leading arcs look up their reverse, by binary search
+// in the row of the smaller end, and must find it with the same weight; the
+// leading and trailing arcs are counted.  The reverse of a leading arc is a
+// trailing arc, distinct arcs have distinct reverses, so equal counts mean
+// every trailing arc is the reverse of a leading one: the arc set is
+// symmetric with equal weights.
 // ---------------------------------------------------------------------------
 __device__ inline bool find_arc(const uint64_t *row_ptr, const uint32_t *col, uint64_t m, uint32_t u,
                                 uint32_t v, uint64_t *pos) {
@@ -57,24 +65,34 @@ __global__ __launch_bounds__(256) void k_validate(uint32_t n, uint64_t m, const 
                                                   const uint32_t *col, const uint32_t *w,
                                                   const uint32_t *fac_cost, uint32_t *err,
                                                   uint32_t *maxw, uint32_t *maxc, uint32_t stripes,
-                                                  uint32_t directed) {
+                                                  uint32_t directed, unsigned long long *lead_trail) {
   const int lane = lane_id();
   const uint64_t u64 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
   if (u64 >= n) return;
   const uint32_t u = (uint32_t)u64;
   uint32_t bad = 0, mw = 0;
+  uint32_t nlead = 0, ntrail = 0;
   const uint64_t a0 = row_ptr[u], a1 = row_ptr[u + 1];
   if (a1 < a0 || a1 > m) bad = 1;
   if (!bad) {
+    const uint64_t du = a1 - a0;
     for (uint64_t a = a0 + lane; a < a1; a += WAVE) {
       uint32_t v = col[a];
       uint32_t wv = w ? w[a] : 1u;
       if (v >= n || v == u || wv == 0) { bad = 1; continue; }
       if (a > a0 && col[a - 1] >= v) { bad = 1; continue; }
       if (!directed) {
-        uint64_t back;
-        if (!find_arc(row_ptr, col, m, v, u, &back)) { bad = 1; continue; }
-        if ((w ? w[back] : 1u) != wv) bad = 1;
+        const uint64_t b0 = row_ptr[v], b1 = row_ptr[v + 1];
+        if (b1 < b0 || b1 > m) { bad = 1; continue; }
+        const uint64_t dv = b1 - b0;
+        if (du > dv || (du == dv && u > v)) {
+          ++nlead;
+          uint64_t back;
+          if (!find_arc(row_ptr, col, m, v, u, &back)) { bad = 1; continue; }
+          if ((w ? w[back] : 1u) != wv) bad = 1;
+        } else {
+          ++ntrail;
+        }
       }
       mw = wv > mw ? wv : mw;
     }
@@ -86,9 +104,12 @@ __global__ __launch_bounds__(256) void k_validate(uint32_t n, uint64_t m, const 
   uint64_t anybad = __ballot(bad != 0);
   mw = wave_min_u32(~mw);
   mw = ~mw;  // wave max
+  const uint64_t lead = wave_sum_u64(nlead), trail = wave_sum_u64(ntrail);
   if (lane == 0) {
     if (anybad) atomicOr(&err[u % stripes], 1u);
     if (mw) atomicMax(&maxw[u % stripes], mw);
+    if (lead) atomicAdd(&lead_trail[2 * (u % stripes)], (unsigned long long)lead);
+    if (trail) atomicAdd(&lead_trail[2 * (u % stripes) + 1], (unsigned long long)trail);
   }
 }
 
@@ -101,21 +122,29 @@ int validate_graph(Ctx &c, const fl_problem *p, bool directed, uint32_t *max_w_o
   c.sync();
   if (ends[0] != 0 || ends[1] != p->n_arcs) return FL_EINVAL;
   uint32_t *d = c.arena->get<uint32_t>(3 * NCTR);
+  uint64_t *lt = c.arena->get<uint64_t>(2 * NCTR);
   fill_u32(c, d, 3 * NCTR, 0);
+  fill_u64(c, lt, 2 * NCTR, 0);
   uint64_t blocks = ceil_div((uint64_t)n * WAVE, 256);
   k_validate<<<(uint32_t)blocks, 256, 0, c.s>>>(n, p->n_arcs, p->row_ptr, p->col, p->w, p->fac_cost,
-                                                 d, d + NCTR, d + 2 * NCTR, NCTR, directed ? 1u : 0u);
+                                                 d, d + NCTR, d + 2 * NCTR, NCTR, directed ? 1u : 0u,
+                                                 reinterpret_cast<unsigned long long *>(lt));
   FL_LAUNCH_CHECK();
   std::vector<uint32_t> h(3 * NCTR);
+  std::vector<uint64_t> hl(2 * NCTR);
   FL_HIP(hipMemcpyAsync(h.data(), d, 3 * NCTR * 4, hipMemcpyDeviceToHost, c.s));
+  FL_HIP(hipMemcpyAsync(hl.data(), lt, 2 * NCTR * 8, hipMemcpyDeviceToHost, c.s));
   c.sync();
   uint32_t err = 0, mw = 1, mc = 0;
+  uint64_t lead = 0, trail = 0;
   for (int i = 0; i < NCTR; ++i) {
     err |= h[i];
     mw = h[NCTR + i] > mw ? h[NCTR + i] : mw;
     mc = h[2 * NCTR + i] > mc ? h[2 * NCTR + i] : mc;
+    lead += hl[2 * i];
+    trail += hl[2 * i + 1];
   }
-  if (err) return FL_EINVAL;
+  if (err || lead != trail) return FL_EINVAL;
   *max_w_out = mw;
   *max_cost_out = mc;
   return FL_OK;
@@ -135,6 +164,8 @@ __global__ void k_check_ends(const EndsDesc *d, uint32_t G, uint32_t *err) {
 void validate_graphs(Ctx &c, const fl_problem *const *ps, uint32_t G, bool directed, std::vector<int> &rc,
                      std::vector<uint32_t> &max_w, std::vector<uint32_t> &max_cost) {
   uint32_t *d = c.arena->get<uint32_t>((size_t)3 * G);
+  uint64_t *lt = c.arena->get<uint64_t>((size_t)2 * G);
+  fill_u64(c, lt, (size_t)2 * G, 0);
   EndsDesc *ed = c.arena->get<EndsDesc>(G);
   std::vector<EndsDesc> hd(G);
   for (uint32_t g = 0; g < G; ++g) hd[g] = EndsDesc{ps[g]->row_ptr, ps[g]->n, ps[g]->n_arcs};
@@ -147,17 +178,20 @@ void validate_graphs(Ctx &c, const fl_problem *const *ps, uint32_t G, bool direc
     const fl_problem *p = ps[g];
     const uint64_t blocks = ceil_div((uint64_t)p->n * WAVE, 256);
     k_validate<<<(uint32_t)blocks, 256, 0, c.s>>>(p->n, p->n_arcs, p->row_ptr, p->col, p->w, p->fac_cost,
-                                                   d + 3 * g, d + 3 * g + 1, d + 3 * g + 2, 1, directed ? 1u : 0u);
+                                                   d + 3 * g, d + 3 * g + 1, d + 3 * g + 2, 1, directed ? 1u : 0u,
+                                                   reinterpret_cast<unsigned long long *>(lt + 2 * g));
     FL_LAUNCH_CHECK();
   }
   std::vector<uint32_t> h((size_t)3 * G);
+  std::vector<uint64_t> hl((size_t)2 * G);
   FL_HIP(hipMemcpyAsync(h.data(), d, h.size() * 4, hipMemcpyDeviceToHost, c.s));
+  FL_HIP(hipMemcpyAsync(hl.data(), lt, hl.size() * 8, hipMemcpyDeviceToHost, c.s));
   c.sync();
   rc.assign(G, FL_OK);
   max_w.assign(G, 1);
   max_cost.assign(G, 0);
   for (uint32_t g = 0; g < G; ++g) {
-    if (h[3 * g]) rc[g] = FL_EINVAL;
+    if (h[3 * g] || hl[2 * g] != hl[2 * g + 1]) rc[g] = FL_EINVAL;
     max_w[g] = h[3 * g + 1] > 1 ? h[3 * g + 1] : 1u;
     max_cost[g] = h[3 * g + 2];
   }

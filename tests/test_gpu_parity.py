@@ -167,6 +167,24 @@ def test_error_codes():
     with pytest.raises(fl.FlError) as e:
         fl.solve(fl.to_device(bad), 4, 1)
     assert e.value.code == fl._lib.FL_EINVAL
+    # a star with one arc dropped: the leaf's arc to the hub is checked only
+    # through the arc counts, the hub's arc to the leaf by its lookup
+    for drop_from_hub in (True, False):
+        st = gg.with_problem(gg.star(20), 1)
+        rows = [list(st.col[st.row_ptr[v]:st.row_ptr[v + 1]]) for v in range(st.n)]
+        if drop_from_hub:
+            rows[0].remove(5)
+        else:
+            rows[5].remove(0)
+        rp = np.zeros(st.n + 1, np.uint64)
+        rp[1:] = np.cumsum([len(r) for r in rows])
+        cut = gg.Graph(st.n, rp, np.array([x for r in rows for x in r], np.uint32), None, st.fac_cost)
+        assert O.validate(cut, 4, 0.1) == O.EINVAL
+        with pytest.raises(fl.FlError) as e:
+            fl.solve(fl.to_device(cut), 4, 1)
+        assert e.value.code == fl._lib.FL_EINVAL
+        outs = fl.solve_batch([fl.to_device(cut), dg], 4, 1, check=False)
+        assert outs[0]["status"] == fl._lib.FL_EINVAL and outs[1]["status"] == 0
     big = gg.with_problem(gg.path(5, wmax=None), 1)
     big.w = np.full(big.n_arcs, 300, np.uint32)   # beyond the slot ring
     with pytest.raises(fl.FlError) as e:
