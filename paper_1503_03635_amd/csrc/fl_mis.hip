@@ -56,6 +56,9 @@ struct SweepArgs {
 // One arc step of a push (every lane calls, converged; lanes with valid ==
 // false have no arc this step): lower the pending label of the arc's head at
 // distance j + w when that is within R, and queue the head once per slot.
+// A head whose settled minimum is already at most the label is skipped: it
+// reached that minimum at a smaller distance, so the push could never settle
+// (a concurrent settle only lowers ml, which keeps the test safe).
 __device__ inline void sweep_arc(const SweepArgs &S, bool valid, uint64_t a, uint32_t lab, uint32_t j, uint32_t R) {
   const int lane = lane_id();
   {
@@ -64,7 +67,7 @@ __device__ inline void sweep_arc(const SweepArgs &S, bool valid, uint64_t a, uin
     if (valid) {
       y = S.col[a];
       const uint32_t wv = S.w ? S.w[a] : 1u;
-      if ((uint64_t)j + wv <= R) {
+      if ((uint64_t)j + wv <= R && lab < __hip_atomic_load(&S.ml[y], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
         s = (j + wv) % S.NS;
         uint32_t *p = &S.pend[(size_t)s * S.n + y];
         if (lab < __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
