@@ -29,6 +29,7 @@
 #ifndef FL_H_
 #define FL_H_
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -235,6 +236,24 @@ const char *fl_strerror(int code);
 int fl_last_hip_error(void);
 /* Frees the cached workspace of the current device. */
 void fl_release_workspace(void);
+
+/* Device-memory hooks (optional; the library's own resources, not part of
+ * the method).  With alloc set, every device allocation the library makes
+ * (the cached per-device workspace, the batch and server workspaces, sketch
+ * handles) goes through alloc(bytes, device, ctx) and later
+ * free_fn(ptr, bytes, device, ctx) instead of hipMalloc/hipFree, e.g. so that
+ * a framework's caching allocator backs it.  `device` is the HIP device that
+ * is current for the call.  alloc returns NULL on failure (the call then
+ * reports FL_ENOMEM); the memory must stay valid until free_fn is called and
+ * be usable from any stream.  fl_set_allocator(NULL, NULL, NULL) restores
+ * hipMalloc/hipFree.  Cached workspaces are released first, each through the
+ * hooks it came from; a live sketch handle keeps its hooks until
+ * fl_sketch_free.  Returns FL_EBUSY while a server exists, FL_EINVAL if only
+ * one of alloc and free_fn is NULL, else FL_OK.  Not to be called while
+ * another library call is running. */
+typedef void *(*fl_alloc_fn)(size_t bytes, int device, void *ctx);
+typedef void (*fl_free_fn)(void *ptr, size_t bytes, int device, void *ctx);
+int fl_set_allocator(fl_alloc_fn alloc, fl_free_fn free_fn, void *ctx);
 
 #ifdef __cplusplus
 }

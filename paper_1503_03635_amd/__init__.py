@@ -17,6 +17,7 @@ from ._lib import (FL_FLAG_DIRECTED, FL_FLAG_LUBY_MIS, FL_FLAG_NO_DENSE, FL_NONE
                    FL_RUNG_NONE, FlError, lib)
 
 __all__ = ["DeviceGraph", "to_device", "solve", "solve_batch", "Server", "ads_build", "rank_of", "priority_of",
+           "use_torch_allocator",
            "FlError", "FL_NONE", "FL_NOT_FACILITY", "FL_RUNG_NONE", "FL_RUNG_GUARD", "FL_RUNG_END",
            "FL_FLAG_NO_DENSE", "FL_FLAG_LUBY_MIS", "FL_FLAG_DIRECTED", "lib"]
 
@@ -218,6 +219,38 @@ class Server:
 
     def __exit__(self, *a):
         self.close()
+
+
+_hooks = None  # the registered callbacks (kept alive while the library may call them)
+
+
+def use_torch_allocator(enable: bool = True):
+    """Back the library's device workspace and sketch handles with torch's
+    caching allocator (fl_set_allocator), or go back to hipMalloc/hipFree.
+    Not while a Server exists or a call is running."""
+    global _hooks
+    L = lib()
+    if not enable:
+        rc = L.fl_set_allocator(None, None, None)
+        if rc != _lib.FL_OK:
+            raise FlError(rc, "fl_set_allocator")
+        _hooks = None
+        return
+
+    def _alloc(nbytes, device, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device=int(device))
+        except Exception:  # out of memory: the library reports FL_ENOMEM
+            return None
+
+    def _free(ptr, nbytes, device, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    hooks = (_lib.ALLOC_FN(_alloc), _lib.FREE_FN(_free))
+    rc = L.fl_set_allocator(C.cast(hooks[0], C.c_void_p), C.cast(hooks[1], C.c_void_p), None)
+    if rc != _lib.FL_OK:
+        raise FlError(rc, "fl_set_allocator")
+    _hooks = hooks
 
 
 def ads_build(dg: DeviceGraph, k: int, seed: int, flags: int = 0, stream=None):

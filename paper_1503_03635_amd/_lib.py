@@ -74,7 +74,12 @@ SIGNATURES = {
     "fl_server_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_int)]),
     "fl_server_wait": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_int)]),
     "fl_server_destroy": (None, [C.c_void_p]),
+    "fl_set_allocator": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
 }
+
+# fl_alloc_fn / fl_free_fn of include/fl.h
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_int, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p)
 
 _lib = None
 

@@ -26,23 +26,77 @@ namespace fl {
 static std::atomic<int> g_last_hip{0};
 void set_last_hip_error(int e) { g_last_hip.store(e); }
 
+// ---- device memory: hipMalloc/hipFree, or the caller's hooks --------------
+struct AllocHooks {
+  fl_alloc_fn alloc = nullptr;
+  fl_free_fn free_fn = nullptr;
+  void *ctx = nullptr;
+};
+struct HookedBlock {
+  AllocHooks h;
+  size_t bytes;
+  int device;
+};
+static std::mutex g_hooks_mu;
+static AllocHooks g_hooks;
+static std::unordered_map<void *, HookedBlock> g_hooked;  // blocks from the hooks, by address
+static std::atomic<int> g_servers{0};
+
+// nullptr on failure
+static void *dev_alloc(size_t bytes) {
+  AllocHooks h;
+  {
+    std::lock_guard<std::mutex> lk(g_hooks_mu);
+    h = g_hooks;
+  }
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  if (h.alloc) {
+    void *p = h.alloc(bytes, dev, h.ctx);
+    if (p) {
+      std::lock_guard<std::mutex> lk(g_hooks_mu);
+      g_hooked[p] = HookedBlock{h, bytes, dev};
+    }
+    return p;
+  }
+  void *p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+// frees through whatever allocated the block
+static void dev_free(void *p) {
+  if (!p) return;
+  HookedBlock b;
+  bool hooked = false;
+  {
+    std::lock_guard<std::mutex> lk(g_hooks_mu);
+    auto it = g_hooked.find(p);
+    if (it != g_hooked.end()) {
+      b = it->second;
+      g_hooked.erase(it);
+      hooked = true;
+    }
+  }
+  if (hooked) b.h.free_fn(p, b.bytes, b.device, b.h.ctx);
+  else (void)hipFree(p);
+}
+
 void Arena::reserve(size_t bytes) {
   bytes = (bytes + (size_t(1) << 21) - 1) & ~((size_t(1) << 21) - 1);
   if (bytes <= cap_) return;
   release();
-  void *p = nullptr;
-  hipError_t e = hipMalloc(&p, bytes);
-  if (std::getenv("FL_DEBUG")) std::fprintf(stderr, "[fl] workspace %zu bytes: %s\n", bytes, hipGetErrorString(e));
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    throw Error{FL_ENOMEM};
-  }
+  void *p = dev_alloc(bytes);
+  if (std::getenv("FL_DEBUG")) std::fprintf(stderr, "[fl] workspace %zu bytes: %s\n", bytes, p ? "ok" : "failed");
+  if (!p) throw Error{FL_ENOMEM};
   base_ = static_cast<char *>(p);
   cap_ = bytes;
   used_ = 0;
 }
 void Arena::release() {
-  if (base_) (void)hipFree(base_);
+  dev_free(base_);
   base_ = nullptr;
   cap_ = used_ = 0;
 }
@@ -1034,8 +1088,8 @@ int fl_ads_build(const fl_problem *p, const fl_params *prm, fl_sketch **out, voi
     sk->k = prm->k;
     sk->total = total;
     const size_t bytes = ((size_t)n + 1) * 8 + total * 12 + 1024;
-    if (hipMalloc(&sk->mem, bytes) != hipSuccess) {
-      (void)hipGetLastError();
+    sk->mem = fl::dev_alloc(bytes);
+    if (!sk->mem) {
       delete sk;
       return FL_ENOMEM;
     }
@@ -1070,7 +1124,7 @@ int fl_sketch_view(const fl_sketch *s, fl_sketch_view_t *v) {
 
 void fl_sketch_free(fl_sketch *s) {
   if (!s) return;
-  (void)hipFree(s->mem);
+  fl::dev_free(s->mem);
   delete s;
 }
 
@@ -1114,6 +1168,7 @@ int fl_server_create(uint64_t hbm_budget_bytes, uint32_t slots, fl_server **out)
       S.slots.push_back(sl);
     }
     for (fl::Slot *sl : S.slots) sl->th = std::thread(fl::slot_main, sl);
+    fl::g_servers.fetch_add(1);
     *out = sv;
     return FL_OK;
   } catch (fl::Error &e) {
@@ -1195,6 +1250,26 @@ void fl_server_destroy(fl_server *sv) {
   }
   for (auto &kv : S.reqs) delete kv.second;
   delete sv;
+  fl::g_servers.fetch_sub(1);
+}
+
+int fl_set_allocator(fl_alloc_fn alloc, fl_free_fn free_fn, void *ctx) {
+  if ((alloc == nullptr) != (free_fn == nullptr)) return FL_EINVAL;
+  if (fl::g_servers.load() > 0) return FL_EBUSY;
+  // cached workspaces go back through the hooks they came from
+  for (int d = 0; d < 64; ++d) {
+    {
+      std::lock_guard<std::mutex> lk(fl::g_cache[d].mu);
+      fl::g_cache[d].arena.release();
+    }
+    for (int w = 0; w < fl::BATCH_WORKERS; ++w) {
+      std::lock_guard<std::mutex> lk(fl::g_pool[d].dc[w].mu);
+      fl::g_pool[d].dc[w].arena.release();
+    }
+  }
+  std::lock_guard<std::mutex> lk(fl::g_hooks_mu);
+  fl::g_hooks = fl::AllocHooks{alloc, free_fn, alloc ? ctx : nullptr};
+  return FL_OK;
 }
 
 void fl_release_workspace(void) {
