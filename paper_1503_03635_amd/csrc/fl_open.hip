@@ -135,6 +135,11 @@ __device__ inline bool try_open(const OpenArgs &A, uint32_t fi, uint32_t f, doub
   return false;
 }
 
+// live lists up to this long are rescanned by the light kernel (a thread per
+// facility); longer ones, and facilities with newly crossed entries, take
+// the heavy kernel (a wave per facility)
+constexpr uint32_t LIGHT_RESCAN = 32;
+
 // 256 threads per block (block_append)
 __global__ __launch_bounds__(256) void k_open_light(OpenArgs A, uint32_t t) {
   const uint32_t fi = blockIdx.x * blockDim.x + threadIdx.x;
@@ -146,11 +151,45 @@ __global__ __launch_bounds__(256) void k_open_light(OpenArgs A, uint32_t t) {
     const RungParam &R = A.rp[g];
     if (R.run) {
       const uint32_t nx = A.nxt[fi];
-      heavy = (R.frz_prev && A.nlive[fi] > 0) || (nx != INF32 && (double)nx <= R.alpha);
+      const uint32_t nl = A.nlive[fi];
+      const bool rescan = R.frz_prev && nl > 0;
+      heavy = (nx != INF32 && (double)nx <= R.alpha) || (rescan && nl > LIGHT_RESCAN);
       if (!heavy) {
-        // N unchanged: Eq. 3 with the stored estimate (0 when nothing is live;
-        // at the first rung an empty Eq. 2 sum is 0 as well)
-        const double inc = R.eps_alpha * A.nhat[fi];
+        double nh = A.nhat[fi];
+        if (rescan) {
+          // a short live list: drop the clients that froze, as the heavy
+          // kernel does (exact subtraction, entries after the first gap move)
+          const size_t base = (size_t)f * A.cap, trow = (size_t)fi * A.cap;
+          uint64_t rhi = 0, rlo = 0;
+          uint32_t wpos = 0;
+          for (uint32_t i = 0; i < nl; ++i) {
+            const uint32_t id = A.sk_rank[base + i];
+            if (A.frz[id] != FL_RUNG_NONE) {
+              const Fix52 x = fix52_of(hip_weight(A.thr[trow + i]));
+              rhi += x.hi;
+              rlo += x.lo;
+            } else {
+              if (wpos != i) {
+                A.sk_rank[base + wpos] = id;
+                A.thr[trow + wpos] = A.thr[trow + i];
+                A.sk_dist[base + wpos] = A.sk_dist[base + i];
+              }
+              ++wpos;
+            }
+          }
+          if (wpos != nl) {
+            const uint64_t shi = A.shi[fi] - rhi, slo = A.slo[fi] - rlo;
+            A.shi[fi] = shi;
+            A.slo[fi] = slo;
+            A.nlive[fi] = wpos;
+            nh = fix52_to_double(shi, slo);
+            A.nhat[fi] = nh;
+          }
+        }
+        // Eq. 3 with the current estimate (0 when nothing is live; at the
+        // first rung nothing is live on this path, and an empty Eq. 2 sum is
+        // 0 as well)
+        const double inc = R.eps_alpha * nh;
         const double qn = A.q[fi] + inc;
         A.q[fi] = qn;
         opened = try_open(A, fi, f, qn, t);
