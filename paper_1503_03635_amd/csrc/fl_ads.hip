@@ -1021,13 +1021,18 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
   uint64_t active_prev = n;
   uint32_t rounds = 0;
   std::vector<uint32_t> hwl(NS);
+  bool hwl_valid = false;  // hwl holds the slot counts read back after the previous round
   for (uint32_t D = 1;; ++D) {
     const uint32_t slot = D % NS;
     const TaskList *T = &tl_dense;
     if (sparse) {
-      FL_HIP(hipMemcpyAsync(c.h_status, P.wl_cnt + slot, 4, hipMemcpyDeviceToHost, c.s));
-      c.sync();
-      const uint32_t count = (uint32_t)(c.h_status[0] & 0xFFFFFFFFu);
+      // slot D is filled by rounds before D, so the previous readback is exact
+      uint32_t count = hwl[slot];
+      if (!hwl_valid) {
+        FL_HIP(hipMemcpyAsync(c.h_status, P.wl_cnt + slot, 4, hipMemcpyDeviceToHost, c.s));
+        c.sync();
+        count = (uint32_t)(c.h_status[0] & 0xFFFFFFFFu);
+      }
       build_tasks(c, g, P.wl + (size_t)slot * n, count, ts, tl);
       T = &tl;
     }
@@ -1063,6 +1068,7 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
     FL_HIP(hipMemcpyAsync(c.h_status + 1, P.ctr + 64, 64 * 8, hipMemcpyDeviceToHost, c.s));
     FL_HIP(hipMemcpyAsync(hwl.data(), P.wl_cnt, NS * 4, hipMemcpyDeviceToHost, c.s));
     c.sync();
+    hwl_valid = true;
     if (T->ntasks) {
       float ms = 0.f, ms2 = 0.f;
       FL_HIP(hipEventElapsedTime(&ms, e0, em));
