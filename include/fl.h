@@ -250,7 +250,9 @@ void fl_release_workspace(void);
  * hooks it came from; a live sketch handle keeps its hooks until
  * fl_sketch_free.  Returns FL_EBUSY while a server exists, FL_EINVAL if only
  * one of alloc and free_fn is NULL, else FL_OK.  Not to be called while
- * another library call is running. */
+ * another library call is running.  The hooks run inside library calls
+ * (possibly on the server's worker threads) and must not call into this
+ * library themselves. */
 typedef void *(*fl_alloc_fn)(size_t bytes, int device, void *ctx);
 typedef void (*fl_free_fn)(void *ptr, size_t bytes, int device, void *ctx);
 int fl_set_allocator(fl_alloc_fn alloc, fl_free_fn free_fn, void *ctx);
