@@ -228,11 +228,10 @@ static void sweep(Ctx &c, MisWork &M, const uint32_t *src, uint32_t nsrc, uint32
     }
     if (!pending) break;
     // k_sweep_round reads its slot's count on the device: small rounds run
-    // several distances per host check (an idle distance costs two short
-    // launches, far less than a host round trip).  A frontier can grow from a handful
+    // several distances per host check.  A frontier can grow from a handful
     // of vertices to most of the graph within a burst, so burst launches get
     // a grid for any frontier (blocks past the count exit at once).
-    const uint32_t burst = hmax > 65536 ? 1u : hmax > 2048 ? 8u : 32u;
+    const uint32_t burst = hmax > 65536 ? 1u : 8u;
     uint64_t want = ceil_div((uint64_t)hmax * 2, 256);
     if (burst > 1) want = std::max<uint64_t>(want, std::min<uint64_t>(ceil_div(S.n, 256), 2048));
     const uint32_t blocks = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(want, 4), 8192);

@@ -161,3 +161,33 @@ def test_directed_input_errors():
     outs = fl.solve_batch([fl.to_device(g), fl.to_device(bad)], 4, 1, check=False)
     torch.cuda.synchronize()
     assert outs[0]["status"] == 0 and outs[1]["status"] == fl._lib.FL_EINVAL
+
+
+def _degenerate():
+    out = []
+    g = gg.with_problem(gg.empty(7, directed=True), 1, cost="uniform", cost_hi=20, fac_frac=0.5)
+    out.append(("no arcs, half facilities", g))
+    one = gg.empty(1, directed=True)
+    one.fac_cost = np.array([3], np.uint32)
+    out.append(("single vertex", one))
+    # a DAG: arcs only from lower to higher ids, facilities at the top end only
+    rng = np.random.default_rng(4)
+    u = rng.integers(0, 400, 1600)
+    v = rng.integers(0, 400, 1600)
+    lo, hi = np.minimum(u, v), np.maximum(u, v)
+    dag = gg.from_arcs(400, lo, hi, 9, rng, name="dag400")
+    dag.fac_cost = np.where(np.arange(400) >= 350, rng.integers(1, 100, 400), gg.NOT_FACILITY).astype(np.uint32)
+    out.append(("DAG, facilities downstream", dag))
+    out.append(("directed path+cycle+isolated", gg.with_problem(gg.disjoint_union(
+        gg.path(30, directed=True), gg.cycle(11, directed=True), gg.empty(4, directed=True)), 2, cost="uniform",
+        cost_hi=40)))
+    return out
+
+
+@pytest.mark.parametrize("ci", range(4))
+def test_directed_degenerate_cases(ci):
+    name, g = _degenerate()[ci]
+    print(f"[directed degenerate] {name}", flush=True)
+    got, want = assert_solve_equal(g, 8, 3)
+    if ci == 2:
+        assert want["n_unreachable"] > 0      # clients with no facility downstream
