@@ -32,6 +32,10 @@ sys.path.insert(0, ROOT)
 METRIC = "ADS edge-relaxations/s + facility-location solves/s, batched vs plain, 1 GPU"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ads_round_rmat22_traffic.json")
+ISSUE_FILE = os.path.join(ROOT, "profiles", "ads_round_rmat22_issue.json")
+# VALU issue peak: each CU's 4 SIMDs complete one wave64 VALU instruction per
+# 4 cycles each, i.e. one per CU per cycle: 256 CUs x 2.4 GHz
+VALU_PEAK_INSTS = 256 * 2.4e9
 ROUND_KERNEL = "k_ads_tasks"
 CALIB_BYTES = 1 << 30
 
@@ -104,6 +108,29 @@ def write_traffic(fetch_dir, write_dir):
            "calibration": {"bytes": CALIB_BYTES, "fetch_kib": fc, "write_kib": wc,
                            "fetch_scale": f_scale, "write_scale": w_scale}}
     json.dump(out, open(TRAFFIC_FILE, "w"), indent=1)
+    print(json.dumps(out))
+
+
+def write_issue(sq_dir):
+    """Per-launch instruction counts of the sketch-round kernel from one
+    rocprofv3 counter run (SQ_INSTS_VALU, SQ_INSTS_SALU, SQ_INSTS_LDS,
+    SQ_INSTS_VMEM_RD; wave instructions summed over the chip per dispatch)."""
+    import csv
+    import glob
+    path = glob.glob(os.path.join(sq_dir, "**", "*counter_collection.csv"), recursive=True)
+    assert path, f"no counter_collection.csv under {sq_dir}"
+    per = {}
+    for row in csv.DictReader(open(path[0])):
+        if ROUND_KERNEL not in row["Kernel_Name"]:
+            continue
+        d = per.setdefault(row["Dispatch_Id"], {})
+        d[row["Counter_Name"]] = d.get(row["Counter_Name"], 0.0) + float(row["Counter_Value"])
+    assert per, f"{ROUND_KERNEL} missing in {path[0]}"
+    names = ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD")
+    out = {"kernel": ROUND_KERNEL, "kernel_source_hash": kernel_hash(), "launches": len(per)}
+    for nm in names:
+        out[nm.lower() + "_per_launch"] = round(sum(d.get(nm, 0.0) for d in per.values()) / len(per))
+    json.dump(out, open(ISSUE_FILE, "w"), indent=1)
     print(json.dumps(out))
 
 
@@ -345,11 +372,16 @@ def main():
                     help="run the HIP-estimator accuracy experiment instead and print its JSON")
     ap.add_argument("--pmc-calibration", action="store_true",
                     help="run a 1 GiB device copy first (counter calibration)")
+    ap.add_argument("--issue", metavar="SQ_DIR",
+                    help="write the instruction-count file from a rocprofv3 SQ counter run and exit")
     ap.add_argument("--traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the measured traffic file from two rocprofv3 counter runs and exit")
     args = ap.parse_args()
     if args.traffic:
         write_traffic(*args.traffic)
+        return
+    if args.issue:
+        write_issue(args.issue)
         return
     if args.sweep:
         print(json.dumps({"sweep": sweep_experiment(args.seed)}), flush=True)
@@ -420,11 +452,25 @@ def main():
                 traffic = tf.get("bytes_per_launch")
         except (OSError, ValueError):
             traffic = None
+    # the kernel's own limit, from committed counters: VALU wave instructions
+    # per launch over the average launch time, against the issue peak
+    issue = None
+    if os.path.exists(ISSUE_FILE):
+        try:
+            isf = json.load(open(ISSUE_FILE))
+            if isf.get("kernel_source_hash") == kernel_hash():
+                rate = isf["sq_insts_valu_per_launch"] / (kern_ms / max(launches, 1) * 1e-3)
+                issue = {"valu_insts_per_launch": isf["sq_insts_valu_per_launch"],
+                         "valu_insts_per_s": round(rate), "valu_peak_insts_per_s": VALU_PEAK_INSTS,
+                         "valu_issue_frac": round(rate / VALU_PEAK_INSTS, 4)}
+        except (OSError, ValueError, KeyError):
+            issue = None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": ROUND_KERNEL, "avg_launch_ms": round(kern_ms / max(launches, 1), 3),
             "alg_bytes_per_launch": round(alg_bytes / max(launches, 1)),
-            "merge_ms_per_step": round(sum(s["ms_ads_merge"] for s in stats) / args.steps, 2)}
+            "merge_ms_per_step": round(sum(s["ms_ads_merge"] for s in stats) / args.steps, 2),
+            "issue": issue}
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "edge-relaxations/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 2),
