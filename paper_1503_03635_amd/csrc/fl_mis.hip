@@ -51,6 +51,7 @@ struct SweepArgs {
   uint32_t *touched_cnt;
   uint64_t *heavy;    // pieces of the long rows queued in the current distance
   uint32_t *heavy_cnt;  // [2] by distance parity
+  const uint32_t *tbits;  // bitmap of the vertices whose result is read (nullptr: all)
 };
 
 // One arc step of a push (every lane calls, converged; lanes with valid ==
@@ -58,7 +59,9 @@ struct SweepArgs {
 // distance j + w when that is within R, and queue the head once per slot.
 // A head whose settled minimum is already at most the label is skipped: it
 // reached that minimum at a smaller distance, so the push could never settle
-// (a concurrent settle only lowers ml, which keeps the test safe).
+// (a concurrent settle only lowers ml, which keeps the test safe).  A label
+// landing at distance exactly R goes no further, so there it is kept only at
+// the sweep's targets, the vertices whose minimum is read afterwards.
 __device__ inline void sweep_arc(const SweepArgs &S, bool valid, uint64_t a, uint32_t lab, uint32_t j, uint32_t R) {
   const int lane = lane_id();
   {
@@ -67,7 +70,9 @@ __device__ inline void sweep_arc(const SweepArgs &S, bool valid, uint64_t a, uin
     if (valid) {
       y = S.col[a];
       const uint32_t wv = S.w ? S.w[a] : 1u;
-      if ((uint64_t)j + wv <= R && lab < __hip_atomic_load(&S.ml[y], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+      const uint64_t d = (uint64_t)j + wv;
+      const bool keep = d < R || (d == R && (!S.tbits || ((S.tbits[y >> 5] >> (y & 31)) & 1u)));
+      if (keep && lab < __hip_atomic_load(&S.ml[y], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
         s = (j + wv) % S.NS;
         uint32_t *p = &S.pend[(size_t)s * S.n + y];
         if (lab < __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
@@ -101,9 +106,12 @@ __device__ inline void sweep_push_lanes(const SweepArgs &S, bool want, uint32_t 
   uint64_t a0 = 0, deg = 0;
   uint32_t R = 0;
   if (want) {
+    R = S.Rg[seg_of(S.gid, x)];
+    want = j < R;  // arcs weigh at least 1: a label settled at distance R goes no further
+  }
+  if (want) {
     a0 = S.row_ptr[x];
     deg = S.row_ptr[x + 1] - a0;
-    R = S.Rg[seg_of(S.gid, x)];
   }
   const bool heavy = want && deg > FLAT_MAX;
   push_pieces(S.heavy, S.heavy_cnt + (j & 1), heavy, x, deg);
@@ -189,6 +197,8 @@ __global__ void k_sweep_reset(SweepArgs S) {
 struct MisWork {
   SweepArgs S;
   const Graph *g;
+  uint32_t *cbits;   // [n / 32] clients of the current step
+  uint32_t *fbits;   // [n / 32] active facilities of the current round
   uint32_t *lab;     // [n] source labels
   uint32_t *pm;      // [n] pi_min of clients
   uint32_t *act;     // [n] list of active facilities
@@ -204,9 +214,14 @@ enum class Toward { clients, facilities };
 // run one sweep to completion; results in S.ml (caller resets afterwards).
 // Toward::clients: from facilities f to every x with d(x, f) <= R (in-arcs);
 // Toward::facilities: from clients c to every x with d(c, x) <= R (out-arcs).
-static void sweep(Ctx &c, MisWork &M, const uint32_t *src, uint32_t nsrc, uint32_t R, Toward dir) {
+// S.ml is exact at the vertices of the bitmap targets and at every vertex
+// closer than R; a vertex at distance exactly R outside targets may keep no
+// label.
+static void sweep(Ctx &c, MisWork &M, const uint32_t *src, uint32_t nsrc, uint32_t R, Toward dir,
+                  const uint32_t *targets) {
   SweepArgs &S = M.S;
   if (nsrc == 0) return;
+  S.tbits = targets;
   const bool in = dir == Toward::clients;
   S.row_ptr = in ? M.g->in_ptr : M.g->row_ptr;
   S.col = in ? M.g->in_col : M.g->col;
@@ -424,6 +439,19 @@ __global__ void k_guard_open(uint32_t n, const uint32_t *orung, uint8_t *open) {
   const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v < n) open[v] = orung[v] == FL_RUNG_GUARD ? 1 : 0;
 }
+// bitmap membership of the vertices of a list (set or clear)
+__global__ void k_mark_bits(const uint32_t *list, uint32_t cnt, uint32_t *bits, int set) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  const uint32_t x = list[i];
+  if (set) atomicOr(&bits[x >> 5], 1u << (x & 31));
+  else atomicAnd(&bits[x >> 5], ~(1u << (x & 31)));
+}
+static void mark_bits(Ctx &c, const uint32_t *list, uint32_t cnt, uint32_t *bits, int set) {
+  if (!cnt) return;
+  k_mark_bits<<<(uint32_t)ceil_div(cnt, 256), 256, 0, c.s>>>(list, cnt, bits, set);
+  FL_LAUNCH_CHECK();
+}
 __global__ void k_open_list(const uint32_t *list, uint32_t cnt, uint8_t *open) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < cnt) open[list[i]] = 1;
@@ -535,6 +563,10 @@ int mis_phase(Ctx &c, const MisIn &in, uint8_t *open, std::vector<uint32_t> &rou
   M.cov = c.arena->get<uint32_t>(n);
   M.src = c.arena->get<uint32_t>(n);
   M.cnts = c.arena->get<uint32_t>(8);
+  const size_t nwords = ((size_t)n + 31) / 32;
+  M.cbits = c.arena->get<uint32_t>(nwords);
+  M.fbits = c.arena->get<uint32_t>(nwords);
+  M.S.tbits = nullptr;
   uint32_t *ct_list = c.arena->get<uint32_t>(n);  // clients of the current step
   uint32_t *gact = c.arena->get<uint32_t>(G);     // graphs active in a round
   RangeBuf rb;
@@ -546,6 +578,8 @@ int mis_phase(Ctx &c, const MisIn &in, uint8_t *open, std::vector<uint32_t> &rou
   fill_u32(c, M.S.tl_cnt, NS, 0);
   fill_u32(c, M.S.touched_cnt, 1, 0);
   fill_u32(c, M.S.heavy_cnt, 2, 0);
+  fill_u32(c, M.cbits, nwords, 0);
+  fill_u32(c, M.fbits, nwords, 0);
 
   // each graph's non-empty rungs, in order
   std::vector<std::vector<uint32_t>> lists(G);
@@ -594,6 +628,7 @@ int mis_phase(Ctx &c, const MisIn &in, uint8_t *open, std::vector<uint32_t> &rou
     uint32_t na = gather(c, flist, fr, rb, M.act);
     const uint32_t ncl = gather(c, clist, cr, rb, ct_list);
     const uint32_t *Ct = ct_list;
+    mark_bits(c, Ct, ncl, M.cbits, 1);
     uint32_t guard_rounds = 0, step_round = 0;
     uint32_t nf_max = 0;
     for (auto &r : fr) nf_max = std::max(nf_max, r.second);
@@ -607,11 +642,12 @@ int mis_phase(Ctx &c, const MisIn &in, uint8_t *open, std::vector<uint32_t> &rou
         FL_LAUNCH_CHECK();
         FL_HIP(hipMemcpyAsync(hact.data(), gact, G * 4, hipMemcpyDeviceToHost, c.s));
       }
+      mark_bits(c, M.act, na, M.fbits, 1);
       // 1. pi_min at the clients of the rung
       k_set_key_labels<<<(uint32_t)ceil_div(na, 256), 256, 0, c.s>>>(M.act, na, M.lab, in.gid, in.seg,
                                                                      luby_round);
       FL_LAUNCH_CHECK();
-      sweep(c, M, M.act, na, Rmax, Toward::clients);
+      sweep(c, M, M.act, na, Rmax, Toward::clients, M.cbits);
       if (G > 1) {
         for (uint32_t q = 0; q < G; ++q) rounds_out[q] += hact[q];
       } else {
@@ -625,7 +661,7 @@ int mis_phase(Ctx &c, const MisIn &in, uint8_t *open, std::vector<uint32_t> &rou
       sweep_reset(c, M);
       const uint32_t ns2 = read_u32(c, M.cnts);
       // 2. smallest pi_min around each active facility; joins
-      sweep(c, M, M.src, ns2, Rmax, Toward::facilities);
+      sweep(c, M, M.src, ns2, Rmax, Toward::facilities, M.fbits);
       k_join<<<(uint32_t)ceil_div(na, 256), 256, 0, c.s>>>(M.act, na, M.S.ml, in.gid, in.seg, luby_round, open,
                                                            M.joined, M.cnts + 1, M.act2, M.cnts + 2);
       FL_LAUNCH_CHECK();
@@ -634,11 +670,14 @@ int mis_phase(Ctx &c, const MisIn &in, uint8_t *open, std::vector<uint32_t> &rou
       c.sync();
       const uint32_t nj = (uint32_t)(c.h_status[0] >> 32);
       const uint32_t nr = (uint32_t)(c.h_status[1] & 0xFFFFFFFFu);
-      if (nr == 0) break;
+      if (nr == 0) {
+        mark_bits(c, M.act, na, M.fbits, 0);
+        break;
+      }
       // 3. clients covered by a joined facility
       k_set_const_labels<<<(uint32_t)ceil_div(nj, 256), 256, 0, c.s>>>(M.joined, nj, M.lab, 0);
       FL_LAUNCH_CHECK();
-      sweep(c, M, M.joined, nj, Rmax, Toward::clients);
+      sweep(c, M, M.joined, nj, Rmax, Toward::clients, M.cbits);
       if (ncl) {
         k_collect_hit<<<(uint32_t)ceil_div(ncl, 256), 256, 0, c.s>>>(Ct, ncl, M.S.ml, M.cov, M.cnts + 3, 1);
         FL_LAUNCH_CHECK();
@@ -648,12 +687,14 @@ int mis_phase(Ctx &c, const MisIn &in, uint8_t *open, std::vector<uint32_t> &rou
       // 4. facilities next to a covered client retire
       k_set_const_labels<<<(uint32_t)ceil_div(ncov ? ncov : 1, 256), 256, 0, c.s>>>(M.cov, ncov, M.lab, 0);
       FL_LAUNCH_CHECK();
-      sweep(c, M, M.cov, ncov, Rmax, Toward::facilities);
+      sweep(c, M, M.cov, ncov, Rmax, Toward::facilities, M.fbits);  // read at the rest, a subset of act
+      mark_bits(c, M.act, na, M.fbits, 0);  // before act is rewritten
       k_collect_hit<<<(uint32_t)ceil_div(nr, 256), 256, 0, c.s>>>(M.act2, nr, M.S.ml, M.act, M.cnts + 4, 0);
       FL_LAUNCH_CHECK();
       sweep_reset(c, M);
       na = read_u32(c, M.cnts + 4);
     }
+    mark_bits(c, Ct, ncl, M.cbits, 0);
   }
   return FL_OK;
 }
