@@ -33,7 +33,9 @@
 namespace fl {
 
 // status counters per graph: field f of graph g, stripe s at
-// [(g * OC_NFIELD + f) * stripes + s]
+// [((g * OC_NFIELD + f) * stripes + s) * sstride]; a single graph stripes
+// its counters over 64 words on separate 128-byte lines, so that the blocks'
+// atomics do not queue on one line
 enum { OC_HEAVY = 0, OC_OPENED, OC_FROZEN, OC_FINITE, OC_NUF_DEC, OC_LIVE, OC_NFIELD };
 
 // per-graph parameters of the current rung
@@ -47,7 +49,7 @@ struct RungParam {
 
 struct OpenArgs {
   uint32_t n, nF, cap;
-  uint32_t stripes;
+  uint32_t stripes, sstride;
   const uint32_t *gid;        // graph of each vertex (nullptr: one graph)
   const SegInfo *seg;
   const RungParam *rp;        // [G]
@@ -69,11 +71,37 @@ struct OpenArgs {
   uint32_t *heavy_cnt;        // [1]
   uint32_t *opened;           // [nF] vertex ids opened this rung
   uint32_t *opened_cnt;       // [1]
-  uint32_t *ctr;              // [OC_NFIELD * 64]
+  uint32_t *ctr;              // [G * OC_NFIELD * stripes * sstride]
 };
 
 __device__ inline void ctr_add(const OpenArgs &A, uint32_t g, int field, uint32_t v) {
-  if (v) atomicAdd(&A.ctr[((size_t)g * OC_NFIELD + field) * A.stripes + (blockIdx.x % A.stripes)], v);
+  if (v) atomicAdd(&A.ctr[(((size_t)g * OC_NFIELD + field) * A.stripes + (blockIdx.x % A.stripes)) * A.sstride], v);
+}
+
+// Block-aggregated counter adds of a single graph (every thread of a
+// 256-thread block calls it, in uniform control flow): for fields f0, f1 and
+// f2 (-1: none), the number of the block's threads with v0, v1 or v2 set, one
+// atomic per block and field.
+__device__ inline void block_ctr(const OpenArgs &A, int f0, bool v0, int f1, bool v1, int f2, bool v2) {
+  __shared__ uint32_t s_c[3][256 / WAVE];
+  const int wv = threadIdx.x / WAVE;
+  const uint32_t c0 = (uint32_t)__popcll(__ballot(v0));
+  const uint32_t c1 = (uint32_t)__popcll(__ballot(v1));
+  const uint32_t c2 = (uint32_t)__popcll(__ballot(v2));
+  if (lane_id() == 0) {
+    s_c[0][wv] = c0;
+    s_c[1][wv] = c1;
+    s_c[2][wv] = c2;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const int i = (int)threadIdx.x;
+    const int f = i == 0 ? f0 : (i == 1 ? f1 : f2);
+    uint32_t tot = 0;
+    for (int w = 0; w < 256 / WAVE; ++w) tot += s_c[i][w];
+    if (f >= 0) ctr_add(A, 0, f, tot);
+  }
+  __syncthreads();  // s_c may be reused
 }
 
 // wave-aggregated append of x to list (lanes with want)
@@ -197,18 +225,14 @@ __global__ __launch_bounds__(256) void k_open_light(OpenArgs A, uint32_t t) {
       }
     }
   }
+  // late rungs open facilities in most waves: block-level appends and counts
   block_append(A.heavy, A.heavy_cnt, heavy, fi);
-  wave_append(A.opened, A.opened_cnt, opened, f);
+  block_append(A.opened, A.opened_cnt, opened, f);
   if (A.gid) {
     if (opened) ctr_add(A, g, OC_OPENED, 1);
     if (nuf) ctr_add(A, g, OC_NUF_DEC, 1);
   } else {
-    const uint32_t no = (uint32_t)__popcll(__ballot(opened));
-    const uint32_t nd = (uint32_t)__popcll(__ballot(nuf));
-    if (lane_id() == 0) {
-      ctr_add(A, 0, OC_OPENED, no);
-      ctr_add(A, 0, OC_NUF_DEC, nd);
-    }
+    block_ctr(A, OC_OPENED, opened, OC_NUF_DEC, nuf, -1, false);
   }
 }
 
@@ -451,14 +475,7 @@ __global__ __launch_bounds__(256) void k_freeze(OpenArgs A, const uint64_t *dlab
     seg_add32(A.ctr, valid, g, OC_FINITE, OC_NFIELD, A.stripes, finite ? 1u : 0u);
     seg_add32(A.ctr, valid, g, OC_NUF_DEC, OC_NFIELD, A.stripes, nuf ? 1u : 0u);
   } else {
-    const uint32_t a = (uint32_t)__popcll(__ballot(froze));
-    const uint32_t b = (uint32_t)__popcll(__ballot(finite));
-    const uint32_t e = (uint32_t)__popcll(__ballot(nuf));
-    if (lane_id() == 0) {
-      ctr_add(A, 0, OC_FROZEN, a);
-      ctr_add(A, 0, OC_FINITE, b);
-      ctr_add(A, 0, OC_NUF_DEC, e);
-    }
+    block_ctr(A, OC_FROZEN, froze, OC_FINITE, finite, OC_NUF_DEC, nuf);
   }
 }
 
@@ -481,7 +498,7 @@ __global__ __launch_bounds__(256) void k_stuck_scan(OpenArgs A) {
     const uint32_t id = id_of(A.sk_rank[base + j], rm);
     live |= A.ceff[id] && A.frz[id] == FL_RUNG_NONE;
   }
-  if (__ballot(live) && lane == 0) atomicAdd(&A.ctr[((size_t)g * OC_NFIELD + OC_LIVE) * A.stripes], 1u);
+  if (__ballot(live) && lane == 0) atomicAdd(&A.ctr[((size_t)g * OC_NFIELD + OC_LIVE) * A.stripes * A.sstride], 1u);
 }
 
 // graphs flagged in gflag[g] & 1: stall guard; & 2: end phase
@@ -502,12 +519,12 @@ __global__ void k_endphase(uint32_t n, const uint32_t *gid, const uint8_t *gflag
 
 // per-graph sums of the striped counters
 static void read_ctr(Ctx &c, const OpenArgs &A, uint32_t G, std::vector<uint64_t> &out) {
-  std::vector<uint32_t> h((size_t)G * OC_NFIELD * A.stripes);
+  std::vector<uint32_t> h((size_t)G * OC_NFIELD * A.stripes * A.sstride);
   FL_HIP(hipMemcpyAsync(h.data(), A.ctr, h.size() * 4, hipMemcpyDeviceToHost, c.s));
   c.sync();
   out.assign((size_t)G * OC_NFIELD, 0);
   for (size_t i = 0; i < out.size(); ++i)
-    for (uint32_t s = 0; s < A.stripes; ++s) out[i] += h[i * A.stripes + s];
+    for (uint32_t s = 0; s < A.stripes; ++s) out[i] += h[(i * A.stripes + s) * A.sstride];
 }
 
 int open_phase(Ctx &c, const OpenIn &in, OpenOut &out) {
@@ -517,7 +534,10 @@ int open_phase(Ctx &c, const OpenIn &in, OpenOut &out) {
   A.n = n;
   A.nF = nF;
   A.cap = in.ads->cap;
+  // one graph: 64 stripes, 32 words (128 B) apart; a union: one plain
+  // counter per graph and field (seg_add32 indexes it unstrided)
   A.stripes = G == 1 ? 64 : 1;
+  A.sstride = G == 1 ? 32 : 1;
   A.gid = in.gid;
   A.seg = in.seg;
   A.fac_list = in.fac_list;
@@ -542,7 +562,8 @@ int open_phase(Ctx &c, const OpenIn &in, OpenOut &out) {
   uint32_t *cnts = c.arena->get<uint32_t>(2);
   A.heavy_cnt = cnts;
   A.opened_cnt = cnts + 1;
-  A.ctr = c.arena->get<uint32_t>((size_t)G * OC_NFIELD * A.stripes);
+  const size_t ctr_words = (size_t)G * OC_NFIELD * A.stripes * A.sstride;
+  A.ctr = c.arena->get<uint32_t>(ctr_words);
   RungParam *d_rp = c.arena->get<RungParam>(G);
   A.rp = d_rp;
   uint8_t *d_gflag = c.arena->get<uint8_t>(G);
@@ -588,7 +609,7 @@ int open_phase(Ctx &c, const OpenIn &in, OpenOut &out) {
     }
     if (any_stuck) {
       upload();
-      fill_u32(c, A.ctr, (size_t)G * OC_NFIELD * A.stripes, 0);
+      fill_u32(c, A.ctr, ctr_words, 0);
       k_stuck_scan<<<(uint32_t)ceil_div((uint64_t)(nF ? nF : 1) * WAVE, 256), 256, 0, c.s>>>(A);
       FL_LAUNCH_CHECK();
       read_ctr(c, A, G, ctr);
@@ -672,7 +693,7 @@ int open_phase(Ctx &c, const OpenIn &in, OpenOut &out) {
     }
     upload();
     fill_u32(c, cnts, 2, 0);
-    fill_u32(c, A.ctr, (size_t)G * OC_NFIELD * A.stripes, 0);
+    fill_u32(c, A.ctr, ctr_words, 0);
     k_open_light<<<fblocks, 256, 0, c.s>>>(A, t);
     FL_LAUNCH_CHECK();
     k_open_heavy<<<hblocks, 256, 0, c.s>>>(A, t);
@@ -697,7 +718,7 @@ int open_phase(Ctx &c, const OpenIn &in, OpenOut &out) {
     }
     if (any_freeze) {
       upload();
-      fill_u32(c, A.ctr, (size_t)G * OC_NFIELD * A.stripes, 0);
+      fill_u32(c, A.ctr, ctr_words, 0);
       k_freeze<<<vblocks, 256, 0, c.s>>>(A, dlab, t, in.fac_idx);
       FL_LAUNCH_CHECK();
       read_ctr(c, A, G, ctr);
