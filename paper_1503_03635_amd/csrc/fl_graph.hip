@@ -411,9 +411,50 @@ void ads_totals(Ctx &c, const Graph &g, const uint32_t *gid, uint32_t G, const u
 // the iteration number).  The fixed point is the lexicographic minimum over
 // sources of (init value + distance, tie).
 // ---------------------------------------------------------------------------
+// Appends to the next frontier, staged per wave in LDS (2 WAVE entries) and
+// written WAVE at a time with one atomic: every wave of a large frontier
+// appends at nearly every step, and per-step atomics queue on the one count.
+struct WaveQ {
+  uint32_t *buf;  // this wave's LDS staging area
+  uint32_t cnt;   // staged entries (wave-uniform, < WAVE between calls)
+  uint32_t *next, *nnext;
+};
+
+// every lane calls, converged
+__device__ inline void wq_push(WaveQ &q, bool add, uint32_t y) {
+  const int lane = lane_id();
+  const uint64_t m = __ballot(add);
+  if (!m) return;
+  if (add) q.buf[q.cnt + lanes_below(m)] = y;
+  q.cnt += (uint32_t)__popcll(m);
+  if (q.cnt < (uint32_t)WAVE) return;
+  wave_lds_sync();
+  uint32_t base = 0;
+  if (lane == 0) base = atomicAdd(q.nnext, (uint32_t)WAVE);
+  base = __shfl(base, 0, WAVE);
+  q.next[base + lane] = q.buf[lane];
+  q.cnt -= WAVE;
+  const uint32_t rest = (uint32_t)lane < q.cnt ? q.buf[WAVE + lane] : 0u;
+  wave_lds_sync();
+  if ((uint32_t)lane < q.cnt) q.buf[lane] = rest;
+  wave_lds_sync();
+}
+
+// the staged remainder (every lane calls, converged, before the wave exits)
+__device__ inline void wq_flush(WaveQ &q) {
+  if (!q.cnt) return;
+  const int lane = lane_id();
+  wave_lds_sync();
+  uint32_t base = 0;
+  if (lane == 0) base = atomicAdd(q.nnext, q.cnt);
+  base = __shfl(base, 0, WAVE);
+  if ((uint32_t)lane < q.cnt) q.next[base + lane] = q.buf[lane];
+  q.cnt = 0;
+}
+
 // one arc step (every lane calls, converged): relax arc a with label L
 __device__ inline void sssp_arc(const uint32_t *col, const uint32_t *w, uint64_t *labels, bool valid, uint64_t a,
-                                uint64_t L, uint32_t *next, uint32_t *nnext, uint32_t *stamp, uint32_t iter) {
+                                uint64_t L, WaveQ &q, uint32_t *stamp, uint32_t iter) {
   bool add = false;
   uint32_t y = 0;
   if (valid) {
@@ -424,13 +465,7 @@ __device__ inline void sssp_arc(const uint32_t *col, const uint32_t *w, uint64_t
       if (nl < old) add = atomicMax(&stamp[y], iter) < iter;
     }
   }
-  const uint64_t mask = __ballot(add);
-  if (mask) {
-    uint32_t base = 0;
-    if (lane_id() == 0) base = atomicAdd(nnext, (uint32_t)__popcll(mask));
-    base = __shfl(base, 0, WAVE);
-    if (add) next[base + lanes_below(mask)] = y;
-  }
+  wq_push(q, add, y);
 }
 
 // One lane per frontier vertex: short rows flattened over the wave, long rows
@@ -440,6 +475,8 @@ __global__ __launch_bounds__(256) void k_sssp_push(const uint64_t *row_ptr, cons
                                                    const uint32_t *front, const uint32_t *nfront,
                                                    uint32_t *next, uint32_t *nnext, uint32_t *stamp,
                                                    uint32_t iter, uint64_t *heavy, uint32_t *nheavy) {
+  __shared__ uint32_t s_q[256 / WAVE][2 * WAVE];
+  WaveQ q{s_q[threadIdx.x / WAVE], 0u, next, nnext};
   const uint32_t nf = *nfront;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x; b < nf; b += stride) {
@@ -456,9 +493,10 @@ __global__ __launch_bounds__(256) void k_sssp_push(const uint64_t *row_ptr, cons
     const bool hv = want && deg > FLAT_MAX;
     push_pieces(heavy, nheavy + (iter & 1), hv, v, deg);
     flat_arcs(want && !hv, a0, deg, [&](bool valid, uint64_t a, int o) {
-      sssp_arc(col, w, labels, valid, a, shfl_u64(L, o), next, nnext, stamp, iter);
+      sssp_arc(col, w, labels, valid, a, shfl_u64(L, o), q, stamp, iter);
     });
   }
+  wq_flush(q);
 }
 
 // Long rows of iteration iter, one wave per row.  Also clears the count of
@@ -468,6 +506,8 @@ __global__ __launch_bounds__(256) void k_sssp_heavy(const uint64_t *row_ptr, con
                                                     uint64_t *labels, uint32_t *next, uint32_t *nnext,
                                                     uint32_t *stamp, uint32_t iter, const uint64_t *heavy,
                                                     uint32_t *nheavy, uint32_t *nconsumed) {
+  __shared__ uint32_t s_q[256 / WAVE][2 * WAVE];
+  WaveQ q{s_q[threadIdx.x / WAVE], 0u, next, nnext};
   const int lane = lane_id();
   const uint32_t cnt = nheavy[iter & 1];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -480,8 +520,9 @@ __global__ __launch_bounds__(256) void k_sssp_heavy(const uint64_t *row_ptr, con
     const uint32_t v = piece_arcs(heavy[i], row_ptr, &a0, &a1);
     const uint64_t L = __hip_atomic_load(&labels[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (uint64_t c = a0; c < a1; c += WAVE)
-      sssp_arc(col, w, labels, c + lane < a1, c + lane, L, next, nnext, stamp, iter);
+      sssp_arc(col, w, labels, c + lane < a1, c + lane, L, q, stamp, iter);
   }
+  wq_flush(q);
 }
 
 void sssp_alloc(Ctx &c, SsspWork &wk, uint32_t n, uint64_t m) {
