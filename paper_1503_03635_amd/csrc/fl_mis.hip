@@ -54,6 +54,75 @@ struct SweepArgs {
   const uint32_t *tbits;  // bitmap of the vertices whose result is read (nullptr: all)
 };
 
+// Queue appends (vertex y to the list of slot s), staged per wave in LDS
+// (2 WAVE entries) and written WAVE at a time with one atomic per distinct
+// slot among them: with per-step atomics the waves of a large frontier queue
+// on the slot's one count.
+struct SlotQ {
+  uint32_t *ys, *ss;  // this wave's LDS staging: vertices and their slots
+  uint32_t cnt;       // staged entries (wave-uniform, < WAVE between calls)
+};
+
+// write nw staged entries (lanes below nw hold one each)
+__device__ inline void slotq_write(const SweepArgs &S, bool have, uint32_t y, uint32_t s) {
+  const int lane = lane_id();
+  uint64_t pendm = __ballot(have);
+  while (pendm) {
+    const int lead = __ffsll((long long)pendm) - 1;
+    const uint32_t sl = __shfl(s, lead, WAVE);
+    const bool mine = have && s == sl;
+    const uint64_t grp = __ballot(mine);
+    uint32_t base = 0;
+    if (lane == lead) base = atomicAdd(&S.tl_cnt[sl], (uint32_t)__popcll(grp));
+    base = __shfl(base, lead, WAVE);
+    if (mine) {
+      S.tl[(size_t)sl * S.n + base + lanes_below(grp)] = y;
+      have = false;
+    }
+    pendm &= ~grp;
+  }
+}
+
+// every lane calls, converged
+__device__ inline void slotq_push(const SweepArgs &S, SlotQ &q, bool add, uint32_t y, uint32_t s) {
+  const int lane = lane_id();
+  const uint64_t m = __ballot(add);
+  if (!m) return;
+  if (add) {
+    q.ys[q.cnt + lanes_below(m)] = y;
+    q.ss[q.cnt + lanes_below(m)] = s;
+  }
+  q.cnt += (uint32_t)__popcll(m);
+  if (q.cnt < (uint32_t)WAVE) return;
+  wave_lds_sync();
+  slotq_write(S, true, q.ys[lane], q.ss[lane]);
+  q.cnt -= WAVE;
+  const bool more = (uint32_t)lane < q.cnt;
+  const uint32_t ry = more ? q.ys[WAVE + lane] : 0u, rs = more ? q.ss[WAVE + lane] : 0u;
+  wave_lds_sync();
+  if (more) {
+    q.ys[lane] = ry;
+    q.ss[lane] = rs;
+  }
+  wave_lds_sync();
+}
+
+// the staged remainder (every lane calls, converged, before the wave exits)
+__device__ inline void slotq_flush(const SweepArgs &S, SlotQ &q) {
+  if (!q.cnt) return;
+  const int lane = lane_id();
+  wave_lds_sync();
+  const bool have = (uint32_t)lane < q.cnt;
+  slotq_write(S, have, have ? q.ys[lane] : 0u, have ? q.ss[lane] : 0u);
+  q.cnt = 0;
+}
+
+// LDS staging for the 256 / WAVE waves of a block
+#define SLOTQ_DECL(q)                                   \
+  __shared__ uint32_t q##_ys[256 / WAVE][2 * WAVE];     \
+  __shared__ uint32_t q##_ss[256 / WAVE][2 * WAVE];     \
+  SlotQ q{q##_ys[threadIdx.x / WAVE], q##_ss[threadIdx.x / WAVE], 0u}
+
 // One arc step of a push (every lane calls, converged; lanes with valid ==
 // false have no arc this step): lower the pending label of the arc's head at
 // distance j + w when that is within R, and queue the head once per slot.
@@ -62,8 +131,8 @@ struct SweepArgs {
 // (a concurrent settle only lowers ml, which keeps the test safe).  A label
 // landing at distance exactly R goes no further, so there it is kept only at
 // the sweep's targets, the vertices whose minimum is read afterwards.
-__device__ inline void sweep_arc(const SweepArgs &S, bool valid, uint64_t a, uint32_t lab, uint32_t j, uint32_t R) {
-  const int lane = lane_id();
+__device__ inline void sweep_arc(const SweepArgs &S, SlotQ &q, bool valid, uint64_t a, uint32_t lab, uint32_t j,
+                                 uint32_t R) {
   {
     bool add = false;
     uint32_t y = 0, s = 0;
@@ -81,28 +150,14 @@ __device__ inline void sweep_arc(const SweepArgs &S, bool valid, uint64_t a, uin
         }
       }
     }
-    // append y to tl[s] (group lanes by slot)
-    uint64_t pendm = __ballot(add);
-    while (pendm) {
-      const int lead = __ffsll((long long)pendm) - 1;
-      const uint32_t sl = __shfl(s, lead, WAVE);
-      const bool mine = add && s == sl;
-      const uint64_t grp = __ballot(mine);
-      uint32_t base = 0;
-      if (lane == lead) base = atomicAdd(&S.tl_cnt[sl], (uint32_t)__popcll(grp));
-      base = __shfl(base, lead, WAVE);
-      if (mine) {
-        S.tl[(size_t)sl * S.n + base + lanes_below(grp)] = y;
-        add = false;
-      }
-      pendm &= ~grp;
-    }
+    slotq_push(S, q, add, y, s);
   }
 }
 
 // Push the labels of the lanes' vertices (want) from distance j: short rows
 // flattened over the wave, long rows queued for k_sweep_heavy.
-__device__ inline void sweep_push_lanes(const SweepArgs &S, bool want, uint32_t x, uint32_t lab, uint32_t j) {
+__device__ inline void sweep_push_lanes(const SweepArgs &S, SlotQ &q, bool want, uint32_t x, uint32_t lab,
+                                        uint32_t j) {
   uint64_t a0 = 0, deg = 0;
   uint32_t R = 0;
   if (want) {
@@ -116,7 +171,7 @@ __device__ inline void sweep_push_lanes(const SweepArgs &S, bool want, uint32_t 
   const bool heavy = want && deg > FLAT_MAX;
   push_pieces(S.heavy, S.heavy_cnt + (j & 1), heavy, x, deg);
   flat_arcs(want && !heavy, a0, deg, [&](bool valid, uint64_t a, int o) {
-    sweep_arc(S, valid, a, __shfl(lab, o, WAVE), j, __shfl(R, o, WAVE));
+    sweep_arc(S, q, valid, a, __shfl(lab, o, WAVE), j, __shfl(R, o, WAVE));
   });
 }
 
@@ -128,6 +183,7 @@ __device__ inline void touch(const SweepArgs &S, bool first, uint32_t x) {
 // sources: set ml and push at distance 0 (one lane per source)
 __global__ __launch_bounds__(256) void k_sweep_init(SweepArgs S, const uint32_t *src, uint32_t nsrc,
                                                     const uint32_t *lab) {
+  SLOTQ_DECL(q);
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool want = false;
   uint32_t x = 0, l = INF32;
@@ -138,11 +194,13 @@ __global__ __launch_bounds__(256) void k_sweep_init(SweepArgs S, const uint32_t 
     if (want) S.ml[x] = l;
   }
   touch(S, want, x);
-  sweep_push_lanes(S, want, x, l, 0);
+  sweep_push_lanes(S, q, want, x, l, 0);
+  slotq_flush(S, q);
 }
 
 // distance j: settle the pending labels of slot j (one lane per vertex)
 __global__ __launch_bounds__(256) void k_sweep_round(SweepArgs S, uint32_t j) {
+  SLOTQ_DECL(q);
   const uint32_t slot = j % S.NS;
   const uint32_t cnt = S.tl_cnt[slot];
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -162,8 +220,9 @@ __global__ __launch_bounds__(256) void k_sweep_round(SweepArgs S, uint32_t j) {
       }
     }
     touch(S, first, y);
-    sweep_push_lanes(S, want, y, v, j);
+    sweep_push_lanes(S, q, want, y, v, j);
   }
+  slotq_flush(S, q);
 }
 
 // the pieces of long rows queued at distance j: one wave per piece; the label
@@ -171,6 +230,7 @@ __global__ __launch_bounds__(256) void k_sweep_round(SweepArgs S, uint32_t j) {
 // clears slot j (consumed) and the long-row counter of distance j + 1 (its
 // last use, distance j - 1, is over).
 __global__ __launch_bounds__(256) void k_sweep_heavy(SweepArgs S, uint32_t j) {
+  SLOTQ_DECL(q);
   const int lane = lane_id();
   const uint32_t cnt = S.heavy_cnt[j & 1];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -183,8 +243,9 @@ __global__ __launch_bounds__(256) void k_sweep_heavy(SweepArgs S, uint32_t j) {
     const uint32_t x = piece_arcs(S.heavy[i], S.row_ptr, &a0, &a1);
     const uint32_t lab = S.ml[x];
     const uint32_t R = S.Rg[seg_of(S.gid, x)];
-    for (uint64_t b = a0; b < a1; b += WAVE) sweep_arc(S, b + lane < a1, b + lane, lab, j, R);
+    for (uint64_t b = a0; b < a1; b += WAVE) sweep_arc(S, q, b + lane < a1, b + lane, lab, j, R);
   }
+  slotq_flush(S, q);
 }
 
 __global__ void k_sweep_reset(SweepArgs S) {
