@@ -236,12 +236,35 @@ __global__ __launch_bounds__(256) void k_open_light(OpenArgs A, uint32_t t) {
   }
 }
 
+// The heavy kernel gives each facility a group of OPEN_G lanes, so that a
+// wave follows WAVE / OPEN_G facilities' chains of dependent loads (cursor,
+// entries, the clients' freeze state, sums) at once.
+constexpr int OPEN_G = 16;
+
+// sum over the lane's OPEN_G-lane group (the group's lanes converged)
+__device__ inline uint64_t group_sum_u64(uint64_t x) {
+#pragma unroll
+  for (int d = OPEN_G / 2; d >= 1; d >>= 1) {
+    const uint32_t lo = __shfl_xor((uint32_t)x, d, WAVE), hi = __shfl_xor((uint32_t)(x >> 32), d, WAVE);
+    x += ((uint64_t)hi << 32) | lo;
+  }
+  return x;
+}
+
 __global__ __launch_bounds__(256) void k_open_heavy(OpenArgs A, uint32_t t) {
   const int lane = lane_id();
+  const int sub = lane % OPEN_G;
+  const int lead = lane - sub;  // the group's first lane
+  const uint32_t below = (1u << sub) - 1u;
+  // lanes of this group with cond set, as OPEN_G group-relative bits
+  auto gballot = [&](bool cond) -> uint32_t {
+    return (uint32_t)(__ballot(cond) >> lead) & ((1u << OPEN_G) - 1u);
+  };
   const uint32_t nh = *A.heavy_cnt;
-  const uint64_t wid = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
-  const uint64_t nw = ((uint64_t)gridDim.x * blockDim.x) / WAVE;
-  for (uint64_t h = wid; h < nh; h += nw) {
+  constexpr uint32_t GPW = WAVE / OPEN_G;
+  const uint64_t h0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE * GPW + (uint64_t)(lane / OPEN_G);
+  const uint64_t ng = ((uint64_t)gridDim.x * blockDim.x) / WAVE * GPW;
+  for (uint64_t h = h0; h < nh; h += ng) {
     const uint32_t fi = A.heavy[h];
     const uint32_t f = A.fac_list[fi];
     const uint32_t g = seg_of(A.gid, f);
@@ -261,14 +284,14 @@ __global__ __launch_bounds__(256) void k_open_heavy(OpenArgs A, uint32_t t) {
       // drop the clients that froze: subtract their weights from the exact
       // sum and close the gaps (entries before the first gap stay in place)
       uint32_t wpos = 0;
-      for (uint32_t b = 0; b < nl; b += WAVE) {
-        const uint32_t i = b + lane;
+      for (uint32_t b = 0; b < nl; b += OPEN_G) {
+        const uint32_t i = b + sub;
         const bool valid = i < nl;
         const uint32_t id = valid ? A.sk_rank[base + i] : 0u;
         const bool gone = valid && A.frz[id] != FL_RUNG_NONE;
         const bool keep = valid && !gone;
-        const uint64_t mk = __ballot(keep);
-        const uint32_t p = wpos + lanes_below(mk);
+        const uint32_t mk = gballot(keep);
+        const uint32_t p = wpos + (uint32_t)__popc(mk & below);
         const bool move = keep && p != i;
         uint32_t T = 0, d = 0;
         if (gone || move) T = A.thr[trow + i];
@@ -283,19 +306,18 @@ __global__ __launch_bounds__(256) void k_open_heavy(OpenArgs A, uint32_t t) {
           A.thr[trow + p] = T;
           A.sk_dist[base + p] = d;
         }
-        wpos += (uint32_t)__popcll(mk);
+        wpos += (uint32_t)__popc(mk);
       }
       nl = wpos;
     }
     // cross entries with distance <= alpha (entries are sorted by distance)
     while (cur < c) {
-      const uint32_t j = cur + lane;
+      const uint32_t j = cur + sub;
       const bool valid = j < c;
       uint32_t d = INF32;
       if (valid) d = A.sk_dist[base + j];
       const bool cross = valid && (double)d <= alpha;
-      const uint64_t mc = __ballot(cross);
-      const uint32_t ncross = (uint32_t)__popcll(mc);
+      const uint32_t ncross = (uint32_t)__popc(gballot(cross));
       if (ncross == 0) break;
       bool keep = false;
       uint32_t id = 0, T = 0;
@@ -304,9 +326,9 @@ __global__ __launch_bounds__(256) void k_open_heavy(OpenArgs A, uint32_t t) {
         T = A.thr[trow + j];
         keep = A.ceff[id] && A.frz[id] == FL_RUNG_NONE;
       }
-      const uint64_t mk = __ballot(keep);
+      const uint32_t mk = gballot(keep);
       if (keep) {
-        const uint32_t p = nl + lanes_below(mk);
+        const uint32_t p = nl + (uint32_t)__popc(mk & below);
         A.sk_rank[base + p] = id;
         A.thr[trow + p] = T;
         A.sk_dist[base + p] = d;
@@ -314,36 +336,34 @@ __global__ __launch_bounds__(256) void k_open_heavy(OpenArgs A, uint32_t t) {
         lhi += x.hi;
         llo += x.lo;
       }
-      nl += (uint32_t)__popcll(mk);
+      nl += (uint32_t)__popc(mk);
       cur += ncross;
-      if (ncross < WAVE) break;
+      if (ncross < (uint32_t)OPEN_G) break;
     }
-    lhi = wave_sum_u64(lhi);
-    llo = wave_sum_u64(llo);
-    rhi = wave_sum_u64(rhi);
-    rlo = wave_sum_u64(rlo);
+    lhi = group_sum_u64(lhi);
+    llo = group_sum_u64(llo);
+    rhi = group_sum_u64(rhi);
+    rlo = group_sum_u64(rlo);
     // each word is a sum over the live entries, so removing a subset keeps it
     // exact (no word goes below zero)
     uint64_t shi = A.shi[fi] - rhi + lhi;
     uint64_t slo = A.slo[fi] - rlo + llo;
     const double nh_ = fix52_to_double(shi, slo);
-    double inc;
-    if (t == 1) {
-      // Eq. 2: sum over the live entries, in sketch order, of
-      // a_j ((1+eps) alpha - beta(d_j)); beta is a[0] or a[1] here
-      double s = 0.0;
-      if (lane == 0) {
+    if (sub == 0) {
+      double inc;
+      if (t == 1) {
+        // Eq. 2: sum over the live entries, in sketch order, of
+        // a_j ((1+eps) alpha - beta(d_j)); beta is a[0] or a[1] here
+        double s = 0.0;
         for (uint32_t i = 0; i < nl; ++i) {
           const double dj = (double)A.sk_dist[base + i];
           const double b = dj <= R.a0 ? R.a0 : R.a1;
           s = s + hip_weight(A.thr[trow + i]) * (R.ae - b);
         }
+        inc = s;
+      } else {
+        inc = R.eps_alpha * nh_;
       }
-      inc = __shfl(s, 0, WAVE);
-    } else {
-      inc = R.eps_alpha * nh_;
-    }
-    if (lane == 0) {
       A.shi[fi] = shi;
       A.slo[fi] = slo;
       A.nlive[fi] = nl;
