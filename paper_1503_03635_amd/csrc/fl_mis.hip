@@ -63,7 +63,8 @@ struct SlotQ {
   uint32_t cnt;       // staged entries (wave-uniform, < WAVE between calls)
 };
 
-// write nw staged entries (lanes below nw hold one each)
+// append y to the list of slot s on the lanes with have set: one atomic per
+// distinct slot among them
 __device__ inline void slotq_write(const SweepArgs &S, bool have, uint32_t y, uint32_t s) {
   const int lane = lane_id();
   uint64_t pendm = __ballot(have);
@@ -133,25 +134,23 @@ __device__ inline void slotq_flush(const SweepArgs &S, SlotQ &q) {
 // the sweep's targets, the vertices whose minimum is read afterwards.
 __device__ inline void sweep_arc(const SweepArgs &S, SlotQ &q, bool valid, uint64_t a, uint32_t lab, uint32_t j,
                                  uint32_t R) {
-  {
-    bool add = false;
-    uint32_t y = 0, s = 0;
-    if (valid) {
-      y = S.col[a];
-      const uint32_t wv = S.w ? S.w[a] : 1u;
-      const uint64_t d = (uint64_t)j + wv;
-      const bool keep = d < R || (d == R && (!S.tbits || ((S.tbits[y >> 5] >> (y & 31)) & 1u)));
-      if (keep && lab < __hip_atomic_load(&S.ml[y], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-        s = (j + wv) % S.NS;
-        uint32_t *p = &S.pend[(size_t)s * S.n + y];
-        if (lab < __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-          const uint32_t old = atomicMin(p, lab);
-          add = old == INF32;
-        }
+  bool add = false;
+  uint32_t y = 0, s = 0;
+  if (valid) {
+    y = S.col[a];
+    const uint32_t wv = S.w ? S.w[a] : 1u;
+    const uint64_t d = (uint64_t)j + wv;
+    const bool keep = d < R || (d == R && (!S.tbits || ((S.tbits[y >> 5] >> (y & 31)) & 1u)));
+    if (keep && lab < __hip_atomic_load(&S.ml[y], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+      s = (j + wv) % S.NS;
+      uint32_t *p = &S.pend[(size_t)s * S.n + y];
+      if (lab < __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        const uint32_t old = atomicMin(p, lab);
+        add = old == INF32;
       }
     }
-    slotq_push(S, q, add, y, s);
   }
+  slotq_push(S, q, add, y, s);
 }
 
 // Push the labels of the lanes' vertices (want) from distance j: short rows

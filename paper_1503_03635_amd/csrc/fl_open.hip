@@ -11,7 +11,7 @@
 //   light kernel  (thread per facility): when nothing crossed and no client
 //                 froze in the previous rung, N is unchanged; update q and
 //                 test the opening condition q >= c(f) directly.
-//   heavy kernel  (wave per facility): drop frozen clients from the live
+//   heavy kernel  (16 lanes per facility): drop frozen clients from the live
 //                 list when clients froze in the previous rung, append newly
 //                 crossed entries, recompute N exactly, then update q with
 //                 Eq. 2 (first rung, sequential sum in sketch order) or Eq. 3
@@ -165,7 +165,7 @@ __device__ inline bool try_open(const OpenArgs &A, uint32_t fi, uint32_t f, doub
 
 // live lists up to this long are rescanned by the light kernel (a thread per
 // facility); longer ones, and facilities with newly crossed entries, take
-// the heavy kernel (a wave per facility)
+// the heavy kernel (16 lanes per facility)
 constexpr uint32_t LIGHT_RESCAN = 32;
 
 // 256 threads per block (block_append)

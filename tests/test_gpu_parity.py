@@ -74,6 +74,10 @@ SOLVE_CASES = [
                                                                     cost="lognormal", fac_frac=0.1), 32),
     ("grid 15x15 w1..4", lambda: gg.with_problem(gg.grid(15, 15, wmax=4), 4, cost="uniform", cost_lo=1,
                                                  cost_hi=60), 8),
+    # unit weights and many ties: MIS radii land exactly on the distances of
+    # many clients (the sweeps keep labels at the radius only at targets)
+    ("grid 20x20 unit costs 1..30", lambda: gg.with_problem(gg.grid(20, 20), 11, cost="uniform", cost_lo=1,
+                                                             cost_hi=30), 4),
     ("Chung-Lu n=2000 w1..20", lambda: gg.with_problem(gg.chung_lu(2000, 3, 2.2, 10.0, 20), 3,
                                                        cost="uniform"), 32),
     ("half clients", lambda: gg.with_problem(gg.er(300, 4, 5, wmax=6), 5, cost="uniform", cost_hi=100,
