@@ -209,6 +209,60 @@ def directed_bench(scale, edge_factor, k, seed, steps):
             "n_reach_guard": s0["n_reach_guard"]}
 
 
+def large_bench(scale, edge_factor, k, seed, steps):
+    """The large single-graph configuration: R-MAT 2^scale with
+    edge_factor * 2^scale samples, weights 1..100, 10% of the vertices
+    facilities with lognormal(5, 1) costs, every vertex a client, k as given.
+    One untimed solve, then `steps` timed ones, and checks of the result that
+    hold at any size: opened vertices are facilities, every served client is
+    assigned to an opened one, and the total cost is the opening costs plus the
+    assigned distances."""
+    import numpy as np
+    import torch
+    import graphgen as gg
+    import paper_1503_03635_amd as fl
+    t0 = time.perf_counter()
+    g = gg.rmat_weighted_fac10(scale, edge_factor, seed)
+    dg = fl.to_device(g, "cuda:0")
+    torch.cuda.synchronize()
+    log(f"[bench] large R-MAT 2^{scale} w1..100: n={g.n} arcs={g.n_arcs} in {time.perf_counter() - t0:.1f}s")
+    outputs = fl._alloc_outputs(g.n, dg.col.device, False)
+    t0 = time.perf_counter()
+    r = fl.solve(dg, k, seed, 0.1, outputs=outputs)
+    torch.cuda.synchronize()
+    log(f"[bench] large: untimed solve {time.perf_counter() - t0:.1f}s")
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = fl.solve(dg, k, seed, 0.1, outputs=outputs)
+        stats.append(r["stats"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    dev = outputs["open"].device
+    fac = torch.from_numpy(g.fac_cost.astype(np.int64)).to(dev)
+    is_open = outputs["open"].bool()
+    assign = outputs["assign"].to(torch.int64) & 0xFFFFFFFF
+    served = assign != 0xFFFFFFFF
+    dist = outputs["dist"].to(torch.int64) & 0xFFFFFFFF
+    checks = {
+        "opened_are_facilities": bool((fac[is_open] != 0xFFFFFFFF).all()),
+        "served_assigned_to_opened": bool(is_open[assign[served]].all()),
+        "total_cost_matches": int(fac[is_open].sum()) + int(dist[served].sum()) == r["total_cost"],
+    }
+    s0 = stats[0]
+    log(f"[bench] large: {elapsed / steps * 1e3:.1f} ms per solve, open={r['n_open']} checks={checks}")
+    return {"workload": f"rmat{scale}_w100_fac10_lognormal_k{k}", "n": g.n, "arcs": g.n_arcs,
+            "edge_samples": edge_factor << scale, "steps": steps,
+            "ms_per_solve": round(elapsed / steps * 1e3, 2),
+            "relax_per_s": round(sum(x["relax_alg"] for x in stats) / elapsed, 1),
+            "relax_alg_per_solve": s0["relax_alg"], "ads_entries_per_solve": s0["ads_entries"],
+            "ads_rounds": s0["ads_rounds"], "rungs": s0["rungs"], "mis_rounds": s0["mis_rounds"],
+            "phase_ms": {p: round(sum(x[f"ms_{p}"] for x in stats) / steps, 2)
+                         for p in ("validate", "ads", "gamma", "open", "mis", "assign", "total")},
+            "n_open": r["n_open"], "n_unreachable": r["n_unreachable"], "total_cost": r["total_cost"],
+            "checks": checks}
+
+
 def serve_bench(count, seed, rate, slots):
     """Continuous batching: a Poisson stream of count requests at `rate`
     requests/s (Chung-Lu graphs, exponent 2.2, average degree 12, weights
@@ -368,6 +422,10 @@ def main():
                     help="timed solves of the directed reading of the same R-MAT samples (0: skip)")
     ap.add_argument("--sweep", action="store_true",
                     help="run the k and eps sweeps instead and print their JSON")
+    ap.add_argument("--large", action="store_true",
+                    help="run the large weighted configuration (R-MAT 2^24, weights 1..100, 10%% facilities, "
+                         "k = 32) instead and print its JSON")
+    ap.add_argument("--large-steps", type=int, default=1)
     ap.add_argument("--accuracy", action="store_true",
                     help="run the HIP-estimator accuracy experiment instead and print its JSON")
     ap.add_argument("--pmc-calibration", action="store_true",
@@ -385,6 +443,9 @@ def main():
         return
     if args.sweep:
         print(json.dumps({"sweep": sweep_experiment(args.seed)}), flush=True)
+        return
+    if args.large:
+        print(json.dumps({"large": large_bench(24, 16, 32, args.seed, args.large_steps)}), flush=True)
         return
     if args.accuracy:
         print(json.dumps({"accuracy": accuracy_experiment([4, 8, 16, 32, 64], 100, args.seed)}), flush=True)

@@ -418,6 +418,15 @@ def with_problem(g: Graph, seed: int, cost: str = "uniform", cost_lo: int = 1, c
 # --------------------------------------------------------------------------
 # the benchmark workloads (names describe the workload and its sizes)
 # --------------------------------------------------------------------------
+def rmat_weighted_fac10(scale: int = 24, edge_factor: int = 16, seed: int = 1) -> Graph:
+    """R-MAT 2^scale with edge_factor * 2^scale edge samples (average degree
+    about 2 * edge_factor), weights uniform 1..100, 10% of the vertices
+    facilities (seeded) with opening costs lognormal(5, 1) rounded to
+    integers, every vertex a client."""
+    g = rmat(scale, edge_factor << scale, seed, wmax=100)
+    return with_problem(g, seed, cost="lognormal", fac_frac=0.1)
+
+
 def tiny_er(seed: int = 1) -> Graph:
     """Erdos-Renyi n=2,000, average degree 8, weights 1..10, every vertex a
     client and a facility of cost 50."""
