@@ -10,8 +10,9 @@
 // Entries move along arcs, so on a directed graph the sketch of u holds the
 // vertices that reach u, at d(v, u) (an undirected graph is read as both arcs).
 //
-// Work items.  A vertex with at most TASK_ARCS arcs is one task; a larger one
-// is split into tasks of TASK_ARCS arcs.  Each task (one wave64) streams the
+// Work items.  A vertex with at most TASK_ARCS arcs (TASK_ARCS_SPARSE in
+// rounds run from worklists) is one task; a larger one is split into tasks of
+// that many arcs.  Each task (one wave64) streams the
 // entries its neighbours inserted at distance D - w (pull), drops those whose
 // rank is not below T_u (the k-th smallest rank of u's sketch so far: k
 // entries that all come first have a smaller rank) and those already in u's
@@ -47,7 +48,13 @@ constexpr int TASK_WPB = 1;         // waves per block of the round kernels: a b
                                     // freed when its own task ends (task lengths vary widely)
 constexpr uint32_t ADS_SB = 1024;   // survivor ids per wave: one level of one sketch plus a chunk
 static_assert((ADS_SB & (ADS_SB - 1)) == 0, "wave_sort_lds pads to a power of two inside the buffer");
-constexpr uint32_t TASK_ARCS = 256; // arcs per task of a split vertex
+constexpr uint32_t TASK_ARCS = 256; // arcs per task of a split vertex (dense rounds, the most a task has)
+// Sparse rounds (worklists) cut only longer rows: there a hub is active in
+// most rounds but few of its arcs bring candidates, and every split costs a
+// merge that prunes the tasks' kept sets again.  Results do not depend on the
+// cut (a candidate accepted over all arcs is accepted within its piece, and
+// the merge prunes the union exactly).
+constexpr uint32_t TASK_ARCS_SPARSE = 2048;
 constexpr uint32_t NBKT = 64;       // id buckets of the level prune (one per lane)
 constexpr uint32_t LONG_LIST = 24;  // entry lists at least this long are streamed one arc at a time
 
@@ -600,7 +607,7 @@ __device__ inline void level_commit(const AdsArgs &P, uint32_t u, uint32_t D, Le
 template <bool UNITW>
 __global__ __launch_bounds__(TASK_WPB * WAVE) void k_ads_tasks(AdsArgs P, uint32_t D, const uint32_t *task_u,
                                                    const uint32_t *task_sub, const uint32_t *task_slot,
-                                                   uint32_t ntasks, int sparse, int mark) {
+                                                   uint32_t ntasks, uint32_t task_arcs, int sparse, int mark) {
   __shared__ uint32_t lds_id[TASK_WPB][ADS_SB];
   __shared__ uint32_t lds_tmp[TASK_WPB][ADS_SB];
   __shared__ __align__(16) uint32_t lds_cnt[TASK_WPB][3 * WAVE];
@@ -623,8 +630,8 @@ __global__ __launch_bounds__(TASK_WPB * WAVE) void k_ads_tasks(AdsArgs P, uint32
   const uint64_t r0 = P.row_ptr[u], r1 = P.row_ptr[u + 1];
   uint64_t a0 = r0, a1 = r1;
   if (slot != INF32) {
-    a0 = r0 + (uint64_t)sub * TASK_ARCS;
-    a1 = a0 + TASK_ARCS < r1 ? a0 + TASK_ARCS : r1;
+    a0 = r0 + (uint64_t)sub * task_arcs;
+    a1 = a0 + task_arcs < r1 ? a0 + task_arcs : r1;
   }
   const uint64_t examined = gather_arcs<UNITW>(P, D, a0, a1, L, s_id, s_tmp, s_cnt);
   if (lane == 0) {
@@ -766,13 +773,13 @@ __global__ __launch_bounds__(256) void k_hip_thresholds(uint32_t rows, const uin
 // ---------------------------------------------------------------------------
 // task lists
 // ---------------------------------------------------------------------------
-__global__ void k_task_count(const uint32_t *list, uint32_t count, const uint64_t *row_ptr, uint32_t *ntask,
-                             uint32_t *nslot, uint32_t *isplit) {
+__global__ void k_task_count(const uint32_t *list, uint32_t count, const uint64_t *row_ptr, uint32_t task_arcs,
+                             uint32_t *ntask, uint32_t *nslot, uint32_t *isplit) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
   const uint32_t u = list[i];
   const uint64_t d = row_ptr[u + 1] - row_ptr[u];
-  const uint32_t nt = d <= TASK_ARCS ? 1u : (uint32_t)((d + TASK_ARCS - 1) / TASK_ARCS);
+  const uint32_t nt = d <= task_arcs ? 1u : (uint32_t)((d + task_arcs - 1) / task_arcs);
   ntask[i] = nt;
   nslot[i] = nt > 1 ? nt : 0u;
   isplit[i] = nt > 1 ? 1u : 0u;
@@ -804,6 +811,7 @@ struct TaskList {
   uint32_t *task_u, *task_sub, *task_slot;
   uint32_t *split_u, *split_first, *split_nt;
   uint32_t ntasks = 0, nsplit = 0, nslots = 0;
+  uint32_t task_arcs = TASK_ARCS;  // arcs per task of a split vertex
 };
 
 // scratch of build_tasks: 3 count arrays + 3 offset arrays
@@ -812,12 +820,14 @@ struct TaskScratch {
   uint64_t *toff, *soff, *poff;
 };
 
-static void build_tasks(Ctx &c, const Graph &g, const uint32_t *list, uint32_t count, TaskScratch &ts,
-                        TaskList &tl) {
+// task_arcs >= TASK_ARCS: the scratch slots are sized for TASK_ARCS
+static void build_tasks(Ctx &c, const Graph &g, const uint32_t *list, uint32_t count, uint32_t task_arcs,
+                        TaskScratch &ts, TaskList &tl) {
   tl.ntasks = tl.nsplit = tl.nslots = 0;
+  tl.task_arcs = task_arcs;
   if (count == 0) return;
   const uint32_t blocks = (uint32_t)ceil_div(count, 256);
-  k_task_count<<<blocks, 256, 0, c.s>>>(list, count, g.in_ptr, ts.ntask, ts.nslot, ts.isplit);
+  k_task_count<<<blocks, 256, 0, c.s>>>(list, count, g.in_ptr, task_arcs, ts.ntask, ts.nslot, ts.isplit);
   FL_LAUNCH_CHECK();
   scan_u32_to_u64(c, ts.ntask, ts.toff, count);
   scan_u32_to_u64(c, ts.nslot, ts.soff, count);
@@ -988,7 +998,7 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
     c.sync();
     n_dense = (uint32_t)c.h_status[0];
     alloc_list(tl_dense);
-    build_tasks(c, g, dense, n_dense, ts, tl_dense);
+    build_tasks(c, g, dense, n_dense, TASK_ARCS, ts, tl_dense);
   }
   // a round marks (so that the next one runs on worklists) once the previous
   // round changed at most a quarter of the dense list
@@ -1033,7 +1043,7 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
         c.sync();
         count = (uint32_t)(c.h_status[0] & 0xFFFFFFFFu);
       }
-      build_tasks(c, g, P.wl + (size_t)slot * n, count, ts, tl);
+      build_tasks(c, g, P.wl + (size_t)slot * n, count, TASK_ARCS_SPARSE, ts, tl);
       T = &tl;
     }
     // marking decision for this round (decides the mode of the next one)
@@ -1044,10 +1054,10 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
       const uint32_t tb = (uint32_t)ceil_div(T->ntasks, TASK_WPB);
       if (unit)
         k_ads_tasks<true><<<tb, TASK_WPB * WAVE, 0, c.s>>>(P, D, T->task_u, T->task_sub, T->task_slot, T->ntasks,
-                                               sparse ? 1 : 0, mark ? 1 : 0);
+                                               T->task_arcs, sparse ? 1 : 0, mark ? 1 : 0);
       else
         k_ads_tasks<false><<<tb, TASK_WPB * WAVE, 0, c.s>>>(P, D, T->task_u, T->task_sub, T->task_slot, T->ntasks,
-                                                sparse ? 1 : 0, mark ? 1 : 0);
+                                                T->task_arcs, sparse ? 1 : 0, mark ? 1 : 0);
       FL_LAUNCH_CHECK();
       FL_HIP(hipEventRecord(em, c.s));
       if (T->nsplit) {
