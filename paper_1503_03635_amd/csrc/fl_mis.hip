@@ -260,7 +260,6 @@ struct MisWork {
   uint32_t *cbits;   // [n / 32] clients of the current step
   uint32_t *fbits;   // [n / 32] active facilities of the current round
   uint32_t *lab;     // [n] source labels
-  uint32_t *pm;      // [n] pi_min of clients
   uint32_t *act;     // [n] list of active facilities
   uint32_t *act2;    // [n]
   uint32_t *joined;  // [n]
@@ -344,7 +343,8 @@ __global__ void k_set_const_labels(const uint32_t *list, uint32_t cnt, uint32_t 
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < cnt) lab[list[i]] = v;
 }
-// clients of the rung: pm[c] = ml[c]; sources for sweep 2 are those with a value
+// clients of the rung: their pi_min (ml[c]) becomes their label; sources for
+// sweep 2 are those with a value
 __global__ void k_take_pmin(const uint32_t *cl, uint32_t ncl, const uint32_t *ml, uint32_t *lab,
                             uint32_t *src, uint32_t *nsrc) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -616,7 +616,6 @@ int mis_phase(Ctx &c, const MisIn &in, uint8_t *open, std::vector<uint32_t> &rou
   M.S.heavy = c.arena->get<uint64_t>(piece_capacity(n, g.m));
   M.S.heavy_cnt = c.arena->get<uint32_t>(2);
   M.lab = c.arena->get<uint32_t>(n);
-  M.pm = c.arena->get<uint32_t>(n);
   M.act = c.arena->get<uint32_t>(n);
   M.act2 = c.arena->get<uint32_t>(n);
   M.joined = c.arena->get<uint32_t>(n);
