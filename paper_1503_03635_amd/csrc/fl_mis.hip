@@ -270,6 +270,10 @@ struct MisWork {
 
 enum class Toward { clients, facilities };
 
+// sweeps from at most this many sources skip the first readback of the
+// frontier counts
+constexpr uint32_t SWEEP_BLIND_SRC = 4096;
+
 // run one sweep to completion; results in S.ml (caller resets afterwards).
 // Toward::clients: from facilities f to every x with d(x, f) <= R (in-arcs);
 // Toward::facilities: from clients c to every x with d(c, x) <= R (out-arcs).
@@ -291,15 +295,22 @@ static void sweep(Ctx &c, MisWork &M, const uint32_t *src, uint32_t nsrc, uint32
   FL_LAUNCH_CHECK();
   std::vector<uint32_t> h(S.NS);
   uint32_t j = 1;
+  // few sources: run the first burst without reading the counts back (its
+  // grid fits any frontier, and an empty distance costs one short launch)
+  bool blind = nsrc <= SWEEP_BLIND_SRC;
   while (j <= R) {
-    FL_HIP(hipMemcpyAsync(h.data(), S.tl_cnt, S.NS * 4, hipMemcpyDeviceToHost, c.s));
-    c.sync();
-    uint64_t pending = 0;
+    uint64_t pending = 1;
     uint32_t hmax = 0;
-    for (uint32_t s = 0; s < S.NS; ++s) {
-      pending += h[s];
-      hmax = std::max(hmax, h[s]);
+    if (!blind) {
+      FL_HIP(hipMemcpyAsync(h.data(), S.tl_cnt, S.NS * 4, hipMemcpyDeviceToHost, c.s));
+      c.sync();
+      pending = 0;
+      for (uint32_t s = 0; s < S.NS; ++s) {
+        pending += h[s];
+        hmax = std::max(hmax, h[s]);
+      }
     }
+    blind = false;
     if (!pending) break;
     // k_sweep_round reads its slot's count on the device: small rounds run
     // several distances per host check.  A frontier can grow from a handful
