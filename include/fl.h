@@ -46,7 +46,7 @@ extern "C" {
 #define FL_ENOMEM 3   /* workspace does not fit the device (or the budget) */
 #define FL_EHIP 4     /* a HIP runtime error; see fl_last_hip_error() */
 #define FL_EBUSY 5    /* server queue full (non-blocking submit) */
-#define FL_ENOTIMPL 6 /* a limit of this build: k > 64, max weight > 255,
+#define FL_ENOTIMPL 6 /* a limit of this library: k > 64, max weight > 255,
                          sketch capacity above 65535 entries per vertex */
 
 /* ---- sentinels ---------------------------------------------------------- */
