@@ -48,13 +48,14 @@ constexpr int TASK_WPB = 1;         // waves per block of the round kernels: a b
                                     // freed when its own task ends (task lengths vary widely)
 constexpr uint32_t ADS_SB = 1024;   // survivor ids per wave: one level of one sketch plus a chunk
 static_assert((ADS_SB & (ADS_SB - 1)) == 0, "wave_sort_lds pads to a power of two inside the buffer");
-constexpr uint32_t TASK_ARCS = 256; // arcs per task of a split vertex (dense rounds, the most a task has)
+constexpr uint32_t TASK_ARCS = 1024;  // arcs per task of a split vertex in dense rounds (the fewest)
 // Sparse rounds (worklists) cut only longer rows: there a hub is active in
 // most rounds but few of its arcs bring candidates, and every split costs a
 // merge that prunes the tasks' kept sets again.  Results do not depend on the
 // cut (a candidate accepted over all arcs is accepted within its piece, and
 // the merge prunes the union exactly).
 constexpr uint32_t TASK_ARCS_SPARSE = 2048;
+static_assert(TASK_ARCS_SPARSE >= TASK_ARCS, "scratch slots are sized for TASK_ARCS");
 constexpr uint32_t NBKT = 64;       // id buckets of the level prune (one per lane)
 constexpr uint32_t LONG_LIST = 24;  // entry lists at least this long are streamed one arc at a time
 
