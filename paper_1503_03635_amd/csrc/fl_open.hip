@@ -240,6 +240,8 @@ __global__ __launch_bounds__(256) void k_open_light(OpenArgs A, uint32_t t) {
 // wave follows WAVE / OPEN_G facilities' chains of dependent loads (cursor,
 // entries, the clients' freeze state, sums) at once.
 constexpr int OPEN_G = 16;
+static_assert(OPEN_G >= 2 && OPEN_G < 32 && (OPEN_G & (OPEN_G - 1)) == 0,
+              "group masks are 32-bit: a power of two below 32 lanes");
 
 // sum over the lane's OPEN_G-lane group (the group's lanes converged)
 __device__ inline uint64_t group_sum_u64(uint64_t x) {
