@@ -57,7 +57,7 @@ constexpr uint32_t TASK_ARCS = 1024;  // arcs per task of a split vertex in dens
 constexpr uint32_t TASK_ARCS_SPARSE = 2048;
 static_assert(TASK_ARCS_SPARSE >= TASK_ARCS, "scratch slots are sized for TASK_ARCS");
 constexpr uint32_t NBKT = 64;       // id buckets of the level prune (one per lane)
-constexpr uint32_t LONG_LIST = 24;  // entry lists at least this long are streamed one arc at a time
+constexpr uint32_t LONG_LIST = 64;  // entry lists at least this long are streamed one arc at a time
 
 struct AdsArgs {
   uint32_t n, k, cap, W, NS, FW;
