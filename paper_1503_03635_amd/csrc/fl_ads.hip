@@ -509,7 +509,7 @@ __device__ inline uint64_t gather_arcs(const AdsArgs &P, uint32_t D, uint64_t a0
         }
       }
     }
-    // long lists: one arc at a time, the whole wave on its list, two loads in
+    // long lists: one arc at a time, the whole wave on its list, four loads in
     // flight.  A level is stored in increasing rank order, so once a rank
     // reaches T0 the rest of the list cannot enter u's sketch.
     uint64_t lm = __ballot(cn >= LONG_LIST);
@@ -520,14 +520,21 @@ __device__ inline uint64_t gather_arcs(const AdsArgs &P, uint32_t D, uint64_t a0
       const uint32_t stj = __shfl(st, j, WAVE);
       const uint32_t cnj = __shfl(cn, j, WAVE);
       const uint32_t *src = P.sk_rank + (size_t)vj * P.cap + stj;
-      for (uint32_t c0 = 0; c0 < cnj && !L.overflow; c0 += 2 * WAVE) {
-        const uint32_t i0 = c0 + lane, i1 = i0 + WAVE;
+      for (uint32_t c0 = 0; c0 < cnj && !L.overflow; c0 += 4 * WAVE) {
+        const uint32_t i0 = c0 + lane, i1 = i0 + WAVE, i2 = i1 + WAVE, i3 = i2 + WAVE;
         const uint32_t r0 = i0 < cnj ? src[i0] : INF32;
         const uint32_t r1 = i1 < cnj ? src[i1] : INF32;
-        examined += cnj - c0 < 2 * WAVE ? cnj - c0 : 2 * WAVE;
+        const uint32_t r2 = i2 < cnj ? src[i2] : INF32;
+        const uint32_t r3 = i3 < cnj ? src[i3] : INF32;
+        examined += cnj - c0 < 4 * WAVE ? cnj - c0 : 4 * WAVE;
         level_offer(P, L, i0 < cnj, r0, false, 0, s_id, s_tmp, s_cnt);
+        if (L.full0 && __ballot(i0 < cnj && r0 >= L.T0)) break;
         if (c0 + WAVE < cnj) level_offer(P, L, i1 < cnj, r1, false, 0, s_id, s_tmp, s_cnt);
-        if (L.full0 && __ballot((i0 < cnj && r0 >= L.T0) || (i1 < cnj && r1 >= L.T0))) break;
+        if (L.full0 && __ballot(i1 < cnj && r1 >= L.T0)) break;
+        if (c0 + 2 * WAVE < cnj) level_offer(P, L, i2 < cnj, r2, false, 0, s_id, s_tmp, s_cnt);
+        if (L.full0 && __ballot(i2 < cnj && r2 >= L.T0)) break;
+        if (c0 + 3 * WAVE < cnj) level_offer(P, L, i3 < cnj, r3, false, 0, s_id, s_tmp, s_cnt);
+        if (L.full0 && __ballot(i3 < cnj && r3 >= L.T0)) break;
       }
     }
     // short lists: flattened over the group, owner lane found by binary search
