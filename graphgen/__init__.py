@@ -415,6 +415,34 @@ def with_problem(g: Graph, seed: int, cost: str = "uniform", cost_lo: int = 1, c
     return g
 
 
+def with_facilities(g: Graph, ids, costs, client_mask=None) -> Graph:
+    """Only the listed vertices are facilities, with the given opening costs
+    (a scalar or one per id); every vertex is a client unless client_mask
+    (uint8 [n]) says otherwise.  Few cheap facilities far from most clients
+    make every facility open while some clients are still unfrozen."""
+    c = np.full(g.n, NOT_FACILITY, np.uint32)
+    c[np.asarray(ids, np.int64)] = np.asarray(costs, np.uint32)
+    g.fac_cost = c
+    g.is_client = None if client_mask is None else np.ascontiguousarray(client_mask, np.uint8)
+    return g
+
+
+def end_phase_problems():
+    """Small problems whose opening loop ends with every facility open and
+    clients left unfrozen (each returned with a short name)."""
+    return [
+        ("path 30, one facility at an end", with_facilities(path(30), [0], 1)),
+        ("grid 12x12 w1..9, three corner facilities",
+         with_facilities(grid(12, 12, wmax=9, seed=3), [0, 11, 143], [2, 3, 2])),
+        ("path 40 w1..5, facilities 0, 1, 39", with_facilities(path(40, wmax=5, seed=2), [0, 1, 39], 1)),
+        ("ER 300 w1..20, five facilities, unreachable clients",
+         with_facilities(er(300, 3, 4, wmax=20), [3, 50, 100, 200, 250], [1, 2, 3, 4, 5])),
+        ("directed path 30, facility at the far end", with_facilities(path(30, directed=True), [29], 1)),
+        ("directed cycle 40 w1..7, two facilities",
+         with_facilities(cycle(40, wmax=7, seed=1, directed=True), [0, 20], 1)),
+    ]
+
+
 # --------------------------------------------------------------------------
 # the benchmark workloads (names describe the workload and its sizes)
 # --------------------------------------------------------------------------

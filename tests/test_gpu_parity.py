@@ -131,8 +131,89 @@ def test_solve_stall_guard():
     pytest.fail("no seed for the guard case")
 
 
+END_CASES = gg.end_phase_problems()
+
+
+@pytest.mark.parametrize("idx", range(len(END_CASES)), ids=[c[0] for c in END_CASES])
+def test_solve_end_phase(idx):
+    """Alg. 4's end phase (every facility open, clients left unfrozen): END
+    rungs, open set, assignment, q and cost equal the oracle's, and the
+    branch really fires on each input."""
+    name, g = END_CASES[idx]
+    for k, seed in ((4, 1), (16, 2)):
+        print(f"[solve end] {name} k={k} seed={seed}", flush=True)
+        got, want = assert_solve_equal(g, k, seed)
+        assert (want["freeze_rung"] == O.RUNG_END).any(), "the end phase must fire"
+        assert (got["freeze_rung"] == fl.FL_RUNG_END).sum() == (want["freeze_rung"] == O.RUNG_END).sum()
+
+
+def test_solve_end_phase_batched():
+    """The end-phase inputs solved together in one batch (directed and
+    undirected mixed) give each element the oracle's result."""
+    gs = [g for _, g in END_CASES]
+    print(f"[solve end] batch of {len(gs)}", flush=True)
+    outs = fl.solve_batch([fl.to_device(g) for g in gs], 8, 3, diagnostics=True)
+    torch.cuda.synchronize()
+    for (name, g), r in zip(END_CASES, outs):
+        rc, want = O.solve(g, 8, 3, 0.1)
+        assert rc == 0 and r["status"] == 0
+        assert (want["freeze_rung"] == O.RUNG_END).any(), name
+        for key in ("open", "assign", "dist", "open_rung", "freeze_rung"):
+            got = r[key].cpu().numpy()
+            got = got.view(np.uint32) if key != "open" else got
+            assert np.array_equal(got, want[key]), f"{name}: {key}"
+        assert r["total_cost"] == want["total_cost"], name
+
+
+# Rounds run from worklists (every round of a weighted graph) cut rows of more
+# than 2,048 arcs into several tasks whose kept sets a merge wave prunes
+# again: the inputs below have such hubs with weights 1..100.
+SPLIT_ARCS_SPARSE = 2048
+
+
+def _weighted_in_star(n, seed):
+    """Directed star: every leaf has an arc into the hub, weights 1..100."""
+    leaves = np.arange(1, n, dtype=np.uint32)
+    return gg.from_arcs(n, leaves, np.zeros(n - 1, np.uint32), 100, np.random.Generator(np.random.PCG64(seed)),
+                        name=f"instar_{n}")
+
+
+WEIGHTED_HUB_CASES = [
+    ("star 5000 w1..100", lambda: gg.star(5000, wmax=100, seed=3), 32),
+    ("in-star 5000 w1..100", lambda: _weighted_in_star(5000, 4), 16),
+    ("RMAT 2^14 x16 w1..100", lambda: gg.rmat(14, 16 << 14, 22, wmax=100), 32),
+]
+
+
+def _max_in_degree(g):
+    return int(np.bincount(g.col, minlength=g.n).max()) if g.n_arcs else 0
+
+
+@pytest.mark.parametrize("name,make,k", WEIGHTED_HUB_CASES, ids=[c[0] for c in WEIGHTED_HUB_CASES])
+def test_sketches_weighted_split_hubs(name, make, k):
+    """Weighted hubs above the split threshold: the split tasks, their kept
+    sets and the merge that prunes them again give the oracle's sketches."""
+    g = make()
+    assert _max_in_degree(g) > SPLIT_ARCS_SPARSE
+    print(f"[sketch] {name} n={g.n} arcs={g.n_arcs} max in-degree {_max_in_degree(g)} k={k}", flush=True)
+    assert_sketch_equal(g, k, seed=5)
+
+
+@pytest.mark.parametrize("name,make,k", WEIGHTED_HUB_CASES, ids=[c[0] for c in WEIGHTED_HUB_CASES])
+def test_solve_weighted_split_hubs(name, make, k):
+    """Full solves on the same inputs with the large weighted recipe's problem
+    (10% facilities, lognormal costs, every vertex a client)."""
+    g = gg.with_problem(make(), 23, cost="lognormal", fac_frac=0.1)
+    assert _max_in_degree(g) > SPLIT_ARCS_SPARSE
+    print(f"[solve] {name} 10% lognormal facilities k={k}", flush=True)
+    assert_solve_equal(g, k, 1)
+
+
 def test_solve_degenerate_inputs():
     cases = []
+    nocl = gg.with_problem(gg.er(40, 4, 2, wmax=3), 2, cost="uniform", cost_hi=20)
+    nocl.is_client = np.zeros(nocl.n, np.uint8)
+    cases.append(("no clients", nocl))
     one = gg.empty(1)
     one.fac_cost = np.array([5], np.uint32)
     cases.append(("single vertex", one))

@@ -284,6 +284,11 @@ def _problems():
 
 
 PROBLEMS = _problems()
+# problems whose opening loop ends with O = F and U non-empty (the end phase
+# of Alg. 4); they also run through every pin over PROBLEMS below
+END_PROBLEMS = [g for _, g in gg.end_phase_problems()]
+N_BASE = len(PROBLEMS)
+PROBLEMS = PROBLEMS + END_PROBLEMS
 
 
 def _solve(g, k, seed, eps=0.1):
@@ -294,6 +299,80 @@ def _solve(g, k, seed, eps=0.1):
 
 def _ladder(r, count):
     return O.ladder(r["alpha0"], 0.1, count) if count else np.zeros(0)
+
+
+def _gamma_from_scipy(g, D):
+    """Sec. 4.1 from library shortest paths: gamma_c = min_f (c(f) + d(c, f))
+    for every client that reaches a facility, and the served set."""
+    isF = g.fac_cost != O.NOT_FACILITY
+    isC = np.ones(g.n, bool) if g.is_client is None else g.is_client.astype(bool)
+    if not isF.any():
+        return np.full(g.n, np.inf), np.zeros(g.n, bool), isF, isC
+    gam = (g.fac_cost[isF].astype(np.float64)[None, :] + D[:, isF]).min(axis=1)
+    served = isC & np.isfinite(gam)
+    return gam, served, isF, isC
+
+
+@pytest.mark.parametrize("pi", range(len(PROBLEMS)))
+@pytest.mark.parametrize("eps", [0.1, 0.01, 1.0])
+def test_gamma_and_alpha0_from_scipy(pi, eps):
+    """Sec. 4.1: gamma = max over served clients of min_f (c(f) + d(c, f))
+    with d from scipy; unreachable clients are those with no facility in
+    reach; alpha_0 = gamma / (m m) (1 + eps) with m = |F| |C_eff| (one
+    rounding per operation), and the ladder grows by (1 + eps) per rung.  A
+    gamma without c(f), one taken over unreachable clients or an m counting
+    every client fails here."""
+    g = PROBLEMS[pi]
+    rc, r = O.solve(g, 8, 5, eps)
+    assert rc == 0
+    D = apsp(g)
+    gam, served, isF, isC = _gamma_from_scipy(g, D)
+    n_ceff = int(served.sum())
+    assert r["n_unreachable"] == int(isC.sum()) - n_ceff
+    want_gamma = int(gam[served].max()) if n_ceff else 0
+    assert r["gamma"] == want_gamma
+    if n_ceff and isF.any():
+        m = float(int(isF.sum()) * n_ceff)
+        a0 = (float(want_gamma) / (m * m)) * (1.0 + eps)
+        assert r["alpha0"] == a0
+        lad = O.ladder(r["alpha0"], eps, 50)
+        x = a0
+        for t in range(50):
+            assert lad[t] == x
+            x = x * (1.0 + eps)
+    else:
+        assert r["alpha0"] == 0.0
+    # assignment exclusion: unreachable clients are not served
+    assert np.array_equal(r["assign"] != O.NONE, served)
+
+
+@pytest.mark.parametrize("pi", range(len(END_PROBLEMS)))
+def test_end_phase(pi):
+    """Alg. 4's closing branch: when every facility is open and clients are
+    still unfrozen, those clients are tied to their nearest facility at rung
+    END.  With O = F after the last rung T, a served client is never frozen
+    exactly when d(c, F) > (1 + eps) a[T] (scipy distances), so the END
+    clients are that set, and every facility opened at a real rung."""
+    g = END_PROBLEMS[pi]
+    eps = 0.1
+    for k, seed in ((4, 1), (8, 2), (16, 3)):
+        rc, r = O.solve(g, k, seed, eps)
+        assert rc == 0
+        T = r["n_rungs"]
+        lad = O.ladder(r["alpha0"], eps, T + 2)
+        D = apsp(g)
+        gam, served, isF, isC = _gamma_from_scipy(g, D)
+        orung = r["open_rung"]
+        assert ((orung[isF] >= 1) & (orung[isF] <= T)).all()     # O = F, no guard
+        assert r["n_guard"] == 0
+        dF = D[:, isF].min(axis=1)
+        rho = (1.0 + eps) * lad[T]
+        want_end = served & (dF > rho)
+        got_end = r["freeze_rung"] == O.RUNG_END
+        assert want_end.any()                                     # the branch fires
+        assert np.array_equal(got_end, want_end)
+        # every served client gets a rung: a real one, or END
+        assert (r["freeze_rung"][served] != O.RUNG_NONE).all()
 
 
 @pytest.mark.parametrize("pi", range(len(PROBLEMS)))
@@ -683,7 +762,7 @@ def _as_directed(g):
     return h
 
 
-@pytest.mark.parametrize("pi", [0, 1, 3, 4])
+@pytest.mark.parametrize("pi", [0, 1, 3, 4, N_BASE, N_BASE + 1])
 def test_directed_reading_of_symmetric_input_is_undirected(pi):
     """A symmetric arc set read as directed is the undirected graph: the same
     sketches and the same solve, bit for bit (every search direction
