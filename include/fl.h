@@ -157,6 +157,29 @@ typedef struct {
 int fl_solve(const fl_problem *p, const fl_params *prm, fl_result *out, void *stream);
 
 /*
+ * fl_solve_static -- for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The same solve, arguments and results as fl_solve, but the
+ * library's workspace is carved from one fixed device array of
+ * FL_STATIC_SCRATCH_BYTES that every device loading the library holds until
+ * the process ends.  The call allocates no device or pinned host memory and
+ * creates no HIP events (the ms_* statistics stay 0); its host bookkeeping
+ * uses the ordinary C++ heap.  The caller still passes every input and output.
+ *   - FL_ENOMEM when the solve needs more than the array: at once, before any
+ *     device work, when the sketch rows alone (n x capacity x 8 bytes, the
+ *     capacity being about k (1 + ln(n/k)) entries plus a margin) do not
+ *     fit; otherwise as soon as a further piece of the workspace would cross
+ *     the array's end (no pointer past it is ever handed out).
+ *   - Every call on a device uses that device's one array and finds the
+ *     previous call's contents there; the solve initialises all it reads.
+ *     Two calls whose device work overlapped on one device would race on the
+ *     array, so calls on a device are serialised and each synchronises its
+ *     stream before it returns.
+ */
+#define FL_STATIC_SCRATCH_BYTES (256ull << 20)
+int fl_solve_static(const fl_problem *p, const fl_params *prm, fl_result *out, void *stream);
+
+/*
  * fl_solve_batch -- `count` independent solves; per element the same contract
  * and the same results as fl_solve (its status field says whether it
  * succeeded).  Elements with equal k, eps and flags are solved together as one

@@ -109,23 +109,36 @@ def _collect(res, out):
     return out
 
 
-def solve(dg: DeviceGraph, k: int, seed: int, eps: float = 0.1, flags: int = 0,
-          diagnostics: bool = False, stream=None, outputs=None, check=True):
-    """One facility-location solve (fl_solve).  Returns a dict of device
-    tensors (open, assign, dist[, open_rung, freeze_rung, q]) and host scalars
-    (total_cost, n_open, n_unreachable, stats)."""
+def _solve_with(fn, name, dg, k, seed, eps, flags, diagnostics, stream, outputs, check):
     device = dg.col.device if dg.n_arcs else dg.row_ptr.device
     out = outputs if outputs is not None else _alloc_outputs(dg.n, device, diagnostics)
     prob = _problem(dg)
     prm = _lib.FlParams(k, seed, eps, _flags(dg, flags))
     res = _result_struct(out)
-    rc = lib().fl_solve(C.byref(prob), C.byref(prm), C.byref(res), C.c_void_p(_stream_ptr(stream)))
+    rc = fn(C.byref(prob), C.byref(prm), C.byref(res), C.c_void_p(_stream_ptr(stream)))
     out["rc"] = rc
     if rc != _lib.FL_OK:
         if check:
-            raise FlError(rc, "fl_solve")
+            raise FlError(rc, name)
         return out
     return _collect(res, out)
+
+
+def solve(dg: DeviceGraph, k: int, seed: int, eps: float = 0.1, flags: int = 0,
+          diagnostics: bool = False, stream=None, outputs=None, check=True):
+    """One facility-location solve (fl_solve).  Returns a dict of device
+    tensors (open, assign, dist[, open_rung, freeze_rung, q]) and host scalars
+    (total_cost, n_open, n_unreachable, stats)."""
+    return _solve_with(lib().fl_solve, "fl_solve", dg, k, seed, eps, flags, diagnostics, stream, outputs, check)
+
+
+def solve_static(dg: DeviceGraph, k: int, seed: int, eps: float = 0.1, flags: int = 0,
+                 diagnostics: bool = False, stream=None, outputs=None, check=True):
+    """fl_solve_static: the same solve with the workspace in the library's
+    fixed device array (no device allocation by the library; pass `outputs`
+    to keep the call free of torch allocations too)."""
+    return _solve_with(lib().fl_solve_static, "fl_solve_static", dg, k, seed, eps, flags, diagnostics, stream,
+                       outputs, check)
 
 
 def solve_batch(dgs, k, seed, eps=0.1, flags=0, diagnostics=False, stream=None, check=True, outputs=None):

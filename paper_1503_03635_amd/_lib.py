@@ -58,6 +58,7 @@ class FlSketchView(C.Structure):
 # every symbol include/fl.h declares, with its ctypes signature
 SIGNATURES = {
     "fl_solve": (C.c_int, [C.POINTER(FlProblem), C.POINTER(FlParams), C.POINTER(FlResult), C.c_void_p]),
+    "fl_solve_static": (C.c_int, [C.POINTER(FlProblem), C.POINTER(FlParams), C.POINTER(FlResult), C.c_void_p]),
     "fl_solve_batch": (C.c_int, [C.POINTER(FlProblem), C.POINTER(FlParams), C.POINTER(FlResult),
                                  C.c_uint32, C.c_void_p]),
     "fl_ads_build": (C.c_int, [C.POINTER(FlProblem), C.POINTER(FlParams), C.POINTER(C.c_void_p), C.c_void_p]),

@@ -1021,16 +1021,18 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
     FL_LAUNCH_CHECK();
   }
   bool sparse = mark;  // mode of round 1
-  hipEvent_t e0, em, e1;
-  FL_HIP(hipEventCreate(&e0));
-  FL_HIP(hipEventCreate(&em));
-  FL_HIP(hipEventCreate(&e1));
+  hipEvent_t e0 = nullptr, em = nullptr, e1 = nullptr;
+  if (c.timing) {
+    FL_HIP(hipEventCreate(&e0));
+    FL_HIP(hipEventCreate(&em));
+    FL_HIP(hipEventCreate(&e1));
+  }
   struct EvDel {
     hipEvent_t a, b, c;
     ~EvDel() {
-      (void)hipEventDestroy(a);
-      (void)hipEventDestroy(b);
-      (void)hipEventDestroy(c);
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+      if (c) (void)hipEventDestroy(c);
     }
   } evdel{e0, em, e1};
   o.kernel_ms = 0.0;
@@ -1058,7 +1060,7 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
     mark = !dense_ok || active_prev <= dense_threshold;
     fill_u64(c, P.ctr + 64, 64, 0);
     if (T->ntasks) {
-      FL_HIP(hipEventRecord(e0, c.s));
+      if (c.timing) FL_HIP(hipEventRecord(e0, c.s));
       const uint32_t tb = (uint32_t)ceil_div(T->ntasks, TASK_WPB);
       if (unit)
         k_ads_tasks<true><<<tb, TASK_WPB * WAVE, 0, c.s>>>(P, D, T->task_u, T->task_sub, T->task_slot, T->ntasks,
@@ -1067,7 +1069,7 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
         k_ads_tasks<false><<<tb, TASK_WPB * WAVE, 0, c.s>>>(P, D, T->task_u, T->task_sub, T->task_slot, T->ntasks,
                                                 T->task_arcs, sparse ? 1 : 0, mark ? 1 : 0);
       FL_LAUNCH_CHECK();
-      FL_HIP(hipEventRecord(em, c.s));
+      if (c.timing) FL_HIP(hipEventRecord(em, c.s));
       if (T->nsplit) {
         const uint32_t mb = (uint32_t)ceil_div(T->nsplit, TASK_WPB);
         if (unit)
@@ -1078,7 +1080,7 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
                                                   mark ? 1 : 0);
         FL_LAUNCH_CHECK();
       }
-      FL_HIP(hipEventRecord(e1, c.s));
+      if (c.timing) FL_HIP(hipEventRecord(e1, c.s));
     }
     if (sparse) fill_u32(c, P.wl_cnt + slot, 1, 0);
     ++rounds;
@@ -1089,8 +1091,10 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
     hwl_valid = true;
     if (T->ntasks) {
       float ms = 0.f, ms2 = 0.f;
-      FL_HIP(hipEventElapsedTime(&ms, e0, em));
-      FL_HIP(hipEventElapsedTime(&ms2, em, e1));
+      if (c.timing) {
+        FL_HIP(hipEventElapsedTime(&ms, e0, em));
+        FL_HIP(hipEventElapsedTime(&ms2, em, e1));
+      }
       o.kernel_ms += ms;
       o.merge_ms += ms2;
       o.launches += 1;

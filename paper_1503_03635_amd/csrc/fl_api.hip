@@ -85,6 +85,7 @@ static void dev_free(void *p) {
 }
 
 void Arena::reserve(size_t bytes) {
+  if (fixed_) return;  // a fixed buffer never grows; get() reports exhaustion
   bytes = (bytes + (size_t(1) << 21) - 1) & ~((size_t(1) << 21) - 1);
   if (bytes <= cap_) return;
   release();
@@ -96,7 +97,8 @@ void Arena::reserve(size_t bytes) {
   used_ = 0;
 }
 void Arena::release() {
-  dev_free(base_);
+  if (!fixed_) dev_free(base_);
+  fixed_ = false;
   base_ = nullptr;
   cap_ = used_ = 0;
 }
@@ -105,6 +107,7 @@ struct DeviceCache {
   std::mutex mu;
   Arena arena;
   uint64_t *h_status = nullptr;
+  bool timing = true;  // per-phase HIP events
   void release_all() {
     arena.release();
     if (h_status) (void)hipHostFree(h_status);
@@ -122,6 +125,20 @@ struct BatchPool {
   hipStream_t st[BATCH_WORKERS] = {};
 };
 static BatchPool g_pool[64];
+
+// Workspace of fl_solve_static: one fixed device array, never allocated or
+// freed by the library.  Each device that loads the library holds its own
+// copy until the process ends; host code reaches it only through the
+// address hipGetSymbolAddress returns for the current device (the array's
+// name denotes a host-side stand-in, not device memory).
+static __device__ __align__(256) char scratch[FL_STATIC_SCRATCH_BYTES];
+struct StaticWorkspace {
+  std::mutex mu;
+  char *ptr = nullptr;      // device address of `scratch` on this device
+  DeviceCache dc;           // arena over ptr, host status words below, no timing events
+  uint64_t h_status[4096];  // readback words (ordinary host memory, no pinned allocation)
+};
+static StaticWorkspace g_static[64];
 
 static DeviceCache &cache_for_current() {
   int dev = 0;
@@ -337,6 +354,7 @@ static size_t union_bytes(uint32_t G, uint64_t n, uint64_t m, bool weighted) {
 }
 
 static double ms_between(hipEvent_t a, hipEvent_t b) {
+  if (!a || !b) return 0.0;
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.0;
   return (double)ms;
@@ -374,16 +392,22 @@ static void solve_group(const fl_problem *const *ps, const fl_params *const *pr,
   c.s = s;
   c.arena = &dc.arena;
   c.h_status = dc.h_status;
+  c.timing = dc.timing;
 
-  hipEvent_t ev[8];
-  for (auto &e : ev) FL_HIP(hipEventCreate(&e));
+  hipEvent_t ev[8] = {};
+  if (c.timing)
+    for (auto &e : ev) FL_HIP(hipEventCreate(&e));
   struct EvGuard {
     hipEvent_t *e;
     ~EvGuard() {
-      for (int i = 0; i < 8; ++i) (void)hipEventDestroy(e[i]);
+      for (int i = 0; i < 8; ++i)
+        if (e[i]) (void)hipEventDestroy(e[i]);
     }
   } evg{ev};
-  FL_HIP(hipEventRecord(ev[0], s));
+  auto mark = [&](int i) {
+    if (ev[i]) FL_HIP(hipEventRecord(ev[i], s));
+  };
+  mark(0);
 
   // ---- validation per graph; failing graphs leave the group
   std::vector<uint32_t> mw(G0, 1), mc(G0, 0);
@@ -425,7 +449,7 @@ static void solve_group(const fl_problem *const *ps, const fl_params *const *pr,
   const bool weighted = weighted0;
   const uint32_t NS = (weighted ? max_w : 1u) + 1;
   const size_t need = estimate_bytes(n, M0, n, k, cap0, NS) + union_bytes(G, N0, M0, weighted) + tr0;
-  if (need > dc.arena.capacity()) {
+  if (!dc.arena.fixed() && need > dc.arena.capacity()) {
     if (depth > 0) {
       for (auto &r : rc_out) r = FL_ENOMEM;
       return;
@@ -485,7 +509,7 @@ static void solve_group(const fl_problem *const *ps, const fl_params *const *pr,
     g = Graph{n, M0, d_rp, d_col, d_w, weighted ? max_w : 1u};
   }
   set_in_arcs(c, g, directed);
-  FL_HIP(hipEventRecord(ev[1], s));
+  mark(1);
 
   // ---- facilities
   uint32_t *flag = c.arena->get<uint32_t>(n);
@@ -526,7 +550,7 @@ static void solve_group(const fl_problem *const *ps, const fl_params *const *pr,
   }
   std::vector<uint64_t> relax, entries;
   ads_totals(c, g, gid, G, ads.cnt, relax, entries);
-  FL_HIP(hipEventRecord(ev[2], s));
+  mark(2);
 
   // ---- gamma (Sec. 4.1) and served clients
   const uint32_t stripes = G == 1 ? 64 : 1;
@@ -562,7 +586,7 @@ static void solve_group(const fl_problem *const *ps, const fl_params *const *pr,
     lad[i].push_back(lad[i][0] * one_eps);
     outs[i]->stats.alpha0 = lad[i][0];
   }
-  FL_HIP(hipEventRecord(ev[3], s));
+  mark(3);
 
   // ---- outputs: the caller's arrays for one graph, union arrays otherwise
   fl_result *o0 = outs[0];
@@ -591,7 +615,7 @@ static void solve_group(const fl_problem *const *ps, const fl_params *const *pr,
       FL_LAUNCH_CHECK();
     }
   }
-  FL_HIP(hipEventRecord(ev[4], s));
+  mark(4);
 
   // ---- MIS per rung (Sec. 4.3, Alg. 6)
   MisIn mi{&g, G, gid, seg, oo.rungs, &lad, eps, orung, frz, (flags & FL_FLAG_LUBY_MIS) != 0};
@@ -601,7 +625,7 @@ static void solve_group(const fl_problem *const *ps, const fl_params *const *pr,
     for (auto &r : rc_out) r = rc;
     return;
   }
-  FL_HIP(hipEventRecord(ev[5], s));
+  mark(5);
 
   // ---- assignment and objective (Sec. 3.1)
   uint64_t *al = c.arena->get<uint64_t>(n);
@@ -646,8 +670,9 @@ static void solve_group(const fl_problem *const *ps, const fl_params *const *pr,
     c.sync();  // hd is read by the copy above
   }
   const std::vector<uint64_t> ao = read_seg_ctr(c, actr, G, AO_NFIELD, stripes);
-  FL_HIP(hipEventRecord(ev[6], s));
-  FL_HIP(hipEventSynchronize(ev[6]));
+  mark(6);
+  if (ev[6]) FL_HIP(hipEventSynchronize(ev[6]));
+  else c.sync();
   for (uint32_t i = 0; i < G; ++i) {
     fl_result *o = outs[i];
     if (oo.rc[i] != FL_OK) {
@@ -881,6 +906,66 @@ int fl_solve(const fl_problem *p, const fl_params *prm, fl_result *out, void *st
     std::vector<int> rc;
     fl::solve_group(&p, &prm, &out, 1, (hipStream_t)stream, dc, rc);
     if (rc[0] != FL_OK) out->n_open = 0;
+    out->status = rc[0];
+    return rc[0];
+  } catch (fl::Error &e) {
+    if (out) out->n_open = 0;
+    if (out) out->status = e.code;
+    return e.code;
+  } catch (std::bad_alloc &) {
+    if (out) out->n_open = 0;
+    if (out) out->status = FL_ENOMEM;
+    return FL_ENOMEM;
+  }
+}
+
+int fl_solve_static(const fl_problem *p, const fl_params *prm, fl_result *out, void *stream) {
+  if (out) out->n_open = 0;
+  if (out) out->status = FL_EINVAL;
+  try {
+    if (out) std::memset(&out->stats, 0, sizeof(out->stats));
+    int pc = fl::check_params(p, prm);
+    if (pc) return pc;
+    if (!p->fac_cost || !out || !out->open || !out->assign) return FL_EINVAL;
+    // the sketch rows alone must fit: refuse before any device work
+    if ((uint64_t)p->n * fl::ads_capacity(p->n, prm->k) * 8ull > FL_STATIC_SCRATCH_BYTES) {
+      out->status = FL_ENOMEM;
+      return FL_ENOMEM;
+    }
+    int dev = 0;
+    FL_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return FL_EINVAL;
+    fl::StaticWorkspace &w = fl::g_static[dev];
+    std::lock_guard<std::mutex> lk(w.mu);
+    if (!w.ptr) {
+      // once per device, with that device current
+      void *ptr = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(fl::scratch));
+      if (e != hipSuccess || !ptr) {
+        fl::set_last_hip_error((int)e);
+        out->status = FL_EHIP;
+        return FL_EHIP;
+      }
+      w.ptr = static_cast<char *>(ptr);
+      w.dc.arena.attach(w.ptr, FL_STATIC_SCRATCH_BYTES);
+      w.dc.h_status = w.h_status;
+      w.dc.timing = false;
+    }
+    w.dc.arena.reset();
+    std::vector<int> rc(1, FL_OK);
+    try {
+      fl::solve_group(&p, &prm, &out, 1, (hipStream_t)stream, w.dc, rc);
+    } catch (fl::Error &e) {
+      rc[0] = e.code;
+    } catch (std::bad_alloc &) {
+      rc[0] = FL_ENOMEM;
+    }
+    if (rc[0] != FL_OK) {
+      // work enqueued before the failure may still read the array: it must
+      // end before the next call may use it
+      (void)hipStreamSynchronize((hipStream_t)stream);
+      out->n_open = 0;
+    }
     out->status = rc[0];
     return rc[0];
   } catch (fl::Error &e) {

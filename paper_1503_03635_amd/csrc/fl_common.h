@@ -336,10 +336,19 @@ __device__ inline void seg_max(unsigned long long *ctr, bool valid, uint32_t g, 
 // ---------------------------------------------------------------------------
 inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 
-// A bump arena over one cached device allocation.
+// A bump arena over one cached device allocation, or over a fixed buffer
+// the arena does not own (attach): that one never grows, and running out of
+// it throws FL_ENOMEM before any pointer past its end is handed out.
 class Arena {
  public:
   void reserve(size_t bytes);
+  void attach(char *base, size_t cap) {
+    base_ = base;
+    cap_ = cap;
+    used_ = peak_ = 0;
+    fixed_ = true;
+  }
+  bool fixed() const { return fixed_; }
   void reset() { used_ = 0; }
   void rewind(size_t mark) { used_ = mark; }
   template <class T>
@@ -362,12 +371,14 @@ class Arena {
  private:
   char *base_ = nullptr;
   size_t cap_ = 0, used_ = 0, peak_ = 0;
+  bool fixed_ = false;
 };
 
 // Per-call context: stream, arena, pinned host scratch for status readbacks.
 struct Ctx {
   hipStream_t s = nullptr;
   Arena *arena = nullptr;
+  bool timing = true;            // per-phase HIP events (none when false)
   uint64_t *h_status = nullptr;  // pinned, 4096 u64
   uint64_t *d_status = nullptr;  // device, 4096 u64
   void sync() { FL_HIP(hipStreamSynchronize(s)); }
