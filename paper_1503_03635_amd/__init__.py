@@ -16,7 +16,7 @@ from . import _lib
 from ._lib import (FL_FLAG_DIRECTED, FL_FLAG_LUBY_MIS, FL_FLAG_NO_DENSE, FL_NONE, FL_NOT_FACILITY, FL_RUNG_END, FL_RUNG_GUARD,
                    FL_RUNG_NONE, FlError, lib)
 
-__all__ = ["DeviceGraph", "to_device", "solve", "solve_batch", "Server", "ads_build", "rank_of", "priority_of",
+__all__ = ["DeviceGraph", "to_device", "solve", "solve_static", "release_workspace", "solve_batch", "Server", "ads_build", "rank_of", "priority_of",
            "use_torch_allocator",
            "FlError", "FL_NONE", "FL_NOT_FACILITY", "FL_RUNG_NONE", "FL_RUNG_GUARD", "FL_RUNG_END",
            "FL_FLAG_NO_DENSE", "FL_FLAG_LUBY_MIS", "FL_FLAG_DIRECTED", "lib"]
@@ -264,6 +264,12 @@ def use_torch_allocator(enable: bool = True):
     if rc != _lib.FL_OK:
         raise FlError(rc, "fl_set_allocator")
     _hooks = hooks
+
+
+def release_workspace():
+    """fl_release_workspace: frees the library's cached workspaces on the
+    current device."""
+    lib().fl_release_workspace()
 
 
 def ads_build(dg: DeviceGraph, k: int, seed: int, flags: int = 0, stream=None):

@@ -20,6 +20,15 @@
 // sets in scratch; a merge wave prunes their union (the prune is associative
 // and idempotent, so the split does not change the result).
 //
+// Level records and arc planes.  The level a vertex commits at distance D is
+// described in slot D % NS of its record ring (start, count and its two
+// smallest ranks), so a level of one or two entries needs no further read and
+// a level whose smallest rank fails the reader's threshold is skipped whole.
+// In rounds run from worklists, the committing vertex also sets, for each arc
+// it marks, the bit of the arc's position in the head's in-arc row in the
+// bit plane of the round the level reaches the head; a task then reads only
+// the arcs whose bits are set instead of every in-arc.
+//
 // Level prune.  A candidate of level D is accepted iff fewer than k ranks
 // below its own belong to entries that come first: the sketch so far, or
 // level-D candidates with a smaller vertex id (ties in distance go by id).
@@ -56,6 +65,10 @@ constexpr uint32_t TASK_ARCS = 1024;  // arcs per task of a split vertex in dens
 // the merge prunes the union exactly).
 constexpr uint32_t TASK_ARCS_SPARSE = 2048;
 static_assert(TASK_ARCS_SPARSE >= TASK_ARCS, "scratch slots are sized for TASK_ARCS");
+// With arc bit planes a task reads only the arcs that carry a level, so its
+// cost follows those, not its length: rows are cut far less often.
+constexpr uint32_t TASK_ARCS_FLAGGED = 8192;
+static_assert(TASK_ARCS_FLAGGED >= TASK_ARCS, "scratch slots are sized for TASK_ARCS");
 constexpr uint32_t NBKT = 64;       // id buckets of the level prune (one per lane)
 constexpr uint32_t LONG_LIST = 64;  // entry lists at least this long are streamed one arc at a time
 
@@ -76,13 +89,20 @@ struct AdsArgs {
   uint32_t *sk_dist;
   uint32_t *bk;
   uint32_t *cnt;
-  uint64_t *dinfo;
+  uint4 *lvl;          // [NS * n] level records, slot (D % NS) of each vertex
   uint32_t *flags;
   uint32_t *wl;
   uint32_t *wl_cnt;
+  // arc bit planes of the rounds run from worklists (nullptr: scan every in-arc)
+  uint32_t *plane;            // [NS * pw] bit of in-arc position p set in plane D % NS: a level reaches it in round D
+  uint64_t pw;                // words per plane
+  const uint32_t *out_to_in;  // [m] out-arc -> in-arc position
   uint32_t *kept;      // [slots * ADS_SB] kept ids of split tasks
   uint32_t *kept_cnt;  // [slots]
-  uint64_t *ctr;       // [64] relax_exec, [64] active vertices this round, [64] survivors, [64] prunes
+  uint64_t *ctr;       // [64] relax_exec, [64] active vertices this round, [64] survivors, [64] prunes,
+                       // with dbg also [64] arcs scanned, [64] level records matched, [64] arcs
+                       // examined for marking, [64] targets that passed the marking filter
+  uint32_t dbg;
   uint32_t *status;    // [0] capacity overflow, [1] survivor-buffer overflow
   uint32_t *thr;             // [rows * cap] threshold rows: canonical-order ranks until the last pass
   const uint32_t *thr_idx;   // [n] threshold row of each vertex (INF32 = none); nullptr = row u
@@ -92,8 +112,14 @@ __device__ inline uint32_t thr_row(const AdsArgs &P, uint32_t u) {
   return P.thr ? (P.thr_idx ? P.thr_idx[u] : u) : INF32;
 }
 
-__device__ inline uint64_t pack_info(uint32_t round, uint32_t start, uint32_t count) {
-  return ((uint64_t)round << 32) | ((uint64_t)start << 16) | (uint64_t)count;
+// The level a vertex committed at distance D stays in slot D % NS until the
+// level at D + NS reuses it: {D, its smallest rank, its second smallest rank
+// (INF32 for a single entry), start | count << 16}.  A level is stored in
+// increasing rank order, so a reader whose threshold is at most the smallest
+// rank skips it whole, and a level of one or two entries is read from the
+// record alone.
+__device__ inline uint4 level_record(uint32_t D, uint32_t r0, uint32_t r1, uint32_t start, uint32_t count) {
+  return make_uint4(D, r0, r1, start | (count << 16));
 }
 
 // Append y to the worklist of slot s once (flag bit per (vertex, slot)).
@@ -125,20 +151,34 @@ __device__ inline void mark_targets(const AdsArgs &P, bool want, uint32_t y, uin
   }
 }
 
+// u committed a level at distance D: queue each head y of an arc u -> y for
+// round D + w, and set the arc's bit in that round's plane.
 template <bool UNITW>
 __device__ inline void mark_neighbours(const AdsArgs &P, uint32_t u, uint32_t D) {
   const int lane = lane_id();
   const uint64_t a0 = P.out_ptr[u], a1 = P.out_ptr[u + 1];
   for (uint64_t b = a0; b < a1; b += WAVE) {
     const uint64_t a = b + lane;
-    const bool valid = a < a1;
+    bool want = a < a1;
     uint32_t y = 0, s = 0;
-    if (valid) {
+    if (want) {
       y = P.out_col[a];
       const uint32_t wv = UNITW ? 1u : P.out_w[a];
       s = (D + wv) % P.NS;
+      if (P.plane) {
+        const uint32_t p = P.out_to_in[a];
+        atomicOr(&P.plane[(size_t)s * P.pw + (p >> 5)], 1u << (p & 31));
+      }
     }
-    mark_targets<UNITW>(P, valid, y, s);
+    if (P.dbg) {
+      const uint64_t wm = __ballot(want);
+      if (lane == 0) {
+        atomicAdd((unsigned long long *)&P.ctr[384 + (blockIdx.x & 63)],
+                  (unsigned long long)(a1 - b < WAVE ? a1 - b : WAVE));
+        atomicAdd((unsigned long long *)&P.ctr[448 + (blockIdx.x & 63)], (unsigned long long)__popcll(wm));
+      }
+    }
+    mark_targets<UNITW>(P, want, y, s);
   }
 }
 
@@ -157,7 +197,7 @@ __global__ __launch_bounds__(256) void k_ads_init(AdsArgs P, int mark) {
     if (tr != INF32) P.thr[(size_t)tr * P.cap] = r;
     P.bk[(size_t)u * P.k] = r;
     P.cnt[u] = 1;
-    P.dinfo[u] = pack_info(0, 0, 1);  // slot 0
+    P.lvl[u] = level_record(0, r, INF32, 0, 1);  // slot 0
   }
   if (mark) mark_neighbours<UNITW>(P, u, 0);
 }
@@ -420,6 +460,7 @@ struct Level {
   RankMap rm;            // ranks and id buckets of u's graph
   bool overflow;
   uint32_t nsurv, nprune;  // statistics
+  uint32_t nmatch;         // level records found (per lane; with dbg only)
 };
 
 __device__ inline void level_init(const AdsArgs &P, uint32_t u, Level &L, uint32_t *s_cnt) {
@@ -436,7 +477,7 @@ __device__ inline void level_init(const AdsArgs &P, uint32_t u, Level &L, uint32
   L.ns = 0;
   L.tb = L.T0;
   L.overflow = false;
-  L.nsurv = L.nprune = 0;
+  L.nsurv = L.nprune = L.nmatch = 0;
 }
 
 // One candidate per lane (valid, rank r, id if known): keep it if its rank is
@@ -488,26 +529,42 @@ __device__ inline void level_offer(const AdsArgs &P, Level &L, bool valid, uint3
   wave_lds_sync();
 }
 
-// Stream the candidates of arcs [a0, a1) of u for level D.
+// One in-arc per lane (arc index a, valid): the level each arc's tail
+// committed at distance D - w is offered to u's level D.  Levels of one or
+// two entries come from the record; longer ones from the tail's sketch row,
+// the whole wave on one list at a time when it is long (a level is stored in
+// increasing rank order, so once a rank reaches T0 the rest cannot enter).
 template <bool UNITW>
-__device__ inline uint64_t gather_arcs(const AdsArgs &P, uint32_t D, uint64_t a0, uint64_t a1, Level &L,
-                                       uint32_t *s_id, uint32_t *s_tmp, uint32_t *s_cnt) {
+__device__ inline uint64_t gather_batch(const AdsArgs &P, uint32_t D, uint64_t a, bool valid, Level &L,
+                                        uint32_t *s_id, uint32_t *s_tmp, uint32_t *s_cnt) {
   const int lane = lane_id();
   uint64_t examined = 0;
-  for (uint64_t b = a0; b < a1 && !L.overflow; b += WAVE) {
-    const uint64_t a = b + lane;
-    uint32_t v = 0, st = 0, cn = 0;
-    if (a < a1) {
+  {
+    uint32_t v = 0, st = 0, cn = 0, r0 = INF32, r1 = INF32;
+    if (valid) {
       v = P.col[a];
       const uint32_t wv = UNITW ? 1u : P.w[a];
       if (wv <= D) {
         const uint32_t src = D - wv;
-        const uint64_t info = P.dinfo[(size_t)(src % P.NS) * P.n + v];
-        if ((uint32_t)(info >> 32) == src) {
-          st = (uint32_t)(info >> 16) & 0xFFFFu;
-          cn = (uint32_t)info & 0xFFFFu;
+        const uint4 rec = P.lvl[(size_t)(src % P.NS) * P.n + v];
+        // a level whose smallest rank is not below T0 has nothing for u
+        if (P.dbg && rec.x == src) ++L.nmatch;
+        if (rec.x == src && (!L.full0 || rec.y < L.T0)) {
+          r0 = rec.y;
+          r1 = rec.z;
+          st = rec.w & 0xFFFFu;
+          cn = rec.w >> 16;
         }
       }
+    }
+    // levels of one or two entries: the ranks are in the record
+    {
+      const bool one = cn != 0 && cn <= 2;
+      const bool two = cn == 2;
+      examined += __popcll(__ballot(one)) + __popcll(__ballot(two));
+      level_offer(P, L, one, r0, false, 0, s_id, s_tmp, s_cnt);
+      if (__ballot(two) && !L.overflow) level_offer(P, L, two, r1, false, 0, s_id, s_tmp, s_cnt);
+      if (cn <= 2) cn = 0;
     }
     // long lists: one arc at a time, the whole wave on its list, four loads in
     // flight.  A level is stored in increasing rank order, so once a rank
@@ -526,14 +583,25 @@ __device__ inline uint64_t gather_arcs(const AdsArgs &P, uint32_t D, uint64_t a0
         const uint32_t r1 = i1 < cnj ? src[i1] : INF32;
         const uint32_t r2 = i2 < cnj ? src[i2] : INF32;
         const uint32_t r3 = i3 < cnj ? src[i3] : INF32;
-        examined += cnj - c0 < 4 * WAVE ? cnj - c0 : 4 * WAVE;
+        // entries offered (a block past the stop test is loaded, not counted)
+        const uint32_t left = cnj - c0;
+        examined += left < WAVE ? left : WAVE;
         level_offer(P, L, i0 < cnj, r0, false, 0, s_id, s_tmp, s_cnt);
         if (L.full0 && __ballot(i0 < cnj && r0 >= L.T0)) break;
-        if (c0 + WAVE < cnj) level_offer(P, L, i1 < cnj, r1, false, 0, s_id, s_tmp, s_cnt);
+        if (c0 + WAVE < cnj) {
+          examined += left - WAVE < WAVE ? left - WAVE : WAVE;
+          level_offer(P, L, i1 < cnj, r1, false, 0, s_id, s_tmp, s_cnt);
+        }
         if (L.full0 && __ballot(i1 < cnj && r1 >= L.T0)) break;
-        if (c0 + 2 * WAVE < cnj) level_offer(P, L, i2 < cnj, r2, false, 0, s_id, s_tmp, s_cnt);
+        if (c0 + 2 * WAVE < cnj) {
+          examined += left - 2 * WAVE < WAVE ? left - 2 * WAVE : WAVE;
+          level_offer(P, L, i2 < cnj, r2, false, 0, s_id, s_tmp, s_cnt);
+        }
         if (L.full0 && __ballot(i2 < cnj && r2 >= L.T0)) break;
-        if (c0 + 3 * WAVE < cnj) level_offer(P, L, i3 < cnj, r3, false, 0, s_id, s_tmp, s_cnt);
+        if (c0 + 3 * WAVE < cnj) {
+          examined += left - 3 * WAVE < WAVE ? left - 3 * WAVE : WAVE;
+          level_offer(P, L, i3 < cnj, r3, false, 0, s_id, s_tmp, s_cnt);
+        }
         if (L.full0 && __ballot(i3 < cnj && r3 >= L.T0)) break;
       }
     }
@@ -563,6 +631,70 @@ __device__ inline uint64_t gather_arcs(const AdsArgs &P, uint32_t D, uint64_t a0
   return examined;
 }
 
+// Stream the candidates of arcs [a0, a1) of u for level D (every in-arc is
+// looked at: rounds run over the dense vertex list).
+template <bool UNITW>
+__device__ inline uint64_t gather_arcs(const AdsArgs &P, uint32_t D, uint64_t a0, uint64_t a1, Level &L,
+                                       uint32_t *s_id, uint32_t *s_tmp, uint32_t *s_cnt) {
+  const int lane = lane_id();
+  uint64_t examined = 0;
+  for (uint64_t b = a0; b < a1 && !L.overflow; b += WAVE)
+    examined += gather_batch<UNITW>(P, D, b + lane, b + lane < a1, L, s_id, s_tmp, s_cnt);
+  return examined;
+}
+
+// Rounds run from worklists: a tail that committed a level set the bit of
+// each arc it marked, at the arc's position in the in-arc rows, in the plane
+// of the round the level reaches the head.  Only those arcs of [a0, a1) are
+// read: 64 plane words per step, their set bits compacted over the wave.
+template <bool UNITW>
+__device__ inline uint64_t gather_flagged(const AdsArgs &P, uint32_t D, uint64_t a0, uint64_t a1, Level &L,
+                                          uint32_t *s_id, uint32_t *s_tmp, uint32_t *s_cnt) {
+  const int lane = lane_id();
+  const uint32_t *plane = P.plane + (size_t)(D % P.NS) * P.pw;
+  const uint64_t w0 = a0 >> 5, w1 = (a1 + 31) >> 5;
+  uint64_t examined = 0;
+  for (uint64_t wb = w0; wb < w1 && !L.overflow; wb += WAVE) {
+    const uint64_t wi = wb + lane;
+    uint32_t bits = 0;
+    if (wi < w1) {
+      bits = plane[wi];
+      const uint64_t base = wi << 5;  // arcs [base, base + 32) of this word
+      if (base < a0) bits &= ~0u << (uint32_t)(a0 - base);
+      if (a1 - base < 32) bits &= (1u << (uint32_t)(a1 - base)) - 1u;
+    }
+    const uint32_t nb = (uint32_t)__popc(bits);
+    const uint32_t incl = wave_scan_incl(nb);
+    const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
+    for (uint32_t c0 = 0; c0 < total && !L.overflow; c0 += WAVE) {
+      const uint32_t idx = c0 + lane;
+      uint32_t pos = 0;  // word (lane) holding set bit idx: first lane whose inclusive count exceeds idx
+#pragma unroll
+      for (uint32_t sh = 32; sh >= 1; sh >>= 1) {
+        const uint32_t val = __shfl(incl, (int)(pos + sh - 1), WAVE);
+        if (val <= idx) pos += sh;
+      }
+      const bool valid = idx < total;
+      const uint32_t src = valid ? pos : 0u;
+      uint32_t x = __shfl(bits, (int)src, WAVE);
+      uint32_t kth = idx - (__shfl(incl, (int)src, WAVE) - (uint32_t)__popc(x));
+      uint32_t bit = 0;  // position of the kth set bit of x
+#pragma unroll
+      for (uint32_t sh = 16; sh >= 1; sh >>= 1) {
+        const uint32_t cnt = (uint32_t)__popc(x & ((1u << sh) - 1u));
+        if (kth >= cnt) {
+          kth -= cnt;
+          x >>= sh;
+          bit += sh;
+        }
+      }
+      const uint64_t a = ((wb + src) << 5) + bit;
+      examined += gather_batch<UNITW>(P, D, a, valid, L, s_id, s_tmp, s_cnt);
+    }
+  }
+  return examined;
+}
+
 // Final prune of u's level-D candidates and the append of the accepted ones.
 template <bool UNITW>
 __device__ inline void level_commit(const AdsArgs &P, uint32_t u, uint32_t D, Level &L, int mark, uint32_t *s_id,
@@ -586,6 +718,7 @@ __device__ inline void level_commit(const AdsArgs &P, uint32_t u, uint32_t D, Le
     for (uint32_t i = lane; i < m; i += WAVE) trow[i] = rank_of(s_tmp[i], L.rm);
   }
   const size_t base = (size_t)u * P.cap + cu;
+  uint32_t x0, x1;  // the two smallest ranks of the level, for its record
   if (m <= (uint32_t)WAVE) {
     uint32_t x = (uint32_t)lane < m ? rank_of(s_tmp[lane], L.rm) : INF32;
     x = wave_sort_reg(x);
@@ -593,6 +726,8 @@ __device__ inline void level_commit(const AdsArgs &P, uint32_t u, uint32_t D, Le
       P.sk_rank[base + lane] = x;
       P.sk_dist[base + lane] = D;
     }
+    x0 = __shfl(x, 0, WAVE);
+    x1 = __shfl(x, 1, WAVE);
   } else {
     for (uint32_t i = lane; i < m; i += WAVE) s_id[i] = rank_of(s_tmp[i], L.rm);
     wave_sort_lds(s_id, m);  // m <= ADS_SB
@@ -600,11 +735,13 @@ __device__ inline void level_commit(const AdsArgs &P, uint32_t u, uint32_t D, Le
       P.sk_rank[base + i] = s_id[i];
       P.sk_dist[base + i] = D;
     }
+    x0 = s_id[0];
+    x1 = s_id[1];
   }
   if ((uint32_t)lane < nset) P.bk[(size_t)u * P.k + lane] = setv;
   if (lane == 0) {
     P.cnt[u] = cu + m;
-    P.dinfo[(size_t)(D % P.NS) * P.n + u] = pack_info(D, cu, m);
+    P.lvl[(size_t)(D % P.NS) * P.n + u] = level_record(D, x0, x1, cu, m);
     atomicAdd((unsigned long long *)&P.ctr[64 + (blockIdx.x & 63)], 1ull);
   }
   if (mark) mark_neighbours<UNITW>(P, u, D);
@@ -641,11 +778,19 @@ __global__ __launch_bounds__(TASK_WPB * WAVE) void k_ads_tasks(AdsArgs P, uint32
     a0 = r0 + (uint64_t)sub * task_arcs;
     a1 = a0 + task_arcs < r1 ? a0 + task_arcs : r1;
   }
-  const uint64_t examined = gather_arcs<UNITW>(P, D, a0, a1, L, s_id, s_tmp, s_cnt);
+  const uint64_t examined = (sparse && P.plane) ? gather_flagged<UNITW>(P, D, a0, a1, L, s_id, s_tmp, s_cnt)
+                                                 : gather_arcs<UNITW>(P, D, a0, a1, L, s_id, s_tmp, s_cnt);
   if (lane == 0) {
     atomicAdd((unsigned long long *)&P.ctr[blockIdx.x & 63], (unsigned long long)examined);
     atomicAdd((unsigned long long *)&P.ctr[128 + (blockIdx.x & 63)], (unsigned long long)L.nsurv);
     atomicAdd((unsigned long long *)&P.ctr[192 + (blockIdx.x & 63)], (unsigned long long)L.nprune);
+  }
+  if (P.dbg) {
+    const uint64_t nm = wave_sum_u64(L.nmatch);
+    if (lane == 0) {
+      atomicAdd((unsigned long long *)&P.ctr[256 + (blockIdx.x & 63)], (unsigned long long)(a1 - a0));
+      atomicAdd((unsigned long long *)&P.ctr[320 + (blockIdx.x & 63)], (unsigned long long)nm);
+    }
   }
   if (L.overflow) {
     if (lane == 0) atomicOr(&P.status[1], 1u);
@@ -853,6 +998,29 @@ static void build_tasks(Ctx &c, const Graph &g, const uint32_t *list, uint32_t c
   tl.nsplit = (uint32_t)h[2];
 }
 
+// Undirected graph: the position of each arc (v, y) within row y, i.e. of the
+// reverse arc (y, v) (rows are sorted and free of repeats, validated).
+__global__ void k_reverse_arcs(uint32_t n, uint64_t m, const uint64_t *row_ptr, const uint32_t *col,
+                               uint32_t *out_to_in) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; a < m; a += stride) {
+    uint32_t lo = 0, hi = n;  // tail: row_ptr[lo] <= a < row_ptr[hi]
+    while (hi - lo > 1) {
+      const uint32_t mid = lo + ((hi - lo) >> 1);
+      if (row_ptr[mid] <= a) lo = mid;
+      else hi = mid;
+    }
+    const uint32_t y = col[a];
+    uint64_t b0 = row_ptr[y], b1 = row_ptr[y + 1];  // first position in row y with col >= lo
+    while (b0 < b1) {
+      const uint64_t mid = b0 + ((b1 - b0) >> 1);
+      if (col[mid] < lo) b0 = mid + 1;
+      else b1 = mid;
+    }
+    out_to_in[a] = (uint32_t)b0;
+  }
+}
+
 // list of vertices with at least one in-arc
 __global__ void k_nonisolated_flags(uint32_t n, const uint64_t *row_ptr, uint32_t *flag) {
   uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -905,7 +1073,8 @@ size_t ads_scratch_bytes(uint32_t n, uint64_t m, uint32_t k, uint32_t NS) {
   const uint64_t tasks = (uint64_t)n + m / TASK_ARCS + 64;
   size_t b = 0;
   b += (size_t)n * k * 4;                  // bottom-k sets
-  b += (size_t)NS * n * (8 + 4);           // per-slot entry index + worklists
+  b += (size_t)NS * n * (16 + 4);          // per-slot level records + worklists
+  b += (size_t)m * 4 + (size_t)NS * (m / 32 + 2) * 4;  // reverse-arc positions, arc bit planes
   b += (size_t)n * FW * 4;                 // worklist flags
   b += (size_t)slots * (ADS_SB + 1) * 4;   // kept sets of split tasks
   b += (size_t)tasks * 4 * 3 * 2 + (size_t)n * 4 * 3 * 2;  // two task lists
@@ -943,18 +1112,37 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
   P.sk_dist = o.sk_dist;
   P.bk = c.arena->get<uint32_t>((size_t)n * k);
   P.cnt = o.cnt;
-  P.dinfo = c.arena->get<uint64_t>((size_t)NS * n);
+  P.lvl = c.arena->get<uint4>((size_t)NS * n);
   P.flags = c.arena->get<uint32_t>((size_t)n * FW);
   P.wl = c.arena->get<uint32_t>((size_t)NS * n);
   P.wl_cnt = c.arena->get<uint32_t>(NS);
-  P.ctr = c.arena->get<uint64_t>(256);
+  P.ctr = c.arena->get<uint64_t>(512);
+  P.dbg = std::getenv("FL_DEBUG") ? 1u : 0u;
   P.status = c.arena->get<uint32_t>(4);
   P.thr = o.thr;
   P.thr_idx = o.thr ? cfg.thr_idx : nullptr;
-  fill_u64(c, P.dinfo, (size_t)NS * n, INF64);
+  // arc bit planes for the rounds run from worklists (arc positions must fit 32 bits)
+  const bool planes = g.m > 0 && g.m < 0xFFFFFFFFull;
+  P.plane = nullptr;
+  P.pw = g.m / 32 + 2;
+  P.out_to_in = nullptr;
+  if (planes) {
+    P.plane = c.arena->get<uint32_t>((size_t)NS * P.pw);
+    fill_u32(c, P.plane, (size_t)NS * P.pw, 0);
+    if (g.out_to_in) {
+      P.out_to_in = g.out_to_in;
+    } else {
+      uint32_t *o2i = c.arena->get<uint32_t>(g.m);
+      const uint32_t blocks = (uint32_t)std::min<uint64_t>(ceil_div(g.m, 256), 16384);
+      k_reverse_arcs<<<blocks, 256, 0, c.s>>>(n, g.m, g.row_ptr, g.col, o2i);
+      FL_LAUNCH_CHECK();
+      P.out_to_in = o2i;
+    }
+  }
+  fill_u64(c, reinterpret_cast<uint64_t *>(P.lvl), (size_t)NS * n * 2, INF64);  // no level anywhere
   fill_u32(c, P.flags, (size_t)n * FW, 0);
   fill_u32(c, P.wl_cnt, NS, 0);
-  fill_u64(c, P.ctr, 256, 0);
+  fill_u64(c, P.ctr, 512, 0);
   fill_u32(c, P.status, 4, 0);
 
   // scratch slots: enough for every vertex split at once
@@ -1053,7 +1241,7 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
         c.sync();
         count = (uint32_t)(c.h_status[0] & 0xFFFFFFFFu);
       }
-      build_tasks(c, g, P.wl + (size_t)slot * n, count, TASK_ARCS_SPARSE, ts, tl);
+      build_tasks(c, g, P.wl + (size_t)slot * n, count, P.plane ? TASK_ARCS_FLAGGED : TASK_ARCS_SPARSE, ts, tl);
       T = &tl;
     }
     // marking decision for this round (decides the mode of the next one)
@@ -1083,6 +1271,8 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
       if (c.timing) FL_HIP(hipEventRecord(e1, c.s));
     }
     if (sparse) fill_u32(c, P.wl_cnt + slot, 1, 0);
+    // the plane of this round is read; commits of later rounds refill it
+    if (P.plane) fill_u32(c, P.plane + (size_t)slot * P.pw, P.pw, 0);
     ++rounds;
     FL_HIP(hipMemcpyAsync(c.h_status, P.status, 8, hipMemcpyDeviceToHost, c.s));
     FL_HIP(hipMemcpyAsync(c.h_status + 1, P.ctr + 64, 64 * 8, hipMemcpyDeviceToHost, c.s));
@@ -1099,20 +1289,25 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
       o.merge_ms += ms2;
       o.launches += 1;
       if (std::getenv("FL_DEBUG")) {
-        std::vector<uint64_t> hs(256);
-        FL_HIP(hipMemcpy(hs.data(), P.ctr, 256 * 8, hipMemcpyDeviceToHost));
-        uint64_t ex = 0, sv = 0, pr = 0;
+        std::vector<uint64_t> hs(512);
+        FL_HIP(hipMemcpy(hs.data(), P.ctr, 512 * 8, hipMemcpyDeviceToHost));
+        uint64_t ex = 0, sv = 0, pr = 0, sc = 0, mt = 0, ma = 0, mp = 0;
         for (int i = 0; i < 64; ++i) {
           ex += hs[i];
           sv += hs[128 + i];
           pr += hs[192 + i];
+          sc += hs[256 + i];
+          mt += hs[320 + i];
+          ma += hs[384 + i];
+          mp += hs[448 + i];
         }
         uint64_t act = 0;
         for (int i = 0; i < 64; ++i) act += hs[64 + i];
-        std::fprintf(stderr, "[fl] round %u: %s, %u tasks, %u split, %llu changed, %.2f ms, examined(cum) %.3fG "
-                     "survivors(cum) %.3fG prunes(cum) %.3fM\n",
-                     D, sparse ? "sparse" : "dense", T->ntasks, T->nsplit, (unsigned long long)act, ms, ex / 1e9,
-                     sv / 1e9, pr / 1e6);
+        std::fprintf(stderr, "[fl] round %u: %s, %u tasks, %u split, %llu changed, %.2f ms, merge %.2f ms, "
+                     "examined(cum) %.3fG survivors(cum) %.3fG prunes(cum) %.3fM scanned(cum) %.3fG "
+                     "matched(cum) %.3fG markarcs(cum) %.3fG marked(cum) %.3fG\n",
+                     D, sparse ? "sparse" : "dense", T->ntasks, T->nsplit, (unsigned long long)act, ms, ms2,
+                     ex / 1e9, sv / 1e9, pr / 1e6, sc / 1e9, mt / 1e9, ma / 1e9, mp / 1e9);
       }
     }
     const uint32_t st0 = (uint32_t)(c.h_status[0] & 0xFFFFFFFFu);

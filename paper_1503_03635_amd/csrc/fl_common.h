@@ -408,6 +408,9 @@ struct Graph {
   const uint64_t *in_ptr = nullptr;
   const uint32_t *in_col = nullptr;
   const uint32_t *in_w = nullptr;
+  // out-arc a -> its position in the in-arc rows (directed graphs: filled by
+  // set_in_arcs; undirected: nullptr, the sketch rounds derive it)
+  const uint32_t *out_to_in = nullptr;
 };
 
 // fill / utility launches (fl_graph.hip)

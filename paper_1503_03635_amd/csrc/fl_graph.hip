@@ -319,7 +319,7 @@ __global__ void k_in_degree(uint64_t m, const uint32_t *col, uint32_t *deg) {
 // every col < n, so the tail search stays in [0, n) and p < in_ptr[v + 1].
 __global__ void k_in_scatter(uint32_t n, uint64_t m, const uint64_t *row_ptr, const uint32_t *col,
                              const uint32_t *w, const uint64_t *in_ptr, uint32_t *cur, uint32_t *in_col,
-                             uint32_t *in_w) {
+                             uint32_t *in_w, uint32_t *out_to_in) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; a < m; a += stride) {
     uint32_t lo = 0, hi = n;  // row_ptr[lo] <= a < row_ptr[hi]
@@ -332,11 +332,12 @@ __global__ void k_in_scatter(uint32_t n, uint64_t m, const uint64_t *row_ptr, co
     const uint64_t p = in_ptr[v] + atomicAdd(&cur[v], 1u);
     in_col[p] = lo;
     if (w) in_w[p] = w[a];
+    if (out_to_in) out_to_in[a] = (uint32_t)p;
   }
 }
 
 size_t transpose_bytes(uint32_t n, uint64_t m, bool weighted) {
-  return (size_t)(n + 1) * 8 + (size_t)n * 4 + (size_t)m * (weighted ? 8 : 4) + ((size_t)1 << 20);
+  return (size_t)(n + 1) * 8 + (size_t)n * 4 + (size_t)m * (weighted ? 12 : 8) + ((size_t)1 << 20);
 }
 
 void set_in_arcs(Ctx &c, Graph &g, bool directed) {
@@ -352,6 +353,8 @@ void set_in_arcs(Ctx &c, Graph &g, bool directed) {
   uint64_t *ip = c.arena->get<uint64_t>((size_t)n + 1);
   uint32_t *ic = c.arena->get<uint32_t>(m ? m : 1);
   uint32_t *iw = g.w ? c.arena->get<uint32_t>(m ? m : 1) : nullptr;
+  // arc positions fit 32 bits below 2^32 arcs; beyond, the sketch rounds scan every in-arc
+  uint32_t *o2i = m < 0xFFFFFFFFull ? c.arena->get<uint32_t>(m ? m : 1) : nullptr;
   fill_u32(c, deg, n, 0);
   const uint32_t blocks = (uint32_t)std::min<uint64_t>(ceil_div(m ? m : 1, 256), 16384);
   if (m) {
@@ -361,12 +364,13 @@ void set_in_arcs(Ctx &c, Graph &g, bool directed) {
   scan_u32_to_u64(c, deg, ip, n);
   fill_u32(c, deg, n, 0);  // now the per-row cursor
   if (m) {
-    k_in_scatter<<<blocks, 256, 0, c.s>>>(n, m, g.row_ptr, g.col, g.w, ip, deg, ic, iw);
+    k_in_scatter<<<blocks, 256, 0, c.s>>>(n, m, g.row_ptr, g.col, g.w, ip, deg, ic, iw, o2i);
     FL_LAUNCH_CHECK();
   }
   g.in_ptr = ip;
   g.in_col = ic;
   g.in_w = iw;
+  g.out_to_in = o2i;
 }
 
 // ---------------------------------------------------------------------------

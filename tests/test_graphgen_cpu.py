@@ -43,3 +43,41 @@ def test_rmat_weighted_fac10_is_seeded():
     c = gg.rmat_weighted_fac10(9, 8, 6)
     assert np.array_equal(a.col, b.col) and np.array_equal(a.w, b.w) and np.array_equal(a.fac_cost, b.fac_cost)
     assert not (np.array_equal(a.col, c.col) and np.array_equal(a.fac_cost, c.fac_cost))
+
+
+# ---------------------------------------------------------------- device generators (run on CPU tensors here)
+def test_device_rmat_weighted_recipe():
+    """The device R-MAT of the large weighted recipe is a valid symmetric CSR
+    (checked by the oracle's validator), equal weights on both arcs of an edge,
+    weights in 1..100, an exact 10% of facilities with lognormal costs, and the
+    same arrays for the same seed."""
+    import torch
+    import graphgen.device as gd
+    import oracle as O
+    a = gd.rmat_weighted_fac10(12, 32, 3, device="cpu")
+    b = gd.rmat_weighted_fac10(12, 32, 3, device="cpu")
+    assert torch.equal(a.col, b.col) and torch.equal(a.w, b.w) and torch.equal(a.fac_cost, b.fac_cost)
+    g = gd.to_host(a)
+    assert O.validate(g, 8, 0.1) == O.OK
+    assert g.w.min() >= 1 and g.w.max() <= 100
+    isF = g.fac_cost != gg.NOT_FACILITY
+    assert isF.sum() == round(0.1 * g.n)
+    c = g.fac_cost[isF].astype(np.float64)
+    assert c.min() >= 1 and 4.5 < np.log(c).mean() < 5.5
+    assert g.n == 1 << 12 and 20 < g.n_arcs / g.n < 32
+    c2 = gd.to_host(gd.rmat_weighted_fac10(12, 32, 4, device="cpu"))
+    assert not np.array_equal(c2.col[:1000], g.col[:1000])
+
+
+def test_device_directed_and_batch_generators():
+    """Directed R-MAT keeps arcs (no symmetry needed, validated as directed);
+    the Chung-Lu batch gives valid graphs with n in range and weights 1..20."""
+    import graphgen.device as gd
+    import oracle as O
+    h = gd.to_host(gd.rmat_unit(10, 16, 2, directed=True, device="cpu"))
+    assert h.directed and O.validate(h, 4, 0.1) == O.OK
+    for dg in gd.powerlaw_batch(3, 5, n_lo=500, n_hi=5000, device="cpu"):
+        x = gd.to_host(dg)
+        assert 500 <= x.n <= 5000 and O.validate(x, 4, 0.1) == O.OK
+        assert x.w.min() >= 1 and x.w.max() <= 20
+        assert (x.fac_cost >= 1).all() and (x.fac_cost <= 1000).all()
