@@ -411,8 +411,8 @@ def mis_compare(seed):
                        ("rmat22_unit", lambda: gd.rmat_unit(22, 16, seed)),
                        ("forestfire10k_w1..100", lambda: fl.to_device(gg.with_problem(
                            gg.forest_fire(10000, seed, wmax=100), seed, cost="uniform"), "cuda:0")),
-                       ("forestfire30k_w1..100", lambda: fl.to_device(gg.with_problem(
-                           gg.forest_fire(30000, seed, wmax=100), seed, cost="uniform"), "cuda:0"))):
+                       ("forestfire20k_w1..100", lambda: fl.to_device(gg.with_problem(
+                           gg.forest_fire(20000, seed, wmax=100), seed, cost="uniform"), "cuda:0"))):
         dg = make()
         fixed, luby = point(dg, 0), point(dg, fl.FL_FLAG_LUBY_MIS)
         row = {"graph": name, "n": dg.n, "arcs": dg.n_arcs, "fixed": fixed, "luby": luby,
