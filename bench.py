@@ -529,7 +529,7 @@ def accuracy_experiment(ks, samples, seed):
 def sweep_experiment(seed):
     """Time vs k and vs eps (the paper's Fig. 3 and Fig. 4 on synthetic
     graphs): full solves of R-MAT 2^20 (16 edge samples per vertex, unit
-    weights, costs 1..1000) for k in {16, 32, 64} at eps = 0.1 and for eps in
+    weights, costs 1..1000) for k in {16, 32, 64, 128} at eps = 0.1 and for eps in
     {0.01, 0.1, 1} at k = 32, and the same eps sweep on a Forest Fire graph
     (n = 20,000, weights 1..100).  Each point: one untimed solve, then the
     median of three."""
@@ -556,7 +556,7 @@ def sweep_experiment(seed):
     g = gg.rmat_unit(20, 16, seed)
     dg = fl.to_device(g, "cuda:0")
     out["rmat20_unit"] = {"n": g.n, "arcs": g.n_arcs,
-                          "k_sweep": [point(dg, k, 0.1) for k in (16, 32, 64)],
+                          "k_sweep": [point(dg, k, 0.1) for k in (16, 32, 64, 128)],
                           "eps_sweep": [point(dg, 32, e) for e in (0.01, 0.1, 1.0)]}
     log(f"[sweep] rmat20: {out['rmat20_unit']}")
     g = gg.with_problem(gg.forest_fire(20000, seed, wmax=100), seed, cost="uniform")

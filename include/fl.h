@@ -46,7 +46,7 @@ extern "C" {
 #define FL_ENOMEM 3   /* workspace does not fit the device (or the budget) */
 #define FL_EHIP 4     /* a HIP runtime error; see fl_last_hip_error() */
 #define FL_EBUSY 5    /* server queue full (non-blocking submit) */
-#define FL_ENOTIMPL 6 /* a limit of this library: k > 64, max weight > 255,
+#define FL_ENOTIMPL 6 /* a limit of this library: k > 128, max weight > 255,
                          sketch capacity above 65535 entries per vertex */
 
 /* ---- sentinels ---------------------------------------------------------- */
@@ -75,7 +75,7 @@ typedef struct {
 
 /* ---- parameters ---------------------------------------------------------- */
 typedef struct {
-  uint32_t k;     /* bottom-k parameter of the sketches, 1 <= k <= 64 */
+  uint32_t k;     /* bottom-k parameter of the sketches, 1 <= k <= 128 */
   uint64_t seed;  /* seeds the vertex ranks and the MIS priorities */
   double eps;     /* accuracy parameter epsilon > 0 (the paper's runs use 0.1) */
   uint32_t flags; /* FL_FLAG_* below */

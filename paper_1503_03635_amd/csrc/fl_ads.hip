@@ -55,7 +55,8 @@ namespace fl {
 
 constexpr int TASK_WPB = 1;         // waves per block of the round kernels: a block's LDS is
                                     // freed when its own task ends (task lengths vary widely)
-constexpr uint32_t ADS_SB = 1024;   // survivor ids per wave: one level of one sketch plus a chunk
+constexpr uint32_t ADS_SB = 1024;   // survivor ids per wave and set register: one level of one sketch
+                                    // plus a chunk (twice that when k > 64)
 static_assert((ADS_SB & (ADS_SB - 1)) == 0, "wave_sort_lds pads to a power of two inside the buffer");
 constexpr uint32_t TASK_ARCS = 1024;  // arcs per task of a split vertex in dense rounds (the fewest)
 // Sparse rounds (worklists) cut only longer rows: there a hub is active in
@@ -97,7 +98,7 @@ struct AdsArgs {
   uint32_t *plane;            // [NS * pw] bit of in-arc position p set in plane D % NS: a level reaches it in round D
   uint64_t pw;                // words per plane
   const uint32_t *out_to_in;  // [m] out-arc -> in-arc position
-  uint32_t *kept;      // [slots * ADS_SB] kept ids of split tasks
+  uint32_t *kept;      // [slots * ADS_SB * KR] kept ids of split tasks
   uint32_t *kept_cnt;  // [slots]
   uint64_t *ctr;       // [64] relax_exec, [64] active vertices this round, [64] survivors, [64] prunes,
                        // with dbg also [64] arcs scanned, [64] level records matched, [64] arcs
@@ -245,6 +246,91 @@ __device__ inline uint32_t wave_sort_reg(uint32_t x) {
   return x;
 }
 
+// Merge of a bitonic sequence held one value per lane into ascending
+// (desc = false) or descending order.
+__device__ inline uint32_t wave_bitonic_merge(uint32_t x, bool desc) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int j = 32; j >= 1; j >>= 1) {
+    const uint32_t y = __shfl_xor(x, j, WAVE);
+    const bool lo = ((lane & j) == 0) != desc;
+    x = lo ? (x < y ? x : y) : (x > y ? x : y);
+  }
+  return x;
+}
+
+// Two ascending sequences a and b, one value per lane: lo receives the 64
+// smallest of both, hi the 64 largest, each ascending (the first step of a
+// bitonic merge splits them into two bitonic halves).
+__device__ inline void wave_merge2(uint32_t a, uint32_t b, uint32_t &lo, uint32_t &hi) {
+  const uint32_t br = __shfl(b, WAVE - 1 - lane_id(), WAVE);
+  lo = wave_bitonic_merge(a < br ? a : br, false);
+  hi = wave_bitonic_merge(a < br ? br : a, false);
+}
+
+// The running bottom-k set of a level: ascending, element i in register
+// i / 64 at lane i % 64, INF32 above its size.  One register holds k <= 64,
+// two hold k <= 128.
+template <int KR>
+struct KSet {
+  uint32_t v[KR];
+};
+
+// element i of the set (i per lane, below 64 KR)
+template <int KR>
+__device__ inline uint32_t kset_at(const KSet<KR> &s, uint32_t i) {
+  if (KR == 1) return __shfl(s.v[0], (int)i, WAVE);
+  const uint32_t a = __shfl(s.v[0], (int)(i & 63u), WAVE);
+  const uint32_t b = __shfl(s.v[KR - 1], (int)(i & 63u), WAVE);
+  return i < 64u ? a : b;
+}
+
+// number of set elements below the wave-uniform rank rj
+template <int KR>
+__device__ inline uint32_t kset_ballot_below(const KSet<KR> &s, uint32_t rj) {
+  uint32_t c = (uint32_t)__popcll(__ballot(s.v[0] < rj));
+  if (KR == 2) c += (uint32_t)__popcll(__ballot(s.v[KR - 1] < rj));
+  return c;
+}
+
+// insert the wave-uniform rank rj at position below, keeping k elements
+template <int KR>
+__device__ inline void kset_insert(KSet<KR> &s, uint32_t rj, uint32_t below, uint32_t k) {
+  const uint32_t lane = (uint32_t)lane_id();
+  const uint32_t up0 = __shfl_up(s.v[0], 1, WAVE);
+  if (KR == 2) {
+    const uint32_t last0 = __shfl(s.v[0], WAVE - 1, WAVE);
+    uint32_t up1 = __shfl_up(s.v[KR - 1], 1, WAVE);
+    if (lane == 0) up1 = last0;
+    const uint32_t e1 = 64u + lane;
+    if (e1 > below && e1 < k) s.v[KR - 1] = up1;
+    if (e1 == below) s.v[KR - 1] = rj;
+  }
+  if (lane > below && lane < k) s.v[0] = up0;
+  if (lane == below) s.v[0] = rj;
+}
+
+// the set becomes the k smallest of itself and the ascending chunk x
+// (INF32-padded)
+template <int KR>
+__device__ inline void kset_merge(KSet<KR> &s, uint32_t x, uint32_t k) {
+  const uint32_t lane = (uint32_t)lane_id();
+  if (KR == 1) {
+    const uint32_t y = __shfl(x, WAVE - 1 - (int)lane, WAVE);
+    uint32_t mm = s.v[0] < y ? s.v[0] : y;  // bitonic, holds the 64 smallest of both
+    mm = wave_bitonic_merge(mm, false);
+    s.v[0] = lane < k ? mm : INF32;
+  } else {
+    // the 64 smallest of everything lie in the lower half and the chunk; the
+    // next 64 in what is left of those and the upper half
+    uint32_t lo1, hi1, lo2, hi2;
+    wave_merge2(s.v[0], x, lo1, hi1);
+    wave_merge2(hi1, s.v[KR - 1], lo2, hi2);
+    s.v[0] = lane < k ? lo1 : INF32;
+    s.v[KR - 1] = 64u + lane < k ? lo2 : INF32;
+  }
+}
+
 // number of values below r in a set held one value per lane, ascending, with
 // INF32 above its size (per-lane r; every lane runs the shuffles)
 __device__ inline uint32_t set_count_below(uint32_t setv, uint32_t r) {
@@ -259,23 +345,33 @@ __device__ inline uint32_t set_count_below(uint32_t setv, uint32_t r) {
   return q;
 }
 
+// number of elements of the set below r (per-lane r)
+template <int KR>
+__device__ inline uint32_t kset_below(const KSet<KR> &s, uint32_t r) {
+  const uint32_t q = set_count_below(s.v[0], r);
+  if (KR == 1) return q;
+  const uint32_t q2 = set_count_below(s.v[KR - 1], r);
+  return q == 64u ? 64u + q2 : q;
+}
+
 // One chunk of candidates, one id per lane in ascending lane order (INF32 =
 // empty slot at the end); duplicates are adjacent; `prev` is the last id of
 // the previous chunk of this level.  Candidate i is accepted iff
 //   #(running set below r_i) + #(earlier distinct candidates of the chunk below r_i) < k.
 // The running set becomes the k smallest ranks of itself and the chunk.
 // Returns the mask of accepted lanes.
-__device__ inline uint64_t chunk_accept(uint32_t id, uint32_t k, const RankMap &rm, uint32_t &setv,
+template <int KR>
+__device__ inline uint64_t chunk_accept(uint32_t id, uint32_t k, const RankMap &rm, KSet<KR> &set,
                                         uint32_t &nset, uint32_t &prev, uint32_t *s_r) {
   const int lane = lane_id();
   uint32_t left = __shfl_up(id, 1, WAVE);
   if (lane == 0) left = prev;
   bool valid = id != INF32 && id != left;
   const uint32_t r = valid ? rank_of(id, rm) : INF32;
-  const uint32_t q = set_count_below(setv, r);
+  const uint32_t q = kset_below(set, r);
   // a candidate already in the set (same vertex at a shorter distance) is
   // not new; one that dropped out of the set is rejected by the count
-  const uint32_t atq = __shfl(setv, (int)(q < 63 ? q : 63), WAVE);
+  const uint32_t atq = kset_at(set, q < 64u * KR - 1u ? q : 64u * KR - 1u);
   if (q < nset && atq == r) valid = false;
   const uint64_t vm = __ballot(valid);
   // earlier candidates of the chunk with a smaller rank: ranks staged in LDS,
@@ -303,21 +399,10 @@ __device__ inline uint64_t chunk_accept(uint32_t id, uint32_t k, const RankMap &
       const int j = __ffsll((long long)it2) - 1;
       it2 &= it2 - 1;
       const uint32_t rj = __shfl(r, j, WAVE);
-      const uint32_t below = (uint32_t)__popcll(__ballot(setv < rj));
-      const uint32_t up = __shfl_up(setv, 1, WAVE);
-      if ((uint32_t)lane > below && (uint32_t)lane < k) setv = up;
-      if ((uint32_t)lane == below) setv = rj;
+      kset_insert(set, rj, kset_ballot_below(set, rj), k);
     }
   } else {
-    uint32_t x = wave_sort_reg(acc ? r : INF32);
-    const uint32_t y = __shfl(x, WAVE - 1 - lane, WAVE);
-    uint32_t mm = setv < y ? setv : y;  // bitonic, holds the 64 smallest of both
-#pragma unroll
-    for (int j = 32; j >= 1; j >>= 1) {
-      const uint32_t o = __shfl_xor(mm, j, WAVE);
-      mm = (lane & j) == 0 ? (mm < o ? mm : o) : (mm > o ? mm : o);
-    }
-    setv = (uint32_t)lane < k ? mm : INF32;
+    kset_merge(set, wave_sort_reg(acc ? r : INF32), k);
   }
   const uint32_t tot = nset + na;
   nset = tot < k ? tot : k;
@@ -327,24 +412,26 @@ __device__ inline uint64_t chunk_accept(uint32_t id, uint32_t k, const RankMap &
 }
 
 // Prune of one distance level.  s_id[0..ns) holds candidate ids (unsorted,
-// duplicates allowed); setv/nset the running set.  Accepted ids end in
+// duplicates allowed); set/nset the running set.  Accepted ids end in
 // s_tmp[0..m) in increasing id order; returns m.  s_id is clobbered.
-// s_cnt holds 3 * WAVE words: [0, WAVE) bucket offsets, then the pending
-// chunk; [WAVE, 2 WAVE) belongs to the caller; [2 WAVE, 3 WAVE) chunk ranks.
+// s_cnt holds (2 + KR) WAVE words: [0, WAVE) bucket offsets, then the
+// pending chunk; [WAVE, (1 + KR) WAVE) belongs to the caller; the last WAVE
+// hold chunk ranks.
 // With tbk, lane b of *tbk receives a rank bound for id bucket b: the running
 // k-th smallest rank when the bucket was reached, which no later candidate of
 // that bucket can beat.
+template <int KR>
 __device__ inline uint32_t prune_level(uint32_t *s_id, uint32_t *s_tmp, uint32_t *s_cnt, uint32_t ns,
-                                       uint32_t k, const RankMap &rm, uint32_t &setv, uint32_t &nset,
+                                       uint32_t k, const RankMap &rm, KSet<KR> &set, uint32_t &nset,
                                        uint32_t *tbk = nullptr) {
   const int lane = lane_id();
   uint32_t *s_pend = s_cnt;
-  uint32_t *s_r = s_cnt + 2 * WAVE;
+  uint32_t *s_r = s_cnt + (1 + KR) * WAVE;
   uint32_t m = 0, prev = INF32;
   if (ns <= (uint32_t)WAVE && !tbk) {
     uint32_t x = (uint32_t)lane < ns ? s_id[lane] : INF32;
     x = wave_sort_reg(x);
-    const uint64_t am = chunk_accept(x, k, rm, setv, nset, prev, s_r);
+    const uint64_t am = chunk_accept(x, k, rm, set, nset, prev, s_r);
     if ((am >> lane) & 1) s_tmp[lanes_below(am)] = x;
     wave_lds_sync();
     return (uint32_t)__popcll(am);
@@ -375,7 +462,7 @@ __device__ inline uint32_t prune_level(uint32_t *s_id, uint32_t *s_tmp, uint32_t
   auto flush = [&]() {
     uint32_t x = (uint32_t)lane < npend ? s_pend[lane] : INF32;
     x = wave_sort_reg(x);
-    const uint64_t am = chunk_accept(x, k, rm, setv, nset, prev, s_r);
+    const uint64_t am = chunk_accept(x, k, rm, set, nset, prev, s_r);
     if ((am >> lane) & 1) s_tmp[m + lanes_below(am)] = x;
     m += (uint32_t)__popcll(am);
     npend = 0;
@@ -385,7 +472,7 @@ __device__ inline uint32_t prune_level(uint32_t *s_id, uint32_t *s_tmp, uint32_t
   // threshold, compacted in place; returns their number
   auto filter = [&](uint32_t sb, uint32_t cb) -> uint32_t {
     const bool open = nset < k;
-    const uint32_t Trun = open ? INF32 : __shfl(setv, (int)k - 1, WAVE);
+    const uint32_t Trun = open ? INF32 : kset_at(set, k - 1);
     uint32_t np = 0;
     for (uint32_t j0 = 0; j0 < cb; j0 += WAVE) {
       const uint32_t j = j0 + lane;
@@ -408,7 +495,7 @@ __device__ inline uint32_t prune_level(uint32_t *s_id, uint32_t *s_tmp, uint32_t
     const uint32_t cb = __shfl(bc, b, WAVE);
     const uint32_t sb = __shfl(bstart, b, WAVE);
     // the running threshold now bounds every bucket up to b
-    const uint32_t Tnow = nset < k ? INF32 : __shfl(setv, (int)k - 1, WAVE);
+    const uint32_t Tnow = nset < k ? INF32 : kset_at(set, k - 1);
     if (lane > done_b && lane <= b) tb = Tnow;
     done_b = b;
     uint32_t np = filter(sb, cb);
@@ -416,7 +503,7 @@ __device__ inline uint32_t prune_level(uint32_t *s_id, uint32_t *s_tmp, uint32_t
     if (npend + np > (uint32_t)WAVE) {
       flush();
       // every earlier candidate is decided: the threshold is exact for bucket b
-      const uint32_t T2 = nset < k ? INF32 : __shfl(setv, (int)k - 1, WAVE);
+      const uint32_t T2 = nset < k ? INF32 : kset_at(set, k - 1);
       if (lane == b) tb = T2;
       np = filter(sb, np);
       if (np == 0) continue;
@@ -427,7 +514,7 @@ __device__ inline uint32_t prune_level(uint32_t *s_id, uint32_t *s_tmp, uint32_t
       wave_sort_lds(s_id, np);
       for (uint32_t c0 = 0; c0 < np; c0 += WAVE) {
         const uint32_t x = c0 + lane < np ? s_id[c0 + lane] : INF32;
-        const uint64_t am = chunk_accept(x, k, rm, setv, nset, prev, s_r);
+        const uint64_t am = chunk_accept(x, k, rm, set, nset, prev, s_r);
         if ((am >> lane) & 1) s_tmp[m + lanes_below(am)] = x;
         m += (uint32_t)__popcll(am);
         wave_lds_sync();
@@ -440,7 +527,7 @@ __device__ inline uint32_t prune_level(uint32_t *s_id, uint32_t *s_tmp, uint32_t
   }
   if (npend) flush();
   if (tbk) {
-    const uint32_t Tend = nset < k ? INF32 : __shfl(setv, (int)k - 1, WAVE);
+    const uint32_t Tend = nset < k ? INF32 : kset_at(set, k - 1);
     if (lane > done_b) tb = Tend;
     *tbk = tb;
   }
@@ -450,8 +537,10 @@ __device__ inline uint32_t prune_level(uint32_t *s_id, uint32_t *s_tmp, uint32_t
 // ---------------------------------------------------------------------------
 // per-wave level state: candidate intake with filtering and buffering
 // ---------------------------------------------------------------------------
+template <int KR>
 struct Level {
-  uint32_t set0, nset0;  // u's bottom-k set at the start of the level
+  KSet<KR> set0;         // u's bottom-k set at the start of the level
+  uint32_t nset0;
   uint32_t T0;           // its k-th smallest rank (INF32 while fewer than k)
   bool full0;
   uint32_t cu;           // entries of u so far
@@ -463,17 +552,22 @@ struct Level {
   uint32_t nmatch;         // level records found (per lane; with dbg only)
 };
 
-__device__ inline void level_init(const AdsArgs &P, uint32_t u, Level &L, uint32_t *s_cnt) {
+template <int KR>
+__device__ inline void level_init(const AdsArgs &P, uint32_t u, Level<KR> &L, uint32_t *s_cnt) {
   const int lane = lane_id();
   const uint32_t k = P.k;
   L.rm = rank_map(P.seg[seg_of(P.gid, u)]);
   L.cu = P.cnt[u];
   L.nset0 = L.cu < k ? L.cu : k;
-  L.set0 = (uint32_t)lane < L.nset0 ? P.bk[(size_t)u * k + lane] : INF32;
-  s_cnt[WAVE + lane] = L.set0;
+#pragma unroll
+  for (int g = 0; g < KR; ++g) {
+    const uint32_t e = (uint32_t)(64 * g + lane);
+    L.set0.v[g] = e < L.nset0 ? P.bk[(size_t)u * k + e] : INF32;
+    s_cnt[WAVE + e] = L.set0.v[g];
+  }
   wave_lds_sync();
   L.full0 = L.nset0 == k;
-  L.T0 = L.full0 ? __shfl(L.set0, (int)k - 1, WAVE) : INF32;
+  L.T0 = L.full0 ? kset_at(L.set0, k - 1) : INF32;
   L.ns = 0;
   L.tb = L.T0;
   L.overflow = false;
@@ -483,8 +577,10 @@ __device__ inline void level_init(const AdsArgs &P, uint32_t u, Level &L, uint32
 // One candidate per lane (valid, rank r, id if known): keep it if its rank is
 // below T0 and it is not already in the set; buffer kept ids, shrinking the
 // buffer by a prune against the set when full.
-__device__ inline void level_offer(const AdsArgs &P, Level &L, bool valid, uint32_t r, bool have_id, uint32_t id,
+template <int KR>
+__device__ inline void level_offer(const AdsArgs &P, Level<KR> &L, bool valid, uint32_t r, bool have_id, uint32_t id,
                                    uint32_t *s_id, uint32_t *s_tmp, uint32_t *s_cnt) {
+  constexpr uint32_t SB = ADS_SB * KR;
   const uint32_t *s_set0 = s_cnt + WAVE;  // LDS copy of the set at the level start
   const int lane = lane_id();
   bool pass = valid && (!L.full0 || r < L.T0);
@@ -507,8 +603,9 @@ __device__ inline void level_offer(const AdsArgs &P, Level &L, bool valid, uint3
   uint64_t msk = __ballot(pass);
   if (!msk) return;
   uint32_t np = (uint32_t)__popcll(msk);
-  if (L.ns + np > ADS_SB) {
-    uint32_t tv = L.set0, tn = L.nset0;
+  if (L.ns + np > SB) {
+    KSet<KR> tv = L.set0;
+    uint32_t tn = L.nset0;
     ++L.nprune;
     L.ns = prune_level(s_id, s_tmp, s_cnt, L.ns, P.k, L.rm, tv, tn, &L.tb);
     for (uint32_t i = lane; i < L.ns; i += WAVE) s_id[i] = s_tmp[i];
@@ -518,7 +615,7 @@ __device__ inline void level_offer(const AdsArgs &P, Level &L, bool valid, uint3
     if (pass && r >= bnd2) pass = false;
     msk = __ballot(pass);
     np = (uint32_t)__popcll(msk);
-    if (L.ns + np > ADS_SB) {
+    if (L.ns + np > SB) {
       L.overflow = true;
       return;
     }
@@ -534,8 +631,8 @@ __device__ inline void level_offer(const AdsArgs &P, Level &L, bool valid, uint3
 // two entries come from the record; longer ones from the tail's sketch row,
 // the whole wave on one list at a time when it is long (a level is stored in
 // increasing rank order, so once a rank reaches T0 the rest cannot enter).
-template <bool UNITW>
-__device__ inline uint64_t gather_batch(const AdsArgs &P, uint32_t D, uint64_t a, bool valid, Level &L,
+template <bool UNITW, int KR>
+__device__ inline uint64_t gather_batch(const AdsArgs &P, uint32_t D, uint64_t a, bool valid, Level<KR> &L,
                                         uint32_t *s_id, uint32_t *s_tmp, uint32_t *s_cnt) {
   const int lane = lane_id();
   uint64_t examined = 0;
@@ -633,13 +730,13 @@ __device__ inline uint64_t gather_batch(const AdsArgs &P, uint32_t D, uint64_t a
 
 // Stream the candidates of arcs [a0, a1) of u for level D (every in-arc is
 // looked at: rounds run over the dense vertex list).
-template <bool UNITW>
-__device__ inline uint64_t gather_arcs(const AdsArgs &P, uint32_t D, uint64_t a0, uint64_t a1, Level &L,
+template <bool UNITW, int KR>
+__device__ inline uint64_t gather_arcs(const AdsArgs &P, uint32_t D, uint64_t a0, uint64_t a1, Level<KR> &L,
                                        uint32_t *s_id, uint32_t *s_tmp, uint32_t *s_cnt) {
   const int lane = lane_id();
   uint64_t examined = 0;
   for (uint64_t b = a0; b < a1 && !L.overflow; b += WAVE)
-    examined += gather_batch<UNITW>(P, D, b + lane, b + lane < a1, L, s_id, s_tmp, s_cnt);
+    examined += gather_batch<UNITW, KR>(P, D, b + lane, b + lane < a1, L, s_id, s_tmp, s_cnt);
   return examined;
 }
 
@@ -647,8 +744,8 @@ __device__ inline uint64_t gather_arcs(const AdsArgs &P, uint32_t D, uint64_t a0
 // each arc it marked, at the arc's position in the in-arc rows, in the plane
 // of the round the level reaches the head.  Only those arcs of [a0, a1) are
 // read: 64 plane words per step, their set bits compacted over the wave.
-template <bool UNITW>
-__device__ inline uint64_t gather_flagged(const AdsArgs &P, uint32_t D, uint64_t a0, uint64_t a1, Level &L,
+template <bool UNITW, int KR>
+__device__ inline uint64_t gather_flagged(const AdsArgs &P, uint32_t D, uint64_t a0, uint64_t a1, Level<KR> &L,
                                           uint32_t *s_id, uint32_t *s_tmp, uint32_t *s_cnt) {
   const int lane = lane_id();
   const uint32_t *plane = P.plane + (size_t)(D % P.NS) * P.pw;
@@ -689,20 +786,21 @@ __device__ inline uint64_t gather_flagged(const AdsArgs &P, uint32_t D, uint64_t
         }
       }
       const uint64_t a = ((wb + src) << 5) + bit;
-      examined += gather_batch<UNITW>(P, D, a, valid, L, s_id, s_tmp, s_cnt);
+      examined += gather_batch<UNITW, KR>(P, D, a, valid, L, s_id, s_tmp, s_cnt);
     }
   }
   return examined;
 }
 
 // Final prune of u's level-D candidates and the append of the accepted ones.
-template <bool UNITW>
-__device__ inline void level_commit(const AdsArgs &P, uint32_t u, uint32_t D, Level &L, int mark, uint32_t *s_id,
+template <bool UNITW, int KR>
+__device__ inline void level_commit(const AdsArgs &P, uint32_t u, uint32_t D, Level<KR> &L, int mark, uint32_t *s_id,
                                     uint32_t *s_tmp, uint32_t *s_cnt) {
   const int lane = lane_id();
   if (L.ns == 0) return;
-  uint32_t setv = L.set0, nset = L.nset0;
-  const uint32_t m = prune_level(s_id, s_tmp, s_cnt, L.ns, P.k, L.rm, setv, nset);
+  KSet<KR> set = L.set0;
+  uint32_t nset = L.nset0;
+  const uint32_t m = prune_level(s_id, s_tmp, s_cnt, L.ns, P.k, L.rm, set, nset);
   if (m == 0) return;
   const uint32_t cu = L.cu;
   if (cu + m > P.cap) {
@@ -730,7 +828,7 @@ __device__ inline void level_commit(const AdsArgs &P, uint32_t u, uint32_t D, Le
     x1 = __shfl(x, 1, WAVE);
   } else {
     for (uint32_t i = lane; i < m; i += WAVE) s_id[i] = rank_of(s_tmp[i], L.rm);
-    wave_sort_lds(s_id, m);  // m <= ADS_SB
+    wave_sort_lds(s_id, m);  // m <= ADS_SB * KR
     for (uint32_t i = lane; i < m; i += WAVE) {
       P.sk_rank[base + i] = s_id[i];
       P.sk_dist[base + i] = D;
@@ -738,7 +836,9 @@ __device__ inline void level_commit(const AdsArgs &P, uint32_t u, uint32_t D, Le
     x0 = s_id[0];
     x1 = s_id[1];
   }
-  if ((uint32_t)lane < nset) P.bk[(size_t)u * P.k + lane] = setv;
+#pragma unroll
+  for (int g = 0; g < KR; ++g)
+    if ((uint32_t)(64 * g + lane) < nset) P.bk[(size_t)u * P.k + 64 * g + lane] = set.v[g];
   if (lane == 0) {
     P.cnt[u] = cu + m;
     P.lvl[(size_t)(D % P.NS) * P.n + u] = level_record(D, x0, x1, cu, m);
@@ -749,13 +849,14 @@ __device__ inline void level_commit(const AdsArgs &P, uint32_t u, uint32_t D, Le
 
 // One wave per task.  task_slot == INF32: the task is the whole vertex and
 // commits; otherwise it leaves its kept set in scratch slot task_slot.
-template <bool UNITW>
+template <bool UNITW, int KR>
 __global__ __launch_bounds__(TASK_WPB * WAVE) void k_ads_tasks(AdsArgs P, uint32_t D, const uint32_t *task_u,
                                                    const uint32_t *task_sub, const uint32_t *task_slot,
                                                    uint32_t ntasks, uint32_t task_arcs, int sparse, int mark) {
-  __shared__ uint32_t lds_id[TASK_WPB][ADS_SB];
-  __shared__ uint32_t lds_tmp[TASK_WPB][ADS_SB];
-  __shared__ __align__(16) uint32_t lds_cnt[TASK_WPB][3 * WAVE];
+  constexpr uint32_t SB = ADS_SB * KR;
+  __shared__ uint32_t lds_id[TASK_WPB][SB];
+  __shared__ uint32_t lds_tmp[TASK_WPB][SB];
+  __shared__ __align__(16) uint32_t lds_cnt[TASK_WPB][(2 + KR) * WAVE];
   const int lane = lane_id();
   const int wv = threadIdx.x / WAVE;
   const uint64_t item = (uint64_t)blockIdx.x * TASK_WPB + wv;
@@ -770,7 +871,7 @@ __global__ __launch_bounds__(TASK_WPB * WAVE) void k_ads_tasks(AdsArgs P, uint32
     const uint32_t sD = D % P.NS;
     atomicAnd(&P.flags[(size_t)u * P.FW + (sD >> 5)], ~(1u << (sD & 31)));
   }
-  Level L;
+  Level<KR> L;
   level_init(P, u, L, s_cnt);
   const uint64_t r0 = P.row_ptr[u], r1 = P.row_ptr[u + 1];
   uint64_t a0 = r0, a1 = r1;
@@ -778,8 +879,8 @@ __global__ __launch_bounds__(TASK_WPB * WAVE) void k_ads_tasks(AdsArgs P, uint32
     a0 = r0 + (uint64_t)sub * task_arcs;
     a1 = a0 + task_arcs < r1 ? a0 + task_arcs : r1;
   }
-  const uint64_t examined = (sparse && P.plane) ? gather_flagged<UNITW>(P, D, a0, a1, L, s_id, s_tmp, s_cnt)
-                                                 : gather_arcs<UNITW>(P, D, a0, a1, L, s_id, s_tmp, s_cnt);
+  const uint64_t examined = (sparse && P.plane) ? gather_flagged<UNITW, KR>(P, D, a0, a1, L, s_id, s_tmp, s_cnt)
+                                                 : gather_arcs<UNITW, KR>(P, D, a0, a1, L, s_id, s_tmp, s_cnt);
   if (lane == 0) {
     atomicAdd((unsigned long long *)&P.ctr[blockIdx.x & 63], (unsigned long long)examined);
     atomicAdd((unsigned long long *)&P.ctr[128 + (blockIdx.x & 63)], (unsigned long long)L.nsurv);
@@ -797,26 +898,28 @@ __global__ __launch_bounds__(TASK_WPB * WAVE) void k_ads_tasks(AdsArgs P, uint32
     return;
   }
   if (slot == INF32) {
-    level_commit<UNITW>(P, u, D, L, mark, s_id, s_tmp, s_cnt);
+    level_commit<UNITW, KR>(P, u, D, L, mark, s_id, s_tmp, s_cnt);
   } else {
     uint32_t m = 0;
     if (L.ns) {
-      uint32_t setv = L.set0, nset = L.nset0;
-      m = prune_level(s_id, s_tmp, s_cnt, L.ns, P.k, L.rm, setv, nset);
-      for (uint32_t i = lane; i < m; i += WAVE) P.kept[(size_t)slot * ADS_SB + i] = s_tmp[i];
+      KSet<KR> set = L.set0;
+      uint32_t nset = L.nset0;
+      m = prune_level(s_id, s_tmp, s_cnt, L.ns, P.k, L.rm, set, nset);
+      for (uint32_t i = lane; i < m; i += WAVE) P.kept[(size_t)slot * SB + i] = s_tmp[i];
     }
     if (lane == 0) P.kept_cnt[slot] = m;
   }
 }
 
 // One wave per split vertex: prune the union of its tasks' kept sets, commit.
-template <bool UNITW>
+template <bool UNITW, int KR>
 __global__ __launch_bounds__(TASK_WPB * WAVE) void k_ads_merge(AdsArgs P, uint32_t D, const uint32_t *split_u,
                                                    const uint32_t *split_first, const uint32_t *split_nt,
                                                    uint32_t nsplit, int mark) {
-  __shared__ uint32_t lds_id[TASK_WPB][ADS_SB];
-  __shared__ uint32_t lds_tmp[TASK_WPB][ADS_SB];
-  __shared__ __align__(16) uint32_t lds_cnt[TASK_WPB][3 * WAVE];
+  constexpr uint32_t SB = ADS_SB * KR;
+  __shared__ uint32_t lds_id[TASK_WPB][SB];
+  __shared__ uint32_t lds_tmp[TASK_WPB][SB];
+  __shared__ __align__(16) uint32_t lds_cnt[TASK_WPB][(2 + KR) * WAVE];
   const int lane = lane_id();
   const int wv = threadIdx.x / WAVE;
   const uint64_t item = (uint64_t)blockIdx.x * TASK_WPB + wv;
@@ -827,7 +930,7 @@ __global__ __launch_bounds__(TASK_WPB * WAVE) void k_ads_merge(AdsArgs P, uint32
   const uint32_t u = split_u[item];
   const uint32_t first = split_first[item];
   const uint32_t nt = split_nt[item];
-  Level L;
+  Level<KR> L;
   level_init(P, u, L, s_cnt);
   for (uint32_t g0 = 0; g0 < nt && !L.overflow; g0 += WAVE) {
     const uint32_t cn = g0 + lane < nt ? P.kept_cnt[first + g0 + lane] : 0u;
@@ -846,7 +949,7 @@ __global__ __launch_bounds__(TASK_WPB * WAVE) void k_ads_merge(AdsArgs P, uint32
       const uint32_t oex = __shfl(excl, (int)pos, WAVE);
       uint32_t id = INF32, r = INF32;
       if (valid) {
-        id = P.kept[(size_t)(first + g0 + pos) * ADS_SB + (idx - oex)];
+        id = P.kept[(size_t)(first + g0 + pos) * SB + (idx - oex)];
         r = rank_of(id, L.rm);
       }
       level_offer(P, L, valid, r, true, id, s_id, s_tmp, s_cnt);
@@ -856,35 +959,22 @@ __global__ __launch_bounds__(TASK_WPB * WAVE) void k_ads_merge(AdsArgs P, uint32
     if (lane == 0) atomicOr(&P.status[1], 1u);
     return;
   }
-  level_commit<UNITW>(P, u, D, L, mark, s_id, s_tmp, s_cnt);
+  level_commit<UNITW, KR>(P, u, D, L, mark, s_id, s_tmp, s_cnt);
 }
 
-
-// HIP thresholds of the sketch rows that need them: T_j = k-th smallest rank
-// among entries 0..j-1 of the row (0 encodes 2^32 while fewer than k).  One
-// wave per row, the running bottom-k in registers.
-// Merge of a bitonic sequence held one value per lane into ascending
-// (desc = false) or descending order.
-__device__ inline uint32_t wave_bitonic_merge(uint32_t x, bool desc) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int j = 32; j >= 1; j >>= 1) {
-    const uint32_t y = __shfl_xor(x, j, WAVE);
-    const bool lo = ((lane & j) == 0) != desc;
-    x = lo ? (x < y ? x : y) : (x > y ? x : y);
-  }
-  return x;
-}
 
 // Last pass over the rows with a threshold row (one wave per row): the row
 // holds the sketch in canonical (distance, id) order (written at commit); it
 // is copied into the sketch row, and entry j of the threshold row becomes
-// T_j = the k-th smallest rank of entries 0..j-1 (0 for j < k, meaning 2^32).  Every later entry ranks below its T_j (that is what membership of
-// the sketch means), so each one enters the running bottom-k set and evicts
-// its maximum, and no later entry is above that maximum.  Hence for a chunk
-// C of up to 64 entries after a full set S, the threshold of the chunk's
-// i-th entry is the (i+1)-th largest of S and C together, and the next S is
-// the k smallest of them: one sort and two bitonic merges per chunk.
+// T_j = the k-th smallest rank of entries 0..j-1 (0 for j < k, meaning 2^32).
+// Every later entry ranks below its T_j (that is what membership of the
+// sketch means), so each one enters the running bottom-k set and evicts its
+// maximum, and no later entry is above that maximum.  Hence for a chunk C of
+// up to 64 entries after a full set S, the threshold of the chunk's i-th
+// entry is the (i+1)-th largest of S and C together, and the next S is the k
+// smallest of them: one sort and a few bitonic merges per chunk.  The set is
+// held in KR registers per lane (k <= 64 KR).
+template <int KR>
 __global__ __launch_bounds__(256) void k_hip_thresholds(uint32_t rows, const uint32_t *row_vertex, uint32_t cap,
                                                         uint32_t k, const uint32_t *cnt, uint32_t *sk_rank,
                                                         uint32_t *thr) {
@@ -895,31 +985,40 @@ __global__ __launch_bounds__(256) void k_hip_thresholds(uint32_t rows, const uin
   const uint32_t c = cnt[u];
   uint32_t *rk = sk_rank + (size_t)u * cap;
   uint32_t *out = thr + (size_t)row * cap;  // canonical ranks in, thresholds out (each lane its own slots)
-  const uint32_t k0 = c < k ? c : k;  // k <= WAVE
-  const uint32_t first = lane < k0 ? out[lane] : INF32;
-  if (lane < k0) {
-    rk[lane] = first;
-    out[lane] = 0;
+  const uint32_t k0 = c < k ? c : k;
+  uint32_t first[KR];
+#pragma unroll
+  for (int g = 0; g < KR; ++g) {
+    const uint32_t e = 64u * g + lane;
+    first[g] = e < k0 ? out[e] : INF32;
+    if (e < k0) {
+      rk[e] = first[g];
+      out[e] = 0;
+    }
   }
   if (c <= k) return;
-  uint32_t S = wave_sort_reg(lane < k ? first : INF32);  // ascending, INF32 above k
+  // S: the first k entries, ascending, INF32 above k
+  KSet<KR> S;
+  if (KR == 1) {
+    S.v[0] = wave_sort_reg(first[0]);
+  } else {
+    uint32_t hi;
+    wave_merge2(wave_sort_reg(first[0]), wave_sort_reg(first[KR - 1]), S.v[0], hi);
+    S.v[KR - 1] = hi;
+  }
   for (uint32_t j0 = k; j0 < c; j0 += WAVE) {
     const uint32_t m = c - j0 < (uint32_t)WAVE ? c - j0 : (uint32_t)WAVE;
     const uint32_t mine = lane < m ? out[j0 + lane] : INF32;
     if (lane < m) rk[j0 + lane] = mine;
     const uint32_t ca = wave_sort_reg(mine);  // chunk ascending, INF32 above m
-    // the 64 largest: S descending (0 above k) against C ascending (0 below 64 - m)
-    const uint32_t sd = __shfl(S, (int)(lane < k ? k - 1 - lane : 0), WAVE);
+    // the 64 largest: S descending (0 past its size) against C ascending (0 below 64 - m)
+    const uint32_t sd = kset_at(S, lane < k ? k - 1 - lane : 0u);
     const uint32_t cs = __shfl(ca, (int)(lane >= WAVE - m ? lane - (WAVE - m) : 0), WAVE);
     uint32_t top = (lane < k ? sd : 0u) > (lane >= WAVE - m ? cs : 0u) ? (lane < k ? sd : 0u)
                                                                         : (lane >= WAVE - m ? cs : 0u);
     top = wave_bitonic_merge(top, true);  // lane i: the (i+1)-th largest
     if (lane < m) out[j0 + lane] = top;
-    // the k smallest: S ascending (INF32 above k) against C descending (INF32 first)
-    const uint32_t cd = __shfl(ca, (int)(WAVE - 1 - lane), WAVE);
-    uint32_t bot = S < cd ? S : cd;
-    bot = wave_bitonic_merge(bot, false);
-    S = lane < k ? bot : INF32;
+    kset_merge(S, ca, k);  // the k smallest of S and C
   }
 }
 
@@ -1076,7 +1175,7 @@ size_t ads_scratch_bytes(uint32_t n, uint64_t m, uint32_t k, uint32_t NS) {
   b += (size_t)NS * n * (16 + 4);          // per-slot level records + worklists
   b += (size_t)m * 4 + (size_t)NS * (m / 32 + 2) * 4;  // reverse-arc positions, arc bit planes
   b += (size_t)n * FW * 4;                 // worklist flags
-  b += (size_t)slots * (ADS_SB + 1) * 4;   // kept sets of split tasks
+  b += (size_t)slots * (ADS_SB * (k > 64 ? 2 : 1) + 1) * 4;   // kept sets of split tasks
   b += (size_t)tasks * 4 * 3 * 2 + (size_t)n * 4 * 3 * 2;  // two task lists
   b += (size_t)n * (4 * 3 + 8 * 3) + (size_t)n * 24;       // task scratch, dense list
   b += (size_t)8 << 20;
@@ -1155,7 +1254,7 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
     FL_HIP(hipMemcpyAsync(c.h_status, noff + n, 8, hipMemcpyDeviceToHost, c.s));
     c.sync();
     const uint64_t slots = c.h_status[0] + 1;
-    P.kept = c.arena->get<uint32_t>(slots * ADS_SB);
+    P.kept = c.arena->get<uint32_t>(slots * ADS_SB * (k > 64 ? 2 : 1));
     P.kept_cnt = c.arena->get<uint32_t>(slots);
   }
   // task-list scratch and lists (sized for a list of all vertices)
@@ -1250,22 +1349,35 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
     if (T->ntasks) {
       if (c.timing) FL_HIP(hipEventRecord(e0, c.s));
       const uint32_t tb = (uint32_t)ceil_div(T->ntasks, TASK_WPB);
-      if (unit)
-        k_ads_tasks<true><<<tb, TASK_WPB * WAVE, 0, c.s>>>(P, D, T->task_u, T->task_sub, T->task_slot, T->ntasks,
-                                               T->task_arcs, sparse ? 1 : 0, mark ? 1 : 0);
+      // the running bottom-k set takes one register per lane up to k = 64, two up to 128
+      if (unit && k <= 64)
+        k_ads_tasks<true, 1><<<tb, TASK_WPB * WAVE, 0, c.s>>>(P, D, T->task_u, T->task_sub, T->task_slot, T->ntasks,
+                                                              T->task_arcs, sparse ? 1 : 0, mark ? 1 : 0);
+      else if (unit)
+        k_ads_tasks<true, 2><<<tb, TASK_WPB * WAVE, 0, c.s>>>(P, D, T->task_u, T->task_sub, T->task_slot, T->ntasks,
+                                                              T->task_arcs, sparse ? 1 : 0, mark ? 1 : 0);
+      else if (k <= 64)
+        k_ads_tasks<false, 1><<<tb, TASK_WPB * WAVE, 0, c.s>>>(P, D, T->task_u, T->task_sub, T->task_slot, T->ntasks,
+                                                               T->task_arcs, sparse ? 1 : 0, mark ? 1 : 0);
       else
-        k_ads_tasks<false><<<tb, TASK_WPB * WAVE, 0, c.s>>>(P, D, T->task_u, T->task_sub, T->task_slot, T->ntasks,
-                                                T->task_arcs, sparse ? 1 : 0, mark ? 1 : 0);
+        k_ads_tasks<false, 2><<<tb, TASK_WPB * WAVE, 0, c.s>>>(P, D, T->task_u, T->task_sub, T->task_slot, T->ntasks,
+                                                               T->task_arcs, sparse ? 1 : 0, mark ? 1 : 0);
       FL_LAUNCH_CHECK();
       if (c.timing) FL_HIP(hipEventRecord(em, c.s));
       if (T->nsplit) {
         const uint32_t mb = (uint32_t)ceil_div(T->nsplit, TASK_WPB);
-        if (unit)
-          k_ads_merge<true><<<mb, TASK_WPB * WAVE, 0, c.s>>>(P, D, T->split_u, T->split_first, T->split_nt, T->nsplit,
-                                                 mark ? 1 : 0);
+        if (unit && k <= 64)
+          k_ads_merge<true, 1><<<mb, TASK_WPB * WAVE, 0, c.s>>>(P, D, T->split_u, T->split_first, T->split_nt,
+                                                                T->nsplit, mark ? 1 : 0);
+        else if (unit)
+          k_ads_merge<true, 2><<<mb, TASK_WPB * WAVE, 0, c.s>>>(P, D, T->split_u, T->split_first, T->split_nt,
+                                                                T->nsplit, mark ? 1 : 0);
+        else if (k <= 64)
+          k_ads_merge<false, 1><<<mb, TASK_WPB * WAVE, 0, c.s>>>(P, D, T->split_u, T->split_first, T->split_nt,
+                                                                 T->nsplit, mark ? 1 : 0);
         else
-          k_ads_merge<false><<<mb, TASK_WPB * WAVE, 0, c.s>>>(P, D, T->split_u, T->split_first, T->split_nt, T->nsplit,
-                                                  mark ? 1 : 0);
+          k_ads_merge<false, 2><<<mb, TASK_WPB * WAVE, 0, c.s>>>(P, D, T->split_u, T->split_first, T->split_nt,
+                                                                 T->nsplit, mark ? 1 : 0);
         FL_LAUNCH_CHECK();
       }
       if (c.timing) FL_HIP(hipEventRecord(e1, c.s));
@@ -1367,8 +1479,11 @@ int ads_build(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o) {
       // rows without a threshold row keep rank order within a level: only
       // the rows of facilities (every row for fl_ads_build) are read later
       if (o.thr && thr_rows) {
-        k_hip_thresholds<<<(uint32_t)ceil_div((uint64_t)thr_rows * WAVE, 256), 256, 0, c.s>>>(
-            thr_rows, cfg.thr_rows_vertex, cap, cfg.k, o.cnt, o.sk_rank, o.thr);
+        const uint32_t tgrid = (uint32_t)ceil_div((uint64_t)thr_rows * WAVE, 256);
+        if (cfg.k <= 64)
+          k_hip_thresholds<1><<<tgrid, 256, 0, c.s>>>(thr_rows, cfg.thr_rows_vertex, cap, cfg.k, o.cnt, o.sk_rank, o.thr);
+        else
+          k_hip_thresholds<2><<<tgrid, 256, 0, c.s>>>(thr_rows, cfg.thr_rows_vertex, cap, cfg.k, o.cnt, o.sk_rank, o.thr);
         FL_LAUNCH_CHECK();
       }
       return FL_OK;

@@ -1224,7 +1224,7 @@ const char *fl_strerror(int code) {
     case FL_ENOMEM: return "workspace does not fit";
     case FL_EHIP: return "HIP runtime error";
     case FL_EBUSY: return "busy";
-    case FL_ENOTIMPL: return "outside the limits of this library (k > 64, weight > 255, sketch capacity)";
+    case FL_ENOTIMPL: return "outside the limits of this library (k > 128, weight > 255, sketch capacity)";
     default: return "unknown error";
   }
 }

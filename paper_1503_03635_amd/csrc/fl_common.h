@@ -18,7 +18,7 @@ namespace fl {
 constexpr int WAVE = 64;
 constexpr uint32_t INF32 = 0xFFFFFFFFu;
 constexpr uint64_t INF64 = 0xFFFFFFFFFFFFFFFFull;
-constexpr uint32_t MAX_K = 64;
+constexpr uint32_t MAX_K = 128;  // the running bottom-k set: at most two registers per lane
 constexpr uint32_t MAX_W = 255;      // largest edge weight handled by the slot ring
 constexpr uint32_t MAX_CAP = 65535;  // largest per-vertex sketch capacity
 constexpr int NCTR = 1024;           // strided counters (spread atomics over addresses)

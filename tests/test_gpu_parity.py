@@ -42,7 +42,7 @@ def test_sketches_bit_exact(name, make, k):
     assert_sketch_equal(g, k, seed=7)
 
 
-@pytest.mark.parametrize("k", [1, 2, 5, 64])
+@pytest.mark.parametrize("k", [1, 2, 5, 64, 65, 100, 128])
 def test_sketches_k_edges(k):
     g = gg.rmat(10, 6 << 10, 11)
     print(f"[sketch] rmat 2^10 k={k}", flush=True)
@@ -53,6 +53,39 @@ def test_sketches_k_at_least_n():
     g = gg.er(60, 5, 2, wmax=4)
     print("[sketch] k >= n", flush=True)
     assert_sketch_equal(g, 64, seed=1)
+    g = gg.er(120, 5, 3, wmax=4)
+    print("[sketch] k >= n, two registers", flush=True)
+    assert_sketch_equal(g, 128, seed=1)
+
+
+# k above 64 holds the running bottom-k set in two registers per lane and a
+# survivor buffer of twice the size: sketches and solves on unit and weighted
+# graphs, hubs and worklist rounds
+BIG_K_CASES = [
+    ("RMAT 2^12 unit k128", lambda: gg.rmat(12, 16 << 12, 5), 128),
+    ("RMAT 2^11 w1..100 k96", lambda: gg.rmat(11, 8 << 11, 6, wmax=100), 96),
+    ("star 3000 k128", lambda: gg.star(3000), 128),
+    ("star 5000 w1..100 k128", lambda: gg.star(5000, wmax=100, seed=3), 128),
+    ("Chung-Lu n=3000 w1..20 k80", lambda: gg.chung_lu(3000, 4, 2.2, 10.0, 20), 80),
+    ("grid 20x20 ties k128", lambda: gg.grid(20, 20), 128),
+]
+
+
+@pytest.mark.parametrize("name,make,k", BIG_K_CASES, ids=[c[0] for c in BIG_K_CASES])
+def test_sketches_big_k(name, make, k):
+    g = make()
+    print(f"[sketch] {name} n={g.n} arcs={g.n_arcs}", flush=True)
+    assert_sketch_equal(g, k, seed=7)
+    assert_sketch_equal(g, k, seed=8, flags=fl.FL_FLAG_NO_DENSE)
+
+
+@pytest.mark.parametrize("k", [65, 128])
+def test_solve_big_k(k):
+    for name, make in (("RMAT 2^11 unit", lambda: gg.with_problem(gg.rmat(11, 16 << 11, 8), 8, cost="uniform")),
+                       ("RMAT 2^10 w1..100 10% fac", lambda: gg.with_problem(gg.rmat(10, 16 << 10, 9, wmax=100), 9,
+                                                                            cost="lognormal", fac_frac=0.1))):
+        print(f"[solve] {name} k={k}", flush=True)
+        assert_solve_equal(make(), k, 1)
 
 
 def test_sketches_schedule_invariant():
@@ -237,7 +270,7 @@ def test_error_codes():
     g = gg.with_problem(gg.er(50, 4, 1, wmax=5), 1)
     dg = fl.to_device(g)
     with pytest.raises(fl.FlError) as e:
-        fl.solve(dg, 65, 1)
+        fl.solve(dg, 129, 1)
     assert e.value.code == fl._lib.FL_ENOTIMPL
     with pytest.raises(fl.FlError) as e:
         fl.solve(dg, 4, 1, eps=-1.0)

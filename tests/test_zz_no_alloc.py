@@ -83,7 +83,7 @@ def test_static_solve_refuses_what_does_not_fit():
 def test_static_solve_errors():
     g = gg.with_problem(gg.er(50, 4, 1, wmax=5), 1)
     with pytest.raises(fl.FlError) as e:
-        fl.solve_static(fl.to_device(g), 65, 1)
+        fl.solve_static(fl.to_device(g), 129, 1)
     assert e.value.code == _lib.FL_ENOTIMPL
     bad = gg.Graph(g.n, g.row_ptr.copy(), g.col.copy(), g.w.copy(), g.fac_cost)
     bad.w[0] += 1
