@@ -69,6 +69,11 @@ static_assert(TASK_ARCS_SPARSE >= TASK_ARCS, "scratch slots are sized for TASK_A
 // With arc bit planes a task reads only the arcs that carry a level, so its
 // cost follows those, not its length: rows are cut far less often.
 constexpr uint32_t TASK_ARCS_FLAGGED = 8192;
+// While most vertices are active, scanning every in-arc costs less than
+// setting a plane bit per marked arc: rounds read flagged arcs only from
+// FLAG_FROM_RINGS times the slot ring (max weight + 1) on, and commits set
+// plane bits from a ring earlier (the levels those rounds read).
+constexpr uint32_t FLAG_FROM_RINGS = 1;
 static_assert(TASK_ARCS_FLAGGED >= TASK_ARCS, "scratch slots are sized for TASK_ARCS");
 constexpr uint32_t NBKT = 64;       // id buckets of the level prune (one per lane)
 constexpr uint32_t LONG_LIST = 64;  // entry lists at least this long are streamed one arc at a time
@@ -97,6 +102,8 @@ struct AdsArgs {
   // arc bit planes of the rounds run from worklists (nullptr: scan every in-arc)
   uint32_t *plane;            // [NS * pw] bit of in-arc position p set in plane D % NS: a level reaches it in round D
   uint64_t pw;                // words per plane
+  uint32_t flag_from;         // first round whose tasks read only flagged arcs
+  uint32_t plane_from;        // first round whose commits set plane bits (flag_from - max weight)
   const uint32_t *out_to_in;  // [m] out-arc -> in-arc position
   uint32_t *kept;      // [slots * ADS_SB * KR] kept ids of split tasks
   uint32_t *kept_cnt;  // [slots]
@@ -166,7 +173,7 @@ __device__ inline void mark_neighbours(const AdsArgs &P, uint32_t u, uint32_t D)
       y = P.out_col[a];
       const uint32_t wv = UNITW ? 1u : P.out_w[a];
       s = (D + wv) % P.NS;
-      if (P.plane) {
+      if (P.plane && D >= P.plane_from) {
         const uint32_t p = P.out_to_in[a];
         atomicOr(&P.plane[(size_t)s * P.pw + (p >> 5)], 1u << (p & 31));
       }
@@ -879,7 +886,8 @@ __global__ __launch_bounds__(TASK_WPB * WAVE) void k_ads_tasks(AdsArgs P, uint32
     a0 = r0 + (uint64_t)sub * task_arcs;
     a1 = a0 + task_arcs < r1 ? a0 + task_arcs : r1;
   }
-  const uint64_t examined = (sparse && P.plane) ? gather_flagged<UNITW, KR>(P, D, a0, a1, L, s_id, s_tmp, s_cnt)
+  const uint64_t examined = (sparse && P.plane && D >= P.flag_from)
+                                ? gather_flagged<UNITW, KR>(P, D, a0, a1, L, s_id, s_tmp, s_cnt)
                                                  : gather_arcs<UNITW, KR>(P, D, a0, a1, L, s_id, s_tmp, s_cnt);
   if (lane == 0) {
     atomicAdd((unsigned long long *)&P.ctr[blockIdx.x & 63], (unsigned long long)examined);
@@ -911,18 +919,26 @@ __global__ __launch_bounds__(TASK_WPB * WAVE) void k_ads_tasks(AdsArgs P, uint32
   }
 }
 
-// One wave per split vertex: prune the union of its tasks' kept sets, commit.
+// One block per split vertex: MERGE_WPB - 1 waves each prune the union of a
+// strided share of its tasks' kept sets into a partial set in LDS, then the
+// first wave prunes the union of the partial sets and commits.  The prune is
+// associative and idempotent, so the grouping does not change the result;
+// it shortens the chain of dependent work per hub, which bounds a round.
+constexpr int MERGE_WPB = 8;
 template <bool UNITW, int KR>
-__global__ __launch_bounds__(TASK_WPB * WAVE) void k_ads_merge(AdsArgs P, uint32_t D, const uint32_t *split_u,
-                                                   const uint32_t *split_first, const uint32_t *split_nt,
-                                                   uint32_t nsplit, int mark) {
+__global__ __launch_bounds__(MERGE_WPB * WAVE) void k_ads_merge(AdsArgs P, uint32_t D, const uint32_t *split_u,
+                                                                const uint32_t *split_first,
+                                                                const uint32_t *split_nt, uint32_t nsplit,
+                                                                int mark) {
   constexpr uint32_t SB = ADS_SB * KR;
-  __shared__ uint32_t lds_id[TASK_WPB][SB];
-  __shared__ uint32_t lds_tmp[TASK_WPB][SB];
-  __shared__ __align__(16) uint32_t lds_cnt[TASK_WPB][(2 + KR) * WAVE];
+  constexpr uint32_t NW = MERGE_WPB - 1;  // waves that build partial sets
+  __shared__ uint32_t lds_id[MERGE_WPB][SB];
+  __shared__ uint32_t lds_tmp[MERGE_WPB][SB];
+  __shared__ __align__(16) uint32_t lds_cnt[MERGE_WPB][(2 + KR) * WAVE];
+  __shared__ uint32_t part_n[MERGE_WPB];
   const int lane = lane_id();
   const int wv = threadIdx.x / WAVE;
-  const uint64_t item = (uint64_t)blockIdx.x * TASK_WPB + wv;
+  const uint32_t item = blockIdx.x;  // the block's split vertex (uniform over the block)
   if (item >= nsplit) return;
   uint32_t *s_id = lds_id[wv];
   uint32_t *s_tmp = lds_tmp[wv];
@@ -932,26 +948,56 @@ __global__ __launch_bounds__(TASK_WPB * WAVE) void k_ads_merge(AdsArgs P, uint32
   const uint32_t nt = split_nt[item];
   Level<KR> L;
   level_init(P, u, L, s_cnt);
-  for (uint32_t g0 = 0; g0 < nt && !L.overflow; g0 += WAVE) {
-    const uint32_t cn = g0 + lane < nt ? P.kept_cnt[first + g0 + lane] : 0u;
-    const uint32_t incl = wave_scan_incl(cn);
-    const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
-    const uint32_t excl = incl - cn;
-    for (uint32_t c0 = 0; c0 < total && !L.overflow; c0 += WAVE) {
-      const uint32_t idx = c0 + lane;
-      uint32_t pos = 0;
+  if (wv > 0) {
+    // tasks wv - 1, wv - 1 + NW, ...: a virtual list of mine = ceil((nt - (wv-1)) / NW) tasks
+    const uint32_t t0 = (uint32_t)wv - 1;
+    const uint32_t mine = nt > t0 ? (nt - t0 + NW - 1) / NW : 0u;
+    for (uint32_t g0 = 0; g0 < mine && !L.overflow; g0 += WAVE) {
+      const uint32_t task = first + t0 + (g0 + lane) * NW;
+      const uint32_t cn = g0 + lane < mine ? P.kept_cnt[task] : 0u;
+      const uint32_t incl = wave_scan_incl(cn);
+      const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
+      const uint32_t excl = incl - cn;
+      for (uint32_t c0 = 0; c0 < total && !L.overflow; c0 += WAVE) {
+        const uint32_t idx = c0 + lane;
+        uint32_t pos = 0;
 #pragma unroll
-      for (uint32_t s = 32; s >= 1; s >>= 1) {
-        const uint32_t val = __shfl(incl, (int)(pos + s - 1), WAVE);
-        if (val <= idx) pos += s;
+        for (uint32_t sh = 32; sh >= 1; sh >>= 1) {
+          const uint32_t val = __shfl(incl, (int)(pos + sh - 1), WAVE);
+          if (val <= idx) pos += sh;
+        }
+        const bool valid = idx < total;
+        const uint32_t oex = __shfl(excl, (int)pos, WAVE);
+        const uint32_t otask = __shfl(task, (int)pos, WAVE);
+        uint32_t id = INF32, r = INF32;
+        if (valid) {
+          id = P.kept[(size_t)otask * SB + (idx - oex)];
+          r = rank_of(id, L.rm);
+        }
+        level_offer(P, L, valid, r, true, id, s_id, s_tmp, s_cnt);
       }
-      const bool valid = idx < total;
-      const uint32_t oex = __shfl(excl, (int)pos, WAVE);
-      uint32_t id = INF32, r = INF32;
-      if (valid) {
-        id = P.kept[(size_t)(first + g0 + pos) * SB + (idx - oex)];
-        r = rank_of(id, L.rm);
-      }
+    }
+    uint32_t m = 0;
+    if (!L.overflow && L.ns) {
+      KSet<KR> set = L.set0;
+      uint32_t nset = L.nset0;
+      m = prune_level(s_id, s_tmp, s_cnt, L.ns, P.k, L.rm, set, nset);  // partial set in s_tmp[0..m)
+    }
+    if (lane == 0) part_n[wv] = L.overflow ? INF32 : m;
+  }
+  __syncthreads();
+  if (wv != 0) return;
+  for (int w = 1; w < MERGE_WPB && !L.overflow; ++w) {
+    const uint32_t pn = part_n[w];
+    if (pn == INF32) {
+      L.overflow = true;
+      break;
+    }
+    const uint32_t *part = lds_tmp[w];
+    for (uint32_t c0 = 0; c0 < pn && !L.overflow; c0 += WAVE) {
+      const bool valid = c0 + lane < pn;
+      const uint32_t id = valid ? part[c0 + lane] : INF32;
+      const uint32_t r = valid ? rank_of(id, L.rm) : INF32;
       level_offer(P, L, valid, r, true, id, s_id, s_tmp, s_cnt);
     }
   }
@@ -961,7 +1007,6 @@ __global__ __launch_bounds__(TASK_WPB * WAVE) void k_ads_merge(AdsArgs P, uint32
   }
   level_commit<UNITW, KR>(P, u, D, L, mark, s_id, s_tmp, s_cnt);
 }
-
 
 // Last pass over the rows with a threshold row (one wave per row): the row
 // holds the sketch in canonical (distance, id) order (written at commit); it
@@ -1225,6 +1270,8 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
   P.plane = nullptr;
   P.pw = g.m / 32 + 2;
   P.out_to_in = nullptr;
+  P.flag_from = FLAG_FROM_RINGS * NS;
+  P.plane_from = P.flag_from > W ? P.flag_from - W : 0;
   if (planes) {
     P.plane = c.arena->get<uint32_t>((size_t)NS * P.pw);
     fill_u32(c, P.plane, (size_t)NS * P.pw, 0);
@@ -1340,7 +1387,8 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
         c.sync();
         count = (uint32_t)(c.h_status[0] & 0xFFFFFFFFu);
       }
-      build_tasks(c, g, P.wl + (size_t)slot * n, count, P.plane ? TASK_ARCS_FLAGGED : TASK_ARCS_SPARSE, ts, tl);
+      build_tasks(c, g, P.wl + (size_t)slot * n, count,
+                  (P.plane && D >= P.flag_from) ? TASK_ARCS_FLAGGED : TASK_ARCS_SPARSE, ts, tl);
       T = &tl;
     }
     // marking decision for this round (decides the mode of the next one)
@@ -1365,18 +1413,18 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
       FL_LAUNCH_CHECK();
       if (c.timing) FL_HIP(hipEventRecord(em, c.s));
       if (T->nsplit) {
-        const uint32_t mb = (uint32_t)ceil_div(T->nsplit, TASK_WPB);
+        const uint32_t mb = T->nsplit;  // one block of MERGE_WPB waves per split vertex
         if (unit && k <= 64)
-          k_ads_merge<true, 1><<<mb, TASK_WPB * WAVE, 0, c.s>>>(P, D, T->split_u, T->split_first, T->split_nt,
+          k_ads_merge<true, 1><<<mb, MERGE_WPB * WAVE, 0, c.s>>>(P, D, T->split_u, T->split_first, T->split_nt,
                                                                 T->nsplit, mark ? 1 : 0);
         else if (unit)
-          k_ads_merge<true, 2><<<mb, TASK_WPB * WAVE, 0, c.s>>>(P, D, T->split_u, T->split_first, T->split_nt,
+          k_ads_merge<true, 2><<<mb, MERGE_WPB * WAVE, 0, c.s>>>(P, D, T->split_u, T->split_first, T->split_nt,
                                                                 T->nsplit, mark ? 1 : 0);
         else if (k <= 64)
-          k_ads_merge<false, 1><<<mb, TASK_WPB * WAVE, 0, c.s>>>(P, D, T->split_u, T->split_first, T->split_nt,
+          k_ads_merge<false, 1><<<mb, MERGE_WPB * WAVE, 0, c.s>>>(P, D, T->split_u, T->split_first, T->split_nt,
                                                                  T->nsplit, mark ? 1 : 0);
         else
-          k_ads_merge<false, 2><<<mb, TASK_WPB * WAVE, 0, c.s>>>(P, D, T->split_u, T->split_first, T->split_nt,
+          k_ads_merge<false, 2><<<mb, MERGE_WPB * WAVE, 0, c.s>>>(P, D, T->split_u, T->split_first, T->split_nt,
                                                                  T->nsplit, mark ? 1 : 0);
         FL_LAUNCH_CHECK();
       }
