@@ -854,26 +854,14 @@ __device__ inline void level_commit(const AdsArgs &P, uint32_t u, uint32_t D, Le
   if (mark) mark_neighbours<UNITW>(P, u, D);
 }
 
-// One wave per task.  task_slot == INF32: the task is the whole vertex and
-// commits; otherwise it leaves its kept set in scratch slot task_slot.
+// One task, by one wave.  slot == INF32: the task is the whole vertex and
+// commits; otherwise it leaves its kept set in scratch slot `slot`.
 template <bool UNITW, int KR>
-__global__ __launch_bounds__(TASK_WPB * WAVE) void k_ads_tasks(AdsArgs P, uint32_t D, const uint32_t *task_u,
-                                                   const uint32_t *task_sub, const uint32_t *task_slot,
-                                                   uint32_t ntasks, uint32_t task_arcs, int sparse, int mark) {
+__device__ inline void ads_task(const AdsArgs &P, uint32_t D, uint32_t u, uint32_t sub, uint32_t slot,
+                                uint32_t task_arcs, int sparse, int mark, uint32_t *s_id, uint32_t *s_tmp,
+                                uint32_t *s_cnt) {
   constexpr uint32_t SB = ADS_SB * KR;
-  __shared__ uint32_t lds_id[TASK_WPB][SB];
-  __shared__ uint32_t lds_tmp[TASK_WPB][SB];
-  __shared__ __align__(16) uint32_t lds_cnt[TASK_WPB][(2 + KR) * WAVE];
   const int lane = lane_id();
-  const int wv = threadIdx.x / WAVE;
-  const uint64_t item = (uint64_t)blockIdx.x * TASK_WPB + wv;
-  if (item >= ntasks) return;
-  uint32_t *s_id = lds_id[wv];
-  uint32_t *s_tmp = lds_tmp[wv];
-  uint32_t *s_cnt = lds_cnt[wv];
-  const uint32_t u = task_u[item];
-  const uint32_t sub = task_sub[item];
-  const uint32_t slot = task_slot[item];
   if (sparse && sub == 0 && lane == 0) {
     const uint32_t sD = D % P.NS;
     atomicAnd(&P.flags[(size_t)u * P.FW + (sD >> 5)], ~(1u << (sD & 31)));
@@ -919,6 +907,26 @@ __global__ __launch_bounds__(TASK_WPB * WAVE) void k_ads_tasks(AdsArgs P, uint32
   }
 }
 
+// One wave per task.  task_slot == INF32: the task is the whole vertex and
+// commits; otherwise it leaves its kept set in scratch slot task_slot.  With
+// d_ntasks (device) the grid strides over that many tasks (the host does not
+// know the count); otherwise one wave per task.
+template <bool UNITW, int KR>
+__global__ __launch_bounds__(TASK_WPB * WAVE) void k_ads_tasks(AdsArgs P, uint32_t D, const uint32_t *task_u,
+                                                   const uint32_t *task_sub, const uint32_t *task_slot,
+                                                   uint32_t ntasks, const uint64_t *d_ntasks, uint32_t task_arcs,
+                                                   int sparse, int mark) {
+  constexpr uint32_t SB = ADS_SB * KR;
+  __shared__ uint32_t lds_id[TASK_WPB][SB];
+  __shared__ uint32_t lds_tmp[TASK_WPB][SB];
+  __shared__ __align__(16) uint32_t lds_cnt[TASK_WPB][(2 + KR) * WAVE];
+  const int wv = threadIdx.x / WAVE;
+  const uint64_t total = d_ntasks ? *d_ntasks : ntasks;
+  for (uint64_t item = (uint64_t)blockIdx.x * TASK_WPB + wv; item < total; item += (uint64_t)gridDim.x * TASK_WPB)
+    ads_task<UNITW, KR>(P, D, task_u[item], task_sub[item], task_slot[item], task_arcs, sparse, mark, lds_id[wv],
+                        lds_tmp[wv], lds_cnt[wv]);
+}
+
 // One block per split vertex: MERGE_WPB - 1 waves each prune the union of a
 // strided share of its tasks' kept sets into a partial set in LDS, then the
 // first wave prunes the union of the partial sets and commits.  The prune is
@@ -929,7 +937,7 @@ template <bool UNITW, int KR>
 __global__ __launch_bounds__(MERGE_WPB * WAVE) void k_ads_merge(AdsArgs P, uint32_t D, const uint32_t *split_u,
                                                                 const uint32_t *split_first,
                                                                 const uint32_t *split_nt, uint32_t nsplit,
-                                                                int mark) {
+                                                                const uint64_t *d_nsplit, int mark) {
   constexpr uint32_t SB = ADS_SB * KR;
   constexpr uint32_t NW = MERGE_WPB - 1;  // waves that build partial sets
   __shared__ uint32_t lds_id[MERGE_WPB][SB];
@@ -938,74 +946,79 @@ __global__ __launch_bounds__(MERGE_WPB * WAVE) void k_ads_merge(AdsArgs P, uint3
   __shared__ uint32_t part_n[MERGE_WPB];
   const int lane = lane_id();
   const int wv = threadIdx.x / WAVE;
-  const uint32_t item = blockIdx.x;  // the block's split vertex (uniform over the block)
-  if (item >= nsplit) return;
   uint32_t *s_id = lds_id[wv];
   uint32_t *s_tmp = lds_tmp[wv];
   uint32_t *s_cnt = lds_cnt[wv];
-  const uint32_t u = split_u[item];
-  const uint32_t first = split_first[item];
-  const uint32_t nt = split_nt[item];
-  Level<KR> L;
-  level_init(P, u, L, s_cnt);
-  if (wv > 0) {
-    // tasks wv - 1, wv - 1 + NW, ...: a virtual list of mine = ceil((nt - (wv-1)) / NW) tasks
-    const uint32_t t0 = (uint32_t)wv - 1;
-    const uint32_t mine = nt > t0 ? (nt - t0 + NW - 1) / NW : 0u;
-    for (uint32_t g0 = 0; g0 < mine && !L.overflow; g0 += WAVE) {
-      const uint32_t task = first + t0 + (g0 + lane) * NW;
-      const uint32_t cn = g0 + lane < mine ? P.kept_cnt[task] : 0u;
-      const uint32_t incl = wave_scan_incl(cn);
-      const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
-      const uint32_t excl = incl - cn;
-      for (uint32_t c0 = 0; c0 < total && !L.overflow; c0 += WAVE) {
-        const uint32_t idx = c0 + lane;
-        uint32_t pos = 0;
+  // the block's split vertices (uniform over the block): every wave reaches
+  // both barriers of every item
+  const uint64_t total = d_nsplit ? *d_nsplit : nsplit;
+  for (uint64_t item = blockIdx.x; item < total; item += gridDim.x) {
+    const uint32_t u = split_u[item];
+    const uint32_t first = split_first[item];
+    const uint32_t nt = split_nt[item];
+    Level<KR> L;
+    level_init(P, u, L, s_cnt);
+    if (wv > 0) {
+      // tasks wv - 1, wv - 1 + NW, ...: a virtual list of `mine` tasks
+      const uint32_t t0 = (uint32_t)wv - 1;
+      const uint32_t mine = nt > t0 ? (nt - t0 + NW - 1) / NW : 0u;
+      for (uint32_t g0 = 0; g0 < mine && !L.overflow; g0 += WAVE) {
+        const uint32_t task = first + t0 + (g0 + lane) * NW;
+        const uint32_t cn = g0 + lane < mine ? P.kept_cnt[task] : 0u;
+        const uint32_t incl = wave_scan_incl(cn);
+        const uint32_t tot = __shfl(incl, WAVE - 1, WAVE);
+        const uint32_t excl = incl - cn;
+        for (uint32_t c0 = 0; c0 < tot && !L.overflow; c0 += WAVE) {
+          const uint32_t idx = c0 + lane;
+          uint32_t pos = 0;
 #pragma unroll
-        for (uint32_t sh = 32; sh >= 1; sh >>= 1) {
-          const uint32_t val = __shfl(incl, (int)(pos + sh - 1), WAVE);
-          if (val <= idx) pos += sh;
+          for (uint32_t sh = 32; sh >= 1; sh >>= 1) {
+            const uint32_t val = __shfl(incl, (int)(pos + sh - 1), WAVE);
+            if (val <= idx) pos += sh;
+          }
+          const bool valid = idx < tot;
+          const uint32_t oex = __shfl(excl, (int)pos, WAVE);
+          const uint32_t otask = __shfl(task, (int)pos, WAVE);
+          uint32_t id = INF32, r = INF32;
+          if (valid) {
+            id = P.kept[(size_t)otask * SB + (idx - oex)];
+            r = rank_of(id, L.rm);
+          }
+          level_offer(P, L, valid, r, true, id, s_id, s_tmp, s_cnt);
         }
-        const bool valid = idx < total;
-        const uint32_t oex = __shfl(excl, (int)pos, WAVE);
-        const uint32_t otask = __shfl(task, (int)pos, WAVE);
-        uint32_t id = INF32, r = INF32;
-        if (valid) {
-          id = P.kept[(size_t)otask * SB + (idx - oex)];
-          r = rank_of(id, L.rm);
+      }
+      uint32_t m = 0;
+      if (!L.overflow && L.ns) {
+        KSet<KR> set = L.set0;
+        uint32_t nset = L.nset0;
+        m = prune_level(s_id, s_tmp, s_cnt, L.ns, P.k, L.rm, set, nset);  // partial set in s_tmp[0..m)
+      }
+      if (lane == 0) part_n[wv] = L.overflow ? INF32 : m;
+    }
+    __syncthreads();
+    if (wv == 0) {
+      for (int w = 1; w < MERGE_WPB && !L.overflow; ++w) {
+        const uint32_t pn = part_n[w];
+        if (pn == INF32) {
+          L.overflow = true;
+          break;
         }
-        level_offer(P, L, valid, r, true, id, s_id, s_tmp, s_cnt);
+        const uint32_t *part = lds_tmp[w];
+        for (uint32_t c0 = 0; c0 < pn && !L.overflow; c0 += WAVE) {
+          const bool valid = c0 + lane < pn;
+          const uint32_t id = valid ? part[c0 + lane] : INF32;
+          const uint32_t r = valid ? rank_of(id, L.rm) : INF32;
+          level_offer(P, L, valid, r, true, id, s_id, s_tmp, s_cnt);
+        }
+      }
+      if (L.overflow) {
+        if (lane == 0) atomicOr(&P.status[1], 1u);
+      } else {
+        level_commit<UNITW, KR>(P, u, D, L, mark, s_id, s_tmp, s_cnt);
       }
     }
-    uint32_t m = 0;
-    if (!L.overflow && L.ns) {
-      KSet<KR> set = L.set0;
-      uint32_t nset = L.nset0;
-      m = prune_level(s_id, s_tmp, s_cnt, L.ns, P.k, L.rm, set, nset);  // partial set in s_tmp[0..m)
-    }
-    if (lane == 0) part_n[wv] = L.overflow ? INF32 : m;
+    __syncthreads();  // the partial sets are read before the next item rebuilds them
   }
-  __syncthreads();
-  if (wv != 0) return;
-  for (int w = 1; w < MERGE_WPB && !L.overflow; ++w) {
-    const uint32_t pn = part_n[w];
-    if (pn == INF32) {
-      L.overflow = true;
-      break;
-    }
-    const uint32_t *part = lds_tmp[w];
-    for (uint32_t c0 = 0; c0 < pn && !L.overflow; c0 += WAVE) {
-      const bool valid = c0 + lane < pn;
-      const uint32_t id = valid ? part[c0 + lane] : INF32;
-      const uint32_t r = valid ? rank_of(id, L.rm) : INF32;
-      level_offer(P, L, valid, r, true, id, s_id, s_tmp, s_cnt);
-    }
-  }
-  if (L.overflow) {
-    if (lane == 0) atomicOr(&P.status[1], 1u);
-    return;
-  }
-  level_commit<UNITW, KR>(P, u, D, L, mark, s_id, s_tmp, s_cnt);
 }
 
 // Last pass over the rows with a threshold row (one wave per row): the row
@@ -1070,10 +1083,16 @@ __global__ __launch_bounds__(256) void k_hip_thresholds(uint32_t rows, const uin
 // ---------------------------------------------------------------------------
 // task lists
 // ---------------------------------------------------------------------------
-__global__ void k_task_count(const uint32_t *list, uint32_t count, const uint64_t *row_ptr, uint32_t task_arcs,
-                             uint32_t *ntask, uint32_t *nslot, uint32_t *isplit) {
+// count: entries the grid covers; d_count (device, may be null): the list's
+// length when only the device knows it (entries past it count zero tasks)
+__global__ void k_task_count(const uint32_t *list, uint32_t count, const uint32_t *d_count, const uint64_t *row_ptr,
+                             uint32_t task_arcs, uint32_t *ntask, uint32_t *nslot, uint32_t *isplit) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
+  if (d_count && i >= *d_count) {
+    ntask[i] = nslot[i] = isplit[i] = 0;
+    return;
+  }
   const uint32_t u = list[i];
   const uint64_t d = row_ptr[u + 1] - row_ptr[u];
   const uint32_t nt = d <= task_arcs ? 1u : (uint32_t)((d + task_arcs - 1) / task_arcs);
@@ -1082,12 +1101,12 @@ __global__ void k_task_count(const uint32_t *list, uint32_t count, const uint64_
   isplit[i] = nt > 1 ? 1u : 0u;
 }
 
-__global__ void k_task_fill(const uint32_t *list, uint32_t count, const uint32_t *ntask, const uint64_t *task_off,
-                            const uint64_t *slot_off, const uint64_t *split_off, uint32_t *task_u,
-                            uint32_t *task_sub, uint32_t *task_slot, uint32_t *split_u, uint32_t *split_first,
-                            uint32_t *split_nt) {
+__global__ void k_task_fill(const uint32_t *list, uint32_t count, const uint32_t *d_count, const uint32_t *ntask,
+                            const uint64_t *task_off, const uint64_t *slot_off, const uint64_t *split_off,
+                            uint32_t *task_u, uint32_t *task_sub, uint32_t *task_slot, uint32_t *split_u,
+                            uint32_t *split_first, uint32_t *split_nt) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= count) return;
+  if (i >= count || (d_count && i >= *d_count)) return;
   const uint32_t u = list[i];
   const uint32_t nt = ntask[i];
   const uint64_t t0 = task_off[i];
@@ -1117,6 +1136,78 @@ struct TaskScratch {
   uint64_t *toff, *soff, *poff;
 };
 
+// The task list of a worklist whose length only the device knows: each
+// 256-thread block takes TB_ITEMS consecutive entries per thread and reserves
+// the tile's tasks, kept slots and split records with one atomic per counter
+// (the order of the tasks does not matter: the prune does not depend on it).
+// tot: [0] tasks, [1] kept slots, [2] split vertices, zero before the launch.
+constexpr uint32_t TB_ITEMS = 4;
+__global__ __launch_bounds__(256) void k_task_build(const uint32_t *list, const uint32_t *d_count,
+                                                    const uint64_t *row_ptr, uint32_t task_arcs, uint64_t *tot,
+                                                    uint32_t *task_u, uint32_t *task_sub, uint32_t *task_slot,
+                                                    uint32_t *split_u, uint32_t *split_first, uint32_t *split_nt) {
+  __shared__ uint32_t wsum[3][4];
+  __shared__ uint64_t base[3];
+  const uint32_t lane = (uint32_t)lane_id(), wv = threadIdx.x / WAVE;
+  const uint32_t count = *d_count;
+  constexpr uint32_t TILE = 256 * TB_ITEMS;
+  for (uint64_t b = (uint64_t)blockIdx.x * TILE; b < count; b += (uint64_t)gridDim.x * TILE) {
+    uint32_t u[TB_ITEMS], nt[TB_ITEMS];
+    uint32_t c[3] = {0, 0, 0};
+#pragma unroll
+    for (uint32_t j = 0; j < TB_ITEMS; ++j) {
+      const uint64_t i = b + (uint64_t)threadIdx.x * TB_ITEMS + j;
+      u[j] = 0;
+      nt[j] = 0;
+      if (i < count) {
+        u[j] = list[i];
+        const uint64_t d = row_ptr[u[j] + 1] - row_ptr[u[j]];
+        nt[j] = d <= task_arcs ? 1u : (uint32_t)((d + task_arcs - 1) / task_arcs);
+      }
+      c[0] += nt[j];
+      c[1] += nt[j] > 1 ? nt[j] : 0u;
+      c[2] += nt[j] > 1 ? 1u : 0u;
+    }
+    uint32_t incl[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      incl[q] = wave_scan_incl(c[q]);
+      if (lane == WAVE - 1) wsum[q][wv] = incl[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+      const uint32_t q = threadIdx.x;
+      const uint32_t t = wsum[q][0] + wsum[q][1] + wsum[q][2] + wsum[q][3];
+      base[q] = t ? atomicAdd((unsigned long long *)&tot[q], (unsigned long long)t) : 0ull;
+    }
+    __syncthreads();
+    uint64_t off[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      uint64_t o = base[q] + (incl[q] - c[q]);
+      for (uint32_t w = 0; w < wv; ++w) o += wsum[q][w];
+      off[q] = o;
+    }
+    __syncthreads();  // wsum and base are rewritten by the next tile
+#pragma unroll
+    for (uint32_t j = 0; j < TB_ITEMS; ++j) {
+      for (uint32_t t = 0; t < nt[j]; ++t) {
+        task_u[off[0] + t] = u[j];
+        task_sub[off[0] + t] = t;
+        task_slot[off[0] + t] = nt[j] > 1 ? (uint32_t)(off[1] + t) : INF32;
+      }
+      if (nt[j] > 1) {
+        split_u[off[2]] = u[j];
+        split_first[off[2]] = (uint32_t)off[1];
+        split_nt[off[2]] = nt[j];
+        off[1] += nt[j];
+        off[2] += 1;
+      }
+      off[0] += nt[j];
+    }
+  }
+}
+
 // task_arcs >= TASK_ARCS: the scratch slots are sized for TASK_ARCS
 static void build_tasks(Ctx &c, const Graph &g, const uint32_t *list, uint32_t count, uint32_t task_arcs,
                         TaskScratch &ts, TaskList &tl) {
@@ -1124,13 +1215,13 @@ static void build_tasks(Ctx &c, const Graph &g, const uint32_t *list, uint32_t c
   tl.task_arcs = task_arcs;
   if (count == 0) return;
   const uint32_t blocks = (uint32_t)ceil_div(count, 256);
-  k_task_count<<<blocks, 256, 0, c.s>>>(list, count, g.in_ptr, task_arcs, ts.ntask, ts.nslot, ts.isplit);
+  k_task_count<<<blocks, 256, 0, c.s>>>(list, count, nullptr, g.in_ptr, task_arcs, ts.ntask, ts.nslot, ts.isplit);
   FL_LAUNCH_CHECK();
   scan_u32_to_u64(c, ts.ntask, ts.toff, count);
   scan_u32_to_u64(c, ts.nslot, ts.soff, count);
   scan_u32_to_u64(c, ts.isplit, ts.poff, count);
-  k_task_fill<<<blocks, 256, 0, c.s>>>(list, count, ts.ntask, ts.toff, ts.soff, ts.poff, tl.task_u, tl.task_sub,
-                                        tl.task_slot, tl.split_u, tl.split_first, tl.split_nt);
+  k_task_fill<<<blocks, 256, 0, c.s>>>(list, count, nullptr, ts.ntask, ts.toff, ts.soff, ts.poff, tl.task_u,
+                                        tl.task_sub, tl.task_slot, tl.split_u, tl.split_first, tl.split_nt);
   FL_LAUNCH_CHECK();
   uint64_t h[3];
   FL_HIP(hipMemcpyAsync(&h[0], ts.toff + count, 8, hipMemcpyDeviceToHost, c.s));
@@ -1162,6 +1253,19 @@ __global__ void k_reverse_arcs(uint32_t n, uint64_t m, const uint64_t *row_ptr, 
       else b1 = mid;
     }
     out_to_in[a] = (uint32_t)b0;
+  }
+}
+
+// Work still pending after a round of a chunk (every worklist slot) and the
+// round's task count, for the host's readback at the end of the chunk.
+__global__ void k_round_pending(const uint32_t *wl_cnt, uint32_t NS, const uint64_t *d_ntasks, uint64_t *pend,
+                                uint64_t *tasks) {
+  uint64_t sum = 0;
+  for (uint32_t s = threadIdx.x; s < NS; s += WAVE) sum += wl_cnt[s];
+  sum = wave_sum_u64(sum);
+  if (threadIdx.x == 0) {
+    *pend = sum;
+    *tasks = *d_ntasks;
   }
 }
 
@@ -1376,7 +1480,113 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
   uint32_t rounds = 0;
   std::vector<uint32_t> hwl(NS);
   bool hwl_valid = false;  // hwl holds the slot counts read back after the previous round
-  for (uint32_t D = 1;; ++D) {
+  if (!dense_ok) {
+    // Every round runs from worklists.  Rounds are launched RCHUNK at a time
+    // with their task lists built on the device (no count goes to the host
+    // in between); the round kernels stride over the device-side totals.
+    // The host reads back, once per chunk, the work pending after each of
+    // its rounds; rounds after the first with nothing pending find empty
+    // worklists and change nothing.
+    constexpr uint32_t RCHUNK = 16;
+    uint64_t *pend = c.arena->get<uint64_t>(2 * RCHUNK);  // [r] pending after round r, [RCHUNK + r] its tasks
+    std::vector<hipEvent_t> ev(c.timing ? 3 * RCHUNK : 0, nullptr);
+    struct EvVecDel {
+      std::vector<hipEvent_t> &v;
+      ~EvVecDel() {
+        for (hipEvent_t e : v)
+          if (e) (void)hipEventDestroy(e);
+      }
+    } evvd{ev};
+    for (auto &e : ev) FL_HIP(hipEventCreate(&e));
+    const uint32_t GT = (uint32_t)std::min<uint64_t>(max_tasks, 65536);  // one-wave blocks striding over tasks
+    const uint32_t GM = (uint32_t)std::min<uint64_t>(n, 2048);           // merge blocks striding over hubs
+    const uint32_t TB = (uint32_t)std::min<uint64_t>(ceil_div(n, 256 * TB_ITEMS), 1024);  // task-list blocks
+    uint64_t *tot = c.arena->get<uint64_t>(3);
+    const uint64_t *d_ntasks = tot, *d_nsplit = tot + 2;
+    for (uint32_t D0 = 1;; D0 += RCHUNK) {
+      for (uint32_t r = 0; r < RCHUNK; ++r) {
+        const uint32_t D = D0 + r;
+        const uint32_t slot = D % NS;
+        const uint32_t task_arcs = (P.plane && D >= P.flag_from) ? TASK_ARCS_FLAGGED : TASK_ARCS_SPARSE;
+        fill_u64(c, tot, 3, 0);
+        k_task_build<<<TB, 256, 0, c.s>>>(P.wl + (size_t)slot * n, P.wl_cnt + slot, g.in_ptr, task_arcs, tot,
+                                          tl.task_u, tl.task_sub, tl.task_slot, tl.split_u, tl.split_first,
+                                          tl.split_nt);
+        FL_LAUNCH_CHECK();
+        if (c.timing) FL_HIP(hipEventRecord(ev[3 * r], c.s));
+        if (unit && k <= 64)
+          k_ads_tasks<true, 1><<<GT, TASK_WPB * WAVE, 0, c.s>>>(P, D, tl.task_u, tl.task_sub, tl.task_slot, 0,
+                                                                d_ntasks, task_arcs, 1, 1);
+        else if (unit)
+          k_ads_tasks<true, 2><<<GT, TASK_WPB * WAVE, 0, c.s>>>(P, D, tl.task_u, tl.task_sub, tl.task_slot, 0,
+                                                                d_ntasks, task_arcs, 1, 1);
+        else if (k <= 64)
+          k_ads_tasks<false, 1><<<GT, TASK_WPB * WAVE, 0, c.s>>>(P, D, tl.task_u, tl.task_sub, tl.task_slot, 0,
+                                                                 d_ntasks, task_arcs, 1, 1);
+        else
+          k_ads_tasks<false, 2><<<GT, TASK_WPB * WAVE, 0, c.s>>>(P, D, tl.task_u, tl.task_sub, tl.task_slot, 0,
+                                                                 d_ntasks, task_arcs, 1, 1);
+        FL_LAUNCH_CHECK();
+        if (c.timing) FL_HIP(hipEventRecord(ev[3 * r + 1], c.s));
+        if (unit && k <= 64)
+          k_ads_merge<true, 1><<<GM, MERGE_WPB * WAVE, 0, c.s>>>(P, D, tl.split_u, tl.split_first, tl.split_nt, 0,
+                                                                 d_nsplit, 1);
+        else if (unit)
+          k_ads_merge<true, 2><<<GM, MERGE_WPB * WAVE, 0, c.s>>>(P, D, tl.split_u, tl.split_first, tl.split_nt, 0,
+                                                                 d_nsplit, 1);
+        else if (k <= 64)
+          k_ads_merge<false, 1><<<GM, MERGE_WPB * WAVE, 0, c.s>>>(P, D, tl.split_u, tl.split_first, tl.split_nt, 0,
+                                                                  d_nsplit, 1);
+        else
+          k_ads_merge<false, 2><<<GM, MERGE_WPB * WAVE, 0, c.s>>>(P, D, tl.split_u, tl.split_first, tl.split_nt, 0,
+                                                                  d_nsplit, 1);
+        FL_LAUNCH_CHECK();
+        if (c.timing) FL_HIP(hipEventRecord(ev[3 * r + 2], c.s));
+        fill_u32(c, P.wl_cnt + slot, 1, 0);
+        if (P.plane) fill_u32(c, P.plane + (size_t)slot * P.pw, P.pw, 0);
+        k_round_pending<<<1, WAVE, 0, c.s>>>(P.wl_cnt, NS, d_ntasks, pend + r, pend + RCHUNK + r);
+        FL_LAUNCH_CHECK();
+      }
+      std::vector<uint64_t> hp(2 * RCHUNK);
+      FL_HIP(hipMemcpyAsync(c.h_status, P.status, 8, hipMemcpyDeviceToHost, c.s));
+      FL_HIP(hipMemcpyAsync(hp.data(), pend, 2 * RCHUNK * 8, hipMemcpyDeviceToHost, c.s));
+      c.sync();
+      const uint32_t st0 = (uint32_t)(c.h_status[0] & 0xFFFFFFFFu);
+      const uint32_t st1 = (uint32_t)(c.h_status[0] >> 32);
+      if (st0) {
+        *need_more = true;
+        return FL_OK;
+      }
+      if (st1) return FL_ENOMEM;
+      uint32_t used = RCHUNK;
+      bool done = false;
+      for (uint32_t r = 0; r < RCHUNK; ++r)
+        if (hp[r] == 0) {
+          used = r + 1;
+          done = true;
+          break;
+        }
+      for (uint32_t r = 0; r < used; ++r) {
+        if (!hp[RCHUNK + r]) continue;
+        o.launches += 1;
+        if (c.timing) {
+          float ms = 0.f, ms2 = 0.f;
+          FL_HIP(hipEventElapsedTime(&ms, ev[3 * r], ev[3 * r + 1]));
+          FL_HIP(hipEventElapsedTime(&ms2, ev[3 * r + 1], ev[3 * r + 2]));
+          o.kernel_ms += ms;
+          o.merge_ms += ms2;
+        }
+      }
+      rounds = D0 + used - 1;
+      if (std::getenv("FL_DEBUG"))
+        std::fprintf(stderr, "[fl] rounds %u-%u: tasks of the first %llu, pending after the last %llu\n", D0,
+                     D0 + used - 1, (unsigned long long)hp[RCHUNK], (unsigned long long)hp[used - 1]);
+      if (done) break;
+      // a settled entry is at most (n-1) max_w away: more rounds mean a bug
+      if ((uint64_t)D0 + RCHUNK > (uint64_t)(n - 1) * W + 2 + RCHUNK) return FL_EHIP;
+    }
+  }
+  for (uint32_t D = 1; dense_ok; ++D) {
     const uint32_t slot = D % NS;
     const TaskList *T = &tl_dense;
     if (sparse) {
@@ -1400,32 +1610,32 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
       // the running bottom-k set takes one register per lane up to k = 64, two up to 128
       if (unit && k <= 64)
         k_ads_tasks<true, 1><<<tb, TASK_WPB * WAVE, 0, c.s>>>(P, D, T->task_u, T->task_sub, T->task_slot, T->ntasks,
-                                                              T->task_arcs, sparse ? 1 : 0, mark ? 1 : 0);
+                                                              nullptr, T->task_arcs, sparse ? 1 : 0, mark ? 1 : 0);
       else if (unit)
         k_ads_tasks<true, 2><<<tb, TASK_WPB * WAVE, 0, c.s>>>(P, D, T->task_u, T->task_sub, T->task_slot, T->ntasks,
-                                                              T->task_arcs, sparse ? 1 : 0, mark ? 1 : 0);
+                                                              nullptr, T->task_arcs, sparse ? 1 : 0, mark ? 1 : 0);
       else if (k <= 64)
         k_ads_tasks<false, 1><<<tb, TASK_WPB * WAVE, 0, c.s>>>(P, D, T->task_u, T->task_sub, T->task_slot, T->ntasks,
-                                                               T->task_arcs, sparse ? 1 : 0, mark ? 1 : 0);
+                                                               nullptr, T->task_arcs, sparse ? 1 : 0, mark ? 1 : 0);
       else
         k_ads_tasks<false, 2><<<tb, TASK_WPB * WAVE, 0, c.s>>>(P, D, T->task_u, T->task_sub, T->task_slot, T->ntasks,
-                                                               T->task_arcs, sparse ? 1 : 0, mark ? 1 : 0);
+                                                               nullptr, T->task_arcs, sparse ? 1 : 0, mark ? 1 : 0);
       FL_LAUNCH_CHECK();
       if (c.timing) FL_HIP(hipEventRecord(em, c.s));
       if (T->nsplit) {
         const uint32_t mb = T->nsplit;  // one block of MERGE_WPB waves per split vertex
         if (unit && k <= 64)
           k_ads_merge<true, 1><<<mb, MERGE_WPB * WAVE, 0, c.s>>>(P, D, T->split_u, T->split_first, T->split_nt,
-                                                                T->nsplit, mark ? 1 : 0);
+                                                                T->nsplit, nullptr, mark ? 1 : 0);
         else if (unit)
           k_ads_merge<true, 2><<<mb, MERGE_WPB * WAVE, 0, c.s>>>(P, D, T->split_u, T->split_first, T->split_nt,
-                                                                T->nsplit, mark ? 1 : 0);
+                                                                T->nsplit, nullptr, mark ? 1 : 0);
         else if (k <= 64)
           k_ads_merge<false, 1><<<mb, MERGE_WPB * WAVE, 0, c.s>>>(P, D, T->split_u, T->split_first, T->split_nt,
-                                                                 T->nsplit, mark ? 1 : 0);
+                                                                 T->nsplit, nullptr, mark ? 1 : 0);
         else
           k_ads_merge<false, 2><<<mb, MERGE_WPB * WAVE, 0, c.s>>>(P, D, T->split_u, T->split_first, T->split_nt,
-                                                                 T->nsplit, mark ? 1 : 0);
+                                                                 T->nsplit, nullptr, mark ? 1 : 0);
         FL_LAUNCH_CHECK();
       }
       if (c.timing) FL_HIP(hipEventRecord(e1, c.s));

@@ -430,8 +430,10 @@ void validate_graphs(Ctx &c, const fl_problem *const *ps, uint32_t G, bool direc
 // device counters laid out as [(g * nf + f) * stripes + s]
 std::vector<uint64_t> read_seg_ctr(Ctx &c, const uint64_t *d, uint32_t G, uint32_t nf, uint32_t stripes,
                                    bool max_last = false);
-// exclusive scan of u32 counts into u64 offsets (out has n+1 entries)
-void scan_u32_to_u64(Ctx &c, const uint32_t *in, uint64_t *out, uint32_t n);
+// exclusive scan of u32 counts into u64 offsets (out has n+1 entries); sums:
+// scan_sums_count(n) words of scratch, or nullptr to take them from the arena
+void scan_u32_to_u64(Ctx &c, const uint32_t *in, uint64_t *out, uint32_t n, uint64_t *sums = nullptr);
+size_t scan_sums_count(uint32_t n);
 // per graph: sum_v cnt[v] * deg(v) and sum_v cnt[v]
 void ads_totals(Ctx &c, const Graph &g, const uint32_t *gid, uint32_t G, const uint32_t *cnt,
                 std::vector<uint64_t> &relax_alg, std::vector<uint64_t> &entries);

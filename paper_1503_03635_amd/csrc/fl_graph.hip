@@ -293,9 +293,11 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_add(uint64_t *out, uint32_t
     if (base + i < n) out[base + i] += add;
 }
 
-void scan_u32_to_u64(Ctx &c, const uint32_t *in, uint64_t *out, uint32_t n) {
+size_t scan_sums_count(uint32_t n) { return ceil_div(n ? n : 1, SCAN_TILE) + 1; }
+
+void scan_u32_to_u64(Ctx &c, const uint32_t *in, uint64_t *out, uint32_t n, uint64_t *sums) {
   uint32_t tiles = (uint32_t)ceil_div(n ? n : 1, SCAN_TILE);
-  uint64_t *sums = c.arena->get<uint64_t>(tiles + 1);
+  if (!sums) sums = c.arena->get<uint64_t>(tiles + 1);
   k_scan_tiles<<<tiles, SCAN_BLOCK, 0, c.s>>>(in, n, out, sums);
   FL_LAUNCH_CHECK();
   k_scan_sums<<<1, SCAN_BLOCK, 0, c.s>>>(sums, tiles, out + n);
