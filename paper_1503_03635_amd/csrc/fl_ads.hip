@@ -149,7 +149,7 @@ __device__ inline void mark_targets(const AdsArgs &P, bool want, uint32_t y, uin
     const bool mine = add && (UNITW || s == sl);
     const uint64_t grp = __ballot(mine);
     uint32_t base = 0;
-    if (lane == lead) base = atomicAdd(&P.wl_cnt[sl], (uint32_t)__popcll(grp));
+    if (lane == lead) base = atomicAdd(&P.wl_cnt[sl * CNT_PAD], (uint32_t)__popcll(grp));
     base = __shfl(base, lead, WAVE);
     if (mine) {
       P.wl[(size_t)sl * P.n + base + lanes_below(grp)] = y;
@@ -1261,7 +1261,7 @@ __global__ void k_reverse_arcs(uint32_t n, uint64_t m, const uint64_t *row_ptr, 
 __global__ void k_round_pending(const uint32_t *wl_cnt, uint32_t NS, const uint64_t *d_ntasks, uint64_t *pend,
                                 uint64_t *tasks) {
   uint64_t sum = 0;
-  for (uint32_t s = threadIdx.x; s < NS; s += WAVE) sum += wl_cnt[s];
+  for (uint32_t s = threadIdx.x; s < NS; s += WAVE) sum += wl_cnt[s * CNT_PAD];
   sum = wave_sum_u64(sum);
   if (threadIdx.x == 0) {
     *pend = sum;
@@ -1324,6 +1324,7 @@ size_t ads_scratch_bytes(uint32_t n, uint64_t m, uint32_t k, uint32_t NS) {
   b += (size_t)NS * n * (16 + 4);          // per-slot level records + worklists
   b += (size_t)m * 4 + (size_t)NS * (m / 32 + 2) * 4;  // reverse-arc positions, arc bit planes
   b += (size_t)n * FW * 4;                 // worklist flags
+  b += (size_t)NS * CNT_PAD * 4;           // worklist lengths, one per line
   b += (size_t)slots * (ADS_SB * (k > 64 ? 2 : 1) + 1) * 4;   // kept sets of split tasks
   b += (size_t)tasks * 4 * 3 * 2 + (size_t)n * 4 * 3 * 2;  // two task lists
   b += (size_t)n * (4 * 3 + 8 * 3) + (size_t)n * 24;       // task scratch, dense list
@@ -1363,7 +1364,7 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
   P.lvl = c.arena->get<uint4>((size_t)NS * n);
   P.flags = c.arena->get<uint32_t>((size_t)n * FW);
   P.wl = c.arena->get<uint32_t>((size_t)NS * n);
-  P.wl_cnt = c.arena->get<uint32_t>(NS);
+  P.wl_cnt = c.arena->get<uint32_t>((size_t)NS * CNT_PAD);
   P.ctr = c.arena->get<uint64_t>(512);
   P.dbg = std::getenv("FL_DEBUG") ? 1u : 0u;
   P.status = c.arena->get<uint32_t>(4);
@@ -1391,7 +1392,7 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
   }
   fill_u64(c, reinterpret_cast<uint64_t *>(P.lvl), (size_t)NS * n * 2, INF64);  // no level anywhere
   fill_u32(c, P.flags, (size_t)n * FW, 0);
-  fill_u32(c, P.wl_cnt, NS, 0);
+  fill_u32(c, P.wl_cnt, (size_t)NS * CNT_PAD, 0);
   fill_u64(c, P.ctr, 512, 0);
   fill_u32(c, P.status, 4, 0);
 
@@ -1509,7 +1510,7 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
         const uint32_t slot = D % NS;
         const uint32_t task_arcs = (P.plane && D >= P.flag_from) ? TASK_ARCS_FLAGGED : TASK_ARCS_SPARSE;
         fill_u64(c, tot, 3, 0);
-        k_task_build<<<TB, 256, 0, c.s>>>(P.wl + (size_t)slot * n, P.wl_cnt + slot, g.in_ptr, task_arcs, tot,
+        k_task_build<<<TB, 256, 0, c.s>>>(P.wl + (size_t)slot * n, P.wl_cnt + (size_t)slot * CNT_PAD, g.in_ptr, task_arcs, tot,
                                           tl.task_u, tl.task_sub, tl.task_slot, tl.split_u, tl.split_first,
                                           tl.split_nt);
         FL_LAUNCH_CHECK();
@@ -1542,7 +1543,7 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
                                                                   d_nsplit, 1);
         FL_LAUNCH_CHECK();
         if (c.timing) FL_HIP(hipEventRecord(ev[3 * r + 2], c.s));
-        fill_u32(c, P.wl_cnt + slot, 1, 0);
+        fill_u32(c, P.wl_cnt + (size_t)slot * CNT_PAD, 1, 0);
         if (P.plane) fill_u32(c, P.plane + (size_t)slot * P.pw, P.pw, 0);
         k_round_pending<<<1, WAVE, 0, c.s>>>(P.wl_cnt, NS, d_ntasks, pend + r, pend + RCHUNK + r);
         FL_LAUNCH_CHECK();
@@ -1593,7 +1594,7 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
       // slot D is filled by rounds before D, so the previous readback is exact
       uint32_t count = hwl[slot];
       if (!hwl_valid) {
-        FL_HIP(hipMemcpyAsync(c.h_status, P.wl_cnt + slot, 4, hipMemcpyDeviceToHost, c.s));
+        FL_HIP(hipMemcpyAsync(c.h_status, P.wl_cnt + (size_t)slot * CNT_PAD, 4, hipMemcpyDeviceToHost, c.s));
         c.sync();
         count = (uint32_t)(c.h_status[0] & 0xFFFFFFFFu);
       }
@@ -1640,13 +1641,13 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
       }
       if (c.timing) FL_HIP(hipEventRecord(e1, c.s));
     }
-    if (sparse) fill_u32(c, P.wl_cnt + slot, 1, 0);
+    if (sparse) fill_u32(c, P.wl_cnt + (size_t)slot * CNT_PAD, 1, 0);
     // the plane of this round is read; commits of later rounds refill it
     if (P.plane) fill_u32(c, P.plane + (size_t)slot * P.pw, P.pw, 0);
     ++rounds;
     FL_HIP(hipMemcpyAsync(c.h_status, P.status, 8, hipMemcpyDeviceToHost, c.s));
     FL_HIP(hipMemcpyAsync(c.h_status + 1, P.ctr + 64, 64 * 8, hipMemcpyDeviceToHost, c.s));
-    FL_HIP(hipMemcpyAsync(hwl.data(), P.wl_cnt, NS * 4, hipMemcpyDeviceToHost, c.s));
+    FL_HIP(hipMemcpy2DAsync(hwl.data(), 4, P.wl_cnt, CNT_PAD * 4, 4, NS, hipMemcpyDeviceToHost, c.s));
     c.sync();
     hwl_valid = true;
     if (T->ntasks) {

@@ -341,7 +341,8 @@ static size_t estimate_bytes(uint32_t n, uint64_t m, uint64_t nF, uint32_t k, ui
   b += (size_t)nF * cap * 4;               // HIP thresholds
   b += (size_t)n * 32;                     // outputs kept while the sketches are built
   const size_t ads = ads_scratch_bytes(n, m, k, NS);
-  const size_t later = (size_t)NS * n * 8 + (size_t)n * 200 + (size_t)m / 64 + (size_t)nF * 96;  // opening loop, MIS, assignment
+  const size_t later = (size_t)NS * n * 8 + (size_t)NS * CNT_PAD * 4 + (size_t)n * 200 + (size_t)m / 64 +
+                       (size_t)nF * 96;  // opening loop, MIS, assignment
   b += ads > later ? ads : later;
   b += (size_t)64 << 20;                   // counters, scans
   return b;

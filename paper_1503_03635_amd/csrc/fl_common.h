@@ -413,6 +413,17 @@ struct Graph {
   const uint32_t *out_to_in = nullptr;
 };
 
+// Per-slot queue counters, which every wave of a round increments, sit one
+// per 128-byte line (CNT_PAD u32 apart): packed together, the ~100 counters
+// of a weighted graph share a few lines and every append of the round queues
+// on them.
+constexpr uint32_t CNT_PAD = 32;
+// host copy of `count` padded counters (dense on the host); waits
+inline void fetch_padded(Ctx &c, uint32_t *host, const uint32_t *dev, uint32_t count) {
+  FL_HIP(hipMemcpy2DAsync(host, 4, dev, CNT_PAD * 4, 4, count, hipMemcpyDeviceToHost, c.s));
+  c.sync();
+}
+
 // fill / utility launches (fl_graph.hip)
 void fill_u32(Ctx &c, uint32_t *p, uint64_t n, uint32_t v);
 void fill_u64(Ctx &c, uint64_t *p, uint64_t n, uint64_t v);

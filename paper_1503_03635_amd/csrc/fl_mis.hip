@@ -46,7 +46,7 @@ struct SweepArgs {
   uint32_t *ml;       // [n] current minimum label (INF32 = none)
   uint32_t *pend;     // [NS * n] pending label per slot
   uint32_t *tl;       // [NS * n] vertices with a pending label per slot
-  uint32_t *tl_cnt;   // [NS]
+  uint32_t *tl_cnt;   // [NS * CNT_PAD] list length of each slot, one per line
   uint32_t *touched;  // [n] vertices whose ml was set
   uint32_t *touched_cnt;
   uint64_t *heavy;    // pieces of the long rows queued in the current distance
@@ -74,7 +74,7 @@ __device__ inline void slotq_write(const SweepArgs &S, bool have, uint32_t y, ui
     const bool mine = have && s == sl;
     const uint64_t grp = __ballot(mine);
     uint32_t base = 0;
-    if (lane == lead) base = atomicAdd(&S.tl_cnt[sl], (uint32_t)__popcll(grp));
+    if (lane == lead) base = atomicAdd(&S.tl_cnt[sl * CNT_PAD], (uint32_t)__popcll(grp));
     base = __shfl(base, lead, WAVE);
     if (mine) {
       S.tl[(size_t)sl * S.n + base + lanes_below(grp)] = y;
@@ -201,7 +201,7 @@ __global__ __launch_bounds__(256) void k_sweep_init(SweepArgs S, const uint32_t 
 __global__ __launch_bounds__(256) void k_sweep_round(SweepArgs S, uint32_t j) {
   SLOTQ_DECL(q);
   const uint32_t slot = j % S.NS;
-  const uint32_t cnt = S.tl_cnt[slot];
+  const uint32_t cnt = S.tl_cnt[slot * CNT_PAD];
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x; b < cnt; b += stride) {
     const uint64_t i = b + threadIdx.x;
@@ -233,7 +233,7 @@ __global__ __launch_bounds__(256) void k_sweep_heavy(SweepArgs S, uint32_t j) {
   const int lane = lane_id();
   const uint32_t cnt = S.heavy_cnt[j & 1];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    S.tl_cnt[j % S.NS] = 0;
+    S.tl_cnt[(j % S.NS) * CNT_PAD] = 0;
     S.heavy_cnt[(j + 1) & 1] = 0;
   }
   const uint64_t nw = ((uint64_t)gridDim.x * blockDim.x) / WAVE;
@@ -302,8 +302,7 @@ static void sweep(Ctx &c, MisWork &M, const uint32_t *src, uint32_t nsrc, uint32
     uint64_t pending = 1;
     uint32_t hmax = 0;
     if (!blind) {
-      FL_HIP(hipMemcpyAsync(h.data(), S.tl_cnt, S.NS * 4, hipMemcpyDeviceToHost, c.s));
-      c.sync();
+      fetch_padded(c, h.data(), S.tl_cnt, S.NS);
       pending = 0;
       for (uint32_t s = 0; s < S.NS; ++s) {
         pending += h[s];
@@ -621,7 +620,7 @@ int mis_phase(Ctx &c, const MisIn &in, uint8_t *open, std::vector<uint32_t> &rou
   M.S.ml = c.arena->get<uint32_t>(n);
   M.S.pend = c.arena->get<uint32_t>((size_t)NS * n);
   M.S.tl = c.arena->get<uint32_t>((size_t)NS * n);
-  M.S.tl_cnt = c.arena->get<uint32_t>(NS);
+  M.S.tl_cnt = c.arena->get<uint32_t>((size_t)NS * CNT_PAD);
   M.S.touched = c.arena->get<uint32_t>(n);
   M.S.touched_cnt = c.arena->get<uint32_t>(1);
   M.S.heavy = c.arena->get<uint64_t>(piece_capacity(n, g.m));
@@ -645,7 +644,7 @@ int mis_phase(Ctx &c, const MisIn &in, uint8_t *open, std::vector<uint32_t> &rou
   rb.len = c.arena->get<uint32_t>(G);
   fill_u32(c, M.S.ml, n, INF32);
   fill_u32(c, M.S.pend, (size_t)NS * n, INF32);
-  fill_u32(c, M.S.tl_cnt, NS, 0);
+  fill_u32(c, M.S.tl_cnt, (size_t)NS * CNT_PAD, 0);
   fill_u32(c, M.S.touched_cnt, 1, 0);
   fill_u32(c, M.S.heavy_cnt, 2, 0);
   fill_u32(c, M.cbits, nwords, 0);
