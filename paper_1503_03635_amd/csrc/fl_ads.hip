@@ -78,6 +78,22 @@ static_assert(TASK_ARCS_FLAGGED >= TASK_ARCS, "scratch slots are sized for TASK_
 constexpr uint32_t NBKT = 64;       // id buckets of the level prune (one per lane)
 constexpr uint32_t LONG_LIST = 64;  // entry lists at least this long are streamed one arc at a time
 
+// Statistics counters of the sketch rounds, cumulative over a build: one
+// 128-byte line per stripe holds every field, and a block adds into stripe
+// blockIdx.x % CTR_STRIPES (a field striped over consecutive words would put
+// ~16 blocks on each line).
+constexpr uint32_t CTR_STRIPES = 256, CTR_FIELDS = 16;
+enum CtrField : uint32_t {
+  CF_EXAMINED = 0,  // relaxations executed
+  CF_COMMITS,       // levels committed (vertices that changed)
+  CF_SURVIVORS,     // candidates kept after the offer filters
+  CF_PRUNES,        // level prunes
+  CF_SCANNED,       // arcs scanned (dbg)
+  CF_MATCHED,       // level records matched (dbg)
+  CF_MARK_ARCS,     // arcs examined for marking (dbg)
+  CF_MARKED,        // heads that passed the marking filter (dbg)
+  CF_COUNT
+};
 struct AdsArgs {
   uint32_t n, k, cap, W, NS, FW;
   const uint32_t *gid;  // graph of each vertex (nullptr: one graph)
@@ -107,9 +123,7 @@ struct AdsArgs {
   const uint32_t *out_to_in;  // [m] out-arc -> in-arc position
   uint32_t *kept;      // [slots * ADS_SB * KR] kept ids of split tasks
   uint32_t *kept_cnt;  // [slots]
-  uint64_t *ctr;       // [64] relax_exec, [64] active vertices this round, [64] survivors, [64] prunes,
-                       // with dbg also [64] arcs scanned, [64] level records matched, [64] arcs
-                       // examined for marking, [64] targets that passed the marking filter
+  uint64_t *ctr;       // [CTR_STRIPES * CTR_FIELDS] cumulative counters, see CtrField
   uint32_t dbg;
   uint32_t *status;    // [0] capacity overflow, [1] survivor-buffer overflow
   uint32_t *thr;             // [rows * cap] threshold rows: canonical-order ranks until the last pass
@@ -118,6 +132,10 @@ struct AdsArgs {
 
 __device__ inline uint32_t thr_row(const AdsArgs &P, uint32_t u) {
   return P.thr ? (P.thr_idx ? P.thr_idx[u] : u) : INF32;
+}
+
+__device__ inline void ctr_add(const AdsArgs &P, CtrField f, uint64_t v) {
+  atomicAdd((unsigned long long *)&P.ctr[(blockIdx.x % CTR_STRIPES) * CTR_FIELDS + f], (unsigned long long)v);
 }
 
 // The level a vertex committed at distance D stays in slot D % NS until the
@@ -181,9 +199,8 @@ __device__ inline void mark_neighbours(const AdsArgs &P, uint32_t u, uint32_t D)
     if (P.dbg) {
       const uint64_t wm = __ballot(want);
       if (lane == 0) {
-        atomicAdd((unsigned long long *)&P.ctr[384 + (blockIdx.x & 63)],
-                  (unsigned long long)(a1 - b < WAVE ? a1 - b : WAVE));
-        atomicAdd((unsigned long long *)&P.ctr[448 + (blockIdx.x & 63)], (unsigned long long)__popcll(wm));
+        ctr_add(P, CF_MARK_ARCS, a1 - b < WAVE ? a1 - b : WAVE);
+        ctr_add(P, CF_MARKED, __popcll(wm));
       }
     }
     mark_targets<UNITW>(P, want, y, s);
@@ -849,7 +866,7 @@ __device__ inline void level_commit(const AdsArgs &P, uint32_t u, uint32_t D, Le
   if (lane == 0) {
     P.cnt[u] = cu + m;
     P.lvl[(size_t)(D % P.NS) * P.n + u] = level_record(D, x0, x1, cu, m);
-    atomicAdd((unsigned long long *)&P.ctr[64 + (blockIdx.x & 63)], 1ull);
+    ctr_add(P, CF_COMMITS, 1);
   }
   if (mark) mark_neighbours<UNITW>(P, u, D);
 }
@@ -878,15 +895,15 @@ __device__ inline void ads_task(const AdsArgs &P, uint32_t D, uint32_t u, uint32
                                 ? gather_flagged<UNITW, KR>(P, D, a0, a1, L, s_id, s_tmp, s_cnt)
                                                  : gather_arcs<UNITW, KR>(P, D, a0, a1, L, s_id, s_tmp, s_cnt);
   if (lane == 0) {
-    atomicAdd((unsigned long long *)&P.ctr[blockIdx.x & 63], (unsigned long long)examined);
-    atomicAdd((unsigned long long *)&P.ctr[128 + (blockIdx.x & 63)], (unsigned long long)L.nsurv);
-    atomicAdd((unsigned long long *)&P.ctr[192 + (blockIdx.x & 63)], (unsigned long long)L.nprune);
+    ctr_add(P, CF_EXAMINED, examined);
+    ctr_add(P, CF_SURVIVORS, L.nsurv);
+    ctr_add(P, CF_PRUNES, L.nprune);
   }
   if (P.dbg) {
     const uint64_t nm = wave_sum_u64(L.nmatch);
     if (lane == 0) {
-      atomicAdd((unsigned long long *)&P.ctr[256 + (blockIdx.x & 63)], (unsigned long long)(a1 - a0));
-      atomicAdd((unsigned long long *)&P.ctr[320 + (blockIdx.x & 63)], (unsigned long long)nm);
+      ctr_add(P, CF_SCANNED, a1 - a0);
+      ctr_add(P, CF_MATCHED, nm);
     }
   }
   if (L.overflow) {
@@ -1365,7 +1382,7 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
   P.flags = c.arena->get<uint32_t>((size_t)n * FW);
   P.wl = c.arena->get<uint32_t>((size_t)NS * n);
   P.wl_cnt = c.arena->get<uint32_t>((size_t)NS * CNT_PAD);
-  P.ctr = c.arena->get<uint64_t>(512);
+  P.ctr = c.arena->get<uint64_t>((size_t)CTR_STRIPES * CTR_FIELDS);
   P.dbg = std::getenv("FL_DEBUG") ? 1u : 0u;
   P.status = c.arena->get<uint32_t>(4);
   P.thr = o.thr;
@@ -1393,7 +1410,7 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
   fill_u64(c, reinterpret_cast<uint64_t *>(P.lvl), (size_t)NS * n * 2, INF64);  // no level anywhere
   fill_u32(c, P.flags, (size_t)n * FW, 0);
   fill_u32(c, P.wl_cnt, (size_t)NS * CNT_PAD, 0);
-  fill_u64(c, P.ctr, 512, 0);
+  fill_u64(c, P.ctr, (size_t)CTR_STRIPES * CTR_FIELDS, 0);
   fill_u32(c, P.status, 4, 0);
 
   // scratch slots: enough for every vertex split at once
@@ -1478,6 +1495,8 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
   o.merge_ms = 0.0;
   o.launches = 0;
   uint64_t active_prev = n;
+  uint64_t commits_prev = 0;  // commits counted before this round
+  std::vector<uint64_t> hctr((size_t)CTR_STRIPES * CTR_FIELDS);
   uint32_t rounds = 0;
   std::vector<uint32_t> hwl(NS);
   bool hwl_valid = false;  // hwl holds the slot counts read back after the previous round
@@ -1604,7 +1623,6 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
     }
     // marking decision for this round (decides the mode of the next one)
     mark = !dense_ok || active_prev <= dense_threshold;
-    fill_u64(c, P.ctr + 64, 64, 0);
     if (T->ntasks) {
       if (c.timing) FL_HIP(hipEventRecord(e0, c.s));
       const uint32_t tb = (uint32_t)ceil_div(T->ntasks, TASK_WPB);
@@ -1646,9 +1664,8 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
     if (P.plane) fill_u32(c, P.plane + (size_t)slot * P.pw, P.pw, 0);
     ++rounds;
     FL_HIP(hipMemcpyAsync(c.h_status, P.status, 8, hipMemcpyDeviceToHost, c.s));
-    FL_HIP(hipMemcpyAsync(c.h_status + 1, P.ctr + 64, 64 * 8, hipMemcpyDeviceToHost, c.s));
-    FL_HIP(hipMemcpy2DAsync(hwl.data(), 4, P.wl_cnt, CNT_PAD * 4, 4, NS, hipMemcpyDeviceToHost, c.s));
-    c.sync();
+    FL_HIP(hipMemcpyAsync(hctr.data(), P.ctr, hctr.size() * 8, hipMemcpyDeviceToHost, c.s));
+    fetch_padded(c, hwl.data(), P.wl_cnt, NS);  // waits for both
     hwl_valid = true;
     if (T->ntasks) {
       float ms = 0.f, ms2 = 0.f;
@@ -1660,20 +1677,13 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
       o.merge_ms += ms2;
       o.launches += 1;
       if (std::getenv("FL_DEBUG")) {
-        std::vector<uint64_t> hs(512);
-        FL_HIP(hipMemcpy(hs.data(), P.ctr, 512 * 8, hipMemcpyDeviceToHost));
-        uint64_t ex = 0, sv = 0, pr = 0, sc = 0, mt = 0, ma = 0, mp = 0;
-        for (int i = 0; i < 64; ++i) {
-          ex += hs[i];
-          sv += hs[128 + i];
-          pr += hs[192 + i];
-          sc += hs[256 + i];
-          mt += hs[320 + i];
-          ma += hs[384 + i];
-          mp += hs[448 + i];
-        }
-        uint64_t act = 0;
-        for (int i = 0; i < 64; ++i) act += hs[64 + i];
+        std::vector<uint64_t> hs((size_t)CTR_STRIPES * CTR_FIELDS), f(CF_COUNT, 0);
+        FL_HIP(hipMemcpy(hs.data(), P.ctr, hs.size() * 8, hipMemcpyDeviceToHost));
+        for (uint32_t i = 0; i < CTR_STRIPES; ++i)
+          for (uint32_t q = 0; q < CF_COUNT; ++q) f[q] += hs[(size_t)i * CTR_FIELDS + q];
+        const uint64_t ex = f[CF_EXAMINED], sv = f[CF_SURVIVORS], pr = f[CF_PRUNES], sc = f[CF_SCANNED],
+                       mt = f[CF_MATCHED], ma = f[CF_MARK_ARCS], mp = f[CF_MARKED];
+        const uint64_t act = f[CF_COMMITS] - commits_prev;
         std::fprintf(stderr, "[fl] round %u: %s, %u tasks, %u split, %llu changed, %.2f ms, merge %.2f ms, "
                      "examined(cum) %.3fG survivors(cum) %.3fG prunes(cum) %.3fM scanned(cum) %.3fG "
                      "matched(cum) %.3fG markarcs(cum) %.3fG marked(cum) %.3fG\n",
@@ -1688,8 +1698,10 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
       return FL_OK;
     }
     if (st1) return FL_ENOMEM;
-    uint64_t active = 0;
-    for (int i = 0; i < 64; ++i) active += c.h_status[1 + i];
+    uint64_t commits = 0;
+    for (uint32_t i = 0; i < CTR_STRIPES; ++i) commits += hctr[(size_t)i * CTR_FIELDS + CF_COMMITS];
+    const uint64_t active = commits - commits_prev;  // vertices that changed this round
+    commits_prev = commits;
     uint64_t pending = 0;
     for (uint32_t s = 0; s < NS; ++s) pending += hwl[s];
     if (unit) {
@@ -1703,11 +1715,11 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
     if ((uint64_t)D > (uint64_t)(n - 1) * W + 2) return FL_EHIP;
   }
   o.rounds = rounds;
-  std::vector<uint64_t> hc(64);
-  FL_HIP(hipMemcpyAsync(hc.data(), P.ctr, 64 * 8, hipMemcpyDeviceToHost, c.s));
+  std::vector<uint64_t> hc((size_t)CTR_STRIPES * CTR_FIELDS);
+  FL_HIP(hipMemcpyAsync(hc.data(), P.ctr, hc.size() * 8, hipMemcpyDeviceToHost, c.s));
   c.sync();
   o.relax_exec = 0;
-  for (int i = 0; i < 64; ++i) o.relax_exec += hc[i];
+  for (uint32_t i = 0; i < CTR_STRIPES; ++i) o.relax_exec += hc[(size_t)i * CTR_FIELDS + CF_EXAMINED];
   return FL_OK;
 }
 

@@ -418,10 +418,13 @@ struct Graph {
 // of a weighted graph share a few lines and every append of the round queues
 // on them.
 constexpr uint32_t CNT_PAD = 32;
-// host copy of `count` padded counters (dense on the host); waits
+// host copy of `count` padded counters (dense in `host`); waits.  The slot
+// ring has at most MAX_W + 1 counters, so the padded array is at most 32 KB.
 inline void fetch_padded(Ctx &c, uint32_t *host, const uint32_t *dev, uint32_t count) {
-  FL_HIP(hipMemcpy2DAsync(host, 4, dev, CNT_PAD * 4, 4, count, hipMemcpyDeviceToHost, c.s));
+  std::vector<uint32_t> tmp((size_t)count * CNT_PAD);
+  FL_HIP(hipMemcpyAsync(tmp.data(), dev, tmp.size() * 4, hipMemcpyDeviceToHost, c.s));
   c.sync();
+  for (uint32_t i = 0; i < count; ++i) host[i] = tmp[(size_t)i * CNT_PAD];
 }
 
 // fill / utility launches (fl_graph.hip)
