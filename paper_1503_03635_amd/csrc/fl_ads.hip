@@ -178,12 +178,15 @@ __device__ inline void mark_targets(const AdsArgs &P, bool want, uint32_t y, uin
 }
 
 // u committed a level at distance D: queue each head y of an arc u -> y for
-// round D + w, and set the arc's bit in that round's plane.
+// round D + w, and set the arc's bit in that round's plane.  Several waves
+// can share a long row: wave `part` of `parts` takes every parts-th group of
+// 64 arcs.
 template <bool UNITW>
-__device__ inline void mark_neighbours(const AdsArgs &P, uint32_t u, uint32_t D) {
+__device__ inline void mark_neighbours(const AdsArgs &P, uint32_t u, uint32_t D, uint32_t part = 0,
+                                       uint32_t parts = 1) {
   const int lane = lane_id();
   const uint64_t a0 = P.out_ptr[u], a1 = P.out_ptr[u + 1];
-  for (uint64_t b = a0; b < a1; b += WAVE) {
+  for (uint64_t b = a0 + (uint64_t)part * WAVE; b < a1; b += (uint64_t)parts * WAVE) {
     const uint64_t a = b + lane;
     bool want = a < a1;
     uint32_t y = 0, s = 0;
@@ -818,18 +821,18 @@ __device__ inline uint64_t gather_flagged(const AdsArgs &P, uint32_t D, uint64_t
 
 // Final prune of u's level-D candidates and the append of the accepted ones.
 template <bool UNITW, int KR>
-__device__ inline void level_commit(const AdsArgs &P, uint32_t u, uint32_t D, Level<KR> &L, int mark, uint32_t *s_id,
+__device__ inline bool level_commit(const AdsArgs &P, uint32_t u, uint32_t D, Level<KR> &L, int mark, uint32_t *s_id,
                                     uint32_t *s_tmp, uint32_t *s_cnt) {
   const int lane = lane_id();
-  if (L.ns == 0) return;
+  if (L.ns == 0) return false;
   KSet<KR> set = L.set0;
   uint32_t nset = L.nset0;
   const uint32_t m = prune_level(s_id, s_tmp, s_cnt, L.ns, P.k, L.rm, set, nset);
-  if (m == 0) return;
+  if (m == 0) return false;
   const uint32_t cu = L.cu;
   if (cu + m > P.cap) {
     if (lane == 0) atomicOr(&P.status[0], 1u);
-    return;
+    return false;
   }
   // The level is stored in increasing rank order, so that a neighbour reads
   // it only up to its own threshold.  A row with a threshold row also gets the
@@ -869,6 +872,7 @@ __device__ inline void level_commit(const AdsArgs &P, uint32_t u, uint32_t D, Le
     ctr_add(P, CF_COMMITS, 1);
   }
   if (mark) mark_neighbours<UNITW>(P, u, D);
+  return true;
 }
 
 // One task, by one wave.  slot == INF32: the task is the whole vertex and
@@ -961,6 +965,7 @@ __global__ __launch_bounds__(MERGE_WPB * WAVE) void k_ads_merge(AdsArgs P, uint3
   __shared__ uint32_t lds_tmp[MERGE_WPB][SB];
   __shared__ __align__(16) uint32_t lds_cnt[MERGE_WPB][(2 + KR) * WAVE];
   __shared__ uint32_t part_n[MERGE_WPB];
+  __shared__ uint32_t s_mark;  // the item committed a level: its out-arcs are marked
   const int lane = lane_id();
   const int wv = threadIdx.x / WAVE;
   uint32_t *s_id = lds_id[wv];
@@ -1028,13 +1033,19 @@ __global__ __launch_bounds__(MERGE_WPB * WAVE) void k_ads_merge(AdsArgs P, uint3
           level_offer(P, L, valid, r, true, id, s_id, s_tmp, s_cnt);
         }
       }
+      bool committed = false;
       if (L.overflow) {
         if (lane == 0) atomicOr(&P.status[1], 1u);
       } else {
-        level_commit<UNITW, KR>(P, u, D, L, mark, s_id, s_tmp, s_cnt);
+        committed = level_commit<UNITW, KR>(P, u, D, L, 0, s_id, s_tmp, s_cnt);
       }
+      if (lane == 0) s_mark = committed && mark ? 1u : 0u;
     }
-    __syncthreads();  // the partial sets are read before the next item rebuilds them
+    // the partial sets are read before the next item rebuilds them; s_mark is
+    // read by every wave before wave 0 passes the next item's first barrier
+    __syncthreads();
+    // a split vertex is a hub: every wave of the block marks a share of its out-arcs
+    if (s_mark) mark_neighbours<UNITW>(P, u, D, (uint32_t)wv, MERGE_WPB);
   }
 }
 
