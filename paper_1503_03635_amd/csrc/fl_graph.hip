@@ -36,8 +36,12 @@ void fill_f64(Ctx &c, double *p, uint64_t n, double v) { fill_t(c, p, n, v); }
 // ---------------------------------------------------------------------------
 // Validation (a simple undirected graph as a symmetric CSR, Sec. 3.1; a
 // directed graph gives its out-arcs and skips the symmetry test).  One wave
-// per vertex; lanes walk the row.  err bits: 1 = structural error.  Also
-// reduces max weight and max facility cost.
+// per vertex (waves stride over the vertices); lanes walk the row.  err
+// bits: 1 = structural error.  Also reduces max weight and max facility
+// cost.  Each block reduces its waves' results in LDS and adds them to
+// stripe blockIdx.x % stripes, one 128-byte line per stripe: v32[32 s + 0]
+// error bits, [32 s + 1] max weight, [32 s + 2] max cost; lt[16 s + 0]
+// leading arcs, [16 s + 1] trailing arcs.
 //
 // Symmetry: an arc u -> v is "leading" when u has the larger degree (ties:
 // the larger id).  Only leading arcs look up their reverse, by binary search
@@ -61,25 +65,31 @@ __device__ inline bool find_arc(const uint64_t *row_ptr, const uint32_t *col, ui
   return lo < end && col[lo] == v;
 }
 
+constexpr uint32_t VAL_STRIDE32 = 32, VAL_STRIDE64 = 16;  // one 128-byte line per stripe
+constexpr uint32_t VAL_BLOCKS = 4096;                      // grid of a validation launch (at most)
 __global__ __launch_bounds__(256) void k_validate(uint32_t n, uint64_t m, const uint64_t *row_ptr,
                                                   const uint32_t *col, const uint32_t *w,
-                                                  const uint32_t *fac_cost, uint32_t *err,
-                                                  uint32_t *maxw, uint32_t *maxc, uint32_t stripes,
-                                                  uint32_t directed, unsigned long long *lead_trail) {
+                                                  const uint32_t *fac_cost, uint32_t *v32, uint32_t stripes,
+                                                  uint32_t directed, unsigned long long *lt) {
+  __shared__ uint32_t sh_bad[256 / WAVE], sh_mw[256 / WAVE], sh_mc[256 / WAVE];
+  __shared__ unsigned long long sh_lead[256 / WAVE], sh_trail[256 / WAVE];
   const int lane = lane_id();
-  const uint64_t u64 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
-  if (u64 >= n) return;
-  const uint32_t u = (uint32_t)u64;
-  uint32_t bad = 0, mw = 0;
-  uint32_t nlead = 0, ntrail = 0;
-  const uint64_t a0 = row_ptr[u], a1 = row_ptr[u + 1];
-  if (a1 < a0 || a1 > m) bad = 1;
-  if (!bad) {
+  const uint32_t wv = threadIdx.x / WAVE;
+  uint32_t bad = 0, mw = 0, mc = 0;
+  uint64_t nlead = 0, ntrail = 0;
+  const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x / WAVE);
+  for (uint64_t u64 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE; u64 < n; u64 += nwaves) {
+    const uint32_t u = (uint32_t)u64;
+    const uint64_t a0 = row_ptr[u], a1 = row_ptr[u + 1];
+    if (a1 < a0 || a1 > m) {
+      bad = 1;
+      continue;
+    }
     const uint64_t du = a1 - a0;
     for (uint64_t a = a0 + lane; a < a1; a += WAVE) {
       uint32_t v = col[a];
-      uint32_t wv = w ? w[a] : 1u;
-      if (v >= n || v == u || wv == 0) { bad = 1; continue; }
+      uint32_t wv_ = w ? w[a] : 1u;
+      if (v >= n || v == u || wv_ == 0) { bad = 1; continue; }
       if (a > a0 && col[a - 1] >= v) { bad = 1; continue; }
       if (!directed) {
         const uint64_t b0 = row_ptr[v], b1 = row_ptr[v + 1];
@@ -89,28 +99,53 @@ __global__ __launch_bounds__(256) void k_validate(uint32_t n, uint64_t m, const 
           ++nlead;
           uint64_t back;
           if (!find_arc(row_ptr, col, m, v, u, &back)) { bad = 1; continue; }
-          if ((w ? w[back] : 1u) != wv) bad = 1;
+          if ((w ? w[back] : 1u) != wv_) bad = 1;
         } else {
           ++ntrail;
         }
       }
-      mw = wv > mw ? wv : mw;
+      mw = wv_ > mw ? wv_ : mw;
+    }
+    if (fac_cost && lane == 0) {
+      const uint32_t cst = fac_cost[u];
+      if (cst != FL_NOT_FACILITY && cst > mc) mc = cst;
     }
   }
-  if (fac_cost && lane == 0) {
-    uint32_t cst = fac_cost[u];
-    if (cst != FL_NOT_FACILITY) atomicMax(&maxc[u % stripes], cst);
-  }
-  uint64_t anybad = __ballot(bad != 0);
-  mw = wave_min_u32(~mw);
-  mw = ~mw;  // wave max
+  const uint64_t anybad = __ballot(bad != 0);
+  mw = ~wave_min_u32(~mw);  // wave max
+  mc = ~wave_min_u32(~mc);
   const uint64_t lead = wave_sum_u64(nlead), trail = wave_sum_u64(ntrail);
   if (lane == 0) {
-    if (anybad) atomicOr(&err[u % stripes], 1u);
-    if (mw) atomicMax(&maxw[u % stripes], mw);
-    if (lead) atomicAdd(&lead_trail[2 * (u % stripes)], (unsigned long long)lead);
-    if (trail) atomicAdd(&lead_trail[2 * (u % stripes) + 1], (unsigned long long)trail);
+    sh_bad[wv] = anybad ? 1u : 0u;
+    sh_mw[wv] = mw;
+    sh_mc[wv] = mc;
+    sh_lead[wv] = lead;
+    sh_trail[wv] = trail;
   }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t b = 0, x = 0, c = 0;
+    unsigned long long l = 0, t = 0;
+    for (uint32_t i = 0; i < blockDim.x / WAVE; ++i) {
+      b |= sh_bad[i];
+      x = sh_mw[i] > x ? sh_mw[i] : x;
+      c = sh_mc[i] > c ? sh_mc[i] : c;
+      l += sh_lead[i];
+      t += sh_trail[i];
+    }
+    const uint32_t st = blockIdx.x % stripes;
+    uint32_t *q = v32 + (size_t)st * VAL_STRIDE32;
+    unsigned long long *r = lt + (size_t)st * VAL_STRIDE64;
+    if (b) atomicOr(&q[0], 1u);
+    if (x) atomicMax(&q[1], x);
+    if (c) atomicMax(&q[2], c);
+    if (l) atomicAdd(&r[0], l);
+    if (t) atomicAdd(&r[1], t);
+  }
+}
+
+static uint32_t validate_blocks(uint32_t n) {
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(ceil_div((uint64_t)n * WAVE, 256), VAL_BLOCKS));
 }
 
 int validate_graph(Ctx &c, const fl_problem *p, bool directed, uint32_t *max_w_out, uint32_t *max_cost_out) {
@@ -121,28 +156,28 @@ int validate_graph(Ctx &c, const fl_problem *p, bool directed, uint32_t *max_w_o
   FL_HIP(hipMemcpyAsync(&ends[1], p->row_ptr + n, 8, hipMemcpyDeviceToHost, c.s));
   c.sync();
   if (ends[0] != 0 || ends[1] != p->n_arcs) return FL_EINVAL;
-  uint32_t *d = c.arena->get<uint32_t>(3 * NCTR);
-  uint64_t *lt = c.arena->get<uint64_t>(2 * NCTR);
-  fill_u32(c, d, 3 * NCTR, 0);
-  fill_u64(c, lt, 2 * NCTR, 0);
-  uint64_t blocks = ceil_div((uint64_t)n * WAVE, 256);
-  k_validate<<<(uint32_t)blocks, 256, 0, c.s>>>(n, p->n_arcs, p->row_ptr, p->col, p->w, p->fac_cost,
-                                                 d, d + NCTR, d + 2 * NCTR, NCTR, directed ? 1u : 0u,
-                                                 reinterpret_cast<unsigned long long *>(lt));
+  constexpr uint32_t S = 64;  // stripes
+  uint32_t *d = c.arena->get<uint32_t>((size_t)S * VAL_STRIDE32);
+  uint64_t *lt = c.arena->get<uint64_t>((size_t)S * VAL_STRIDE64);
+  fill_u32(c, d, (size_t)S * VAL_STRIDE32, 0);
+  fill_u64(c, lt, (size_t)S * VAL_STRIDE64, 0);
+  k_validate<<<validate_blocks(n), 256, 0, c.s>>>(n, p->n_arcs, p->row_ptr, p->col, p->w, p->fac_cost, d, S,
+                                                  directed ? 1u : 0u, reinterpret_cast<unsigned long long *>(lt));
   FL_LAUNCH_CHECK();
-  std::vector<uint32_t> h(3 * NCTR);
-  std::vector<uint64_t> hl(2 * NCTR);
-  FL_HIP(hipMemcpyAsync(h.data(), d, 3 * NCTR * 4, hipMemcpyDeviceToHost, c.s));
-  FL_HIP(hipMemcpyAsync(hl.data(), lt, 2 * NCTR * 8, hipMemcpyDeviceToHost, c.s));
+  std::vector<uint32_t> h((size_t)S * VAL_STRIDE32);
+  std::vector<uint64_t> hl((size_t)S * VAL_STRIDE64);
+  FL_HIP(hipMemcpyAsync(h.data(), d, h.size() * 4, hipMemcpyDeviceToHost, c.s));
+  FL_HIP(hipMemcpyAsync(hl.data(), lt, hl.size() * 8, hipMemcpyDeviceToHost, c.s));
   c.sync();
   uint32_t err = 0, mw = 1, mc = 0;
   uint64_t lead = 0, trail = 0;
-  for (int i = 0; i < NCTR; ++i) {
-    err |= h[i];
-    mw = h[NCTR + i] > mw ? h[NCTR + i] : mw;
-    mc = h[2 * NCTR + i] > mc ? h[2 * NCTR + i] : mc;
-    lead += hl[2 * i];
-    trail += hl[2 * i + 1];
+  for (uint32_t i = 0; i < S; ++i) {
+    const uint32_t *q = &h[(size_t)i * VAL_STRIDE32];
+    err |= q[0];
+    mw = q[1] > mw ? q[1] : mw;
+    mc = q[2] > mc ? q[2] : mc;
+    lead += hl[(size_t)i * VAL_STRIDE64];
+    trail += hl[(size_t)i * VAL_STRIDE64 + 1];
   }
   if (err || lead != trail) return FL_EINVAL;
   *max_w_out = mw;
@@ -158,32 +193,33 @@ struct EndsDesc {
 };
 __global__ void k_check_ends(const EndsDesc *d, uint32_t G, uint32_t *err) {
   const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g < G && (d[g].row_ptr[0] != 0 || d[g].row_ptr[d[g].n] != d[g].m)) err[3 * g] |= 2u;
+  if (g < G && (d[g].row_ptr[0] != 0 || d[g].row_ptr[d[g].n] != d[g].m)) err[(size_t)g * VAL_STRIDE32] |= 2u;
 }
 
 void validate_graphs(Ctx &c, const fl_problem *const *ps, uint32_t G, bool directed, std::vector<int> &rc,
                      std::vector<uint32_t> &max_w, std::vector<uint32_t> &max_cost) {
-  uint32_t *d = c.arena->get<uint32_t>((size_t)3 * G);
-  uint64_t *lt = c.arena->get<uint64_t>((size_t)2 * G);
-  fill_u64(c, lt, (size_t)2 * G, 0);
+  // one stripe (a 128-byte line of counters) per graph
+  uint32_t *d = c.arena->get<uint32_t>((size_t)VAL_STRIDE32 * G);
+  uint64_t *lt = c.arena->get<uint64_t>((size_t)VAL_STRIDE64 * G);
+  fill_u64(c, lt, (size_t)VAL_STRIDE64 * G, 0);
   EndsDesc *ed = c.arena->get<EndsDesc>(G);
   std::vector<EndsDesc> hd(G);
   for (uint32_t g = 0; g < G; ++g) hd[g] = EndsDesc{ps[g]->row_ptr, ps[g]->n, ps[g]->n_arcs};
-  fill_u32(c, d, (size_t)3 * G, 0);
+  fill_u32(c, d, (size_t)VAL_STRIDE32 * G, 0);
   FL_HIP(hipMemcpyAsync(ed, hd.data(), G * sizeof(EndsDesc), hipMemcpyHostToDevice, c.s));
   k_check_ends<<<(uint32_t)ceil_div(G, 256), 256, 0, c.s>>>(ed, G, d);
   FL_LAUNCH_CHECK();
   // the row checks read row_ptr only inside [0, n_arcs], whatever its values
   for (uint32_t g = 0; g < G; ++g) {
     const fl_problem *p = ps[g];
-    const uint64_t blocks = ceil_div((uint64_t)p->n * WAVE, 256);
-    k_validate<<<(uint32_t)blocks, 256, 0, c.s>>>(p->n, p->n_arcs, p->row_ptr, p->col, p->w, p->fac_cost,
-                                                   d + 3 * g, d + 3 * g + 1, d + 3 * g + 2, 1, directed ? 1u : 0u,
-                                                   reinterpret_cast<unsigned long long *>(lt + 2 * g));
+    k_validate<<<validate_blocks(p->n), 256, 0, c.s>>>(p->n, p->n_arcs, p->row_ptr, p->col, p->w, p->fac_cost,
+                                                       d + (size_t)VAL_STRIDE32 * g, 1, directed ? 1u : 0u,
+                                                       reinterpret_cast<unsigned long long *>(lt) +
+                                                           (size_t)VAL_STRIDE64 * g);
     FL_LAUNCH_CHECK();
   }
-  std::vector<uint32_t> h((size_t)3 * G);
-  std::vector<uint64_t> hl((size_t)2 * G);
+  std::vector<uint32_t> h((size_t)VAL_STRIDE32 * G);
+  std::vector<uint64_t> hl((size_t)VAL_STRIDE64 * G);
   FL_HIP(hipMemcpyAsync(h.data(), d, h.size() * 4, hipMemcpyDeviceToHost, c.s));
   FL_HIP(hipMemcpyAsync(hl.data(), lt, hl.size() * 8, hipMemcpyDeviceToHost, c.s));
   c.sync();
@@ -191,9 +227,11 @@ void validate_graphs(Ctx &c, const fl_problem *const *ps, uint32_t G, bool direc
   max_w.assign(G, 1);
   max_cost.assign(G, 0);
   for (uint32_t g = 0; g < G; ++g) {
-    if (h[3 * g] || hl[2 * g] != hl[2 * g + 1]) rc[g] = FL_EINVAL;
-    max_w[g] = h[3 * g + 1] > 1 ? h[3 * g + 1] : 1u;
-    max_cost[g] = h[3 * g + 2];
+    const uint32_t *q = &h[(size_t)VAL_STRIDE32 * g];
+    const uint64_t *r = &hl[(size_t)VAL_STRIDE64 * g];
+    if (q[0] || r[0] != r[1]) rc[g] = FL_EINVAL;
+    max_w[g] = q[1] > 1 ? q[1] : 1u;
+    max_cost[g] = q[2];
   }
 }
 
