@@ -266,6 +266,33 @@ __device__ inline uint32_t wave_sort_reg(uint32_t x) {
   return x;
 }
 
+// Values of lanes 0..n-1 (n <= 64; lanes from n on hold INF32) sorted
+// ascending onto lanes 0..n-1, INF32 above.  Each lane counts the staged
+// values that come before its own (smaller, or equal on a lower lane), four
+// per LDS read, and writes its value there: for a few values this is cheaper
+// than the 21 exchange steps of the bitonic network.  s_r: 64 words, 16-byte
+// aligned, free on entry and on return.
+constexpr uint32_t COUNT_SORT_MAX = 16;
+__device__ inline uint32_t wave_sort_few(uint32_t x, uint32_t n, uint32_t *s_r) {
+  const uint32_t lane = (uint32_t)lane_id();
+  s_r[lane] = x;
+  wave_lds_sync();
+  uint32_t pos = 0;
+  for (uint32_t j4 = 0; j4 < n; j4 += 4) {
+    const uint4 v = *reinterpret_cast<const uint4 *>(&s_r[j4]);
+    pos += (v.x < x || (v.x == x && j4 + 0 < lane)) ? 1u : 0u;
+    pos += (v.y < x || (v.y == x && j4 + 1 < lane)) ? 1u : 0u;
+    pos += (v.z < x || (v.z == x && j4 + 2 < lane)) ? 1u : 0u;
+    pos += (v.w < x || (v.w == x && j4 + 3 < lane)) ? 1u : 0u;
+  }
+  wave_lds_sync();
+  if (lane < n) s_r[pos] = x;
+  wave_lds_sync();
+  const uint32_t y = lane < n ? s_r[lane] : INF32;
+  wave_lds_sync();
+  return y;
+}
+
 // Merge of a bitonic sequence held one value per lane into ascending
 // (desc = false) or descending order.
 __device__ inline uint32_t wave_bitonic_merge(uint32_t x, bool desc) {
@@ -450,7 +477,7 @@ __device__ inline uint32_t prune_level(uint32_t *s_id, uint32_t *s_tmp, uint32_t
   uint32_t m = 0, prev = INF32;
   if (ns <= (uint32_t)WAVE && !tbk) {
     uint32_t x = (uint32_t)lane < ns ? s_id[lane] : INF32;
-    x = wave_sort_reg(x);
+    x = ns <= COUNT_SORT_MAX ? wave_sort_few(x, ns, s_r) : wave_sort_reg(x);
     const uint64_t am = chunk_accept(x, k, rm, set, nset, prev, s_r);
     if ((am >> lane) & 1) s_tmp[lanes_below(am)] = x;
     wave_lds_sync();
@@ -481,7 +508,7 @@ __device__ inline uint32_t prune_level(uint32_t *s_id, uint32_t *s_tmp, uint32_t
   uint32_t npend = 0;
   auto flush = [&]() {
     uint32_t x = (uint32_t)lane < npend ? s_pend[lane] : INF32;
-    x = wave_sort_reg(x);
+    x = npend <= COUNT_SORT_MAX ? wave_sort_few(x, npend, s_r) : wave_sort_reg(x);
     const uint64_t am = chunk_accept(x, k, rm, set, nset, prev, s_r);
     if ((am >> lane) & 1) s_tmp[m + lanes_below(am)] = x;
     m += (uint32_t)__popcll(am);
@@ -839,7 +866,7 @@ __device__ inline bool level_commit(const AdsArgs &P, uint32_t u, uint32_t D, Le
   uint32_t x0, x1;  // the two smallest ranks of the level, for its record
   if (m <= (uint32_t)WAVE) {
     uint32_t x = (uint32_t)lane < m ? rank_of(s_tmp[lane], L.rm) : INF32;
-    x = wave_sort_reg(x);
+    x = m <= COUNT_SORT_MAX ? wave_sort_few(x, m, s_cnt + (1 + KR) * WAVE) : wave_sort_reg(x);
     if ((uint32_t)lane < m) {
       P.sk_rank[base + lane] = x;
       P.sk_dist[base + lane] = D;
