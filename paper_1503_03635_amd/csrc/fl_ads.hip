@@ -55,9 +55,14 @@ namespace fl {
 
 constexpr int TASK_WPB = 1;         // waves per block of the round kernels: a block's LDS is
                                     // freed when its own task ends (task lengths vary widely)
-constexpr uint32_t ADS_SB = 1024;   // survivor ids per wave and set register: one level of one sketch
-                                    // plus a chunk (twice that when k > 64)
+// Survivor buffer of a level (ids per wave): ADS_SB for k <= 64, twice that
+// for k <= 128.  A level accepts about k (1 + ln(N / k)) of its N candidates
+// (453 for k = 32 and N = 2^24), so k <= 32 starts with half the buffer: the
+// round kernel then fits 5 waves per SIMD instead of 4.  A level that
+// overflows it anyway restarts the build with the full buffer.
+constexpr uint32_t ADS_SB = 1024;
 static_assert((ADS_SB & (ADS_SB - 1)) == 0, "wave_sort_lds pads to a power of two inside the buffer");
+inline uint32_t ads_full_sb(uint32_t k) { return k > 64 ? 2 * ADS_SB : ADS_SB; }
 constexpr uint32_t TASK_ARCS = 1024;  // arcs per task of a split vertex in dense rounds (the fewest)
 // Sparse rounds (worklists) cut only longer rows: there a hub is active in
 // most rounds but few of its arcs bring candidates, and every split costs a
@@ -121,7 +126,8 @@ struct AdsArgs {
   uint32_t flag_from;         // first round whose tasks read only flagged arcs
   uint32_t plane_from;        // first round whose commits set plane bits (flag_from - max weight)
   const uint32_t *out_to_in;  // [m] out-arc -> in-arc position
-  uint32_t *kept;      // [slots * ADS_SB * KR] kept ids of split tasks
+  uint32_t *kept;      // [slots * sb] kept ids of split tasks
+  uint32_t sb;         // survivor buffer of the build (the round kernels' template argument)
   uint32_t *kept_cnt;  // [slots]
   uint64_t *ctr;       // [CTR_STRIPES * CTR_FIELDS] cumulative counters, see CtrField
   uint32_t dbg;
@@ -624,10 +630,9 @@ __device__ inline void level_init(const AdsArgs &P, uint32_t u, Level<KR> &L, ui
 // One candidate per lane (valid, rank r, id if known): keep it if its rank is
 // below T0 and it is not already in the set; buffer kept ids, shrinking the
 // buffer by a prune against the set when full.
-template <int KR>
+template <int KR, uint32_t SB>
 __device__ inline void level_offer(const AdsArgs &P, Level<KR> &L, bool valid, uint32_t r, bool have_id, uint32_t id,
                                    uint32_t *s_id, uint32_t *s_tmp, uint32_t *s_cnt) {
-  constexpr uint32_t SB = ADS_SB * KR;
   const uint32_t *s_set0 = s_cnt + WAVE;  // LDS copy of the set at the level start
   const int lane = lane_id();
   bool pass = valid && (!L.full0 || r < L.T0);
@@ -678,7 +683,7 @@ __device__ inline void level_offer(const AdsArgs &P, Level<KR> &L, bool valid, u
 // two entries come from the record; longer ones from the tail's sketch row,
 // the whole wave on one list at a time when it is long (a level is stored in
 // increasing rank order, so once a rank reaches T0 the rest cannot enter).
-template <bool UNITW, int KR>
+template <bool UNITW, int KR, uint32_t SB>
 __device__ inline uint64_t gather_batch(const AdsArgs &P, uint32_t D, uint64_t a, bool valid, Level<KR> &L,
                                         uint32_t *s_id, uint32_t *s_tmp, uint32_t *s_cnt) {
   const int lane = lane_id();
@@ -706,8 +711,8 @@ __device__ inline uint64_t gather_batch(const AdsArgs &P, uint32_t D, uint64_t a
       const bool one = cn != 0 && cn <= 2;
       const bool two = cn == 2;
       examined += __popcll(__ballot(one)) + __popcll(__ballot(two));
-      level_offer(P, L, one, r0, false, 0, s_id, s_tmp, s_cnt);
-      if (__ballot(two) && !L.overflow) level_offer(P, L, two, r1, false, 0, s_id, s_tmp, s_cnt);
+      level_offer<KR, SB>(P, L, one, r0, false, 0, s_id, s_tmp, s_cnt);
+      if (__ballot(two) && !L.overflow) level_offer<KR, SB>(P, L, two, r1, false, 0, s_id, s_tmp, s_cnt);
       if (cn <= 2) cn = 0;
     }
     // long lists: one arc at a time, the whole wave on its list, four loads in
@@ -730,21 +735,21 @@ __device__ inline uint64_t gather_batch(const AdsArgs &P, uint32_t D, uint64_t a
         // entries offered (a block past the stop test is loaded, not counted)
         const uint32_t left = cnj - c0;
         examined += left < WAVE ? left : WAVE;
-        level_offer(P, L, i0 < cnj, r0, false, 0, s_id, s_tmp, s_cnt);
+        level_offer<KR, SB>(P, L, i0 < cnj, r0, false, 0, s_id, s_tmp, s_cnt);
         if (L.full0 && __ballot(i0 < cnj && r0 >= L.T0)) break;
         if (c0 + WAVE < cnj) {
           examined += left - WAVE < WAVE ? left - WAVE : WAVE;
-          level_offer(P, L, i1 < cnj, r1, false, 0, s_id, s_tmp, s_cnt);
+          level_offer<KR, SB>(P, L, i1 < cnj, r1, false, 0, s_id, s_tmp, s_cnt);
         }
         if (L.full0 && __ballot(i1 < cnj && r1 >= L.T0)) break;
         if (c0 + 2 * WAVE < cnj) {
           examined += left - 2 * WAVE < WAVE ? left - 2 * WAVE : WAVE;
-          level_offer(P, L, i2 < cnj, r2, false, 0, s_id, s_tmp, s_cnt);
+          level_offer<KR, SB>(P, L, i2 < cnj, r2, false, 0, s_id, s_tmp, s_cnt);
         }
         if (L.full0 && __ballot(i2 < cnj && r2 >= L.T0)) break;
         if (c0 + 3 * WAVE < cnj) {
           examined += left - 3 * WAVE < WAVE ? left - 3 * WAVE : WAVE;
-          level_offer(P, L, i3 < cnj, r3, false, 0, s_id, s_tmp, s_cnt);
+          level_offer<KR, SB>(P, L, i3 < cnj, r3, false, 0, s_id, s_tmp, s_cnt);
         }
         if (L.full0 && __ballot(i3 < cnj && r3 >= L.T0)) break;
       }
@@ -769,7 +774,7 @@ __device__ inline uint64_t gather_batch(const AdsArgs &P, uint32_t D, uint64_t a
       const uint32_t oex = __shfl(excl, (int)pos, WAVE);
       uint32_t r = INF32;
       if (valid) r = P.sk_rank[(size_t)ov * P.cap + ost + (idx - oex)];
-      level_offer(P, L, valid, r, false, 0, s_id, s_tmp, s_cnt);
+      level_offer<KR, SB>(P, L, valid, r, false, 0, s_id, s_tmp, s_cnt);
     }
   }
   return examined;
@@ -777,13 +782,13 @@ __device__ inline uint64_t gather_batch(const AdsArgs &P, uint32_t D, uint64_t a
 
 // Stream the candidates of arcs [a0, a1) of u for level D (every in-arc is
 // looked at: rounds run over the dense vertex list).
-template <bool UNITW, int KR>
+template <bool UNITW, int KR, uint32_t SB>
 __device__ inline uint64_t gather_arcs(const AdsArgs &P, uint32_t D, uint64_t a0, uint64_t a1, Level<KR> &L,
                                        uint32_t *s_id, uint32_t *s_tmp, uint32_t *s_cnt) {
   const int lane = lane_id();
   uint64_t examined = 0;
   for (uint64_t b = a0; b < a1 && !L.overflow; b += WAVE)
-    examined += gather_batch<UNITW, KR>(P, D, b + lane, b + lane < a1, L, s_id, s_tmp, s_cnt);
+    examined += gather_batch<UNITW, KR, SB>(P, D, b + lane, b + lane < a1, L, s_id, s_tmp, s_cnt);
   return examined;
 }
 
@@ -791,7 +796,7 @@ __device__ inline uint64_t gather_arcs(const AdsArgs &P, uint32_t D, uint64_t a0
 // each arc it marked, at the arc's position in the in-arc rows, in the plane
 // of the round the level reaches the head.  Only those arcs of [a0, a1) are
 // read: 64 plane words per step, their set bits compacted over the wave.
-template <bool UNITW, int KR>
+template <bool UNITW, int KR, uint32_t SB>
 __device__ inline uint64_t gather_flagged(const AdsArgs &P, uint32_t D, uint64_t a0, uint64_t a1, Level<KR> &L,
                                           uint32_t *s_id, uint32_t *s_tmp, uint32_t *s_cnt) {
   const int lane = lane_id();
@@ -833,7 +838,7 @@ __device__ inline uint64_t gather_flagged(const AdsArgs &P, uint32_t D, uint64_t
         }
       }
       const uint64_t a = ((wb + src) << 5) + bit;
-      examined += gather_batch<UNITW, KR>(P, D, a, valid, L, s_id, s_tmp, s_cnt);
+      examined += gather_batch<UNITW, KR, SB>(P, D, a, valid, L, s_id, s_tmp, s_cnt);
     }
   }
   return examined;
@@ -875,7 +880,7 @@ __device__ inline bool level_commit(const AdsArgs &P, uint32_t u, uint32_t D, Le
     x1 = __shfl(x, 1, WAVE);
   } else {
     for (uint32_t i = lane; i < m; i += WAVE) s_id[i] = rank_of(s_tmp[i], L.rm);
-    wave_sort_lds(s_id, m);  // m <= ADS_SB * KR
+    wave_sort_lds(s_id, m);  // m <= SB
     for (uint32_t i = lane; i < m; i += WAVE) {
       P.sk_rank[base + i] = s_id[i];
       P.sk_dist[base + i] = D;
@@ -897,11 +902,10 @@ __device__ inline bool level_commit(const AdsArgs &P, uint32_t u, uint32_t D, Le
 
 // One task, by one wave.  slot == INF32: the task is the whole vertex and
 // commits; otherwise it leaves its kept set in scratch slot `slot`.
-template <bool UNITW, int KR>
+template <bool UNITW, int KR, uint32_t SB>
 __device__ inline void ads_task(const AdsArgs &P, uint32_t D, uint32_t u, uint32_t sub, uint32_t slot,
                                 uint32_t task_arcs, int sparse, int mark, uint32_t *s_id, uint32_t *s_tmp,
                                 uint32_t *s_cnt) {
-  constexpr uint32_t SB = ADS_SB * KR;
   const int lane = lane_id();
   if (sparse && sub == 0 && lane == 0) {
     const uint32_t sD = D % P.NS;
@@ -916,8 +920,8 @@ __device__ inline void ads_task(const AdsArgs &P, uint32_t D, uint32_t u, uint32
     a1 = a0 + task_arcs < r1 ? a0 + task_arcs : r1;
   }
   const uint64_t examined = (sparse && P.plane && D >= P.flag_from)
-                                ? gather_flagged<UNITW, KR>(P, D, a0, a1, L, s_id, s_tmp, s_cnt)
-                                                 : gather_arcs<UNITW, KR>(P, D, a0, a1, L, s_id, s_tmp, s_cnt);
+                                ? gather_flagged<UNITW, KR, SB>(P, D, a0, a1, L, s_id, s_tmp, s_cnt)
+                                                 : gather_arcs<UNITW, KR, SB>(P, D, a0, a1, L, s_id, s_tmp, s_cnt);
   if (lane == 0) {
     ctr_add(P, CF_EXAMINED, examined);
     ctr_add(P, CF_SURVIVORS, L.nsurv);
@@ -952,19 +956,17 @@ __device__ inline void ads_task(const AdsArgs &P, uint32_t D, uint32_t u, uint32
 // commits; otherwise it leaves its kept set in scratch slot task_slot.  With
 // d_ntasks (device) the grid strides over that many tasks (the host does not
 // know the count); otherwise one wave per task.
-template <bool UNITW, int KR>
-__global__ __launch_bounds__(TASK_WPB * WAVE) void k_ads_tasks(AdsArgs P, uint32_t D, const uint32_t *task_u,
-                                                   const uint32_t *task_sub, const uint32_t *task_slot,
-                                                   uint32_t ntasks, const uint64_t *d_ntasks, uint32_t task_arcs,
-                                                   int sparse, int mark) {
-  constexpr uint32_t SB = ADS_SB * KR;
+template <bool UNITW, int KR, uint32_t SB>
+__global__ __launch_bounds__(TASK_WPB * WAVE) __attribute__((amdgpu_waves_per_eu(SB <= ADS_SB / 2 ? 5 : 4)))
+void k_ads_tasks(AdsArgs P, uint32_t D, const uint32_t *task_u, const uint32_t *task_sub, const uint32_t *task_slot,
+                 uint32_t ntasks, const uint64_t *d_ntasks, uint32_t task_arcs, int sparse, int mark) {
   __shared__ uint32_t lds_id[TASK_WPB][SB];
   __shared__ uint32_t lds_tmp[TASK_WPB][SB];
   __shared__ __align__(16) uint32_t lds_cnt[TASK_WPB][(2 + KR) * WAVE];
   const int wv = threadIdx.x / WAVE;
   const uint64_t total = d_ntasks ? *d_ntasks : ntasks;
   for (uint64_t item = (uint64_t)blockIdx.x * TASK_WPB + wv; item < total; item += (uint64_t)gridDim.x * TASK_WPB)
-    ads_task<UNITW, KR>(P, D, task_u[item], task_sub[item], task_slot[item], task_arcs, sparse, mark, lds_id[wv],
+    ads_task<UNITW, KR, SB>(P, D, task_u[item], task_sub[item], task_slot[item], task_arcs, sparse, mark, lds_id[wv],
                         lds_tmp[wv], lds_cnt[wv]);
 }
 
@@ -974,12 +976,11 @@ __global__ __launch_bounds__(TASK_WPB * WAVE) void k_ads_tasks(AdsArgs P, uint32
 // associative and idempotent, so the grouping does not change the result;
 // it shortens the chain of dependent work per hub, which bounds a round.
 constexpr int MERGE_WPB = 8;
-template <bool UNITW, int KR>
+template <bool UNITW, int KR, uint32_t SB>
 __global__ __launch_bounds__(MERGE_WPB * WAVE) void k_ads_merge(AdsArgs P, uint32_t D, const uint32_t *split_u,
                                                                 const uint32_t *split_first,
                                                                 const uint32_t *split_nt, uint32_t nsplit,
                                                                 const uint64_t *d_nsplit, int mark) {
-  constexpr uint32_t SB = ADS_SB * KR;
   constexpr uint32_t NW = MERGE_WPB - 1;  // waves that build partial sets
   __shared__ uint32_t lds_id[MERGE_WPB][SB];
   __shared__ uint32_t lds_tmp[MERGE_WPB][SB];
@@ -1026,7 +1027,7 @@ __global__ __launch_bounds__(MERGE_WPB * WAVE) void k_ads_merge(AdsArgs P, uint3
             id = P.kept[(size_t)otask * SB + (idx - oex)];
             r = rank_of(id, L.rm);
           }
-          level_offer(P, L, valid, r, true, id, s_id, s_tmp, s_cnt);
+          level_offer<KR, SB>(P, L, valid, r, true, id, s_id, s_tmp, s_cnt);
         }
       }
       uint32_t m = 0;
@@ -1050,7 +1051,7 @@ __global__ __launch_bounds__(MERGE_WPB * WAVE) void k_ads_merge(AdsArgs P, uint3
           const bool valid = c0 + lane < pn;
           const uint32_t id = valid ? part[c0 + lane] : INF32;
           const uint32_t r = valid ? rank_of(id, L.rm) : INF32;
-          level_offer(P, L, valid, r, true, id, s_id, s_tmp, s_cnt);
+          level_offer<KR, SB>(P, L, valid, r, true, id, s_id, s_tmp, s_cnt);
         }
       }
       bool committed = false;
@@ -1382,16 +1383,58 @@ size_t ads_scratch_bytes(uint32_t n, uint64_t m, uint32_t k, uint32_t NS) {
 
 // Builds the sketches.  Returns FL_OK, or FL_ENOMEM / FL_ENOTIMPL.  The
 // caller provides cap; on capacity overflow the call reports *need_more.
-static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool *need_more) {
+// Launches of the round kernels: the instance is picked by unit weights, the
+// set registers of k and the survivor buffer of the build.
+static void launch_tasks(hipStream_t s, uint32_t grid, bool unit, uint32_t k, uint32_t sb, const AdsArgs &P,
+                         uint32_t D, const uint32_t *tu, const uint32_t *tsub, const uint32_t *tslot, uint32_t nt,
+                         const uint64_t *dnt, uint32_t task_arcs, int sparse, int mark) {
+#define FL_TASKS(U, K, S) \
+  k_ads_tasks<U, K, S><<<grid, TASK_WPB * WAVE, 0, s>>>(P, D, tu, tsub, tslot, nt, dnt, task_arcs, sparse, mark)
+  if (k > 64) {
+    if (unit) FL_TASKS(true, 2, 2 * ADS_SB);
+    else FL_TASKS(false, 2, 2 * ADS_SB);
+  } else if (sb < ADS_SB) {
+    if (unit) FL_TASKS(true, 1, ADS_SB / 2);
+    else FL_TASKS(false, 1, ADS_SB / 2);
+  } else {
+    if (unit) FL_TASKS(true, 1, ADS_SB);
+    else FL_TASKS(false, 1, ADS_SB);
+  }
+#undef FL_TASKS
+}
+static void launch_merge(hipStream_t s, uint32_t grid, bool unit, uint32_t k, uint32_t sb, const AdsArgs &P,
+                         uint32_t D, const uint32_t *su, const uint32_t *sfirst, const uint32_t *snt, uint32_t ns,
+                         const uint64_t *dns, int mark) {
+#define FL_MERGE(U, K, S) \
+  k_ads_merge<U, K, S><<<grid, MERGE_WPB * WAVE, 0, s>>>(P, D, su, sfirst, snt, ns, dns, mark)
+  if (k > 64) {
+    if (unit) FL_MERGE(true, 2, 2 * ADS_SB);
+    else FL_MERGE(false, 2, 2 * ADS_SB);
+  } else if (sb < ADS_SB) {
+    if (unit) FL_MERGE(true, 1, ADS_SB / 2);
+    else FL_MERGE(false, 1, ADS_SB / 2);
+  } else {
+    if (unit) FL_MERGE(true, 1, ADS_SB);
+    else FL_MERGE(false, 1, ADS_SB);
+  }
+#undef FL_MERGE
+}
+
+// sb: survivor buffer (ADS_SB / 2 or ads_full_sb(k)).  *buf_over: a level
+// overflowed it (the caller restarts with a larger one).
+static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool *need_more, uint32_t sb,
+                   bool *buf_over) {
   const uint32_t n = g.n, k = cfg.k, cap = o.cap;
   const uint32_t W = g.w ? g.max_w : 1u;
   const uint32_t NS = W + 1;
   const uint32_t FW = (NS + 31) / 32;
   const bool unit = g.w == nullptr;
   *need_more = false;
+  *buf_over = false;
 
   AdsArgs P{};
   P.n = n;
+  P.sb = sb;
   P.k = k;
   P.cap = cap;
   P.W = W;
@@ -1454,7 +1497,7 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
     FL_HIP(hipMemcpyAsync(c.h_status, noff + n, 8, hipMemcpyDeviceToHost, c.s));
     c.sync();
     const uint64_t slots = c.h_status[0] + 1;
-    P.kept = c.arena->get<uint32_t>(slots * ADS_SB * (k > 64 ? 2 : 1));
+    P.kept = c.arena->get<uint32_t>(slots * sb);
     P.kept_cnt = c.arena->get<uint32_t>(slots);
   }
   // task-list scratch and lists (sized for a list of all vertices)
@@ -1565,32 +1608,11 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
                                           tl.split_nt);
         FL_LAUNCH_CHECK();
         if (c.timing) FL_HIP(hipEventRecord(ev[3 * r], c.s));
-        if (unit && k <= 64)
-          k_ads_tasks<true, 1><<<GT, TASK_WPB * WAVE, 0, c.s>>>(P, D, tl.task_u, tl.task_sub, tl.task_slot, 0,
-                                                                d_ntasks, task_arcs, 1, 1);
-        else if (unit)
-          k_ads_tasks<true, 2><<<GT, TASK_WPB * WAVE, 0, c.s>>>(P, D, tl.task_u, tl.task_sub, tl.task_slot, 0,
-                                                                d_ntasks, task_arcs, 1, 1);
-        else if (k <= 64)
-          k_ads_tasks<false, 1><<<GT, TASK_WPB * WAVE, 0, c.s>>>(P, D, tl.task_u, tl.task_sub, tl.task_slot, 0,
-                                                                 d_ntasks, task_arcs, 1, 1);
-        else
-          k_ads_tasks<false, 2><<<GT, TASK_WPB * WAVE, 0, c.s>>>(P, D, tl.task_u, tl.task_sub, tl.task_slot, 0,
-                                                                 d_ntasks, task_arcs, 1, 1);
+        launch_tasks(c.s, GT, unit, k, sb, P, D, tl.task_u, tl.task_sub, tl.task_slot, 0, d_ntasks, task_arcs, 1,
+                     1);
         FL_LAUNCH_CHECK();
         if (c.timing) FL_HIP(hipEventRecord(ev[3 * r + 1], c.s));
-        if (unit && k <= 64)
-          k_ads_merge<true, 1><<<GM, MERGE_WPB * WAVE, 0, c.s>>>(P, D, tl.split_u, tl.split_first, tl.split_nt, 0,
-                                                                 d_nsplit, 1);
-        else if (unit)
-          k_ads_merge<true, 2><<<GM, MERGE_WPB * WAVE, 0, c.s>>>(P, D, tl.split_u, tl.split_first, tl.split_nt, 0,
-                                                                 d_nsplit, 1);
-        else if (k <= 64)
-          k_ads_merge<false, 1><<<GM, MERGE_WPB * WAVE, 0, c.s>>>(P, D, tl.split_u, tl.split_first, tl.split_nt, 0,
-                                                                  d_nsplit, 1);
-        else
-          k_ads_merge<false, 2><<<GM, MERGE_WPB * WAVE, 0, c.s>>>(P, D, tl.split_u, tl.split_first, tl.split_nt, 0,
-                                                                  d_nsplit, 1);
+        launch_merge(c.s, GM, unit, k, sb, P, D, tl.split_u, tl.split_first, tl.split_nt, 0, d_nsplit, 1);
         FL_LAUNCH_CHECK();
         if (c.timing) FL_HIP(hipEventRecord(ev[3 * r + 2], c.s));
         fill_u32(c, P.wl_cnt + (size_t)slot * CNT_PAD, 1, 0);
@@ -1608,7 +1630,10 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
         *need_more = true;
         return FL_OK;
       }
-      if (st1) return FL_ENOMEM;
+      if (st1) {
+        *buf_over = true;
+        return FL_OK;
+      }
       uint32_t used = RCHUNK;
       bool done = false;
       for (uint32_t r = 0; r < RCHUNK; ++r)
@@ -1657,35 +1682,14 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
     if (T->ntasks) {
       if (c.timing) FL_HIP(hipEventRecord(e0, c.s));
       const uint32_t tb = (uint32_t)ceil_div(T->ntasks, TASK_WPB);
-      // the running bottom-k set takes one register per lane up to k = 64, two up to 128
-      if (unit && k <= 64)
-        k_ads_tasks<true, 1><<<tb, TASK_WPB * WAVE, 0, c.s>>>(P, D, T->task_u, T->task_sub, T->task_slot, T->ntasks,
-                                                              nullptr, T->task_arcs, sparse ? 1 : 0, mark ? 1 : 0);
-      else if (unit)
-        k_ads_tasks<true, 2><<<tb, TASK_WPB * WAVE, 0, c.s>>>(P, D, T->task_u, T->task_sub, T->task_slot, T->ntasks,
-                                                              nullptr, T->task_arcs, sparse ? 1 : 0, mark ? 1 : 0);
-      else if (k <= 64)
-        k_ads_tasks<false, 1><<<tb, TASK_WPB * WAVE, 0, c.s>>>(P, D, T->task_u, T->task_sub, T->task_slot, T->ntasks,
-                                                               nullptr, T->task_arcs, sparse ? 1 : 0, mark ? 1 : 0);
-      else
-        k_ads_tasks<false, 2><<<tb, TASK_WPB * WAVE, 0, c.s>>>(P, D, T->task_u, T->task_sub, T->task_slot, T->ntasks,
-                                                               nullptr, T->task_arcs, sparse ? 1 : 0, mark ? 1 : 0);
+      launch_tasks(c.s, tb, unit, k, sb, P, D, T->task_u, T->task_sub, T->task_slot, T->ntasks, nullptr,
+                   T->task_arcs, sparse ? 1 : 0, mark ? 1 : 0);
       FL_LAUNCH_CHECK();
       if (c.timing) FL_HIP(hipEventRecord(em, c.s));
       if (T->nsplit) {
         const uint32_t mb = T->nsplit;  // one block of MERGE_WPB waves per split vertex
-        if (unit && k <= 64)
-          k_ads_merge<true, 1><<<mb, MERGE_WPB * WAVE, 0, c.s>>>(P, D, T->split_u, T->split_first, T->split_nt,
-                                                                T->nsplit, nullptr, mark ? 1 : 0);
-        else if (unit)
-          k_ads_merge<true, 2><<<mb, MERGE_WPB * WAVE, 0, c.s>>>(P, D, T->split_u, T->split_first, T->split_nt,
-                                                                T->nsplit, nullptr, mark ? 1 : 0);
-        else if (k <= 64)
-          k_ads_merge<false, 1><<<mb, MERGE_WPB * WAVE, 0, c.s>>>(P, D, T->split_u, T->split_first, T->split_nt,
-                                                                 T->nsplit, nullptr, mark ? 1 : 0);
-        else
-          k_ads_merge<false, 2><<<mb, MERGE_WPB * WAVE, 0, c.s>>>(P, D, T->split_u, T->split_first, T->split_nt,
-                                                                 T->nsplit, nullptr, mark ? 1 : 0);
+        launch_merge(c.s, mb, unit, k, sb, P, D, T->split_u, T->split_first, T->split_nt, T->nsplit, nullptr,
+                     mark ? 1 : 0);
         FL_LAUNCH_CHECK();
       }
       if (c.timing) FL_HIP(hipEventRecord(e1, c.s));
@@ -1728,7 +1732,10 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
       *need_more = true;
       return FL_OK;
     }
-    if (st1) return FL_ENOMEM;
+    if (st1) {
+      *buf_over = true;
+      return FL_OK;
+    }
     uint64_t commits = 0;
     for (uint32_t i = 0; i < CTR_STRIPES; ++i) commits += hctr[(size_t)i * CTR_FIELDS + CF_COMMITS];
     const uint64_t active = commits - commits_prev;  // vertices that changed this round
@@ -1760,7 +1767,11 @@ int ads_build(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o) {
   if (g.w && g.max_w > MAX_W) return FL_ENOTIMPL;
   if (!g.in_ptr) return FL_EINVAL;  // the in-arc view is set by set_in_arcs
   uint32_t cap = ads_capacity(cfg.n_cap ? cfg.n_cap : g.n, cfg.k);
-  for (int attempt = 0; attempt < 6; ++attempt) {
+  // half the survivor buffer for k <= 32 (FL_TEST_SMALL_SURVIVOR_BUFFER: for
+  // k <= 64 too, so that tests reach the restart below on small graphs)
+  const uint32_t small_k = std::getenv("FL_TEST_SMALL_SURVIVOR_BUFFER") ? 64u : 32u;
+  uint32_t sb = cfg.k <= small_k ? ADS_SB / 2 : ads_full_sb(cfg.k);
+  for (int attempt = 0; attempt < 7; ++attempt) {
     if (cap > MAX_CAP) return FL_ENOTIMPL;
     const size_t mark = c.arena->used();
     o.cap = cap;
@@ -1771,10 +1782,18 @@ int ads_build(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o) {
     o.thr = thr_rows ? c.arena->get<uint32_t>((size_t)thr_rows * cap) : nullptr;
     o.thr_idx = cfg.thr_idx;
     const size_t after_out = c.arena->used();
-    bool more = false;
-    int rc = ads_run(c, g, cfg, o, &more);
+    bool more = false, buf_over = false;
+    int rc = ads_run(c, g, cfg, o, &more, sb, &buf_over);
     if (rc != FL_OK) return rc;
     c.arena->rewind(after_out);
+    if (buf_over) {
+      // a level overflowed the survivor buffer: again with the full one
+      if (sb >= ads_full_sb(cfg.k)) return FL_ENOMEM;
+      if (std::getenv("FL_DEBUG")) std::fprintf(stderr, "[fl] sketches: survivor buffer %u overflowed\n", sb);
+      sb = ads_full_sb(cfg.k);
+      c.arena->rewind(mark);
+      continue;
+    }
     if (std::getenv("FL_DEBUG"))
       std::fprintf(stderr, "[fl] sketches: cap %u rounds %u overflow %d\n", cap, o.rounds, (int)more);
     if (!more) {

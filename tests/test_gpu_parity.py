@@ -88,6 +88,22 @@ def test_solve_big_k(k):
         assert_solve_equal(make(), k, 1)
 
 
+
+# k <= 32 starts with a survivor buffer of 512 ids per level; a level that
+# accepts more restarts the build with the full buffer.  The hook
+# FL_TEST_SMALL_SURVIVOR_BUFFER starts k <= 64 with the small buffer too, so
+# that a modest input overflows it: the hub of a star with 10^5 leaves accepts
+# about 64 (1 + ln(10^5 / 64)) = 535 leaves in its one level at k = 64.
+@pytest.mark.parametrize("wmax", [None, 1], ids=["unit (dense rounds)", "weights 1 (worklist rounds)"])
+def test_sketches_survivor_buffer_restart(wmax, monkeypatch, capfd):
+    monkeypatch.setenv("FL_TEST_SMALL_SURVIVOR_BUFFER", "1")
+    monkeypatch.setenv("FL_DEBUG", "1")
+    g = gg.star(100_000, wmax=wmax, seed=3)
+    print(f"[sketch] star 10^5 leaves wmax={wmax} k=64, small survivor buffer", flush=True)
+    assert_sketch_equal(g, 64, seed=5)
+    err = capfd.readouterr().err
+    assert "survivor buffer 512 overflowed" in err
+
 def test_sketches_schedule_invariant():
     """Dense rounds and frontier worklists give the same bytes."""
     g = gg.rmat(12, 16 << 12, 9)
