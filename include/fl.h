@@ -116,7 +116,9 @@ typedef struct {
   double alpha0;        /* first ladder value */
   double ms_validate, ms_ads, ms_gamma, ms_open, ms_mis, ms_assign, ms_total;
   double ms_ads_kernel;          /* summed device time of the sketch-round kernel launches
-                                    (k_ads_tasks, one per distance round) */
+                                    (k_ads_tasks, one per distance round; rounds launched 16
+                                    at a time also count the empty rounds that end their last
+                                    chunk) */
   double ms_ads_merge;           /* summed device time of the merges of split hub vertices */
   uint32_t ads_kernel_launches;  /* number of sketch-round kernel launches */
   uint64_t workspace_bytes;

@@ -1642,8 +1642,10 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
           done = true;
           break;
         }
-      for (uint32_t r = 0; r < used; ++r) {
-        if (!hp[RCHUNK + r]) continue;
+      // every round of the chunk launched the round kernel (those past the
+      // last one with work exit at once): all are counted and timed, as a
+      // kernel trace sees them
+      for (uint32_t r = 0; r < RCHUNK; ++r) {
         o.launches += 1;
         if (c.timing) {
           float ms = 0.f, ms2 = 0.f;
