@@ -316,7 +316,9 @@ def _serve_point(fl, srv, dgs, arrivals, seed):
         time.sleep(0.0005)
     lat = (t_done - t_sub) * 1e3
     span = t_done.max() - t_sub.min()
-    return {"requests": count, "offered_per_s": round(count / max(arrivals[-1], 1e-9), 2),
+    # a burst (every arrival at 0) has no offered rate
+    offered = round(count / arrivals[-1], 2) if arrivals[-1] > 0 else None
+    return {"requests": count, "offered_per_s": offered,
             "completed_per_s": round(count / span, 3),
             "p50_ms": round(float(np.percentile(lat, 50)), 1), "p99_ms": round(float(np.percentile(lat, 99)), 1)}
 
