@@ -952,22 +952,351 @@ __device__ inline void ads_task(const AdsArgs &P, uint32_t D, uint32_t u, uint32
   }
 }
 
+// ---------------------------------------------------------------------------
+// Two small tasks per wave (k <= 32, rounds run from worklists).  Lanes
+// 0..31 run one task and lanes 32..63 the next; every step works within the
+// lane's half (shuffles of width 32, ballots cut to the half), so the fixed
+// per-task instructions are shared by two tasks.  A task the halves cannot
+// finish -- a slice of a split vertex, a long entry list, more than 32
+// survivors in its level -- is left to the one-wave kernel, which runs after
+// this one in the same round (pend[t] = 1); it is left before it has written
+// anything but its own flag bit, which that kernel clears again.  Tasks of a
+// round are independent and the prune does not depend on how candidates are
+// grouped, so both kernels give the same levels.
+// ---------------------------------------------------------------------------
+constexpr uint32_t HALF = 32;
+__device__ inline uint32_t half_lane() { return (uint32_t)lane_id() & (HALF - 1); }
+__device__ inline uint32_t half_ballot(bool p) { return (uint32_t)(__ballot(p) >> ((uint32_t)lane_id() & HALF)); }
+__device__ inline uint32_t half_below(uint32_t m) { return (uint32_t)__popc(m & ((1u << half_lane()) - 1u)); }
+__device__ inline uint32_t half_shfl(uint32_t x, uint32_t src) { return __shfl(x, (int)src, HALF); }
+__device__ inline uint32_t half_scan_incl(uint32_t x) {
+  const uint32_t l = half_lane();
+#pragma unroll
+  for (int d = 1; d < (int)HALF; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d, HALF);
+    if (l >= (uint32_t)d) x += y;
+  }
+  return x;
+}
+// ascending sort of one value per lane within each half (bitonic network)
+__device__ inline uint32_t half_sort(uint32_t x) {
+  const uint32_t l = half_lane();
+#pragma unroll
+  for (uint32_t k2 = 2; k2 <= HALF; k2 <<= 1) {
+#pragma unroll
+    for (uint32_t j = k2 >> 1; j > 0; j >>= 1) {
+      const uint32_t y = __shfl_xor(x, (int)j, HALF);
+      const bool keep_min = ((l & k2) == 0) == ((l & j) == 0);
+      x = keep_min ? (x < y ? x : y) : (x > y ? x : y);
+    }
+  }
+  return x;
+}
+// a bitonic sequence within each half, ascending
+__device__ inline uint32_t half_bitonic_merge(uint32_t x) {
+  const uint32_t l = half_lane();
+#pragma unroll
+  for (uint32_t j = HALF / 2; j >= 1; j >>= 1) {
+    const uint32_t y = __shfl_xor(x, (int)j, HALF);
+    x = (l & j) == 0 ? (x < y ? x : y) : (x > y ? x : y);
+  }
+  return x;
+}
+// values below r (per lane) in the half's ascending set (INF32 above its size)
+__device__ inline uint32_t half_count_below(uint32_t setv, uint32_t r) {
+  uint32_t q = 0;
+#pragma unroll
+  for (uint32_t s = HALF / 2; s >= 1; s >>= 1) {
+    const uint32_t val = half_shfl(setv, q + s - 1);
+    if (val < r) q += s;
+  }
+  if (half_shfl(setv, q) < r) ++q;  // all 32 below r
+  return q;
+}
+
+template <bool UNITW>
+__global__ __launch_bounds__(WAVE) void k_ads_pairs(AdsArgs P, uint32_t D, const uint32_t *task_u,
+                                                    const uint32_t *task_sub, const uint32_t *task_slot,
+                                                    const uint64_t *d_ntasks, uint8_t *pend) {
+  __shared__ uint32_t s_id[2][2 * HALF];            // survivors of the level (ids)
+  __shared__ uint32_t s_acc[2][HALF];               // accepted ids, in id order
+  __shared__ uint32_t s_set[2][HALF];               // the set at the level start
+  __shared__ __align__(16) uint32_t s_r[2][HALF];   // chunk ranks
+  const uint32_t lane = (uint32_t)lane_id(), h = lane >> 5, hl = lane & (HALF - 1);
+  const uint32_t k = P.k;
+  const uint64_t total = *d_ntasks;
+  const bool flagged = P.plane && D >= P.flag_from;
+  for (uint64_t pi = blockIdx.x; 2 * pi < total; pi += gridDim.x) {
+    const uint64_t t = 2 * pi + h;
+    const bool live = t < total;
+    uint32_t u = 0, slot = INF32;
+    if (live) {
+      u = task_u[t];
+      slot = task_slot[t];
+    }
+    bool defer = live && slot != INF32;  // a slice of a split vertex
+    bool act = live && !defer;           // half-uniform from here on
+    if (act && hl == 0) {
+      const uint32_t sD = D % P.NS;
+      atomicAnd(&P.flags[(size_t)u * P.FW + (sD >> 5)], ~(1u << (sD & 31)));
+    }
+    const RankMap rm = rank_map(P.seg[seg_of(P.gid, u)]);
+    const uint32_t cu = act ? P.cnt[u] : 0u;
+    const uint32_t nset0 = cu < k ? cu : k;
+    const uint32_t setv = (act && hl < nset0) ? P.bk[(size_t)u * k + hl] : INF32;
+    s_set[h][hl] = setv;
+    wave_lds_sync();
+    const bool full0 = nset0 == k;
+    const uint32_t set_kth = half_shfl(setv, k - 1);
+    const uint32_t T0 = full0 ? set_kth : INF32;
+    uint32_t ns = 0;
+    uint64_t examined = 0;
+    // one candidate per lane: kept if below T0 and not in the start set
+    auto offer = [&](bool valid, uint32_t r) {
+      bool pass = act && valid && (!full0 || r < T0);
+      if (pass) {
+        uint32_t lo = 0, hi = nset0;
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (s_set[h][mid] < r) lo = mid + 1;
+          else hi = mid;
+        }
+        if (lo < nset0 && s_set[h][lo] == r) pass = false;
+      }
+      const uint32_t m = half_ballot(pass);
+      const uint32_t np = (uint32_t)__popc(m);
+      if (ns + np > 2 * HALF) {
+        defer = true;  // more survivors than one chunk: the one-wave kernel
+        act = false;
+      } else {
+        if (pass) s_id[h][ns + half_below(m)] = id_of(r, rm);
+        ns += np;
+      }
+      wave_lds_sync();
+    };
+    // one in-arc per lane: the level its tail committed at D - w
+    auto batch = [&](bool valid, uint64_t a) {
+      uint32_t v = 0, st = 0, cn = 0, r0 = INF32, r1 = INF32;
+      if (act && valid) {
+        v = P.col[a];
+        const uint32_t wv = UNITW ? 1u : P.w[a];
+        if (wv <= D) {
+          const uint32_t src = D - wv;
+          const uint4 rec = P.lvl[(size_t)(src % P.NS) * P.n + v];
+          if (rec.x == src && (!full0 || rec.y < T0)) {
+            r0 = rec.y;
+            r1 = rec.z;
+            st = rec.w & 0xFFFFu;
+            cn = rec.w >> 16;
+          }
+        }
+      }
+      if (half_ballot(cn >= LONG_LIST)) {
+        defer = true;  // a long list is streamed by the whole wave
+        act = false;
+        cn = 0;
+      }
+      const bool one = cn != 0 && cn <= 2, two = cn == 2;
+      examined += (uint32_t)__popc(half_ballot(one)) + (uint32_t)__popc(half_ballot(two));
+      offer(one, r0);
+      offer(two, r1);
+      const uint32_t cs = (act && cn > 2) ? cn : 0u;
+      const uint32_t incl = half_scan_incl(cs);
+      const uint32_t tot = half_shfl(incl, HALF - 1);
+      const uint32_t excl = incl - cs;
+      examined += tot;
+      for (uint32_t c0 = 0;; c0 += HALF) {
+        const bool cm = act && c0 < tot;
+        if (!__ballot(cm)) break;
+        const uint32_t idx = c0 + hl;
+        uint32_t pos = 0;  // owner lane: first lane whose inclusive count exceeds idx
+#pragma unroll
+        for (uint32_t s = HALF / 2; s >= 1; s >>= 1) {
+          const uint32_t val = half_shfl(incl, pos + s - 1);
+          if (val <= idx) pos += s;
+        }
+        const bool ok = cm && idx < tot;
+        const uint32_t ov = half_shfl(v, pos), ost = half_shfl(st, pos), oex = half_shfl(excl, pos);
+        uint32_t r = INF32;
+        if (ok) r = P.sk_rank[(size_t)ov * P.cap + ost + (idx - oex)];
+        offer(ok, r);
+      }
+    };
+    uint64_t a0 = 0, a1 = 0;
+    if (act) {
+      a0 = P.row_ptr[u];
+      a1 = P.row_ptr[u + 1];
+    }
+    if (flagged) {
+      // only the arcs flagged in this round's plane
+      const uint32_t *plane = P.plane + (size_t)(D % P.NS) * P.pw;
+      const uint64_t w0 = a0 >> 5, w1 = (a1 + 31) >> 5;
+      for (uint64_t wb = w0;; wb += HALF) {
+        const bool more = act && wb < w1;
+        if (!__ballot(more)) break;
+        const uint64_t wi = wb + hl;
+        uint32_t bits = 0;
+        if (more && wi < w1) {
+          bits = plane[wi];
+          const uint64_t base = wi << 5;
+          if (base < a0) bits &= ~0u << (uint32_t)(a0 - base);
+          if (a1 - base < 32) bits &= (1u << (uint32_t)(a1 - base)) - 1u;
+        }
+        const uint32_t incl = half_scan_incl((uint32_t)__popc(bits));
+        const uint32_t tot = half_shfl(incl, HALF - 1);
+        for (uint32_t c0 = 0;; c0 += HALF) {
+          const bool cm = act && more && c0 < tot;
+          if (!__ballot(cm)) break;
+          const uint32_t idx = c0 + hl;
+          uint32_t pos = 0;  // word (lane) holding set bit idx
+#pragma unroll
+          for (uint32_t s = HALF / 2; s >= 1; s >>= 1) {
+            const uint32_t val = half_shfl(incl, pos + s - 1);
+            if (val <= idx) pos += s;
+          }
+          const bool ok = cm && idx < tot;
+          const uint32_t src = ok ? pos : 0u;
+          uint32_t x = half_shfl(bits, src);
+          uint32_t kth = idx - (half_shfl(incl, src) - (uint32_t)__popc(x));
+          uint32_t bit = 0;
+#pragma unroll
+          for (uint32_t sh = 16; sh >= 1; sh >>= 1) {
+            const uint32_t cnt = (uint32_t)__popc(x & ((1u << sh) - 1u));
+            if (kth >= cnt) {
+              kth -= cnt;
+              x >>= sh;
+              bit += sh;
+            }
+          }
+          batch(ok, ((wb + src) << 5) + bit);
+        }
+      }
+    } else {
+      for (uint64_t b = a0;; b += HALF) {
+        const bool more = act && b < a1;
+        if (!__ballot(more)) break;
+        batch(more && b + hl < a1, b + hl);
+      }
+    }
+    if (act && ns > HALF) {
+      defer = true;  // more than one chunk of survivors
+      act = false;
+    }
+    // the chunk: survivors sorted by id, each accepted if fewer than k ranks
+    // below its own are in the start set or among earlier candidates
+    uint32_t x = (act && hl < ns) ? s_id[h][hl] : INF32;
+    x = half_sort(x);
+    uint32_t left = __shfl_up(x, 1, HALF);
+    if (hl == 0) left = INF32;
+    bool valid = act && x != INF32 && x != left;
+    const uint32_t r = valid ? rank_of(x, rm) : INF32;
+    const uint32_t q = half_count_below(setv, r);
+    const uint32_t atq = half_shfl(setv, q < HALF - 1 ? q : HALF - 1);
+    if (q < nset0 && atq == r) valid = false;
+    const uint32_t vm = half_ballot(valid);
+    s_r[h][hl] = valid ? r : INF32;
+    wave_lds_sync();
+    uint32_t top = vm ? 32u - (uint32_t)__clz(vm) : 0u;
+    const uint32_t top2 = __shfl_xor(top, (int)HALF, WAVE);
+    top = top > top2 ? top : top2;
+    uint32_t cp = 0;
+    for (uint32_t j4 = 0; j4 < top; j4 += 4) {
+      const uint4 vv = *reinterpret_cast<const uint4 *>(&s_r[h][j4]);
+      cp += (j4 + 0 < hl && vv.x < r) ? 1u : 0u;
+      cp += (j4 + 1 < hl && vv.y < r) ? 1u : 0u;
+      cp += (j4 + 2 < hl && vv.z < r) ? 1u : 0u;
+      cp += (j4 + 3 < hl && vv.w < r) ? 1u : 0u;
+    }
+    const bool acc = valid && q + cp < k;
+    const uint32_t am = half_ballot(acc);
+    const uint32_t m = (uint32_t)__popc(am);
+    if (acc) s_acc[h][half_below(am)] = x;
+    wave_lds_sync();
+    // the level's ranks ascending, and the new set: the k smallest of the
+    // start set and the level
+    // (every shuffle here runs on all lanes: a lane reads another only while
+    // that lane is active)
+    const uint32_t xs = half_sort(acc ? r : INF32);
+    const uint32_t xrev = half_shfl(xs, HALF - 1 - hl);
+    uint32_t ns2 = half_bitonic_merge(setv < xrev ? setv : xrev);
+    ns2 = hl < k ? ns2 : INF32;
+    const uint32_t x0 = half_shfl(xs, 0), x1 = half_shfl(xs, 1);
+    bool committed = false;
+    if (act && m) {
+      if (cu + m > P.cap) {
+        if (hl == 0) atomicOr(&P.status[0], 1u);
+      } else {
+        committed = true;
+        const uint32_t tr = thr_row(P, u);
+        if (tr != INF32 && hl < m) P.thr[(size_t)tr * P.cap + cu + hl] = rank_of(s_acc[h][hl], rm);
+        const size_t base = (size_t)u * P.cap + cu;
+        if (hl < m) {
+          P.sk_rank[base + hl] = xs;
+          P.sk_dist[base + hl] = D;
+        }
+        const uint32_t nset = nset0 + m < k ? nset0 + m : k;
+        if (hl < nset) P.bk[(size_t)u * k + hl] = ns2;
+        if (hl == 0) {
+          P.cnt[u] = cu + m;
+          P.lvl[(size_t)(D % P.NS) * P.n + u] = level_record(D, x0, x1, cu, m);
+        }
+      }
+    }
+    // the heads of u's out-arcs are queued for round D + w
+    uint64_t b0 = 0, b1 = 0;
+    if (committed) {
+      b0 = P.out_ptr[u];
+      b1 = P.out_ptr[u + 1];
+    }
+    for (uint64_t b = b0;; b += HALF) {
+      const bool more = committed && b < b1;
+      if (!__ballot(more)) break;
+      const uint64_t a = b + hl;
+      const bool want = more && a < b1;
+      uint32_t y = 0, s = 0;
+      if (want) {
+        y = P.out_col[a];
+        const uint32_t wv = UNITW ? 1u : P.out_w[a];
+        s = (D + wv) % P.NS;
+        if (P.plane && D >= P.plane_from) {
+          const uint32_t p = P.out_to_in[a];
+          atomicOr(&P.plane[(size_t)s * P.pw + (p >> 5)], 1u << (p & 31));
+        }
+      }
+      mark_targets<UNITW>(P, want, y, s);
+    }
+    if (live && hl == 0) {
+      pend[t] = defer ? 1 : 0;
+      if (!defer) {
+        ctr_add(P, CF_EXAMINED, examined);
+        ctr_add(P, CF_SURVIVORS, ns);
+        if (committed) ctr_add(P, CF_COMMITS, 1);
+      }
+    }
+    wave_lds_sync();  // the half buffers are rewritten by the next pair
+  }
+}
+
 // One wave per task.  task_slot == INF32: the task is the whole vertex and
 // commits; otherwise it leaves its kept set in scratch slot task_slot.  With
 // d_ntasks (device) the grid strides over that many tasks (the host does not
-// know the count); otherwise one wave per task.
+// know the count); otherwise one wave per task.  With `only`, just the tasks
+// t with only[t] != 0 (those the two-task kernel left).
 template <bool UNITW, int KR, uint32_t SB>
 __global__ __launch_bounds__(TASK_WPB * WAVE) __attribute__((amdgpu_waves_per_eu(SB <= ADS_SB / 2 ? 5 : 4)))
 void k_ads_tasks(AdsArgs P, uint32_t D, const uint32_t *task_u, const uint32_t *task_sub, const uint32_t *task_slot,
-                 uint32_t ntasks, const uint64_t *d_ntasks, uint32_t task_arcs, int sparse, int mark) {
+                 uint32_t ntasks, const uint64_t *d_ntasks, uint32_t task_arcs, int sparse, int mark,
+                 const uint8_t *only) {
   __shared__ uint32_t lds_id[TASK_WPB][SB];
   __shared__ uint32_t lds_tmp[TASK_WPB][SB];
   __shared__ __align__(16) uint32_t lds_cnt[TASK_WPB][(2 + KR) * WAVE];
   const int wv = threadIdx.x / WAVE;
   const uint64_t total = d_ntasks ? *d_ntasks : ntasks;
-  for (uint64_t item = (uint64_t)blockIdx.x * TASK_WPB + wv; item < total; item += (uint64_t)gridDim.x * TASK_WPB)
+  for (uint64_t item = (uint64_t)blockIdx.x * TASK_WPB + wv; item < total; item += (uint64_t)gridDim.x * TASK_WPB) {
+    if (only && !only[item]) continue;  // done by the two-task kernel
     ads_task<UNITW, KR, SB>(P, D, task_u[item], task_sub[item], task_slot[item], task_arcs, sparse, mark, lds_id[wv],
-                        lds_tmp[wv], lds_cnt[wv]);
+                            lds_tmp[wv], lds_cnt[wv]);
+  }
 }
 
 // One block per split vertex: MERGE_WPB - 1 waves each prune the union of a
@@ -1377,6 +1706,7 @@ size_t ads_scratch_bytes(uint32_t n, uint64_t m, uint32_t k, uint32_t NS) {
   b += (size_t)slots * (ADS_SB * (k > 64 ? 2 : 1) + 1) * 4;   // kept sets of split tasks
   b += (size_t)tasks * 4 * 3 * 2 + (size_t)n * 4 * 3 * 2;  // two task lists
   b += (size_t)n * (4 * 3 + 8 * 3) + (size_t)n * 24;       // task scratch, dense list
+  b += (size_t)tasks;                      // tasks left by the two-task kernel
   b += (size_t)8 << 20;
   return b;
 }
@@ -1387,9 +1717,11 @@ size_t ads_scratch_bytes(uint32_t n, uint64_t m, uint32_t k, uint32_t NS) {
 // set registers of k and the survivor buffer of the build.
 static void launch_tasks(hipStream_t s, uint32_t grid, bool unit, uint32_t k, uint32_t sb, const AdsArgs &P,
                          uint32_t D, const uint32_t *tu, const uint32_t *tsub, const uint32_t *tslot, uint32_t nt,
-                         const uint64_t *dnt, uint32_t task_arcs, int sparse, int mark) {
-#define FL_TASKS(U, K, S) \
-  k_ads_tasks<U, K, S><<<grid, TASK_WPB * WAVE, 0, s>>>(P, D, tu, tsub, tslot, nt, dnt, task_arcs, sparse, mark)
+                         const uint64_t *dnt, uint32_t task_arcs, int sparse, int mark,
+                         const uint8_t *only = nullptr) {
+#define FL_TASKS(U, K, S)                                                                                          \
+  k_ads_tasks<U, K, S><<<grid, TASK_WPB * WAVE, 0, s>>>(P, D, tu, tsub, tslot, nt, dnt, task_arcs, sparse, mark, \
+                                                        only)
   if (k > 64) {
     if (unit) FL_TASKS(true, 2, 2 * ADS_SB);
     else FL_TASKS(false, 2, 2 * ADS_SB);
@@ -1595,6 +1927,9 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
     const uint32_t GT = (uint32_t)std::min<uint64_t>(max_tasks, 65536);  // one-wave blocks striding over tasks
     const uint32_t GM = (uint32_t)std::min<uint64_t>(n, 2048);           // merge blocks striding over hubs
     const uint32_t TB = (uint32_t)std::min<uint64_t>(ceil_div(n, 256 * TB_ITEMS), 1024);  // task-list blocks
+    const bool pairs = k <= HALF;  // the set of a level fits one half of a wave
+    const uint32_t GP = (uint32_t)std::min<uint64_t>(ceil_div(max_tasks, 2), 65536);  // two-task waves
+    uint8_t *pend_task = pairs ? c.arena->get<uint8_t>(max_tasks) : nullptr;
     uint64_t *tot = c.arena->get<uint64_t>(3);
     const uint64_t *d_ntasks = tot, *d_nsplit = tot + 2;
     for (uint32_t D0 = 1;; D0 += RCHUNK) {
@@ -1608,8 +1943,16 @@ static int ads_run(Ctx &c, const Graph &g, const AdsConfig &cfg, AdsOut &o, bool
                                           tl.split_nt);
         FL_LAUNCH_CHECK();
         if (c.timing) FL_HIP(hipEventRecord(ev[3 * r], c.s));
+        if (pairs) {
+          // k <= 32: two small tasks per wave first, then the one-wave kernel on the rest
+          if (unit)
+            k_ads_pairs<true><<<GP, WAVE, 0, c.s>>>(P, D, tl.task_u, tl.task_sub, tl.task_slot, d_ntasks, pend_task);
+          else
+            k_ads_pairs<false><<<GP, WAVE, 0, c.s>>>(P, D, tl.task_u, tl.task_sub, tl.task_slot, d_ntasks, pend_task);
+          FL_LAUNCH_CHECK();
+        }
         launch_tasks(c.s, GT, unit, k, sb, P, D, tl.task_u, tl.task_sub, tl.task_slot, 0, d_ntasks, task_arcs, 1,
-                     1);
+                     1, pairs ? pend_task : nullptr);
         FL_LAUNCH_CHECK();
         if (c.timing) FL_HIP(hipEventRecord(ev[3 * r + 1], c.s));
         launch_merge(c.s, GM, unit, k, sb, P, D, tl.split_u, tl.split_first, tl.split_nt, 0, d_nsplit, 1);
