@@ -957,8 +957,8 @@ __device__ inline void ads_task(const AdsArgs &P, uint32_t D, uint32_t u, uint32
 // 0..31 run one task and lanes 32..63 the next; every step works within the
 // lane's half (shuffles of width 32, ballots cut to the half), so the fixed
 // per-task instructions are shared by two tasks.  A task the halves cannot
-// finish -- a slice of a split vertex, a long entry list, more than 32
-// survivors in its level -- is left to the one-wave kernel, which runs after
+// finish -- a slice of a split vertex, more than 32 survivors in its level --
+// is left to the one-wave kernel, which runs after
 // this one in the same round (pend[t] = 1); it is left before it has written
 // anything but its own flag bit, which that kernel clears again.  Tasks of a
 // round are independent and the prune does not depend on how candidates are
@@ -1091,16 +1091,35 @@ __global__ __launch_bounds__(WAVE) void k_ads_pairs(AdsArgs P, uint32_t D, const
           }
         }
       }
-      if (half_ballot(cn >= LONG_LIST)) {
-        defer = true;  // a long list is streamed by the whole wave
-        act = false;
-        cn = 0;
-      }
       const bool one = cn != 0 && cn <= 2, two = cn == 2;
       examined += (uint32_t)__popc(half_ballot(one)) + (uint32_t)__popc(half_ballot(two));
       offer(one, r0);
       offer(two, r1);
-      const uint32_t cs = (act && cn > 2) ? cn : 0u;
+      // long lists: one at a time per half, 32 entries per step; a level is
+      // stored in increasing rank order, so once a rank reaches T0 the rest
+      // of the list cannot enter
+      uint32_t lm = half_ballot(act && cn >= LONG_LIST);
+      while (__ballot(lm != 0)) {
+        const bool has = lm != 0;
+        const uint32_t j = has ? (uint32_t)(__ffs(lm) - 1) : 0u;
+        if (has) lm &= lm - 1;
+        const uint32_t vj = half_shfl(v, j), stj = half_shfl(st, j);
+        uint32_t cnj = half_shfl(cn, j);
+        if (!has) cnj = 0;
+        const uint32_t *lst = P.sk_rank + (size_t)vj * P.cap + stj;
+        bool go = has;
+        for (uint32_t c0 = 0;; c0 += HALF) {
+          const bool step = go && act && c0 < cnj;
+          if (!__ballot(step)) break;
+          const uint32_t i = c0 + hl;
+          const bool ok = step && i < cnj;
+          const uint32_t r = ok ? lst[i] : INF32;
+          if (step) examined += cnj - c0 < HALF ? cnj - c0 : HALF;
+          offer(ok, r);
+          if (full0 && half_ballot(ok && r >= T0)) go = false;
+        }
+      }
+      const uint32_t cs = (act && cn > 2 && cn < LONG_LIST) ? cn : 0u;
       const uint32_t incl = half_scan_incl(cs);
       const uint32_t tot = half_shfl(incl, HALF - 1);
       const uint32_t excl = incl - cs;
