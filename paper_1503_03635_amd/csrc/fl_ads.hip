@@ -1014,8 +1014,10 @@ __device__ inline uint32_t half_count_below(uint32_t setv, uint32_t r) {
   return q;
 }
 
+// 6 waves per SIMD (80 registers, a few spilled) measured 2% faster than 5 on
+// the large weighted workload; 8 (64 registers) slower
 template <bool UNITW>
-__global__ __launch_bounds__(WAVE) void k_ads_pairs(AdsArgs P, uint32_t D, const uint32_t *task_u,
+__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_ads_pairs(AdsArgs P, uint32_t D, const uint32_t *task_u,
                                                     const uint32_t *task_sub, const uint32_t *task_slot,
                                                     const uint64_t *d_ntasks, uint8_t *pend) {
   __shared__ uint32_t s_id[2][2 * HALF];            // survivors of the level (ids)
