@@ -41,7 +41,14 @@ HBM_PEAK_GBS = 8000.0
 # VALU issue peak: each CU's 4 SIMDs complete one wave64 VALU instruction per
 # 4 cycles each, i.e. one per CU per cycle: 256 CUs x 2.4 GHz
 VALU_PEAK_INSTS = 256 * 2.4e9
+# The sketch-round kernels of one distance round: the two-task kernel (k <=
+# 32, rounds run from worklists) and the one-wave kernel that runs after it
+# on the tasks it leaves (or on every task).  A "launch" below is one round:
+# per-dispatch counters of both are summed and divided by the rounds (the
+# one-wave kernel's dispatches).
 ROUND_KERNEL = "k_ads_tasks"
+ROUND_KERNELS = ("k_ads_tasks", "k_ads_pairs")
+ROUND_LABEL = "k_ads_pairs + k_ads_tasks (one distance round)"
 CALIB_BYTES = 1 << 30
 LARGE = "rmat24_w100_fac10_lognormal_k32"
 UNIT = "rmat22_unit_k64"
@@ -83,26 +90,28 @@ def write_traffic(fetch_dir, write_dir, workload):
     def read(d, counter):
         path = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
         assert path, f"no counter_collection.csv under {d}"
-        calib, launches = [], {}
+        calib, total, rounds = [], 0.0, set()
         for row in csv.DictReader(open(path[0])):
             if row["Counter_Name"] != counter:
                 continue
             name, val = row["Kernel_Name"], float(row["Counter_Value"])
             if "neg_kernel" in name:
                 calib.append(val)
-            elif ROUND_KERNEL in name:
-                launches[row["Dispatch_Id"]] = launches.get(row["Dispatch_Id"], 0.0) + val
-        assert calib and launches, f"{counter}: calibration copy or {ROUND_KERNEL} missing in {path[0]}"
-        return calib[0], launches
+            elif any(kn in name for kn in ROUND_KERNELS):
+                total += val
+                if ROUND_KERNEL in name:
+                    rounds.add(row["Dispatch_Id"])
+        assert calib and rounds, f"{counter}: calibration copy or {ROUND_KERNEL} missing in {path[0]}"
+        return calib[0], total, len(rounds)
 
-    fc, fl_ = read(fetch_dir, "FETCH_SIZE")
-    wc, wl = read(write_dir, "WRITE_SIZE")
+    fc, ftot, nr = read(fetch_dir, "FETCH_SIZE")
+    wc, wtot, _ = read(write_dir, "WRITE_SIZE")
     f_scale = CALIB_BYTES / (fc * 1024.0)
     w_scale = CALIB_BYTES / (wc * 1024.0)
-    fetch = sum(fl_.values()) / len(fl_) * 1024.0 * f_scale
-    write = sum(wl.values()) / len(wl) * 1024.0 * w_scale
-    out = {"kernel": ROUND_KERNEL, "workload": workload, "kernel_source_hash": kernel_hash(),
-           "launches": len(fl_), "fetch_bytes_per_launch": round(fetch), "write_bytes_per_launch": round(write),
+    fetch = ftot / nr * 1024.0 * f_scale
+    write = wtot / nr * 1024.0 * w_scale
+    out = {"kernel": ROUND_LABEL, "workload": workload, "kernel_source_hash": kernel_hash(),
+           "launches": nr, "fetch_bytes_per_launch": round(fetch), "write_bytes_per_launch": round(write),
            "bytes_per_launch": round(fetch + write),
            "calibration": {"bytes": CALIB_BYTES, "fetch_kib": fc, "write_kib": wc,
                            "fetch_scale": f_scale, "write_scale": w_scale}}
@@ -118,17 +127,18 @@ def write_issue(sq_dir, workload):
     import glob
     path = glob.glob(os.path.join(sq_dir, "**", "*counter_collection.csv"), recursive=True)
     assert path, f"no counter_collection.csv under {sq_dir}"
-    per = {}
+    tot, rounds = {}, set()
     for row in csv.DictReader(open(path[0])):
-        if ROUND_KERNEL not in row["Kernel_Name"]:
+        name = row["Kernel_Name"]
+        if not any(kn in name for kn in ROUND_KERNELS):
             continue
-        d = per.setdefault(row["Dispatch_Id"], {})
-        d[row["Counter_Name"]] = d.get(row["Counter_Name"], 0.0) + float(row["Counter_Value"])
-    assert per, f"{ROUND_KERNEL} missing in {path[0]}"
-    names = sorted({n for d in per.values() for n in d})
-    out = {"kernel": ROUND_KERNEL, "workload": workload, "kernel_source_hash": kernel_hash(), "launches": len(per)}
-    for nm in names:
-        out[nm.lower() + "_per_launch"] = round(sum(d.get(nm, 0.0) for d in per.values()) / len(per))
+        if ROUND_KERNEL in name:
+            rounds.add(row["Dispatch_Id"])
+        tot[row["Counter_Name"]] = tot.get(row["Counter_Name"], 0.0) + float(row["Counter_Value"])
+    assert rounds, f"{ROUND_KERNEL} missing in {path[0]}"
+    out = {"kernel": ROUND_LABEL, "workload": workload, "kernel_source_hash": kernel_hash(), "launches": len(rounds)}
+    for nm in sorted(tot):
+        out[nm.lower() + "_per_launch"] = round(tot[nm] / len(rounds))
     json.dump(out, open(profile_file(workload, "issue"), "w"), indent=1)
     print(json.dumps(out))
 
@@ -197,7 +207,7 @@ def roofline(stats, arcs, weighted, workload):
             issue = None
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": ROUND_KERNEL, "avg_launch_ms": round(avg_ms, 3), "alg_bytes_per_launch": round(per_launch),
+            "kernel": ROUND_LABEL, "avg_launch_ms": round(avg_ms, 3), "alg_bytes_per_launch": round(per_launch),
             "launches_per_solve": round(launches / len(stats), 1),
             "merge_ms_per_solve": round(sum(s["ms_ads_merge"] for s in stats) / len(stats), 2),
             "measured_hbm_gbs": None if traffic is None else round(traffic / (avg_ms * 1e-3) / 1e9, 1),
