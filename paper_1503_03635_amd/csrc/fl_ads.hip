@@ -74,11 +74,13 @@ static_assert(TASK_ARCS_SPARSE >= TASK_ARCS, "scratch slots are sized for TASK_A
 // With arc bit planes a task reads only the arcs that carry a level, so its
 // cost follows those, not its length: rows are cut far less often.
 constexpr uint32_t TASK_ARCS_FLAGGED = 8192;
-// While most vertices are active, scanning every in-arc costs less than
-// setting a plane bit per marked arc: rounds read flagged arcs only from
-// FLAG_FROM_RINGS times the slot ring (max weight + 1) on, and commits set
-// plane bits from a ring earlier (the levels those rounds read).
-constexpr uint32_t FLAG_FROM_RINGS = 1;
+// Rounds read flagged arcs only from FLAG_FROM_RINGS times the slot ring
+// (max weight + 1) on, and commits set plane bits from a ring earlier (the
+// levels those rounds read).  With one task per wave, scanning every in-arc
+// cost less while most vertices were active (1 ring); with two small tasks
+// per wave the planes pay from the first round (0): a task reads only the
+// arcs that carry a level, and rows split at TASK_ARCS_FLAGGED from the start.
+constexpr uint32_t FLAG_FROM_RINGS = 0;
 static_assert(TASK_ARCS_FLAGGED >= TASK_ARCS, "scratch slots are sized for TASK_ARCS");
 constexpr uint32_t NBKT = 64;       // id buckets of the level prune (one per lane)
 constexpr uint32_t LONG_LIST = 64;  // entry lists at least this long are streamed one arc at a time
