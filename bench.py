@@ -298,7 +298,9 @@ def batch_leg(count, plain_count, seed):
             "n_range": [500, 200000], "degree": "Chung-Lu exponent 2.2, average 10", "weights": "1..20",
             "batched_solves_per_s": round(batch_sps, 3), "plain_solves_per_s": round(plain_sps, 3),
             "plain_sample": plain_count, "speedup": round(batch_sps / plain_sps, 2),
-            "batched_relax_per_s": round(relax / t_batch, 1), "batched_s": round(t_batch, 3)}
+            "batched_relax_per_s": round(relax / t_batch, 1), "batched_s": round(t_batch, 3),
+            "design": "disjoint unions within a device-memory budget, up to 3 sub-unions at once on worker "
+                      "streams; the host drives rungs and MIS steps (not one persistent captured launch)"}
 
 
 def _serve_point(fl, srv, dgs, arrivals, seed):
