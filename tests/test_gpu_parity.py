@@ -114,6 +114,23 @@ def test_sketches_schedule_invariant():
         assert np.array_equal(a[key], b[key])
 
 
+
+# At k <= 32 rounds run from worklists take two small tasks per wave; slices
+# of split vertices and levels of more than 32 survivors go to the one-wave
+# kernel.  Unit-weight inputs with hubs (long entry lists, split rows) on the
+# worklist schedule, next to the weighted cases above and below.
+TWO_TASK_UNIT_CASES = [
+    ("star 9000 unit k32", lambda: gg.star(9000), 32),
+    ("RMAT 2^13 unit k16", lambda: gg.rmat(13, 16 << 13, 12), 16),
+]
+
+
+@pytest.mark.parametrize("name,make,k", TWO_TASK_UNIT_CASES, ids=[c[0] for c in TWO_TASK_UNIT_CASES])
+def test_sketches_two_task_unit_worklists(name, make, k):
+    g = make()
+    print(f"[sketch] {name} n={g.n} arcs={g.n_arcs} (worklist rounds)", flush=True)
+    assert_sketch_equal(g, k, seed=4, flags=fl.FL_FLAG_NO_DENSE)
+
 SOLVE_CASES = [
     ("tiny ER n=2000 w1..10 k16 cost50", lambda: gg.tiny_er(1), 16),
     ("ER n=400 w1..10 costs 1..200", lambda: gg.with_problem(gg.er(400, 5, 7, wmax=10), 7, cost="uniform",
