@@ -232,9 +232,9 @@ def test_solve_end_phase_batched():
 
 
 # Rounds run from worklists (every round of a weighted graph) cut rows of more
-# than 2,048 arcs into several tasks whose kept sets a merge wave prunes
+# than 8,192 arcs into several tasks whose kept sets a merge block prunes
 # again: the inputs below have such hubs with weights 1..100.
-SPLIT_ARCS_SPARSE = 2048
+SPLIT_ARCS_SPARSE = 8192
 
 
 def _weighted_in_star(n, seed):
@@ -245,9 +245,10 @@ def _weighted_in_star(n, seed):
 
 
 WEIGHTED_HUB_CASES = [
-    ("star 5000 w1..100", lambda: gg.star(5000, wmax=100, seed=3), 32),
-    ("in-star 5000 w1..100", lambda: _weighted_in_star(5000, 4), 16),
-    ("RMAT 2^14 x16 w1..100", lambda: gg.rmat(14, 16 << 14, 22, wmax=100), 32),
+    ("star 9000 w1..100", lambda: gg.star(9000, wmax=100, seed=3), 32),
+    ("in-star 9000 w1..100", lambda: _weighted_in_star(9000, 4), 16),
+    ("RMAT 2^14 x16 + star 9000, w1..100",
+     lambda: gg.disjoint_union(gg.rmat(14, 16 << 14, 22, wmax=100), gg.star(9000, wmax=100, seed=5)), 32),
 ]
 
 
