@@ -959,7 +959,7 @@ __device__ inline void ads_task(const AdsArgs &P, uint32_t D, uint32_t u, uint32
 // 0..31 run one task and lanes 32..63 the next; every step works within the
 // lane's half (shuffles of width 32, ballots cut to the half), so the fixed
 // per-task instructions are shared by two tasks.  A task the halves cannot
-// finish -- a slice of a split vertex, more than 32 survivors in its level --
+// finish -- a slice of a split vertex, more than 64 survivors in its level --
 // is left to the one-wave kernel, which runs after
 // this one in the same round (pend[t] = 1); it is left before it has written
 // anything but its own flag bit, which that kernel clears again.  Tasks of a
@@ -1023,7 +1023,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(6, 8))) vo
                                                     const uint32_t *task_sub, const uint32_t *task_slot,
                                                     const uint64_t *d_ntasks, uint8_t *pend) {
   __shared__ uint32_t s_id[2][2 * HALF];            // survivors of the level (ids)
-  __shared__ uint32_t s_acc[2][HALF];               // accepted ids, in id order
+  __shared__ uint32_t s_acc[2][2 * HALF];           // accepted ids, in id order
   __shared__ uint32_t s_set[2][HALF];               // the set at the level start
   __shared__ __align__(16) uint32_t s_r[2][HALF];   // chunk ranks
   const uint32_t lane = (uint32_t)lane_id(), h = lane >> 5, hl = lane & (HALF - 1);
@@ -1201,49 +1201,81 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(6, 8))) vo
         batch(more && b + hl < a1, b + hl);
       }
     }
-    if (act && ns > HALF) {
-      defer = true;  // more than one chunk of survivors
-      act = false;
+    // Up to 64 survivors, sorted by id and decided in chunks of 32: each id
+    // is accepted if fewer than k ranks below its own are in the set (which
+    // by the second chunk holds the first chunk's accepted ranks) or among
+    // the chunk's earlier candidates.  (Every shuffle here runs on all lanes:
+    // a lane reads another only while that lane is active.)
+    const bool two = __ballot(act && ns > HALF) != 0;  // some half has a second chunk
+    uint32_t lo = half_sort((act && hl < ns) ? s_id[h][hl] : INF32), hi = INF32;
+    if (two) {
+      const uint32_t xb = half_sort((act && HALF + hl < ns) ? s_id[h][HALF + hl] : INF32);
+      const uint32_t xbr = half_shfl(xb, HALF - 1 - hl);
+      const uint32_t l2 = lo < xbr ? lo : xbr, h2 = lo < xbr ? xbr : lo;
+      lo = half_bitonic_merge(l2);  // the 32 smallest ids
+      hi = half_bitonic_merge(h2);  // the next 32
     }
-    // the chunk: survivors sorted by id, each accepted if fewer than k ranks
-    // below its own are in the start set or among earlier candidates
-    uint32_t x = (act && hl < ns) ? s_id[h][hl] : INF32;
-    x = half_sort(x);
-    uint32_t left = __shfl_up(x, 1, HALF);
-    if (hl == 0) left = INF32;
-    bool valid = act && x != INF32 && x != left;
-    const uint32_t r = valid ? rank_of(x, rm) : INF32;
-    const uint32_t q = half_count_below(setv, r);
-    const uint32_t atq = half_shfl(setv, q < HALF - 1 ? q : HALF - 1);
-    if (q < nset0 && atq == r) valid = false;
-    const uint32_t vm = half_ballot(valid);
-    s_r[h][hl] = valid ? r : INF32;
-    wave_lds_sync();
-    uint32_t top = vm ? 32u - (uint32_t)__clz(vm) : 0u;
-    const uint32_t top2 = __shfl_xor(top, (int)HALF, WAVE);
-    top = top > top2 ? top : top2;
-    uint32_t cp = 0;
-    for (uint32_t j4 = 0; j4 < top; j4 += 4) {
-      const uint4 vv = *reinterpret_cast<const uint4 *>(&s_r[h][j4]);
-      cp += (j4 + 0 < hl && vv.x < r) ? 1u : 0u;
-      cp += (j4 + 1 < hl && vv.y < r) ? 1u : 0u;
-      cp += (j4 + 2 < hl && vv.z < r) ? 1u : 0u;
-      cp += (j4 + 3 < hl && vv.w < r) ? 1u : 0u;
+    // one chunk against the set (setc, nsetc); prevx: the id before the chunk
+    auto decide = [&](uint32_t x, uint32_t prevx, uint32_t setc, uint32_t nsetc, uint32_t &r_out) -> bool {
+      uint32_t left = __shfl_up(x, 1, HALF);
+      if (hl == 0) left = prevx;
+      bool valid = act && x != INF32 && x != left;
+      const uint32_t r = valid ? rank_of(x, rm) : INF32;
+      const uint32_t q = half_count_below(setc, r);
+      const uint32_t atq = half_shfl(setc, q < HALF - 1 ? q : HALF - 1);
+      if (q < nsetc && atq == r) valid = false;
+      const uint32_t vm = half_ballot(valid);
+      s_r[h][hl] = valid ? r : INF32;
+      wave_lds_sync();
+      uint32_t top = vm ? 32u - (uint32_t)__clz(vm) : 0u;
+      const uint32_t top2 = __shfl_xor(top, (int)HALF, WAVE);
+      top = top > top2 ? top : top2;
+      uint32_t cp = 0;
+      for (uint32_t j4 = 0; j4 < top; j4 += 4) {
+        const uint4 vv = *reinterpret_cast<const uint4 *>(&s_r[h][j4]);
+        cp += (j4 + 0 < hl && vv.x < r) ? 1u : 0u;
+        cp += (j4 + 1 < hl && vv.y < r) ? 1u : 0u;
+        cp += (j4 + 2 < hl && vv.z < r) ? 1u : 0u;
+        cp += (j4 + 3 < hl && vv.w < r) ? 1u : 0u;
+      }
+      wave_lds_sync();  // s_r is rewritten by the next chunk
+      r_out = r;
+      return valid && q + cp < k;
+    };
+    // the set after a chunk: the k smallest of the set and the chunk's
+    // accepted ranks (xs, ascending)
+    auto merge_set = [&](uint32_t setc, uint32_t xs) -> uint32_t {
+      const uint32_t xrev = half_shfl(xs, HALF - 1 - hl);
+      const uint32_t mm = half_bitonic_merge(setc < xrev ? setc : xrev);
+      return hl < k ? mm : INF32;
+    };
+    uint32_t r1 = INF32;
+    const bool acc1 = decide(lo, INF32, setv, nset0, r1);
+    const uint32_t am1 = half_ballot(acc1);
+    const uint32_t m1 = (uint32_t)__popc(am1);
+    if (acc1) s_acc[h][half_below(am1)] = lo;
+    const uint32_t xs1 = half_sort(acc1 ? r1 : INF32);
+    uint32_t set1 = merge_set(setv, xs1);
+    uint32_t nset1 = nset0 + m1 < k ? nset0 + m1 : k;
+    uint32_t ra = xs1, rb = INF32, m = m1;  // the level's ranks ascending: ra, then rb
+    if (two) {
+      const uint32_t prevx = half_shfl(lo, HALF - 1);  // the first chunk is full when there is a second
+      uint32_t r2 = INF32;
+      const bool acc2 = decide(hi, prevx, set1, nset1, r2);
+      const uint32_t am2 = half_ballot(acc2);
+      const uint32_t m2 = (uint32_t)__popc(am2);
+      if (acc2) s_acc[h][m1 + half_below(am2)] = hi;
+      const uint32_t xs2 = half_sort(acc2 ? r2 : INF32);
+      set1 = merge_set(set1, xs2);
+      nset1 = nset1 + m2 < k ? nset1 + m2 : k;
+      const uint32_t x2r = half_shfl(xs2, HALF - 1 - hl);
+      const uint32_t l2 = xs1 < x2r ? xs1 : x2r, h2 = xs1 < x2r ? x2r : xs1;
+      ra = half_bitonic_merge(l2);
+      rb = half_bitonic_merge(h2);
+      m = m1 + m2;
     }
-    const bool acc = valid && q + cp < k;
-    const uint32_t am = half_ballot(acc);
-    const uint32_t m = (uint32_t)__popc(am);
-    if (acc) s_acc[h][half_below(am)] = x;
-    wave_lds_sync();
-    // the level's ranks ascending, and the new set: the k smallest of the
-    // start set and the level
-    // (every shuffle here runs on all lanes: a lane reads another only while
-    // that lane is active)
-    const uint32_t xs = half_sort(acc ? r : INF32);
-    const uint32_t xrev = half_shfl(xs, HALF - 1 - hl);
-    uint32_t ns2 = half_bitonic_merge(setv < xrev ? setv : xrev);
-    ns2 = hl < k ? ns2 : INF32;
-    const uint32_t x0 = half_shfl(xs, 0), x1 = half_shfl(xs, 1);
+    wave_lds_sync();  // s_acc is read below
+    const uint32_t x0 = half_shfl(ra, 0), x1 = half_shfl(ra, 1);
     bool committed = false;
     if (act && m) {
       if (cu + m > P.cap) {
@@ -1251,14 +1283,21 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(6, 8))) vo
       } else {
         committed = true;
         const uint32_t tr = thr_row(P, u);
-        if (tr != INF32 && hl < m) P.thr[(size_t)tr * P.cap + cu + hl] = rank_of(s_acc[h][hl], rm);
+        if (tr != INF32) {
+          uint32_t *trow = P.thr + (size_t)tr * P.cap + cu;
+          if (hl < m) trow[hl] = rank_of(s_acc[h][hl], rm);
+          if (HALF + hl < m) trow[HALF + hl] = rank_of(s_acc[h][HALF + hl], rm);
+        }
         const size_t base = (size_t)u * P.cap + cu;
         if (hl < m) {
-          P.sk_rank[base + hl] = xs;
+          P.sk_rank[base + hl] = ra;
           P.sk_dist[base + hl] = D;
         }
-        const uint32_t nset = nset0 + m < k ? nset0 + m : k;
-        if (hl < nset) P.bk[(size_t)u * k + hl] = ns2;
+        if (HALF + hl < m) {
+          P.sk_rank[base + HALF + hl] = rb;
+          P.sk_dist[base + HALF + hl] = D;
+        }
+        if (hl < nset1) P.bk[(size_t)u * k + hl] = set1;
         if (hl == 0) {
           P.cnt[u] = cu + m;
           P.lvl[(size_t)(D % P.NS) * P.n + u] = level_record(D, x0, x1, cu, m);
