@@ -25,6 +25,13 @@
  *   - The library keeps a per-device workspace cache between calls (released
  *     by fl_release_workspace).  Calls that overlap on one device from
  *     several host threads are serialised internally.
+ *
+ * Environment (read at each call; neither changes any result)
+ *   - FL_DEBUG: progress lines of the sketch rounds and the workspace
+ *     allocations on stderr, and extra sketch-round counters.
+ *   - FL_TEST_SMALL_SURVIVOR_BUFFER: test hook.  Sketch builds with k <= 64
+ *     start with the small survivor buffer that k <= 32 uses (512 ids per
+ *     level), so that modest inputs reach the restart with the full buffer.
  */
 #ifndef FL_H_
 #define FL_H_

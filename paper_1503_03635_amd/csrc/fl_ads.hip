@@ -960,11 +960,11 @@ __device__ inline void ads_task(const AdsArgs &P, uint32_t D, uint32_t u, uint32
 // lane's half (shuffles of width 32, ballots cut to the half), so the fixed
 // per-task instructions are shared by two tasks.  A task the halves cannot
 // finish -- a slice of a split vertex, more than 64 survivors in its level --
-// is left to the one-wave kernel, which runs after
-// this one in the same round (pend[t] = 1); it is left before it has written
-// anything but its own flag bit, which that kernel clears again.  Tasks of a
-// round are independent and the prune does not depend on how candidates are
-// grouped, so both kernels give the same levels.
+// is left to the one-wave kernel, which runs after this one in the same round
+// (pend[t] = 1); it is left before it has written anything but its own flag
+// bit, which that kernel clears again.  Tasks of a round are independent and
+// the prune does not depend on how candidates are grouped, so both kernels
+// give the same levels.
 // ---------------------------------------------------------------------------
 constexpr uint32_t HALF = 32;
 __device__ inline uint32_t half_lane() { return (uint32_t)lane_id() & (HALF - 1); }
@@ -1019,9 +1019,9 @@ __device__ inline uint32_t half_count_below(uint32_t setv, uint32_t r) {
 // 6 waves per SIMD (80 registers, a few spilled) measured 2% faster than 5 on
 // the large weighted workload; 8 (64 registers) slower
 template <bool UNITW>
-__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_ads_pairs(AdsArgs P, uint32_t D, const uint32_t *task_u,
-                                                    const uint32_t *task_sub, const uint32_t *task_slot,
-                                                    const uint64_t *d_ntasks, uint8_t *pend) {
+__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(6, 8)))
+void k_ads_pairs(AdsArgs P, uint32_t D, const uint32_t *task_u, const uint32_t *task_sub, const uint32_t *task_slot,
+                 const uint64_t *d_ntasks, uint8_t *pend) {
   __shared__ uint32_t s_id[2][2 * HALF];            // survivors of the level (ids)
   __shared__ uint32_t s_acc[2][2 * HALF];           // accepted ids, in id order
   __shared__ uint32_t s_set[2][HALF];               // the set at the level start
