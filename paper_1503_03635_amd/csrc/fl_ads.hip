@@ -959,14 +959,19 @@ __device__ inline void ads_task(const AdsArgs &P, uint32_t D, uint32_t u, uint32
 // 0..31 run one task and lanes 32..63 the next; every step works within the
 // lane's half (shuffles of width 32, ballots cut to the half), so the fixed
 // per-task instructions are shared by two tasks.  A task the halves cannot
-// finish -- a slice of a split vertex, more than 64 survivors in its level --
-// is left to the one-wave kernel, which runs after this one in the same round
+// finish -- a slice of a split vertex, a row of more than PAIR_ROW_MAX arcs,
+// more than 64 survivors in its level -- is left to the one-wave kernel, which runs after this one in the same round
 // (pend[t] = 1); it is left before it has written anything but its own flag
 // bit, which that kernel clears again.  Tasks of a round are independent and
 // the prune does not depend on how candidates are grouped, so both kernels
 // give the same levels.
 // ---------------------------------------------------------------------------
 constexpr uint32_t HALF = 32;
+// Rows longer than this go to the one-wave kernel too: a wave runs two
+// unrelated tasks, and a long row would keep its partner half idle (2,048
+// and 1,024 measured equal on the large weighted workload, 4,096 and no limit
+// 2-4% slower).
+constexpr uint64_t PAIR_ROW_MAX = 2048;
 __device__ inline uint32_t half_lane() { return (uint32_t)lane_id() & (HALF - 1); }
 __device__ inline uint32_t half_ballot(bool p) { return (uint32_t)(__ballot(p) >> ((uint32_t)lane_id() & HALF)); }
 __device__ inline uint32_t half_below(uint32_t m) { return (uint32_t)__popc(m & ((1u << half_lane()) - 1u)); }
@@ -1149,6 +1154,10 @@ void k_ads_pairs(AdsArgs P, uint32_t D, const uint32_t *task_u, const uint32_t *
     if (act) {
       a0 = P.row_ptr[u];
       a1 = P.row_ptr[u + 1];
+      if (a1 - a0 > PAIR_ROW_MAX) {
+        defer = true;  // a long row: the one-wave kernel
+        act = false;
+      }
     }
     if (flagged) {
       // only the arcs flagged in this round's plane
