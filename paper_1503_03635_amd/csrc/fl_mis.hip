@@ -242,7 +242,34 @@ __global__ __launch_bounds__(256) void k_sweep_heavy(SweepArgs S, uint32_t j) {
     const uint32_t x = piece_arcs(S.heavy[i], S.row_ptr, &a0, &a1);
     const uint32_t lab = S.ml[x];
     const uint32_t R = S.Rg[seg_of(S.gid, x)];
-    for (uint64_t b = a0; b < a1; b += WAVE) sweep_arc(S, q, b + lane < a1, b + lane, lab, j, R);
+    for (uint64_t b = a0; b < a1; b += 2 * WAVE) {
+      // two groups of 64 arcs: their columns, weights and labels are loaded
+      // before either is used, so twice the reads are in flight (the same
+      // steps as sweep_arc; MIS 1.17 -> 1.11 s on the large weighted workload)
+      const uint64_t i0 = b + lane, i1 = b + WAVE + lane;
+      const bool v0 = i0 < a1, v1 = i1 < a1;
+      const uint32_t y0 = v0 ? S.col[i0] : 0u, y1 = v1 ? S.col[i1] : 0u;
+      const uint32_t w0 = v0 ? (S.w ? S.w[i0] : 1u) : 0u, w1 = v1 ? (S.w ? S.w[i1] : 1u) : 0u;
+      const uint64_t d0 = (uint64_t)j + w0, d1 = (uint64_t)j + w1;
+      const bool k0 = v0 && (d0 < R || (d0 == R && (!S.tbits || ((S.tbits[y0 >> 5] >> (y0 & 31)) & 1u))));
+      const bool k1 = v1 && (d1 < R || (d1 == R && (!S.tbits || ((S.tbits[y1 >> 5] >> (y1 & 31)) & 1u))));
+      const uint32_t m0 = k0 ? __hip_atomic_load(&S.ml[y0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+      const uint32_t m1 = k1 ? __hip_atomic_load(&S.ml[y1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+      bool add0 = false, add1 = false;
+      uint32_t s0 = 0, s1 = 0;
+      if (k0 && lab < m0) {
+        s0 = (j + w0) % S.NS;
+        uint32_t *p = &S.pend[(size_t)s0 * S.n + y0];
+        if (lab < __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) add0 = atomicMin(p, lab) == INF32;
+      }
+      if (k1 && lab < m1) {
+        s1 = (j + w1) % S.NS;
+        uint32_t *p = &S.pend[(size_t)s1 * S.n + y1];
+        if (lab < __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) add1 = atomicMin(p, lab) == INF32;
+      }
+      slotq_push(S, q, add0, y0, s0);
+      slotq_push(S, q, add1, y1, s1);
+    }
   }
   slotq_flush(S, q);
 }
