@@ -124,33 +124,73 @@ __device__ inline void slotq_flush(const SweepArgs &S, SlotQ &q) {
   __shared__ uint32_t q##_ss[256 / WAVE][2 * WAVE];     \
   SlotQ q{q##_ys[threadIdx.x / WAVE], q##_ss[threadIdx.x / WAVE], 0u}
 
-// One arc step of a push (every lane calls, converged; lanes with valid ==
-// false have no arc this step): lower the pending label of the arc's head at
-// distance j + w when that is within R, and queue the head once per slot.
+// Two arc steps of a push (every lane calls, converged; a lane with v0 or v1
+// false has no arc in that group): per arc, lower the pending label of the
+// head at distance j + w when that is within R, and queue the head once per
+// slot.  Both groups' columns, weights and head minima are loaded before
+// either group is tested, so a wave keeps two chains of dependent reads in
+// flight instead of one (on the large weighted workload MIS went 1.17 ->
+// 1.11 s from the long rows, then 1.106 -> 1.095 s from the short rows).
 // A head whose settled minimum is already at most the label is skipped: it
 // reached that minimum at a smaller distance, so the push could never settle
 // (a concurrent settle only lowers ml, which keeps the test safe).  A label
 // landing at distance exactly R goes no further, so there it is kept only at
 // the sweep's targets, the vertices whose minimum is read afterwards.
-__device__ inline void sweep_arc(const SweepArgs &S, SlotQ &q, bool valid, uint64_t a, uint32_t lab, uint32_t j,
-                                 uint32_t R) {
-  bool add = false;
-  uint32_t y = 0, s = 0;
-  if (valid) {
-    y = S.col[a];
-    const uint32_t wv = S.w ? S.w[a] : 1u;
-    const uint64_t d = (uint64_t)j + wv;
-    const bool keep = d < R || (d == R && (!S.tbits || ((S.tbits[y >> 5] >> (y & 31)) & 1u)));
-    if (keep && lab < __hip_atomic_load(&S.ml[y], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-      s = (j + wv) % S.NS;
-      uint32_t *p = &S.pend[(size_t)s * S.n + y];
-      if (lab < __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-        const uint32_t old = atomicMin(p, lab);
-        add = old == INF32;
-      }
-    }
+__device__ inline void sweep_arcs2(const SweepArgs &S, SlotQ &q, uint32_t j, bool v0, uint64_t i0, uint32_t lab0,
+                                   uint32_t R0, bool v1, uint64_t i1, uint32_t lab1, uint32_t R1) {
+  const uint32_t y0 = v0 ? S.col[i0] : 0u, y1 = v1 ? S.col[i1] : 0u;
+  const uint32_t w0 = v0 ? (S.w ? S.w[i0] : 1u) : 0u, w1 = v1 ? (S.w ? S.w[i1] : 1u) : 0u;
+  const uint64_t d0 = (uint64_t)j + w0, d1 = (uint64_t)j + w1;
+  const bool k0 = v0 && (d0 < R0 || (d0 == R0 && (!S.tbits || ((S.tbits[y0 >> 5] >> (y0 & 31)) & 1u))));
+  const bool k1 = v1 && (d1 < R1 || (d1 == R1 && (!S.tbits || ((S.tbits[y1 >> 5] >> (y1 & 31)) & 1u))));
+  const uint32_t m0 = k0 ? __hip_atomic_load(&S.ml[y0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+  const uint32_t m1 = k1 ? __hip_atomic_load(&S.ml[y1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+  bool add0 = false, add1 = false;
+  uint32_t s0 = 0, s1 = 0;
+  if (k0 && lab0 < m0) {
+    s0 = (j + w0) % S.NS;
+    uint32_t *p = &S.pend[(size_t)s0 * S.n + y0];
+    if (lab0 < __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) add0 = atomicMin(p, lab0) == INF32;
   }
-  slotq_push(S, q, add, y, s);
+  if (k1 && lab1 < m1) {
+    s1 = (j + w1) % S.NS;
+    uint32_t *p = &S.pend[(size_t)s1 * S.n + y1];
+    if (lab1 < __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) add1 = atomicMin(p, lab1) == INF32;
+  }
+  slotq_push(S, q, add0, y0, s0);
+  slotq_push(S, q, add1, y1, s1);
+}
+
+// The short rows of the lanes flattened over the wave, two steps of 64 arcs
+// per call of f(v0, arc0, owner0, v1, arc1, owner1) (every lane calls,
+// converged): arc c*64 + lane of the concatenated rows is found by a binary
+// search over the running degree sum, as in flat_arcs.
+template <class F>
+__device__ inline void flat_arcs2(bool light, uint64_t a0, uint64_t deg, F &&f) {
+  const int lane = lane_id();
+  const uint32_t d = light ? (uint32_t)deg : 0u;
+  const uint32_t incl = wave_scan_incl(d);
+  const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
+  const uint32_t excl = incl - d;
+  auto locate = [&](uint32_t idx, bool &valid, uint64_t &arc, int &own) {
+    uint32_t pos = 0;  // first lane whose inclusive sum exceeds idx
+#pragma unroll
+    for (uint32_t s = 32; s >= 1; s >>= 1) {
+      const uint32_t val = __shfl(incl, (int)(pos + s - 1), WAVE);
+      if (val <= idx) pos += s;
+    }
+    valid = idx < total;
+    own = valid ? (int)pos : 0;
+    arc = shfl_u64(a0, own) + (idx - __shfl(excl, own, WAVE));
+  };
+  for (uint32_t c0 = 0; c0 < total; c0 += 2 * WAVE) {
+    bool v0, v1;
+    uint64_t x0, x1;
+    int o0, o1;
+    locate(c0 + (uint32_t)lane, v0, x0, o0);
+    locate(c0 + WAVE + (uint32_t)lane, v1, x1, o1);
+    f(v0, x0, o0, v1, x1, o1);
+  }
 }
 
 // Push the labels of the lanes' vertices (want) from distance j: short rows
@@ -169,8 +209,9 @@ __device__ inline void sweep_push_lanes(const SweepArgs &S, SlotQ &q, bool want,
   }
   const bool heavy = want && deg > FLAT_MAX;
   push_pieces(S.heavy, S.heavy_cnt + (j & 1), heavy, x, deg);
-  flat_arcs(want && !heavy, a0, deg, [&](bool valid, uint64_t a, int o) {
-    sweep_arc(S, q, valid, a, __shfl(lab, o, WAVE), j, __shfl(R, o, WAVE));
+  flat_arcs2(want && !heavy, a0, deg, [&](bool v0, uint64_t x0, int o0, bool v1, uint64_t x1, int o1) {
+    sweep_arcs2(S, q, j, v0, x0, __shfl(lab, o0, WAVE), __shfl(R, o0, WAVE), v1, x1, __shfl(lab, o1, WAVE),
+                __shfl(R, o1, WAVE));
   });
 }
 
@@ -243,32 +284,8 @@ __global__ __launch_bounds__(256) void k_sweep_heavy(SweepArgs S, uint32_t j) {
     const uint32_t lab = S.ml[x];
     const uint32_t R = S.Rg[seg_of(S.gid, x)];
     for (uint64_t b = a0; b < a1; b += 2 * WAVE) {
-      // two groups of 64 arcs: their columns, weights and labels are loaded
-      // before either is used, so twice the reads are in flight (the same
-      // steps as sweep_arc; MIS 1.17 -> 1.11 s on the large weighted workload)
       const uint64_t i0 = b + lane, i1 = b + WAVE + lane;
-      const bool v0 = i0 < a1, v1 = i1 < a1;
-      const uint32_t y0 = v0 ? S.col[i0] : 0u, y1 = v1 ? S.col[i1] : 0u;
-      const uint32_t w0 = v0 ? (S.w ? S.w[i0] : 1u) : 0u, w1 = v1 ? (S.w ? S.w[i1] : 1u) : 0u;
-      const uint64_t d0 = (uint64_t)j + w0, d1 = (uint64_t)j + w1;
-      const bool k0 = v0 && (d0 < R || (d0 == R && (!S.tbits || ((S.tbits[y0 >> 5] >> (y0 & 31)) & 1u))));
-      const bool k1 = v1 && (d1 < R || (d1 == R && (!S.tbits || ((S.tbits[y1 >> 5] >> (y1 & 31)) & 1u))));
-      const uint32_t m0 = k0 ? __hip_atomic_load(&S.ml[y0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
-      const uint32_t m1 = k1 ? __hip_atomic_load(&S.ml[y1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
-      bool add0 = false, add1 = false;
-      uint32_t s0 = 0, s1 = 0;
-      if (k0 && lab < m0) {
-        s0 = (j + w0) % S.NS;
-        uint32_t *p = &S.pend[(size_t)s0 * S.n + y0];
-        if (lab < __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) add0 = atomicMin(p, lab) == INF32;
-      }
-      if (k1 && lab < m1) {
-        s1 = (j + w1) % S.NS;
-        uint32_t *p = &S.pend[(size_t)s1 * S.n + y1];
-        if (lab < __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) add1 = atomicMin(p, lab) == INF32;
-      }
-      slotq_push(S, q, add0, y0, s0);
-      slotq_push(S, q, add1, y1, s1);
+      sweep_arcs2(S, q, j, i0 < a1, i0, lab, R, i1 < a1, i1, lab, R);
     }
   }
   slotq_flush(S, q);
