@@ -324,6 +324,56 @@ __global__ void k_pick_u64(const uint64_t *src, const uint32_t *idx, uint32_t cn
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < cnt) dst[i] = src[idx[i]];
 }
+// largest arc weight of each graph of a batch; grid (x: arc blocks, y: graph)
+struct WeightDesc {
+  const uint32_t *w;
+  uint64_t m;
+};
+__global__ __launch_bounds__(256) void k_max_weights(const WeightDesc *d, uint32_t *out) {
+  const WeightDesc D = d[blockIdx.y];
+  uint32_t mx = 0;
+  for (uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; a < D.m; a += (uint64_t)gridDim.x * blockDim.x)
+    mx = D.w[a] > mx ? D.w[a] : mx;
+  for (int o = WAVE / 2; o >= 1; o >>= 1) {
+    const uint32_t t = __shfl_xor(mx, o, WAVE);
+    mx = t > mx ? t : mx;
+  }
+  if (lane_id() == 0 && mx) atomicMax(&out[blockIdx.y], mx);
+}
+
+// Largest weight of each graph (1 for unit weights, at least 1), read before
+// a batch is cut into groups: a group's slot rings hold max weight + 1
+// distances, so its memory estimate needs the bound.  Nothing else is
+// checked here; each group's solve validates its graphs, weights included.
+static std::vector<uint32_t> batch_max_weights(Ctx &c, const fl_problem *const *ps, uint32_t G) {
+  std::vector<uint32_t> mw(G, 1u);
+  std::vector<WeightDesc> hd;
+  std::vector<uint32_t> idx;
+  uint64_t mmax = 0;
+  for (uint32_t g = 0; g < G; ++g)
+    if (ps[g]->w && ps[g]->n_arcs) {
+      hd.push_back(WeightDesc{ps[g]->w, ps[g]->n_arcs});
+      idx.push_back(g);
+      mmax = std::max<uint64_t>(mmax, ps[g]->n_arcs);
+    }
+  if (hd.empty()) return mw;
+  const uint32_t W = (uint32_t)hd.size();
+  WeightDesc *dd = c.arena->get<WeightDesc>(W);
+  uint32_t *dout = c.arena->get<uint32_t>(W);
+  FL_HIP(hipMemcpyAsync(dd, hd.data(), W * sizeof(WeightDesc), hipMemcpyHostToDevice, c.s));
+  fill_u32(c, dout, W, 0);
+  const uint32_t bx = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(ceil_div(mmax, 256 * 64), 1), 64);
+  for (uint32_t g0 = 0; g0 < W; g0 += 65535) {
+    const uint32_t gy = std::min<uint32_t>(W - g0, 65535);
+    k_max_weights<<<dim3(bx, gy), 256, 0, c.s>>>(dd + g0, dout + g0);
+    FL_LAUNCH_CHECK();
+  }
+  std::vector<uint32_t> h(W);
+  FL_HIP(hipMemcpyAsync(h.data(), dout, W * 4, hipMemcpyDeviceToHost, c.s));
+  c.sync();
+  for (uint32_t i = 0; i < W; ++i) mw[idx[i]] = std::max(h[i], 1u);
+  return mw;
+}
 
 static int check_params(const fl_problem *p, const fl_params *prm) {
   if (!p || !prm) return FL_EINVAL;
@@ -1007,6 +1057,22 @@ int fl_solve_batch(const fl_problem *ps, const fl_params *prms, fl_result *outs,
       if (ps[a].n != ps[b].n) return ps[a].n > ps[b].n;
       return a < b;
     });
+    // each weighted graph's largest weight: it sizes the slot rings of the
+    // graph's group in the memory estimate below
+    std::vector<uint32_t> mw(count, 1u);
+    {
+      std::vector<const fl_problem *> wp;
+      for (uint32_t i : ok) wp.push_back(&ps[i]);
+      fl::ensure_host_status(dc);
+      if (!dc.arena.fixed()) dc.arena.reserve(((size_t)ok.size() + 1) * (sizeof(fl::WeightDesc) + 4) + 4096);
+      dc.arena.reset();
+      fl::Ctx c;
+      c.s = (hipStream_t)stream;
+      c.arena = &dc.arena;
+      c.h_status = dc.h_status;
+      const std::vector<uint32_t> m1 = fl::batch_max_weights(c, wp.data(), (uint32_t)wp.size());
+      for (size_t t = 0; t < ok.size(); ++t) mw[ok[t]] = m1[t];
+    }
     size_t free_b = 0, total_b = 0;
     FL_HIP(hipMemGetInfo(&free_b, &total_b));
     int devb = 0;
@@ -1019,7 +1085,7 @@ int fl_solve_batch(const fl_problem *ps, const fl_params *prms, fl_result *outs,
       const fl_params &P0 = prms[ok[i0]];
       size_t i1 = i0;
       uint64_t N = 0, M = 0;
-      uint32_t nmax = 1;
+      uint32_t nmax = 1, wmax = 1;
       bool wt = false;
       while (i1 < ok.size()) {
         const uint32_t j = ok[i1];
@@ -1028,9 +1094,12 @@ int fl_solve_batch(const fl_problem *ps, const fl_params *prms, fl_result *outs,
         const uint64_t N2 = N + ps[j].n, M2 = M + ps[j].n_arcs;
         const uint32_t nm2 = std::max(nmax, ps[j].n);
         const bool wt2 = wt || ps[j].w != nullptr;
+        // a weight beyond MAX_W fails the group's validation; until then it
+        // counts as MAX_W
+        const uint32_t wm2 = std::min(std::max(wmax, ps[j].w ? mw[j] : 1u), fl::MAX_W);
         const uint32_t cap = fl::ads_capacity(nm2, P0.k);
         const size_t need = fl::estimate_bytes((uint32_t)std::min<uint64_t>(N2, 0xFFFFFFFEull), M2, N2, P0.k, cap,
-                                               wt2 ? 256 : 2) +
+                                               wt2 ? wm2 + 1 : 2) +
                             fl::union_bytes((uint32_t)(i1 - i0 + 1), N2, M2, wt2) +
                             ((P0.flags & FL_FLAG_DIRECTED) ? fl::transpose_bytes((uint32_t)std::min<uint64_t>(
                                                                  N2, 0xFFFFFFFEull), M2, wt2)
@@ -1039,6 +1108,7 @@ int fl_solve_batch(const fl_problem *ps, const fl_params *prms, fl_result *outs,
         N = N2;
         M = M2;
         nmax = nm2;
+        wmax = wm2;
         wt = wt2;
         ++i1;
       }

@@ -140,3 +140,23 @@ def test_batch_many_small_graphs():
         alone = fl.solve(dg, 8, 4, 0.1, diagnostics=True)
         torch.cuda.synchronize()
         _assert_same(_host(r), _host(alone), f"graph {i} n={dg.n}")
+
+
+def test_batch_weight_beyond_limit_reports_alone():
+    """An element whose largest weight exceeds the slot ring's limit (255)
+    gets FL_ENOTIMPL; the batch's weight pre-pass counts it at the limit when
+    it sizes the group, and the other elements are solved as usual."""
+    good = _mixed()[:3]
+    heavy = gg.with_problem(gg.er(80, 4, 12, wmax=1000), 12, cost="uniform")
+    assert int(heavy.w.max()) > 255
+    graphs = [good[0][1], heavy, good[1][1], good[2][1]]
+    dgs = [fl.to_device(g) for g in graphs]
+    print("[batch] one element with weights above 255", flush=True)
+    got = fl.solve_batch(dgs, 8, 6, 0.1, diagnostics=True, check=False)
+    torch.cuda.synchronize()
+    assert got[1]["status"] == fl._lib.FL_ENOTIMPL
+    assert got[1]["n_open"] == 0
+    for i in (0, 2, 3):
+        alone = fl.solve(dgs[i], 8, 6, 0.1, diagnostics=True)
+        torch.cuda.synchronize()
+        _assert_same(_host(got[i]), _host(alone), f"element {i}")
