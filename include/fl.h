@@ -195,7 +195,10 @@ int fl_solve_static(const fl_problem *p, const fl_params *prm, fl_result *out, v
  * disjoint union of their graphs: every phase (sketch rounds, opening rungs,
  * MIS sweeps, assignment) runs once for the whole group instead of once per
  * graph, with per-graph ranks, priorities, ladders and rung counters.  Groups
- * are cut to fit the device memory.  Statistics that describe the whole group
+ * are cut to fit 60% of the device memory; the estimate uses each weighted
+ * graph's largest weight, read by one launch over all elements before the
+ * cut, so every element's w must hold n_arcs readable entries (as for
+ * fl_solve).  Statistics that describe the whole group
  * (ads_rounds, relax_exec, the ms_* times, workspace_bytes) are reported for
  * every element of the group.  Returns FL_OK or the first element error.
  */
