@@ -314,6 +314,14 @@ struct MisWork {
 
 enum class Toward { clients, facilities };
 
+// blocks of a long-row sweep launch: twice the other frontier kernels'
+// HEAVY_BLOCKS, 32 waves per CU on 256 CUs.  A hub piece keeps two groups of
+// reads in flight per wave, and the extra waves add more: MIS 1.080 -> 0.954 s
+// on the large weighted workload, timed on one box, identical results (four
+// times gave the same; unit-weight R-MAT 2^22 lost 4 ms of its 42, from the
+// cost of launching empty distances)
+constexpr uint32_t SWEEP_HEAVY_BLOCKS = 2 * HEAVY_BLOCKS;
+
 // sweeps from at most this many sources skip the first readback of the
 // frontier counts
 constexpr uint32_t SWEEP_BLIND_SRC = 4096;
@@ -335,7 +343,7 @@ static void sweep(Ctx &c, MisWork &M, const uint32_t *src, uint32_t nsrc, uint32
   S.w = in ? M.g->in_w : M.g->w;
   k_sweep_init<<<(uint32_t)ceil_div((uint64_t)nsrc, 256), 256, 0, c.s>>>(S, src, nsrc, M.lab);
   FL_LAUNCH_CHECK();
-  k_sweep_heavy<<<HEAVY_BLOCKS, 256, 0, c.s>>>(S, 0);
+  k_sweep_heavy<<<SWEEP_HEAVY_BLOCKS, 256, 0, c.s>>>(S, 0);
   FL_LAUNCH_CHECK();
   std::vector<uint32_t> h(S.NS);
   uint32_t j = 1;
@@ -369,7 +377,7 @@ static void sweep(Ctx &c, MisWork &M, const uint32_t *src, uint32_t nsrc, uint32
     for (uint32_t b = 0; b < burst && j <= R; ++b, ++j) {
       k_sweep_round<<<blocks, 256, 0, c.s>>>(S, j);
       FL_LAUNCH_CHECK();
-      k_sweep_heavy<<<HEAVY_BLOCKS, 256, 0, c.s>>>(S, j);
+      k_sweep_heavy<<<SWEEP_HEAVY_BLOCKS, 256, 0, c.s>>>(S, j);
       FL_LAUNCH_CHECK();
     }
   }
