@@ -193,6 +193,13 @@ __device__ inline void flat_arcs2(bool light, uint64_t a0, uint64_t deg, F &&f) 
   }
 }
 
+// Rows of a sweep flattened over the wave: at most this many arcs (half the
+// other frontier kernels' FLAT_MAX).  Longer rows go to k_sweep_heavy, whose
+// waves keep more reads in flight than a flattened step: MIS 0.898 -> 0.835 s
+// on the large weighted workload against 256, timed on one box, identical
+// results.
+constexpr uint32_t SWEEP_FLAT_MAX = 128;
+
 // Push the labels of the lanes' vertices (want) from distance j: short rows
 // flattened over the wave, long rows queued for k_sweep_heavy.
 __device__ inline void sweep_push_lanes(const SweepArgs &S, SlotQ &q, bool want, uint32_t x, uint32_t lab,
@@ -207,7 +214,7 @@ __device__ inline void sweep_push_lanes(const SweepArgs &S, SlotQ &q, bool want,
     a0 = S.row_ptr[x];
     deg = S.row_ptr[x + 1] - a0;
   }
-  const bool heavy = want && deg > FLAT_MAX;
+  const bool heavy = want && deg > SWEEP_FLAT_MAX;
   push_pieces(S.heavy, S.heavy_cnt + (j & 1), heavy, x, deg);
   flat_arcs2(want && !heavy, a0, deg, [&](bool v0, uint64_t x0, int o0, bool v1, uint64_t x1, int o1) {
     sweep_arcs2(S, q, j, v0, x0, __shfl(lab, o0, WAVE), __shfl(R, o0, WAVE), v1, x1, __shfl(lab, o1, WAVE),
