@@ -325,8 +325,7 @@ enum class Toward { clients, facilities };
 // HEAVY_BLOCKS, 32 waves per CU on 256 CUs.  A hub piece keeps two groups of
 // reads in flight per wave, and the extra waves add more: MIS 1.080 -> 0.954 s
 // on the large weighted workload, timed on one box, identical results (four
-// times gave the same; unit-weight R-MAT 2^22 lost 4 ms of its 42, from the
-// cost of launching empty distances)
+// times gave the same)
 constexpr uint32_t SWEEP_HEAVY_BLOCKS = 2 * HEAVY_BLOCKS;
 
 // sweeps from at most this many sources skip the first readback of the
